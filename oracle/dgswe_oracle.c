@@ -645,10 +645,14 @@ static void element_rhs(or_mesh *M, const double *w, double t, double *dw) {
       hbv[i] = M->hb[v[i]];
       tx[i] = M->nodal[3 * v[i]]; ty[i] = M->nodal[3 * v[i] + 1]; pa[i] = M->nodal[3 * v[i] + 2];
     }
+    /* gradient of a linear nodal field f: sum_v f_v grad lam_v, written as
+     * sum_{v=1,2} (f_v - f_0) grad lam_v (the barycentric gradients sum to
+     * zero), so an ambient offset such as 1e5 Pa of air pressure cancels
+     * exactly instead of swamping the gradient */
     double dhx = 0.0, dhy = 0.0, dpx = 0.0, dpy = 0.0;
-    for (int i = 0; i < 3; ++i) {
-      dhx += hbv[i] * gl[2 * i]; dhy += hbv[i] * gl[2 * i + 1];
-      dpx += pa[i] * gl[2 * i]; dpy += pa[i] * gl[2 * i + 1];
+    for (int i = 1; i < 3; ++i) {
+      dhx += (hbv[i] - hbv[0]) * gl[2 * i]; dhy += (hbv[i] - hbv[0]) * gl[2 * i + 1];
+      dpx += (pa[i] - pa[0]) * gl[2 * i]; dpy += (pa[i] - pa[0]) * gl[2 * i + 1];
     }
     double n = M->frc.manning_elem ? M->frc.manning_elem[e] : M->frc.manning_n;
     int wet = is_wet(M, w, e);
@@ -727,7 +731,8 @@ static void to_vertices(double u0, double u1, double u2, double v[3]) {
  * Hm = zeta_0 + mean(h_b,v)):
  *   Hm <= H0       -> dry: flat depth H_v = Hm, all momentum set to 0;
  *   min H_v < H0   -> vertices below H0 raised to H0, the added volume taken
- *                     from the other vertices in proportion to H_v - H0;
+ *                     from the other vertices in proportion to H_v - H0
+ *                     (flat at Hm if rounding leaves nothing to take from);
  *   otherwise      -> unchanged. */
 int32_t or_postprocess(or_mesh *M, const double *wt, double *out) {
   const int32_t ne = M->ne;
@@ -779,9 +784,15 @@ int32_t or_postprocess(or_mesh *M, const double *wt, double *out) {
             if (Hv[i] < h0) D += h0 - Hv[i];
             else S += Hv[i] - h0;
           }
-          for (int i = 0; i < 3; ++i) {
-            if (Hv[i] < h0) Hv[i] = h0;
-            else Hv[i] = Hv[i] - D * (Hv[i] - h0) / S;
+          if (S > D) {
+            for (int i = 0; i < 3; ++i) {
+              if (Hv[i] < h0) Hv[i] = h0;
+              else Hv[i] = Hv[i] - D * (Hv[i] - h0) / S;
+            }
+          } else {
+            /* S - D = 3 (Hm - H0) > 0 in exact arithmetic; when rounding
+             * makes it vanish the element is made flat at its mean depth */
+            for (int i = 0; i < 3; ++i) Hv[i] = Hm;
           }
           changed = 1;
         }

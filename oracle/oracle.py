@@ -165,8 +165,12 @@ class Oracle:
         self._keep.append(cfun)
         self.L.or_set_extra_source(self.h, cfun, None)
 
-    def set_state(self, w, t=0.0):
+    def set_state(self, w, t=0.0, postprocess=False):
+        """postprocess=True applies the stage post-processing (limiter, then
+        wet/dry) once to `w` before it becomes the state."""
         w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, self.ne)
+        if postprocess:
+            w = self.postprocess(w)
         self.L.or_set_state(self.h, float(t), _d(w))
 
     def state(self):

@@ -275,9 +275,11 @@ def coastal_mesh(n_target: int, seed: int, lx=300.0e3, ly=600.0e3,
                  "xc": xc, "lx": lx, "ly": ly})
 
 
-def coastal_initial_state(mesh: Mesh, h0=H0) -> np.ndarray:
-    """zeta = 0 where the bed is submerged; zeta = H0 - h_b at dry nodes."""
-    zn = np.where(mesh.hb > h0, 0.0, h0 - mesh.hb)
+def coastal_initial_state(mesh: Mesh) -> np.ndarray:
+    """Sea at rest (zeta = 0) where the bed is below the geoid; bare land
+    (zeta = -h_b, no water) above it.  No element starts with its mean depth
+    on the wet/dry threshold."""
+    zn = np.where(mesh.hb > 0.0, 0.0, -mesh.hb)
     return state_from_nodal(mesh.tri, zn)
 
 
@@ -314,6 +316,9 @@ class Workload:
     params: dict
     forcing: dict
     steps: int
+    # the initial state needs the stage post-processing once (wet/dry
+    # fronts cut through elements)
+    postprocess_initial: bool = False
 
 
 def cfg_gaussian_1600(steps=200) -> Workload:
@@ -332,7 +337,7 @@ def cfg_coastal_tide(n_target=600_000, steps=2000, seed=BASE_SEED + 2) -> Worklo
     m = coastal_mesh(n_target, seed)
     w0 = coastal_initial_state(m)
     f = default_forcing(manning_n=0.025, **m2_tide(1.0))
-    return Workload(f"coastal_tide_{m.n_elems}", m, w0, default_params(), f, steps)
+    return Workload(f"coastal_tide_{m.n_elems}", m, w0, default_params(), f, steps, True)
 
 
 def holland_track(mesh: Mesh, speed=5.0, heading=0.0, offshore=100.0e3, y0=300.0e3,
@@ -350,4 +355,4 @@ def cfg_hurricane(n_target=4_000_000, steps=1000, seed=BASE_SEED + 3) -> Workloa
     m = coastal_mesh(n_target, seed)
     w0 = coastal_initial_state(m)
     f = default_forcing(manning_n=0.025, **m2_tide(1.0), **holland_track(m))
-    return Workload(f"hurricane_{m.n_elems}", m, w0, default_params(), f, steps)
+    return Workload(f"hurricane_{m.n_elems}", m, w0, default_params(), f, steps, True)
