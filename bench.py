@@ -1,0 +1,165 @@
+"""Throughput of the gfx950 DG shallow-water step on one MI355X.
+
+Workload: graded unstructured coastal mesh of ~4M triangles (p = 1) with a
+Holland hurricane (60 hPa, Rmax 40 km, 5 m/s across the shelf), M2 tide on
+the open boundary, Manning n = 0.025 and wetting/drying, FP64 - synthetic
+inputs shaped like the paper's Harvey/TX2008 case.
+
+A step is one SSP-RK(2,2) time step (two stages) over the whole mesh;
+metric = element-stage updates per second = n_elems x 2 x steps / time.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(algorithmic bytes / HIP-event duration on the solver's stream, against
+8 TB/s) and the FP64 CPU oracle timed on a bounded sample of the same
+workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "elem-stage updates/s @4M tri p=1, FP64 vs mixed/batched; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel: str, ne: int, ned: int, nn: int, stage2_share=0.5, holland=True) -> float:
+    """Bytes one launch of `kernel` must move if every array is touched once
+    (FP64 path).  Per element: state 72 B, vertex bathymetry 24 B, wet flag
+    1 B; per edge: 3 indices 12 B, normal + half length 24 B, moments 48 B,
+    mode 1 B; per node: forcing 24 B, coordinates 16 B."""
+    if kernel == "k_edge":
+        return ne * (72 + 24 + 1) + ned * (12 + 24 + 48 + 1)
+    if kernel == "k_element":
+        # state in/out, RK base on the second stage, geometry (4 gradients +
+        # area), bathymetry, node ids, edge ids, wet flag, moments + modes,
+        # nodal forcing
+        return ne * (72 + 72 + 72 * stage2_share + 40 + 24 + 12 + 12 + 1) + ned * 49 + nn * 24
+    if kernel == "k_post":
+        # unlimited state in, neighbours ids, bathymetry, inradius, state
+        # out, wet flag out
+        return ne * (72 + 12 + 24 + 8 * stage2_share + 72 + 1)
+    if kernel == "k_forcing":
+        return nn * (16 + 24)
+    raise KeyError(kernel)
+
+
+def cpu_baseline(wl, target_s=12.0):
+    """The FP64 oracle on the same mesh and forcing, on the host cores."""
+    from oracle.oracle import Oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = Oracle(wl.mesh, wl.params, wl.forcing)
+    o.set_state(wl.w0, 0.0, wl.postprocess_initial)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    more = max(0, min(50, int(target_s / max(t1, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    if more:
+        o.step(more)
+    t2 = time.perf_counter() - t0
+    steps, secs = (more, t2) if more else (1, t1)
+    rate = wl.mesh.n_elems * 2 * steps / secs
+    return {"value": rate, "unit": "elem-stage/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} steps of the same {wl.mesh.n_elems}-element workload after 1 untimed step, "
+                      f"{secs:.1f} s, OpenMP threads={threads}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--elems", type=int, default=4_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; a multi-GPU run (domain "
+                                   "decomposition with a per-stage halo exchange) is not implemented",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2508_21208_amd import workloads as W
+    from paper_2508_21208_amd.dgswe import Solver, dgswe_profile, dgswe_profile_read
+
+    t0 = time.perf_counter()
+    wl = W.cfg_hurricane(n_target=args.elems)
+    log(f"mesh {wl.mesh.n_elems} elements, {wl.mesh.n_nodes} nodes in {time.perf_counter() - t0:.1f} s")
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    s = Solver(wl.mesh, wl.params, wl.forcing, hip_stream=stream.cuda_stream)
+    info = s.info()
+    ne, ned, nn = info["n_elems"], info["n_edges"], info["n_nodes"]
+    s.set_state(wl.w0, 0.0, wl.postprocess_initial)
+    log(f"solver ready: {ne} elements, {ned} edges")
+    s.step(args.warmup)
+    s.diagnostics()
+    torch.cuda.synchronize()
+
+    if not args.no_profile:
+        dgswe_profile(s.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = dgswe_profile_read(s.h) if not args.no_profile else {}
+    if not args.no_profile:
+        dgswe_profile(s.h, 0)
+    d = s.diagnostics()
+    log(f"timed {args.steps} steps in {elapsed:.4f} s; t={d['t']:.2f} s, dt={d['dt_last']:.4f}, "
+        f"wet={d['n_wet']} dry={d['n_dry']}")
+    rate = ne * 2 * args.steps / elapsed
+
+    roof = None
+    kernels = {}
+    if prof:
+        for k, (ms, n) in prof.items():
+            if n:
+                kernels[k] = {"avg_us": 1e3 * ms / n, "launches": n, "total_ms": ms}
+        dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+        avg_s = kernels[dom]["avg_us"] * 1e-6
+        b = algorithmic_bytes(dom, ne, ned, nn)
+        ach = b / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(b), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
+        for k in kernels:
+            kb = algorithmic_bytes(k, ne, ned, nn)
+            kernels[k]["alg_GBs"] = round(kb / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
+        log("kernels: " + json.dumps(kernels))
+    s.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU baseline (oracle) ...")
+        cpu = cpu_baseline(wl)
+
+    out = {
+        "metric": METRIC, "value": rate, "unit": "elem-stage/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"hurricane graded coastal mesh, {ne} triangles, p=1, Holland 60 hPa/Rmax 40 km "
+                               f"at 5 m/s, M2 tide, Manning 0.025, wet/dry, FP64 SSP-RK2",
+                   "n_elems": ne, "n_edges": ned, "n_nodes": nn, "p": 1, "precision": "fp64"},
+        "roofline": roof, "kernels": kernels, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * dgswe.h - C ABI of the MI355X (gfx950) discontinuous Galerkin shallow
+ * water step.
+ *
+ * The method (arXiv 2508.21208, "GPU-acceleration of the Discontinuous
+ * Galerkin Shallow Water Equations Model (DG-SWEM) with OpenACC"):
+ *   - 2-D depth-averaged shallow water equations in (zeta, Hu_x, Hu_y) form
+ *     with bathymetry h_b positive downward and H = zeta + h_b
+ *     (Sec. 2.1, Eq. SWE; Sec. 2.2, Eq. cons_form);
+ *   - element weak form with a numerical flux coupling neighbours
+ *     (Sec. 2.2, Eq. elem_weak_form), local Lax-Friedrichs flux;
+ *   - p = 1 orthogonal Dubiner modal basis, diagonal mass matrix
+ *     (Sec. 2.2, Eq. dubiner);
+ *   - explicit SSP Runge-Kutta time stepping of the semi-discrete system
+ *     (Sec. 2.2, Eq. RKSSP), here SSP-RK(2,2), each stage followed by a
+ *     slope limiter and wetting/drying;
+ *   - boundaries: land (no normal flow) and ocean (prescribed tidal
+ *     elevation) (Sec. 2.1 boundary partition; Sec. 6.1 tidal forcing);
+ *   - sources: bathymetric slope, Manning bottom friction, wind stress and
+ *     atmospheric pressure gradient (Sec. 2.1 source list), the latter from
+ *     a moving Holland parametric hurricane or static nodal fields.
+ *
+ * Conventions shared by every entry point:
+ *   - Element vertices are counter-clockwise; local edge l of an element lies
+ *     opposite its vertex l.  The reference triangle has vertices (-1,-1),
+ *     (1,-1), (-1,1) mapped to the element's vertices 0, 1, 2.
+ *   - State layout w[(var*3 + mode)*n_elems + e] in FP64, var in
+ *     {zeta [m], Qx [m^2/s], Qy [m^2/s]}, modes in the order
+ *     [phi_00 = 1, phi_10 = (1 + 2 xi + eta)/2, phi_01 = (1 + 3 eta)/2],
+ *     elements in the caller's order.  The library reorders elements
+ *     internally; this is never visible at the boundary.
+ *   - Every pointer argument is HOST memory, read only during the call; the
+ *     caller keeps ownership and may free it when the call returns.  Output
+ *     buffers are allocated by the caller.  All device memory is owned by the
+ *     solver and released by dgswe_destroy.
+ *   - Every call returns a dgswe_status; nothing throws across the boundary.
+ *     On DGSWE_E_INVALID / DGSWE_E_MESH / DGSWE_E_NOMEM the handle (if any)
+ *     is left unchanged.  dgswe_last_error gives a message for the last
+ *     failed call on a handle.
+ *   - One handle per host thread at a time.  Distinct handles on distinct
+ *     streams are independent.
+ */
+#ifndef DGSWE_H
+#define DGSWE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgswe_solver dgswe_solver;
+
+typedef enum {
+  DGSWE_OK = 0,
+  DGSWE_E_INVALID = 1,   /* bad argument or unsupported option */
+  DGSWE_E_MESH = 2,      /* mesh fails validation */
+  DGSWE_E_NOMEM = 3,     /* device or host allocation failed */
+  DGSWE_E_DEVICE = 4,    /* a HIP call failed */
+  DGSWE_E_NONFINITE = 5, /* a kernel produced a NaN/Inf */
+  DGSWE_E_ALLDRY = 6     /* CFL time step undefined: no wet element and no dt cap */
+} dgswe_status;
+
+enum { DGSWE_BC_LAND = 1, DGSWE_BC_OCEAN = 2, DGSWE_BC_RIVER = 3 /* reserved: rejected */ };
+enum { DGSWE_FP64 = 0, DGSWE_MIXED = 1 };
+
+typedef struct {
+  int32_t p;         /* polynomial degree: 1 */
+  int32_t precision; /* DGSWE_FP64 */
+  double g;          /* gravity [m/s^2], e.g. 9.81 */
+  double rho0;       /* water density [kg/m^3], e.g. 1000 */
+  double h0;         /* wet/dry threshold depth H0 [m], e.g. 0.01 */
+  double cfl;        /* CFL number, used when dt_fixed <= 0 */
+  double dt_fixed;   /* > 0: fixed time step [s] */
+  double dt_max;     /* > 0: upper bound on the CFL time step [s] */
+  int32_t limiter;   /* 1: slope limiter after each stage */
+  int32_t wetdry;    /* 1: wetting/drying after each stage */
+} dgswe_params;
+
+/* Fill `p` with the defaults: p=1, FP64, g=9.81, rho0=1000, h0=0.01,
+ * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1. */
+void dgswe_default_params(dgswe_params *p);
+
+/* Build a solver for one mesh and allocate its device-resident state.
+ * (Sec. 2.2: the triangulation Omega = union of elements; Sec. 2.1: the
+ * boundary partition into ocean and land sections.)
+ *   n_nodes, node_xy [n_nodes][2] (m), node_hb [n_nodes] (bathymetry, m,
+ *     positive downward);
+ *   n_elems, tri [n_elems][3] (0-based node ids, counter-clockwise);
+ *   n_bnd, bnd_nodes [n_bnd][2], bnd_type [n_bnd]: every edge that belongs
+ *     to exactly one triangle, typed DGSWE_BC_LAND or DGSWE_BC_OCEAN;
+ *   prm: parameters (copied);
+ *   hip_stream: a hipStream_t to enqueue all work on, or NULL for a stream
+ *     owned by the solver;
+ *   out: receives the handle (NULL on error).
+ * Validation: indices in range, positive (counter-clockwise) area, no edge
+ * shared by more than two triangles, every boundary edge typed exactly
+ * once -> otherwise DGSWE_E_MESH; DGSWE_BC_RIVER, p != 1 or an unsupported
+ * precision -> DGSWE_E_INVALID.  The initial state is zero at t = 0. */
+dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const double *node_hb,
+                               int32_t n_elems, const int32_t *tri, int32_t n_bnd,
+                               const int32_t *bnd_nodes, const int32_t *bnd_type,
+                               const dgswe_params *prm, void *hip_stream, dgswe_solver **out);
+
+/* Replace the modal state (layout above, caller's element order) and set the
+ * time to t; resets the step counter.  `w` is copied before the call returns.
+ * Every stage of the step starts from a post-processed state (slope limiter,
+ * then wet/dry: a wet element has depth >= h0 at its vertices, a dry one is
+ * flat and at rest).  postprocess != 0 applies that post-processing once to
+ * `w` (use it for initial conditions); 0 takes `w` as is (use it to resume
+ * from a state returned by dgswe_read_state: the continuation is then
+ * bitwise identical to an uninterrupted run). */
+dgswe_status dgswe_set_state(dgswe_solver *s, double t, const double *w, int32_t postprocess);
+
+/* Forcing (Sec. 2.1: bottom friction tau_b, sources F_x, F_y; Sec. 6.1:
+ * tidal elevation on the open boundary).
+ *   manning_n: Manning coefficient, or per element via manning_n_elem
+ *     [n_elems] (caller's order) when non-NULL; friction
+ *     -g n^2 |Q| Q / max(H, h0)^(7/3);
+ *   tide: zeta_b(t) = tide_offset + sum_i amp_i cos(omega_i t + phase_i),
+ *     n_tide <= 8, imposed on ocean edges with the interior momentum;
+ *   wind_tau [n_nodes][2] (N/m^2) and patm [n_nodes] (Pa): static nodal
+ *     fields (either may be NULL), used when holland == 0;
+ *   holland != 0: Holland (1980) vortex centred at (x0 + vx t, y0 + vy t),
+ *     central pressure pn - dp, radius of maximum wind rmax, shape B, air
+ *     density rho_air, Coriolis parameter coriolis_f, surface wind =
+ *     wind_factor x gradient wind, stress rho_air Cd |W| W with
+ *     Cd = min(3.5e-3, (0.75 + 0.067 |W|) 1e-3), evaluated at the nodes at
+ *     every stage time. */
+typedef struct {
+  double manning_n;
+  const double *manning_n_elem;
+  int32_t n_tide;
+  const double *tide_amp, *tide_omega, *tide_phase;
+  double tide_offset;
+  const double *wind_tau;
+  const double *patm;
+  int32_t holland;
+  double x0, y0, vx, vy, dp, pn, rmax, B, rho_air, coriolis_f, wind_factor;
+} dgswe_forcing;
+
+dgswe_status dgswe_set_forcing(dgswe_solver *s, const dgswe_forcing *f);
+
+/* Enqueue n_steps SSP-RK(2,2) steps on the solver's stream and return
+ * without waiting (Sec. 2.2, Eq. RKSSP; Sec. 5.2, Algorithms 1-3).  Each
+ * step computes its dt on the device: dt_fixed if > 0, otherwise
+ * cfl * min over wet elements of 2 r_e / (|Q_mean|/H_mean + sqrt(g H_mean))
+ * (r_e the inradius), capped by dt_max if > 0.  Errors detected by the
+ * kernels (DGSWE_E_NONFINITE, DGSWE_E_ALLDRY) stop all further steps and
+ * are reported by the next dgswe_read_state. */
+dgswe_status dgswe_step(dgswe_solver *s, int32_t n_steps);
+
+typedef struct {
+  double t;        /* model time [s] */
+  double dt_last;  /* dt of the last step [s] */
+  double mass;     /* sum_e A_e zeta_mean_e [m^3] */
+  double volume;   /* sum_e A_e H_mean_e [m^3] */
+  int64_t steps;   /* steps since dgswe_set_state */
+  int32_t n_wet, n_dry;
+} dgswe_diag;
+
+/* Wait for the solver's stream, then copy the state (if w_out != NULL, same
+ * layout as dgswe_set_state) and the diagnostics (if d != NULL).  Returns
+ * the first kernel-detected error, if any (the data are still copied). */
+dgswe_status dgswe_read_state(dgswe_solver *s, double *w_out, dgswe_diag *d);
+
+/* Release the solver and its device memory (NULL is ignored). */
+void dgswe_destroy(dgswe_solver *s);
+
+/* Message for the last failed call on `s` (or the last failed
+ * dgswe_create_mesh in this thread when s is NULL).  Never NULL. */
+const char *dgswe_last_error(const dgswe_solver *s);
+
+/* Kernel timing with HIP events on the solver's stream.  enable != 0 starts
+ * recording (and clears earlier records); 0 stops. */
+dgswe_status dgswe_profile(dgswe_solver *s, int32_t enable);
+
+/* Per-kernel totals since profiling was enabled: for up to max_kernels
+ * kernels writes a NUL-terminated name into names + 32*i (32 bytes each),
+ * the summed duration in ms and the launch count.  *n_out receives the
+ * number of kernels written.  Waits for the stream. */
+dgswe_status dgswe_profile_read(dgswe_solver *s, int32_t max_kernels, char *names, double *total_ms,
+                                int64_t *launches, int32_t *n_out);
+
+/* Sizes after preprocessing: out[0] = nodes, out[1] = elements,
+ * out[2] = edges, out[3] = boundary edges. */
+dgswe_status dgswe_mesh_info(const dgswe_solver *s, int64_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGSWE_H */

@@ -1,0 +1,230 @@
+// Host-side preprocessing of a triangle mesh for the gfx950 step:
+// validation, locality reordering of elements along a Hilbert curve, the
+// edge table (each edge once, oriented from its lower-numbered element),
+// per-element geometry and the element -> edge / neighbour / node tables.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <numeric>
+
+#include "dgswe_internal.h"
+#include "../../include/dgswe.h"
+
+namespace dgswe {
+namespace {
+
+// Index of cell (x, y) along a Hilbert curve filling a 2^order x 2^order grid.
+// Each level picks the quadrant (visiting order 0: lower-left, 1: upper-left,
+// 2: upper-right, 3: lower-right) and reflects/transposes the coordinates so
+// that the sub-curve inside the quadrant starts and ends at the right corners.
+uint64_t hilbert_index(int order, uint32_t x, uint32_t y) {
+  uint64_t d = 0;
+  for (int lvl = order - 1; lvl >= 0; --lvl) {
+    const uint32_t half = 1u << lvl;
+    const uint32_t rx = (x & half) ? 1u : 0u;
+    const uint32_t ry = (y & half) ? 1u : 0u;
+    d += (uint64_t)half * half * ((3u * rx) ^ ry);
+    const uint32_t mask = (half << 1) - 1u;
+    x &= mask >> 1;
+    y &= mask >> 1;
+    if (ry == 0) {
+      if (rx == 1) {
+        x = (half - 1u) - x;
+        y = (half - 1u) - y;
+      }
+      std::swap(x, y);
+    }
+  }
+  return d;
+}
+
+struct HalfEdge {
+  uint64_t key;
+  int e, l;
+};
+
+}  // namespace
+
+int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *tri, int nbnd,
+                 const int *bnd, const int *btype, Prep &P, std::string &err) {
+  if (nn <= 0 || ne <= 0 || nbnd < 0 || !xy || !hb || !tri || (nbnd > 0 && (!bnd || !btype))) {
+    err = "invalid mesh arguments";
+    return DGSWE_E_INVALID;
+  }
+  for (int i = 0; i < nbnd; ++i) {
+    if (btype[i] == DGSWE_BC_RIVER) {
+      err = "river boundaries are not supported";
+      return DGSWE_E_INVALID;
+    }
+    if (btype[i] != DGSWE_BC_LAND && btype[i] != DGSWE_BC_OCEAN) {
+      err = "unknown boundary type";
+      return DGSWE_E_MESH;
+    }
+  }
+  for (int64_t i = 0; i < 3LL * ne; ++i)
+    if (tri[i] < 0 || tri[i] >= nn) {
+      err = "triangle node index out of range";
+      return DGSWE_E_MESH;
+    }
+  for (int e = 0; e < ne; ++e) {
+    const int *v = tri + 3 * e;
+    double ax = xy[2 * v[1]] - xy[2 * v[0]], ay = xy[2 * v[1] + 1] - xy[2 * v[0] + 1];
+    double bx = xy[2 * v[2]] - xy[2 * v[0]], by = xy[2 * v[2] + 1] - xy[2 * v[0] + 1];
+    if (!(ax * by - bx * ay > 0.0)) {
+      err = "triangle " + std::to_string(e) + " is not counter-clockwise with positive area";
+      return DGSWE_E_MESH;
+    }
+  }
+  P.nn = nn;
+  P.ne = ne;
+
+  // --- Hilbert order of the element centroids
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  for (int i = 0; i < nn; ++i) {
+    xmin = std::min(xmin, xy[2 * i]); xmax = std::max(xmax, xy[2 * i]);
+    ymin = std::min(ymin, xy[2 * i + 1]); ymax = std::max(ymax, xy[2 * i + 1]);
+  }
+  const int order = 20;
+  const double span = std::max(xmax - xmin, ymax - ymin);
+  const double scale = span > 0 ? ((double)((1u << order) - 1u)) / span : 0.0;
+  std::vector<uint64_t> key(ne);
+  for (int e = 0; e < ne; ++e) {
+    const int *v = tri + 3 * e;
+    double cx = (xy[2 * v[0]] + xy[2 * v[1]] + xy[2 * v[2]]) / 3.0;
+    double cy = (xy[2 * v[0] + 1] + xy[2 * v[1] + 1] + xy[2 * v[2] + 1]) / 3.0;
+    key[e] = hilbert_index(order, (uint32_t)((cx - xmin) * scale), (uint32_t)((cy - ymin) * scale));
+  }
+  P.perm.resize(ne);
+  std::iota(P.perm.begin(), P.perm.end(), 0);
+  std::stable_sort(P.perm.begin(), P.perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+  P.iperm.resize(ne);
+  for (int i = 0; i < ne; ++i) P.iperm[P.perm[i]] = i;
+
+  // --- edges from half-edges sorted by their node pair
+  std::vector<HalfEdge> he(3 * (size_t)ne);
+  for (int i = 0; i < ne; ++i) {
+    const int *v = tri + 3 * (size_t)P.perm[i];
+    for (int l = 0; l < 3; ++l) {
+      uint64_t a = (uint64_t)v[(l + 1) % 3], b = (uint64_t)v[(l + 2) % 3];
+      he[3 * (size_t)i + l] = {std::min(a, b) * (uint64_t)nn + std::max(a, b), i, l};
+    }
+  }
+  std::sort(he.begin(), he.end(), [](const HalfEdge &a, const HalfEdge &b) {
+    return a.key != b.key ? a.key < b.key : a.e < b.e;
+  });
+  std::vector<std::pair<uint64_t, int>> bkeys(nbnd);
+  for (int i = 0; i < nbnd; ++i) {
+    int a = bnd[2 * i], b = bnd[2 * i + 1];
+    if (a < 0 || a >= nn || b < 0 || b >= nn || a == b) {
+      err = "boundary edge node index out of range";
+      return DGSWE_E_MESH;
+    }
+    bkeys[i] = {(uint64_t)std::min(a, b) * (uint64_t)nn + (uint64_t)std::max(a, b), btype[i]};
+  }
+  std::sort(bkeys.begin(), bkeys.end());
+  for (int i = 1; i < nbnd; ++i)
+    if (bkeys[i].first == bkeys[i - 1].first) {
+      err = "boundary edge listed twice";
+      return DGSWE_E_MESH;
+    }
+  struct Edge { int ep, lp, em, lm, type; };
+  std::vector<Edge> edges;
+  edges.reserve(3 * (size_t)ne / 2 + 64);
+  int nb_found = 0;
+  for (size_t i = 0; i < he.size();) {
+    size_t j = i + 1;
+    while (j < he.size() && he[j].key == he[i].key) ++j;
+    if (j - i > 2) {
+      err = "edge shared by more than two triangles";
+      return DGSWE_E_MESH;
+    }
+    Edge E{he[i].e, he[i].l, -1, -1, 0};
+    if (j - i == 2) {
+      E.em = he[i + 1].e;
+      E.lm = he[i + 1].l;
+    } else {
+      auto it = std::lower_bound(bkeys.begin(), bkeys.end(), std::make_pair(he[i].key, -1));
+      if (it == bkeys.end() || it->first != he[i].key) {
+        err = "boundary edge without a type";
+        return DGSWE_E_MESH;
+      }
+      E.type = it->second;
+      ++nb_found;
+    }
+    edges.push_back(E);
+    i = j;
+  }
+  if (nb_found != nbnd) {
+    err = "a listed boundary edge is not on the mesh boundary";
+    return DGSWE_E_MESH;
+  }
+  std::sort(edges.begin(), edges.end(), [](const Edge &a, const Edge &b) {
+    return a.ep != b.ep ? a.ep < b.ep : a.lp < b.lp;
+  });
+  const int ned = (int)edges.size();
+  P.ned = ned;
+  P.nbnd = nbnd;
+
+  // --- per-element geometry (internal order)
+  P.gx1.resize(ne); P.gy1.resize(ne); P.gx2.resize(ne); P.gy2.resize(ne);
+  P.area.resize(ne); P.inr2.resize(ne); P.hbv.resize(3 * (size_t)ne);
+  P.el_edge.assign(3 * (size_t)ne, -1); P.el_nb.assign(3 * (size_t)ne, -1);
+  P.el_node.resize(3 * (size_t)ne);
+  for (int i = 0; i < ne; ++i) {
+    const int *v = tri + 3 * (size_t)P.perm[i];
+    double X[3], Y[3];
+    for (int k = 0; k < 3; ++k) {
+      X[k] = xy[2 * v[k]];
+      Y[k] = xy[2 * v[k] + 1];
+      P.hbv[(size_t)k * ne + i] = hb[v[k]];
+      P.el_node[(size_t)k * ne + i] = v[k];
+    }
+    double A = 0.5 * ((X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]));
+    // barycentric gradients grad lambda_k = (y_{k+1} - y_{k+2}, x_{k+2} - x_{k+1}) / 2A
+    double lx[3], ly[3];
+    for (int k = 0; k < 3; ++k) {
+      int a = (k + 1) % 3, b = (k + 2) % 3;
+      lx[k] = (Y[a] - Y[b]) / (2.0 * A);
+      ly[k] = (X[b] - X[a]) / (2.0 * A);
+    }
+    // phi_10 = lambda_1 - lambda_0, phi_01 = 2 lambda_2 - lambda_0 - lambda_1
+    P.gx1[i] = lx[1] - lx[0];
+    P.gy1[i] = ly[1] - ly[0];
+    P.gx2[i] = 2.0 * lx[2] - lx[0] - lx[1];
+    P.gy2[i] = 2.0 * ly[2] - ly[0] - ly[1];
+    P.area[i] = A;
+    double per = std::hypot(X[1] - X[2], Y[1] - Y[2]) + std::hypot(X[2] - X[0], Y[2] - Y[0]) +
+                 std::hypot(X[0] - X[1], Y[0] - Y[1]);
+    P.inr2[i] = 4.0 * A / per;
+  }
+  P.ed_ep.resize(ned); P.ed_em.resize(ned); P.ed_info.resize(ned);
+  P.ed_nx.resize(ned); P.ed_ny.resize(ned); P.ed_hlen.resize(ned);
+  for (int d = 0; d < ned; ++d) {
+    const Edge &E = edges[d];
+    P.ed_ep[d] = E.ep;
+    P.ed_em[d] = E.em;
+    P.ed_info[d] = E.lp | ((E.lm < 0 ? 0 : E.lm) << 2) | (E.type << 4);
+    const int *v = tri + 3 * (size_t)P.perm[E.ep];
+    int na = v[(E.lp + 1) % 3], nb = v[(E.lp + 2) % 3];
+    double dx = xy[2 * nb] - xy[2 * na], dy = xy[2 * nb + 1] - xy[2 * na + 1];
+    double len = std::hypot(dx, dy);
+    P.ed_nx[d] = dy / len;
+    P.ed_ny[d] = -dx / len;
+    P.ed_hlen[d] = 0.5 * len;
+    P.el_edge[(size_t)E.lp * ne + E.ep] = d << 1;
+    if (E.em >= 0) {
+      P.el_edge[(size_t)E.lm * ne + E.em] = (d << 1) | 1;
+      P.el_nb[(size_t)E.lp * ne + E.ep] = E.em;
+      P.el_nb[(size_t)E.lm * ne + E.em] = E.ep;
+    }
+  }
+  P.node_x.resize(nn);
+  P.node_y.resize(nn);
+  for (int i = 0; i < nn; ++i) {
+    P.node_x[i] = xy[2 * i];
+    P.node_y[i] = xy[2 * i + 1];
+  }
+  return DGSWE_OK;
+}
+
+}  // namespace dgswe

@@ -1,0 +1,262 @@
+"""ctypes binding of the gfx950 library `libdgswe.so` (include/dgswe.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels.
+The functions keep the C names; `Solver` is a thin owner of one handle.
+There is no fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgswe.so")
+
+DGSWE_OK = 0
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_MESH", 3: "E_NOMEM", 4: "E_DEVICE",
+                5: "E_NONFINITE", 6: "E_ALLDRY"}
+DGSWE_FP64 = 0
+DGSWE_MIXED = 1
+
+EXPORTED = ("dgswe_default_params", "dgswe_create_mesh", "dgswe_set_state", "dgswe_set_forcing",
+            "dgswe_step", "dgswe_read_state", "dgswe_destroy", "dgswe_last_error", "dgswe_profile",
+            "dgswe_profile_read", "dgswe_mesh_info")
+
+
+class dgswe_params(C.Structure):
+    _fields_ = [("p", C.c_int32), ("precision", C.c_int32), ("g", C.c_double), ("rho0", C.c_double),
+                ("h0", C.c_double), ("cfl", C.c_double), ("dt_fixed", C.c_double), ("dt_max", C.c_double),
+                ("limiter", C.c_int32), ("wetdry", C.c_int32)]
+
+
+_dp = C.POINTER(C.c_double)
+
+
+class dgswe_forcing(C.Structure):
+    _fields_ = [("manning_n", C.c_double), ("manning_n_elem", _dp), ("n_tide", C.c_int32),
+                ("tide_amp", _dp), ("tide_omega", _dp), ("tide_phase", _dp), ("tide_offset", C.c_double),
+                ("wind_tau", _dp), ("patm", _dp), ("holland", C.c_int32),
+                ("x0", C.c_double), ("y0", C.c_double), ("vx", C.c_double), ("vy", C.c_double),
+                ("dp", C.c_double), ("pn", C.c_double), ("rmax", C.c_double), ("B", C.c_double),
+                ("rho_air", C.c_double), ("coriolis_f", C.c_double), ("wind_factor", C.c_double)]
+
+
+class dgswe_diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt_last", C.c_double), ("mass", C.c_double), ("volume", C.c_double),
+                ("steps", C.c_int64), ("n_wet", C.c_int32), ("n_dry", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdgswe.so (built by paper_2508_21208_amd.build) and declare its ABI."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2508_21208_amd.build` "
+                           "(there is no non-HIP fallback)")
+    L = C.CDLL(path)
+    ip = C.POINTER(C.c_int32)
+    vp = C.c_void_p
+    L.dgswe_default_params.argtypes = [C.POINTER(dgswe_params)]
+    L.dgswe_default_params.restype = None
+    L.dgswe_create_mesh.argtypes = [C.c_int32, _dp, _dp, C.c_int32, ip, C.c_int32, ip, ip,
+                                    C.POINTER(dgswe_params), vp, C.POINTER(vp)]
+    L.dgswe_create_mesh.restype = C.c_int
+    L.dgswe_set_state.argtypes = [vp, C.c_double, _dp, C.c_int32]
+    L.dgswe_set_state.restype = C.c_int
+    L.dgswe_set_forcing.argtypes = [vp, C.POINTER(dgswe_forcing)]
+    L.dgswe_set_forcing.restype = C.c_int
+    L.dgswe_step.argtypes = [vp, C.c_int32]
+    L.dgswe_step.restype = C.c_int
+    L.dgswe_read_state.argtypes = [vp, _dp, C.POINTER(dgswe_diag)]
+    L.dgswe_read_state.restype = C.c_int
+    L.dgswe_destroy.argtypes = [vp]
+    L.dgswe_destroy.restype = None
+    L.dgswe_last_error.argtypes = [vp]
+    L.dgswe_last_error.restype = C.c_char_p
+    L.dgswe_profile.argtypes = [vp, C.c_int32]
+    L.dgswe_profile.restype = C.c_int
+    L.dgswe_profile_read.argtypes = [vp, C.c_int32, C.c_char_p, _dp, C.POINTER(C.c_int64), ip]
+    L.dgswe_profile_read.restype = C.c_int
+    L.dgswe_mesh_info.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.dgswe_mesh_info.restype = C.c_int
+    _lib = L
+    return L
+
+
+class DgsweError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+# ---- C names -----------------------------------------------------------------
+def dgswe_default_params() -> dgswe_params:
+    p = dgswe_params()
+    load_library().dgswe_default_params(C.byref(p))
+    return p
+
+
+def dgswe_create_mesh(xy, hb, tri, bnd, bnd_type, prm: dgswe_params, hip_stream=None):
+    L = load_library()
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    hb = np.ascontiguousarray(hb, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    bnd = np.ascontiguousarray(bnd, dtype=np.int32).reshape(-1, 2)
+    bt = np.ascontiguousarray(bnd_type, dtype=np.int32)
+    ip = C.POINTER(C.c_int32)
+    h = C.c_void_p()
+    st = L.dgswe_create_mesh(xy.shape[0], _d(xy), _d(hb), tri.shape[0], tri.ctypes.data_as(ip), bnd.shape[0],
+                             bnd.ctypes.data_as(ip), bt.ctypes.data_as(ip), C.byref(prm),
+                             C.c_void_p(hip_stream) if hip_stream else None, C.byref(h))
+    if st != DGSWE_OK:
+        raise DgsweError(st, L.dgswe_last_error(None).decode())
+    return h
+
+
+def _check(h, st):
+    if st != DGSWE_OK:
+        raise DgsweError(st, load_library().dgswe_last_error(h).decode())
+
+
+def dgswe_set_state(h, t, w, postprocess=False):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    _check(h, load_library().dgswe_set_state(h, float(t), _d(w), int(bool(postprocess))))
+
+
+HOLLAND_KEYS = ("x0", "y0", "vx", "vy", "dp", "pn", "rmax", "B", "rho_air", "coriolis_f", "wind_factor")
+
+
+def dgswe_set_forcing(h, f: dict, n_elems: int | None = None, n_nodes: int | None = None):
+    keep = []
+
+    def arr(x, n=None):
+        if x is None:
+            return None
+        a = np.ascontiguousarray(x, dtype=np.float64).ravel()
+        if n is not None and a.size != n:
+            raise ValueError(f"forcing array of size {a.size}, expected {n}")
+        keep.append(a)
+        return _d(a)
+
+    amp = f.get("tide_amp", []) or []
+    fs = dgswe_forcing()
+    fs.manning_n = float(f.get("manning_n", 0.0))
+    fs.manning_n_elem = arr(f.get("manning_n_elem"), n_elems)
+    fs.n_tide = len(amp)
+    fs.tide_amp = arr(amp) if len(amp) else None
+    fs.tide_omega = arr(f.get("tide_omega")) if len(amp) else None
+    fs.tide_phase = arr(f.get("tide_phase")) if len(amp) else None
+    fs.tide_offset = float(f.get("tide_offset", 0.0))
+    fs.wind_tau = arr(f.get("wind_tau"), None if n_nodes is None else 2 * n_nodes)
+    fs.patm = arr(f.get("patm"), n_nodes)
+    fs.holland = int(f.get("holland", 0))
+    for k in HOLLAND_KEYS:
+        setattr(fs, k, float(f.get(k, 0.0)))
+    _check(h, load_library().dgswe_set_forcing(h, C.byref(fs)))
+
+
+def dgswe_step(h, n_steps):
+    _check(h, load_library().dgswe_step(h, int(n_steps)))
+
+
+def dgswe_read_state(h, w_out=None, diag=True):
+    d = dgswe_diag()
+    st = load_library().dgswe_read_state(h, None if w_out is None else _d(w_out), C.byref(d) if diag else None)
+    _check(h, st)
+    return d
+
+
+def dgswe_destroy(h):
+    if h:
+        load_library().dgswe_destroy(h)
+
+
+def dgswe_profile(h, enable):
+    _check(h, load_library().dgswe_profile(h, int(enable)))
+
+
+def dgswe_profile_read(h, max_kernels=16):
+    names = C.create_string_buffer(32 * max_kernels)
+    ms = np.zeros(max_kernels)
+    n = np.zeros(max_kernels, dtype=np.int64)
+    cnt = C.c_int32(0)
+    _check(h, load_library().dgswe_profile_read(h, max_kernels, names, _d(ms),
+                                                n.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(cnt)))
+    out = {}
+    for i in range(cnt.value):
+        nm = names.raw[32 * i:32 * (i + 1)].split(b"\0")[0].decode()
+        out[nm] = (float(ms[i]), int(n[i]))
+    return out
+
+
+def dgswe_mesh_info(h):
+    out = (C.c_int64 * 4)()
+    _check(h, load_library().dgswe_mesh_info(h, out))
+    return dict(n_nodes=out[0], n_elems=out[1], n_edges=out[2], n_boundary=out[3])
+
+
+# ---- owner class -------------------------------------------------------------
+def params_from_dict(p: dict) -> dgswe_params:
+    prm = dgswe_default_params()
+    for k, v in p.items():
+        if hasattr(prm, k):
+            setattr(prm, k, type(getattr(prm, k))(v))
+    return prm
+
+
+class Solver:
+    """One mesh and its device-resident state."""
+
+    def __init__(self, mesh, params: dict | None = None, forcing: dict | None = None, hip_stream=None):
+        self.h = None
+        self.mesh = mesh
+        self.ne = int(mesh.tri.shape[0])
+        self.nn = int(mesh.xy.shape[0])
+        self.h = dgswe_create_mesh(mesh.xy, mesh.hb, mesh.tri, mesh.bnd, mesh.bnd_type,
+                                   params_from_dict(params or {}), hip_stream)
+        if forcing:
+            self.set_forcing(forcing)
+
+    def set_forcing(self, f: dict):
+        dgswe_set_forcing(self.h, f, self.ne, self.nn)
+
+    def set_state(self, w, t=0.0, postprocess=False):
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, self.ne)
+        dgswe_set_state(self.h, t, w, postprocess)
+
+    def step(self, n=1):
+        dgswe_step(self.h, n)
+
+    def state(self):
+        w = np.empty((3, 3, self.ne), dtype=np.float64)
+        self.diag = dgswe_read_state(self.h, w)
+        return w
+
+    def diagnostics(self):
+        d = dgswe_read_state(self.h, None, True)
+        return dict(t=d.t, dt_last=d.dt_last, mass=d.mass, volume=d.volume, steps=d.steps,
+                    n_wet=d.n_wet, n_dry=d.n_dry)
+
+    def info(self):
+        return dgswe_mesh_info(self.h)
+
+    def close(self):
+        if self.h:
+            dgswe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
