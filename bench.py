@@ -34,24 +34,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel: str, ne: int, ned: int, nn: int, stage2_share=0.5, holland=True) -> float:
-    """Bytes one launch of `kernel` must move if every array is touched once
-    (FP64 path).  Per element: state 72 B, vertex bathymetry 24 B, wet flag
-    1 B; per edge: 3 indices 12 B, normal + half length 24 B, moments 48 B,
-    mode 1 B; per node: forcing 24 B, coordinates 16 B."""
-    if kernel == "k_edge":
-        return ne * (72 + 24 + 1) + ned * (12 + 24 + 48 + 1)
-    if kernel == "k_element":
-        # state in/out, RK base on the second stage, geometry (4 gradients +
-        # area), bathymetry, node ids, edge ids, wet flag, moments + modes,
-        # nodal forcing
-        return ne * (72 + 72 + 72 * stage2_share + 40 + 24 + 12 + 12 + 1) + ned * 49 + nn * 24
-    if kernel == "k_post":
-        # unlimited state in, neighbours ids, bathymetry, inradius, state
-        # out, wet flag out
-        return ne * (72 + 12 + 24 + 8 * stage2_share + 72 + 1)
+# Algorithmic bytes of one element-stage of the whole path (FP64), every
+# array loaded once: state in 72 + RK base (second stage only) 36 + state out
+# 72 + vertex bathymetry 24 + inverse Jacobian and area 40 + neighbour ids and
+# orientation 13 + edge normal and length 36 (1.5 edges per element) +
+# Manning n 8 + nodal forcing 12 (0.5 nodes per element) + wet/dry status 2.
+B_ALG_FP64 = 315.0
+
+
+def algorithmic_bytes(kernel: str, ne: int, ned: int, nn: int) -> float:
+    """Algorithmic bytes of one launch: k_stage carries the whole stage
+    (B_ALG_FP64 per element); k_forcing reads node coordinates and writes
+    the nodal wind stress and pressure (40 B per node)."""
+    if kernel == "k_stage":
+        return B_ALG_FP64 * ne
     if kernel == "k_forcing":
-        return nn * (16 + 24)
+        return 40.0 * nn
     raise KeyError(kernel)
 
 
@@ -84,6 +82,8 @@ def main():
     ap.add_argument("--elems", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of 2 GiB (3 times) to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; a multi-GPU run (domain "
@@ -143,6 +143,17 @@ def main():
             kernels[k]["alg_GBs"] = round(kb / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
         log("kernels: " + json.dumps(kernels))
     s.close()
+
+    if args.copy_probe:
+        n = 2 * 1024 ** 3 // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x (read 2 GiB + write 2 GiB)")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

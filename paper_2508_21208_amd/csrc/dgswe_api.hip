@@ -2,6 +2,7 @@
 // transfers (with the internal element permutation), the per-step launch
 // sequence and HIP-event kernel timing.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -14,8 +15,8 @@ using namespace dgswe;
 namespace {
 thread_local std::string g_create_error = "no error";
 
-enum KernelId { K_FORCING = 0, K_EDGE, K_ELEMENT, K_POST, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"k_forcing", "k_edge", "k_element", "k_post"};
+enum KernelId { K_FORCING = 0, K_STAGE, K_COUNT };
+const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage"};
 }  // namespace
 
 struct dgswe_solver {
@@ -32,6 +33,9 @@ struct dgswe_solver {
   double *d_manning = nullptr;
   double *d_diag = nullptr;
   long long steps_enq = 0;
+  int block = 256;         // workgroup size of the stage kernel
+  int cur = 0;             // buffer holding w^n (unlimited unless cur_is_pp)
+  bool cur_is_pp = false;  // w^n is already post-processed (set_state without post-processing)
   bool forcing_dynamic = false;
   std::string err = "no error";
   std::vector<double> stage_buf;
@@ -40,8 +44,8 @@ struct dgswe_solver {
   struct Rec { int k; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
-  double prof_ms[K_COUNT] = {0, 0, 0, 0};
-  long long prof_n[K_COUNT] = {0, 0, 0, 0};
+  double prof_ms[K_COUNT] = {0, 0};
+  long long prof_n[K_COUNT] = {0, 0};
 };
 
 namespace {
@@ -199,17 +203,39 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   chk(upload(S, &m.gx2, P.gx2)); chk(upload(S, &m.gy2, P.gy2));
   chk(upload(S, &m.area, P.area)); chk(upload(S, &m.inr2, P.inr2));
   chk(upload(S, &m.hbv, P.hbv));
-  chk(upload(S, &m.el_edge, P.el_edge)); chk(upload(S, &m.el_nb, P.el_nb));
+  chk(upload(S, &m.el_nb, P.el_nb));
   chk(upload(S, &m.el_node, P.el_node));
-  chk(upload(S, &m.ed_ep, P.ed_ep)); chk(upload(S, &m.ed_em, P.ed_em));
-  chk(upload(S, &m.ed_info, P.ed_info));
-  chk(upload(S, &m.ed_nx, P.ed_nx)); chk(upload(S, &m.ed_ny, P.ed_ny));
-  chk(upload(S, &m.ed_hlen, P.ed_hlen));
   chk(upload(S, &m.node_x, P.node_x)); chk(upload(S, &m.node_y, P.node_y));
   m.manning = nullptr;
+  // chunk size and workgroup size of the stage kernel
+  int chunk = 256, block = 256;
+  if (const char *ev = std::getenv("DGSWE_CHUNK")) chunk = std::atoi(ev);
+  if (const char *ev = std::getenv("DGSWE_BLOCK")) block = std::atoi(ev);
+  if (!stage_block_ok(block) || chunk < 64 || chunk > block) {
+    free_all(S);
+    delete S;
+    return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+  }
+  S->block = block;
+  build_chunks(P, chunk);
+  m.C = P.C; m.nch = P.nch; m.nl_max = P.nl_max; m.nm_max = P.nm_max; m.ed_max = P.ed_max;
+  m.n2_max = P.n2_max;
+  chk(upload(S, &m.h1_off, P.h1_off)); chk(upload(S, &m.h1, P.h1)); chk(upload(S, &m.h1_hb, P.h1_hb));
+  chk(upload(S, &m.h2_off, P.h2_off)); chk(upload(S, &m.h2, P.h2));
+  chk(upload(S, &m.le_off, P.le_off)); chk(upload(S, &m.nb_off, P.nb_off));
+  chk(upload(S, &m.le_pm, P.le_pm)); chk(upload(S, &m.le_info, P.le_info));
+  chk(upload(S, &m.le_nx, P.le_nx)); chk(upload(S, &m.le_ny, P.le_ny)); chk(upload(S, &m.le_hl, P.le_hl));
+  chk(upload(S, &m.le_hA, P.le_hA)); chk(upload(S, &m.le_hB, P.le_hB));
+  chk(upload(S, &m.el_ledge, P.el_ledge)); chk(upload(S, &m.nbl, P.nbl));
+  if (stage_lds_bytes(m) > 80 * 1024 || P.nl_max > 2 * block || P.ed_max > 2 * block) {
+    free_all(S);
+    delete S;
+    return fail(nullptr, DGSWE_E_MESH, "element chunks have halos too large for the LDS (" +
+                                           std::to_string(stage_lds_bytes(m)) + " bytes)");
+  }
   DevState &st = S->s;
-  chk(dev_alloc(S, &st.w0, 9 * ne)); chk(dev_alloc(S, &st.w1, 9 * ne)); chk(dev_alloc(S, &st.wt, 9 * ne));
-  chk(dev_alloc(S, &st.wet, ne)); chk(dev_alloc(S, &st.edge, 6 * ned)); chk(dev_alloc(S, &st.emode, ned));
+  for (int b = 0; b < 3; ++b) chk(dev_alloc(S, &st.buf[b], 9 * ne));
+  chk(dev_alloc(S, &st.wpp, 9 * ne));
   chk(dev_alloc(S, &st.nodal, 3 * nn)); chk(dev_alloc(S, &st.partial, 3 * (size_t)diag_blocks(P.ne)));
   chk(dev_alloc(S, &st.ctrl, 1)); chk(dev_alloc(S, &S->d_diag, 4));
   if (!ok) {
@@ -217,11 +243,13 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
     delete S;
     return fail(nullptr, DGSWE_E_NOMEM, "device allocation or upload failed");
   }
-  // zero state and forcing, wet flags and dt of the zero state
-  chk(hipMemsetAsync(st.w0, 0, 9 * ne * sizeof(double), S->stream));
+  // zero state and forcing, dt of the zero state
+  chk(hipMemsetAsync(st.buf[0], 0, 9 * ne * sizeof(double), S->stream));
   chk(hipMemsetAsync(st.nodal, 0, 3 * nn * sizeof(double), S->stream));
-  chk(launch_init_state(m, st, pp, 0, 0.0, S->stream));
+  chk(launch_init_state(m, st, pp, st.buf[0], 0.0, S->stream));
   chk(hipStreamSynchronize(S->stream));
+  S->cur = 0;
+  S->cur_is_pp = true;
   if (!ok) {
     free_all(S);
     delete S;
@@ -238,17 +266,16 @@ dgswe_status dgswe_set_state(dgswe_solver *S, double t, const double *w, int32_t
   const size_t ne = S->ne;
   S->stage_buf.resize(9 * ne);
   for (size_t j = 0; j < 9; ++j)
-    for (size_t i = 0; i < ne; ++i) S->stage_buf[j * ne + i] = w[j * ne + (size_t)S->perm[i]];
-  double *dst = postprocess ? S->s.wt : S->s.w0;
-  hipError_t e = hipMemcpyAsync(dst, S->stage_buf.data(), 9 * ne * sizeof(double), hipMemcpyHostToDevice,
+    for (size_t i = 0; i < ne; ++i) S->stage_buf[9 * i + j] = w[j * ne + (size_t)S->perm[i]];
+  // The stored state is post-processed by the first stage that reads it;
+  // a state given without post-processing is marked as already done.
+  S->cur = 0;
+  S->cur_is_pp = postprocess == 0;
+  hipError_t e = hipMemcpyAsync(S->s.buf[0], S->stage_buf.data(), 9 * ne * sizeof(double), hipMemcpyHostToDevice,
                                 S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipMemcpyAsync");
-  if (postprocess) {
-    e = launch_post_only(S->m, S->s, S->prm, S->s.w0, S->stream);
-    if (e != hipSuccess) return hip_fail(S, e, "post-processing kernel");
-  }
   S->steps_enq = 0;
-  e = launch_init_state(S->m, S->s, S->prm, 0, t, S->stream);
+  e = launch_init_state(S->m, S->s, S->prm, S->s.buf[0], t, S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "init kernel");
   e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
@@ -308,28 +335,30 @@ dgswe_status dgswe_step(dgswe_solver *S, int32_t n_steps) {
   const DevMesh &m = S->m;
   DevState &st = S->s;
   const Params &p = S->prm;
-  const bool want_dt = !(p.dt_fixed > 0.0);
+  const int want_dt = (p.dt_fixed > 0.0) ? 0 : 1;
   for (int i = 0; i < n_steps; ++i) {
     const int slot = (int)(S->steps_enq & 1);
+    // rotation: w^n in cur, stage 1 -> s1, stage 2 -> nx (both unlimited)
+    const int cur = S->cur, s1 = (cur + 1) % 3, nx = (cur + 2) % 3;
+    const int pp_cur = S->cur_is_pp ? 0 : 1;
     hipError_t e = hipSuccess;
     for (int stage = 0; stage < 2 && e == hipSuccess; ++stage) {
-      const double *win = stage == 0 ? st.w0 : st.w1;
-      double *wout = stage == 0 ? st.w1 : st.w0;
       if (S->forcing_dynamic) {
         Timed t(S, K_FORCING);
         e = launch_forcing(m, st, p, slot, stage, S->stream);
       }
-      if (e == hipSuccess) { Timed t(S, K_EDGE); e = launch_edge(m, st, p, win, slot, stage, S->stream); }
-      if (e == hipSuccess) {
-        Timed t(S, K_ELEMENT);
-        e = launch_element(m, st, p, win, stage == 0 ? nullptr : st.w0, slot, stage, S->stream);
-      }
-      if (e == hipSuccess) {
-        Timed t(S, K_POST);
-        e = launch_post(m, st, p, wout, slot, stage, (stage == 1 && want_dt) ? 1 : 0, S->stream);
-      }
+      if (e != hipSuccess) break;
+      Timed t(S, K_STAGE);
+      if (stage == 0)
+        e = launch_stage(m, st, p, st.buf[cur], nullptr, st.buf[s1], st.wpp, slot, 0, pp_cur, 0, S->block,
+                         S->stream);
+      else
+        e = launch_stage(m, st, p, st.buf[s1], st.wpp, st.buf[nx], nullptr, slot, 1, 1, want_dt, S->block,
+                         S->stream);
     }
     if (e != hipSuccess) return hip_fail(S, e, "kernel launch");
+    S->cur = nx;
+    S->cur_is_pp = false;
     S->steps_enq += 1;
   }
   return DGSWE_OK;
@@ -341,15 +370,24 @@ dgswe_status dgswe_read_state(dgswe_solver *S, double *w_out, dgswe_diag *d) {
   if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
   const size_t ne = S->ne;
   if (w_out) {
+    // the state at the boundary is post-processed
+    const double *src = S->s.buf[S->cur];
+    if (!S->cur_is_pp) {
+      double *tmp = S->s.buf[(S->cur + 1) % 3];
+      e = launch_post_only(S->m, S->s, S->prm, src, tmp, S->stream);
+      if (e != hipSuccess) return hip_fail(S, e, "post-processing kernel");
+      src = tmp;
+    }
     S->stage_buf.resize(9 * ne);
-    e = hipMemcpy(S->stage_buf.data(), S->s.w0, 9 * ne * sizeof(double), hipMemcpyDeviceToHost);
+    e = hipMemcpyAsync(S->stage_buf.data(), src, 9 * ne * sizeof(double), hipMemcpyDeviceToHost, S->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
     for (size_t j = 0; j < 9; ++j)
-      for (size_t i = 0; i < ne; ++i) w_out[j * ne + (size_t)S->perm[i]] = S->stage_buf[j * ne + i];
+      for (size_t i = 0; i < ne; ++i) w_out[j * ne + (size_t)S->perm[i]] = S->stage_buf[9 * i + j];
   }
   Ctrl c{};
   if (d) {
-    e = launch_diag(S->m, S->s, S->prm, S->d_diag, S->stream);
+    e = launch_diag(S->m, S->s, S->prm, S->s.buf[S->cur], S->d_diag, S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "diagnostics kernel");
     double out4[4];
     e = hipMemcpyAsync(out4, S->d_diag, sizeof out4, hipMemcpyDeviceToHost, S->stream);
@@ -363,7 +401,7 @@ dgswe_status dgswe_read_state(dgswe_solver *S, double *w_out, dgswe_diag *d) {
   e = hipMemcpy(&c, S->s.ctrl, sizeof c, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
   if (d) {
-    d->t = c.t;
+    d->t = c.t[c.steps & 1];
     d->dt_last = c.dt_last;
     d->steps = c.steps;
   }

@@ -14,10 +14,14 @@ constexpr int kMaxTide = 8;
 constexpr int kBlock = 256;
 
 // Device control block: one per solver, read by every kernel of a step.
+// Step n (counted from dgswe_set_state) reads t[n & 1] and dtmin[n & 1];
+// its last kernel writes t[(n + 1) & 1] and the CFL candidates of step n + 1
+// into dtmin[(n + 1) & 1], so no kernel writes a value another block of the
+// same kernel reads.
 struct Ctrl {
-  double t;                      // model time at the start of the current step
+  double t[2];                   // model time at the start of a step, per parity
   double dt_last;                // dt of the last completed step
-  unsigned long long dtmin[2];   // bit pattern of the raw CFL minimum, per step parity
+  unsigned long long dtmin[2];   // bit pattern of the raw CFL minimum, per parity
   long long steps;               // completed steps
   int status;                    // first error detected on the device (0 = none)
   int pad;
@@ -31,16 +35,19 @@ struct DevMesh {
   const double *area;                   // A_e
   const double *inr2;                   // 2 x inradius
   const double *hbv;                    // [3][ne] bathymetry at the element's vertices
-  const int *el_edge;                   // [3][ne] edge id << 1 | side (0 = e+, 1 = e-)
   const int *el_nb;                     // [3][ne] neighbour across local edge, -1 none
   const int *el_node;                   // [3][ne] node ids
   const double *manning;                // [ne] or nullptr
-  // edges (sorted by e+)
-  const int *ed_ep, *ed_em;             // elements; em = -1 on the boundary
-  const int *ed_info;                   // lp | lm << 2 | type << 4
-  const double *ed_nx, *ed_ny, *ed_hlen;  // unit normal from e+, half length
   // nodes
   const double *node_x, *node_y;
+  // chunks (see build_chunks)
+  int C, nch, nl_max, nm_max, ed_max, n2_max;
+  const int *h1_off, *h1, *h2_off, *h2, *le_off, *nb_off;  // per-chunk offsets and halo ids
+  const double *h1_hb;             // [3][total ring-1 entries] vertex bathymetry of ring 1
+  const uint32_t *le_pm;           // chunk-local edge: local e+ | local e- << 16 (0xFFFF: boundary)
+  const uint8_t *le_info;          // lp | lm << 2 | type << 4
+  const double *le_nx, *le_ny, *le_hl, *le_hA, *le_hB;  // normal, half length, endpoint bathymetry
+  const uint16_t *el_ledge, *nbl;
 };
 
 struct Params {
@@ -53,14 +60,14 @@ struct Params {
   double x0, y0, vx, vy, dp, pn, rmax, B, rho_air, coriolis_f, wind_factor;
 };
 
-// Buffers of one solver touched by the step.
+// Buffers of one solver touched by the step.  The state lives in three
+// rotating [ne][9] buffers (element-contiguous, [var*3 + mode] within an
+// element, so a halo element is one 72-byte read); each holds a stage result
+// BEFORE its limiter and wet/dry post-processing, which the next stage
+// applies on the fly.
 struct DevState {
-  double *w0;      // [9][ne] state w^n (after post-processing)
-  double *w1;      // [9][ne] first-stage state (after post-processing)
-  double *wt;      // [9][ne] unlimited RK combination of the current stage
-  unsigned char *wet;  // [ne] wet flag of the current stage input
-  double *edge;    // [6][ned] edge flux moments
-  unsigned char *emode;  // [ned] which sides receive the edge flux
+  double *buf[3];
+  double *wpp;     // [ne][9] post-processed w^n of the current step (RK base)
   double *nodal;   // [3][nn] wind stress x, y and pressure at the nodes
   double *partial; // [3][nblk] diagnostics partial sums
   Ctrl *ctrl;
@@ -76,7 +83,22 @@ struct Prep {
   std::vector<int> ed_ep, ed_em, ed_info;
   std::vector<double> ed_nx, ed_ny, ed_hlen;
   std::vector<double> node_x, node_y;
+  // chunks of C consecutive elements with their halos (fused stage kernel)
+  int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
+  std::vector<int> h1_off, h1, h2_off, h2, le_off, le_gid, nb_off;
+  std::vector<double> h1_hb;
+  std::vector<uint32_t> le_pm;
+  std::vector<uint8_t> le_info;
+  std::vector<double> le_nx, le_ny, le_hl, le_hA, le_hB;
+  std::vector<uint16_t> el_ledge, nbl;
 };
+
+// Split the (Hilbert-ordered) elements into chunks of C and build, per chunk:
+// the ring-1 halo (neighbours outside the chunk), the ring-2 halo
+// (neighbours of ring 1 outside chunk and ring 1), the chunk-local edge list
+// and local neighbour / edge indices.  Local element index space of a chunk:
+// [0, Cc) chunk elements, then ring 1, then ring 2.
+void build_chunks(Prep &P, int C);
 
 // Returns 0 on success, else a DGSWE status code with a message in `err`.
 int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *tri, int nbnd,
@@ -85,18 +107,26 @@ int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *
 // Kernel launchers (dgswe_kernels.hip).  Each returns hipGetLastError().
 hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int slot, int stage,
                           hipStream_t st);
-hipError_t launch_edge(const DevMesh &m, const DevState &s, const Params &p, const double *w,
-                       int slot, int stage, hipStream_t st);
-hipError_t launch_element(const DevMesh &m, const DevState &s, const Params &p, const double *w,
-                          const double *wbase, int slot, int stage, hipStream_t st);
-hipError_t launch_post(const DevMesh &m, const DevState &s, const Params &p, double *wout,
-                       int slot, int stage, int want_dt, hipStream_t st);
-hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p, double *wout,
-                            hipStream_t st);
-hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, int slot,
+// One RK stage: post-process `win` (if pp_in), edge fluxes, area integrals,
+// gather, RK combination; writes the unlimited result to `wout`.  The first
+// stage (stage 0) also writes the post-processed input to `wpp`; the second
+// stage reads it back as the RK base `wbase`.
+hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const double *win,
+                        const double *wbase, double *wout, double *wpp, int slot, int stage, int pp_in,
+                        int want_dt, int block, hipStream_t st);
+// thread-block sizes the stage kernel is built for
+constexpr int kStageBlocks[] = {256, 384};
+// Post-process a whole state (win -> wout), e.g. to read it back.
+hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p, const double *win,
+                            double *wout, hipStream_t st);
+// Reset the control block to time t and put the CFL candidates of `w`
+// into dtmin[0].
+hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const double *w,
                              double t, hipStream_t st);
-hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, double *out4,
-                       hipStream_t st);
+hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const double *w,
+                       double *out4, hipStream_t st);
+size_t stage_lds_bytes(const DevMesh &m);
+bool stage_block_ok(int block);
 int diag_blocks(int ne);
 
 }  // namespace dgswe

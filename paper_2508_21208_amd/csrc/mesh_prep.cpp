@@ -227,4 +227,103 @@ int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *
   return DGSWE_OK;
 }
 
+void build_chunks(Prep &P, int C) {
+  const int ne = P.ne;
+  const size_t nes = (size_t)ne;
+  P.C = C;
+  P.nch = (ne + C - 1) / C;
+  P.h1_off.assign(P.nch + 1, 0);
+  P.h2_off.assign(P.nch + 1, 0);
+  P.le_off.assign(P.nch + 1, 0);
+  P.nb_off.assign(P.nch + 1, 0);
+  P.h1.clear(); P.h2.clear(); P.le_gid.clear(); P.nbl.clear();
+  P.le_pm.clear(); P.le_info.clear();
+  P.le_nx.clear(); P.le_ny.clear(); P.le_hl.clear(); P.le_hA.clear(); P.le_hB.clear();
+  P.el_ledge.assign(3 * nes, 0);
+  P.nl_max = P.nm_max = P.ed_max = P.n2_max = 0;
+  std::vector<int> loc(nes, -1);       // global element -> local index in the current chunk
+  std::vector<int> eloc(P.ned, -1);    // global edge -> local edge index in the current chunk
+  std::vector<int> h1, h2, edges;
+  for (int c = 0; c < P.nch; ++c) {
+    const int c0 = c * C, cc = std::min(C, ne - c0);
+    for (int i = 0; i < cc; ++i) loc[c0 + i] = i;
+    h1.clear();
+    for (int i = 0; i < cc; ++i)
+      for (int l = 0; l < 3; ++l) {
+        int f = P.el_nb[(size_t)l * nes + c0 + i];
+        if (f >= 0 && loc[f] < 0) { loc[f] = -2; h1.push_back(f); }
+      }
+    std::sort(h1.begin(), h1.end());
+    for (size_t k = 0; k < h1.size(); ++k) loc[h1[k]] = cc + (int)k;
+    const int nl = cc + (int)h1.size();
+    h2.clear();
+    for (int f : h1)
+      for (int l = 0; l < 3; ++l) {
+        int g = P.el_nb[(size_t)l * nes + f];
+        if (g >= 0 && loc[g] == -1) { loc[g] = -3; h2.push_back(g); }
+      }
+    std::sort(h2.begin(), h2.end());
+    for (size_t k = 0; k < h2.size(); ++k) loc[h2[k]] = nl + (int)k;
+    const int nm = nl + (int)h2.size();
+    // local neighbour table of chunk + ring 1, layout [l][i]
+    P.nb_off[c] = (int)P.nbl.size();
+    for (int l = 0; l < 3; ++l)
+      for (int i = 0; i < nl; ++i) {
+        int g = i < cc ? c0 + i : h1[i - cc];
+        int f = P.el_nb[(size_t)l * nes + g];
+        P.nbl.push_back(f < 0 ? (uint16_t)0xFFFF : (uint16_t)loc[f]);
+      }
+    // chunk-local edges: every edge of a chunk element, once
+    edges.clear();
+    for (int i = 0; i < cc; ++i)
+      for (int l = 0; l < 3; ++l) {
+        int d = P.el_edge[(size_t)l * nes + c0 + i] >> 1;
+        if (eloc[d] < 0) { eloc[d] = 0; edges.push_back(d); }
+      }
+    std::sort(edges.begin(), edges.end());
+    P.le_off[c] = (int)P.le_gid.size();
+    for (size_t k = 0; k < edges.size(); ++k) {
+      int d = edges[k];
+      eloc[d] = (int)k;
+      P.le_gid.push_back(d);
+      const uint32_t ip = (uint32_t)loc[P.ed_ep[d]];
+      const uint32_t im = P.ed_em[d] < 0 ? 0xFFFFu : (uint32_t)loc[P.ed_em[d]];
+      P.le_pm.push_back(ip | (im << 16));
+      P.le_info.push_back((uint8_t)P.ed_info[d]);
+      P.le_nx.push_back(P.ed_nx[d]);
+      P.le_ny.push_back(P.ed_ny[d]);
+      P.le_hl.push_back(P.ed_hlen[d]);
+      const int lp = P.ed_info[d] & 3, ep = P.ed_ep[d];
+      P.le_hA.push_back(P.hbv[(size_t)((lp + 1) % 3) * nes + ep]);
+      P.le_hB.push_back(P.hbv[(size_t)((lp + 2) % 3) * nes + ep]);
+    }
+    for (int i = 0; i < cc; ++i)
+      for (int l = 0; l < 3; ++l) {
+        int code = P.el_edge[(size_t)l * nes + c0 + i];
+        P.el_ledge[(size_t)l * nes + c0 + i] = (uint16_t)((eloc[code >> 1] << 1) | (code & 1));
+      }
+    P.h1_off[c] = (int)P.h1.size();
+    P.h1.insert(P.h1.end(), h1.begin(), h1.end());
+    P.h2_off[c] = (int)P.h2.size();
+    P.h2.insert(P.h2.end(), h2.begin(), h2.end());
+    P.nl_max = std::max(P.nl_max, nl);
+    P.nm_max = std::max(P.nm_max, nm);
+    P.ed_max = std::max(P.ed_max, (int)edges.size());
+    P.n2_max = std::max(P.n2_max, (int)h2.size());
+    // reset the scratch maps
+    for (int i = 0; i < cc; ++i) loc[c0 + i] = -1;
+    for (int f : h1) loc[f] = -1;
+    for (int g : h2) loc[g] = -1;
+    for (int d : edges) eloc[d] = -1;
+  }
+  const size_t nh1 = P.h1.size();
+  P.h1_hb.resize(3 * nh1);
+  for (size_t k = 0; k < nh1; ++k)
+    for (int q = 0; q < 3; ++q) P.h1_hb[q * nh1 + k] = P.hbv[(size_t)q * nes + P.h1[k]];
+  P.h1_off[P.nch] = (int)P.h1.size();
+  P.h2_off[P.nch] = (int)P.h2.size();
+  P.le_off[P.nch] = (int)P.le_gid.size();
+  P.nb_off[P.nch] = (int)P.nbl.size();
+}
+
 }  // namespace dgswe

@@ -59,6 +59,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it with `python -m paper_2508_21208_amd.build` "
                            "(there is no non-HIP fallback)")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7 under
+    # the same soname as ROCm's; load it first so libdgswe binds to the same
+    # runtime (device memory and streams are shared with torch).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     ip = C.POINTER(C.c_int32)
     vp = C.c_void_p
