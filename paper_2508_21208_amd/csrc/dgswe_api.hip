@@ -266,7 +266,7 @@ dgswe_status dgswe_set_state(dgswe_solver *S, double t, const double *w, int32_t
   const size_t ne = S->ne;
   S->stage_buf.resize(9 * ne);
   for (size_t j = 0; j < 9; ++j)
-    for (size_t i = 0; i < ne; ++i) S->stage_buf[9 * i + j] = w[j * ne + (size_t)S->perm[i]];
+    for (size_t i = 0; i < ne; ++i) S->stage_buf[j * ne + i] = w[j * ne + (size_t)S->perm[i]];
   // The stored state is post-processed by the first stage that reads it;
   // a state given without post-processing is marked as already done.
   S->cur = 0;
@@ -383,7 +383,7 @@ dgswe_status dgswe_read_state(dgswe_solver *S, double *w_out, dgswe_diag *d) {
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
     for (size_t j = 0; j < 9; ++j)
-      for (size_t i = 0; i < ne; ++i) w_out[j * ne + (size_t)S->perm[i]] = S->stage_buf[9 * i + j];
+      for (size_t i = 0; i < ne; ++i) w_out[j * ne + (size_t)S->perm[i]] = S->stage_buf[j * ne + i];
   }
   Ctrl c{};
   if (d) {

@@ -61,13 +61,13 @@ struct Params {
 };
 
 // Buffers of one solver touched by the step.  The state lives in three
-// rotating [ne][9] buffers (element-contiguous, [var*3 + mode] within an
-// element, so a halo element is one 72-byte read); each holds a stage result
+// rotating [9][ne] buffers (structure of arrays, so a wavefront reads and
+// writes 64 consecutive elements per array); each holds a stage result
 // BEFORE its limiter and wet/dry post-processing, which the next stage
 // applies on the fly.
 struct DevState {
   double *buf[3];
-  double *wpp;     // [ne][9] post-processed w^n of the current step (RK base)
+  double *wpp;     // [9][ne] post-processed w^n of the current step (RK base)
   double *nodal;   // [3][nn] wind stress x, y and pressure at the nodes
   double *partial; // [3][nblk] diagnostics partial sums
   Ctrl *ctrl;

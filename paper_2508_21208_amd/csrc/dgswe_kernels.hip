@@ -418,12 +418,12 @@ HD double cfl_candidate(const double u[9], double hmean, double inr2, const Para
 HD double mean3(const double h[3]) { return (h[0] + h[1] + h[2]) / 3.0; }
 
 // ---------------------------------------------------------------- global-memory views
-// Element e of an [ne][9] state, post-processed with neighbour means read
+// Element e of a [9][ne] state, post-processed with neighbour means read
 // from the same array (used for the RK base and read-back).
 HD void load_pp_global(const DevMesh &m, const Params &p, const double *w, int e, bool pp, double u[9],
                        double h[3]) {
   const size_t ne = (size_t)m.ne;
-  for (int j = 0; j < 9; ++j) u[j] = w[9 * (size_t)e + j];
+  for (int j = 0; j < 9; ++j) u[j] = w[j * ne + e];
   for (int k = 0; k < 3; ++k) h[k] = m.hbv[k * ne + e];
   if (!pp) return;
   double nbm[3][3];
@@ -431,7 +431,7 @@ HD void load_pp_global(const DevMesh &m, const Params &p, const double *w, int e
   for (int k = 0; k < 3; ++k) {
     const int f = m.el_nb[k * ne + e];
     has[k] = f >= 0;
-    for (int v = 0; v < 3; ++v) nbm[v][k] = has[k] ? w[9 * (size_t)f + 3 * v] : 0.0;
+    for (int v = 0; v < 3; ++v) nbm[v][k] = has[k] ? w[(size_t)(3 * v) * ne + f] : 0.0;
   }
   postprocess(u, nbm, has, h, mean3(h), p);
 }
@@ -526,7 +526,7 @@ HD void phase_load_nl(const DevMesh &m, const ChunkInfo &k, const Lds &L, const 
   const size_t ne = (size_t)m.ne;
   const int g = i < k.cc ? k.c0 + i : m.h1[k.h1o + i - k.cc];
   double u[9];
-  for (int j = 0; j < 9; ++j) u[j] = win[9 * (size_t)g + j];
+  for (int j = 0; j < 9; ++j) u[j] = win[j * ne + g];
   for (int j = 0; j < 9; ++j) L.S[j * L.nls + i] = u[j];
   L.MQ[i] = u[3];
   L.MQ[L.nms + i] = u[6];
@@ -536,9 +536,9 @@ HD void phase_load_nl(const DevMesh &m, const ChunkInfo &k, const Lds &L, const 
 HD void phase_load_h2(const DevMesh &m, const ChunkInfo &k, const Lds &L, const double *win, int j) {
   const size_t ne = (size_t)m.ne;
   const int g = m.h2[k.h2o + j];
-  L.MZ[j] = win[9 * (size_t)g];
-  L.MQ[k.nl() + j] = win[9 * (size_t)g + 3];
-  L.MQ[L.nms + k.nl() + j] = win[9 * (size_t)g + 6];
+  L.MZ[j] = win[g];
+  L.MQ[k.nl() + j] = win[3 * ne + g];
+  L.MQ[L.nms + k.nl() + j] = win[6 * ne + g];
 }
 
 // phase L: geometry of chunk element i into LDS
@@ -583,7 +583,7 @@ HD void phase_post(const DevMesh &m, const Params &p, const ChunkInfo &k, const 
   L.WET[i] = (p.wetdry ? (u[0] + hmean > p.h0) : true) ? 1 : 0;
   if (wpp && i < k.cc) {
     const size_t ne = (size_t)m.ne;
-    for (int j = 0; j < 9; ++j) wpp[9 * (size_t)(k.c0 + i) + j] = u[j];
+    for (int j = 0; j < 9; ++j) wpp[j * ne + k.c0 + i] = u[j];
   }
 }
 
@@ -606,43 +606,52 @@ HD void phase_edge(const Params &p, const Lds &L, double zb, int j, const EdgeRe
   L.EMODE[j] = (unsigned char)mode;
 }
 
-// per-element inputs of phase A that are loaded early
+// per-element inputs of phase A, loaded in phase L and kept in registers
+// (nodal forcing at the vertices, RK base on the second stage)
 struct ElemPre {
   double h[3];
-  double inr2;
-  int node[3];
+  double tx[3], ty[3], pa[3];
+  double wb[9];
+  double inr2, manning;
   int ledge[3];
 };
 
-HD void load_elem_pre(const DevMesh &m, const ChunkInfo &k, int i, ElemPre &P) {
-  const size_t ne = (size_t)m.ne;
+HD void load_elem_pre(const DevMesh &m, const DevState &s, const Params &p, const ChunkInfo &k, int i,
+                      const double *wbase, ElemPre &P) {
+  const size_t ne = (size_t)m.ne, nn = (size_t)m.nn;
   const int e = k.c0 + i;
+  int node[3];
   for (int q = 0; q < 3; ++q) {
     P.h[q] = m.hbv[q * ne + e];
-    P.node[q] = m.el_node[q * ne + e];
+    node[q] = m.el_node[q * ne + e];
     P.ledge[q] = m.el_ledge[q * ne + e];
   }
   P.inr2 = m.inr2[e];
+  P.manning = m.manning ? m.manning[e] : p.manning_n;
+  for (int q = 0; q < 3; ++q) {
+    P.tx[q] = s.nodal[node[q]];
+    P.ty[q] = s.nodal[nn + node[q]];
+    P.pa[q] = s.nodal[2 * nn + node[q]];
+  }
+  if (wbase)
+    for (int j = 0; j < 9; ++j) P.wb[j] = wbase[j * ne + e];
 }
 
 // phase A for chunk element i; returns the CFL candidate of the output when
-// want_dt, and sets bad on a non-finite output.  wbase: post-processed RK
-// base (second stage) or nullptr.
-HD double phase_area(const DevMesh &m, const DevState &s, const Params &p, const ChunkInfo &k, const Lds &L,
-                     const ElemPre &P, const double *wbase, double *wout, double dt, int want_dt, int i, bool &bad) {
-  const size_t ne = (size_t)m.ne, nn = (size_t)m.nn;
+// want_dt, and sets bad on a non-finite output.  base: combine with the
+// post-processed RK base P.wb (second stage).
+HD double phase_area(const DevMesh &m, const Params &p, const ChunkInfo &k, const Lds &L, const ElemPre &P,
+                     bool base, double *wout, double dt, int want_dt, int i, bool &bad) {
+  const size_t ne = (size_t)m.ne;
   const int e = k.c0 + i;
   ElemIn E;
   for (int q = 0; q < 3; ++q) {
     E.h[q] = P.h[q];
-    E.tx[q] = s.nodal[P.node[q]];
-    E.ty[q] = s.nodal[nn + P.node[q]];
-    E.pa[q] = s.nodal[2 * nn + P.node[q]];
+    E.tx[q] = P.tx[q];
+    E.ty[q] = P.ty[q];
+    E.pa[q] = P.pa[q];
   }
-  E.manning = m.manning ? m.manning[e] : p.manning_n;
-  double wb[9];
-  if (wbase)
-    for (int j = 0; j < 9; ++j) wb[j] = wbase[9 * (size_t)e + j];
+  E.manning = P.manning;
   E.g1x = L.GEO[i]; E.g1y = L.GEO[L.cs + i]; E.g2x = L.GEO[2 * L.cs + i]; E.g2y = L.GEO[3 * L.cs + i];
   E.area = L.GEO[4 * L.cs + i];
   double u[9];
@@ -673,8 +682,8 @@ HD double phase_area(const DevMesh &m, const DevState &s, const Params &p, const
   for (int j = 0; j < 9; ++j) {
     double dw = r[j] * imu[j % 3];
     if (!wet && j >= 3) dw = 0.0;
-    out[j] = wbase ? 0.5 * wb[j] + 0.5 * (u[j] + dt * dw) : u[j] + dt * dw;
-    wout[9 * (size_t)e + j] = out[j];
+    out[j] = base ? 0.5 * P.wb[j] + 0.5 * (u[j] + dt * dw) : u[j] + dt * dw;
+    wout[j * ne + e] = out[j];
     fin = fin && __builtin_isfinite(out[j]);
   }
   bad = !fin;
@@ -766,7 +775,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   if (tid + NT < k.ne_loc) load_edge_rec(m, k, tid + NT, r1);
   ElemPre pre;
   if (tid < k.cc) {
-    load_elem_pre(m, k, tid, pre);
+    load_elem_pre(m, s, p, k, tid, stage ? wbase : nullptr, pre);
     phase_load_geo(m, k, L, tid);
   }
   if (i0 < nl) phase_load_nl(m, k, L, win, i0);
@@ -784,7 +793,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   __syncthreads();
   double cand = INFINITY;
   bool bad = false;
-  if (tid < k.cc) cand = phase_area(m, s, p, k, L, pre, stage ? wbase : nullptr, wout, dt, want_dt, tid, bad);
+  if (tid < k.cc) cand = phase_area(m, p, k, L, pre, stage != 0, wout, dt, want_dt, tid, bad);
   if (bad) atomicCAS(&ctl->status, 0, (int)DGSWE_E_NONFINITE);
   if (want_dt) {
     const double bm = block_min<NT>(cand, red);
@@ -804,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, const
   if (e >= m.ne) return;
   double u[9], h[3];
   load_pp_global(m, p, win, e, true, u, h);
-  for (int j = 0; j < 9; ++j) wout[9 * (size_t)e + j] = u[j];
+  for (int j = 0; j < 9; ++j) wout[(size_t)j * m.ne + e] = u[j];
 }
 
 __global__ void k_ctrl_reset(Ctrl *c, double t) {
@@ -826,7 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DevMesh m, DevState s, Params p
   if (e < m.ne) {
     const size_t ne = (size_t)m.ne;
     double u[9];
-    for (int j = 0; j < 9; ++j) u[j] = w[9 * (size_t)e + j];
+    for (int j = 0; j < 9; ++j) u[j] = w[j * ne + e];
     const double h[3] = {m.hbv[e], m.hbv[ne + e], m.hbv[2 * ne + e]};
     cand = cfl_candidate(u, mean3(h), m.inr2[e], p);
   }
@@ -846,7 +855,7 @@ __global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, DevState s, Params 
   if (e < m.ne) {
     const double h[3] = {m.hbv[e], m.hbv[ne + e], m.hbv[2 * ne + e]};
     const double hmean = mean3(h);
-    const double z = w[9 * (size_t)e];
+    const double z = w[e];
     a = m.area[e] * z;
     b = m.area[e] * (z + hmean);
     c = (p.wetdry ? (z + hmean > p.h0) : true) ? 1.0 : 0.0;
