@@ -66,7 +66,7 @@ enum { DGSWE_FP64 = 0, DGSWE_MIXED = 1 };
 
 typedef struct {
   int32_t p;         /* polynomial degree: 1 */
-  int32_t precision; /* DGSWE_FP64 */
+  int32_t precision; /* DGSWE_FP64, or DGSWE_MIXED (see below) */
   double g;          /* gravity [m/s^2], e.g. 9.81 */
   double rho0;       /* water density [kg/m^3], e.g. 1000 */
   double h0;         /* wet/dry threshold depth H0 [m], e.g. 0.01 */
@@ -76,6 +76,17 @@ typedef struct {
   int32_t limiter;   /* 1: slope limiter after each stage */
   int32_t wetdry;    /* 1: wetting/drying after each stage */
 } dgswe_params;
+
+/* Precision.  DGSWE_FP64 computes and stores everything in FP64.
+ * DGSWE_MIXED (the paper computes in FP32 throughout, Sec. 5) keeps in
+ * FP64 the zeta modes, the bathymetry, element areas, every slope-limiter
+ * and wet/dry operation, the hydrostatic term and the zeta jump of the
+ * flux, the zeta right-hand side and its Runge-Kutta update; the momentum
+ * modes are stored in FP32 and the flux, volume and source arithmetic runs
+ * in FP32.  Each edge's mass flux is added to one element and subtracted
+ * from the other in FP64, so the total mass is conserved to FP64 rounding
+ * in both modes.  States cross this interface as FP64 in both modes (the
+ * momentum rounded to FP32 on dgswe_set_state). */
 
 /* Fill `p` with the defaults: p=1, FP64, g=9.81, rho0=1000, h0=0.01,
  * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1. */

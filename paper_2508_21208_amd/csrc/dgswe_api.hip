@@ -31,7 +31,10 @@ struct dgswe_solver {
   DevMesh m{};
   DevState s{};
   double *d_manning = nullptr;
+  float *d_manningf = nullptr;
   double *d_diag = nullptr;
+  int precision = DGSWE_FP64;
+  double *rb = nullptr;  // FP64 [9][ne] read-back buffer (mixed path)
   long long steps_enq = 0;
   int block = 256;         // workgroup size of the stage kernel
   int cur = 0;             // buffer holding w^n (unlimited unless cur_is_pp)
@@ -39,6 +42,7 @@ struct dgswe_solver {
   bool forcing_dynamic = false;
   std::string err = "no error";
   std::vector<double> stage_buf;
+  std::vector<unsigned char> stage_raw;
   // kernel timing
   bool prof = false;
   struct Rec { int k; hipEvent_t a, b; };
@@ -79,6 +83,32 @@ hipError_t upload(dgswe_solver *S, const T **dst, const std::vector<T> &v) {
   return e;
 }
 
+// FP32 copy of an FP64 array (mixed-precision path)
+hipError_t upload_f32(dgswe_solver *S, const float **dst, const std::vector<double> &v) {
+  std::vector<float> f(v.size());
+  for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
+  return upload(S, dst, f);
+}
+
+// Host image of a caller-order FP64 [9][ne] state in the internal order and
+// the solver's buffer layout (zeta FP64, momentum FP64 or FP32).
+void pack_state(dgswe_solver *S, const double *w) {
+  const size_t ne = S->ne;
+  S->stage_raw.resize(state_bytes(ne, S->precision));
+  double *z = (double *)S->stage_raw.data();
+  for (size_t j = 0; j < 3; ++j)
+    for (size_t i = 0; i < ne; ++i) z[j * ne + i] = w[j * ne + (size_t)S->perm[i]];
+  if (S->precision == DGSWE_MIXED) {
+    float *q = (float *)(z + 3 * ne);
+    for (size_t j = 0; j < 6; ++j)
+      for (size_t i = 0; i < ne; ++i) q[j * ne + i] = (float)w[(3 + j) * ne + (size_t)S->perm[i]];
+  } else {
+    double *q = z + 3 * ne;
+    for (size_t j = 0; j < 6; ++j)
+      for (size_t i = 0; i < ne; ++i) q[j * ne + i] = w[(3 + j) * ne + (size_t)S->perm[i]];
+  }
+}
+
 void free_all(dgswe_solver *S) {
   for (void *p : S->allocs) (void)hipFree(p);
   S->allocs.clear();
@@ -93,7 +123,10 @@ void free_all(dgswe_solver *S) {
 bool validate_params(const dgswe_params *p, std::string &msg) {
   if (!p) { msg = "params is NULL"; return false; }
   if (p->p != 1) { msg = "only p = 1 is supported"; return false; }
-  if (p->precision != DGSWE_FP64) { msg = "only FP64 precision is supported"; return false; }
+  if (p->precision != DGSWE_FP64 && p->precision != DGSWE_MIXED) {
+    msg = "precision must be DGSWE_FP64 or DGSWE_MIXED";
+    return false;
+  }
   if (!(p->g > 0) || !(p->rho0 > 0) || !(p->h0 > 0)) { msg = "g, rho0 and h0 must be positive"; return false; }
   if (!(p->dt_fixed > 0) && !(p->cfl > 0)) { msg = "cfl must be positive when dt_fixed <= 0"; return false; }
   return true;
@@ -188,6 +221,8 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   S->uprm = *prm;
   S->nn = P.nn; S->ne = P.ne; S->ned = P.ned; S->nbnd = P.nbnd;
   S->perm = P.perm;
+  S->precision = prm->precision;
+  const bool mixed = S->precision == DGSWE_MIXED;
   Params &pp = S->prm;
   pp.g = prm->g; pp.rho0 = prm->rho0; pp.h0 = prm->h0; pp.cfl = prm->cfl;
   pp.dt_fixed = prm->dt_fixed; pp.dt_max = prm->dt_max;
@@ -207,6 +242,12 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   chk(upload(S, &m.el_node, P.el_node));
   chk(upload(S, &m.node_x, P.node_x)); chk(upload(S, &m.node_y, P.node_y));
   m.manning = nullptr;
+  m.manningf = nullptr;
+  m.gx1f = m.gy1f = m.gx2f = m.gy2f = m.le_nxf = m.le_nyf = m.le_hlf = nullptr;
+  if (mixed) {
+    chk(upload_f32(S, &m.gx1f, P.gx1)); chk(upload_f32(S, &m.gy1f, P.gy1));
+    chk(upload_f32(S, &m.gx2f, P.gx2)); chk(upload_f32(S, &m.gy2f, P.gy2));
+  }
   // chunk size and workgroup size of the stage kernel
   int chunk = 256, block = 256;
   if (const char *ev = std::getenv("DGSWE_CHUNK")) chunk = std::atoi(ev);
@@ -227,15 +268,30 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   chk(upload(S, &m.le_nx, P.le_nx)); chk(upload(S, &m.le_ny, P.le_ny)); chk(upload(S, &m.le_hl, P.le_hl));
   chk(upload(S, &m.le_hA, P.le_hA)); chk(upload(S, &m.le_hB, P.le_hB));
   chk(upload(S, &m.el_ledge, P.el_ledge)); chk(upload(S, &m.nbl, P.nbl));
-  if (stage_lds_bytes(m) > 80 * 1024 || P.nl_max > 2 * block || P.ed_max > 2 * block) {
+  if (mixed) {
+    chk(upload_f32(S, &m.le_nxf, P.le_nx)); chk(upload_f32(S, &m.le_nyf, P.le_ny));
+    chk(upload_f32(S, &m.le_hlf, P.le_hl));
+  }
+  const size_t lds = stage_lds_bytes(m, S->precision);
+  if (lds > 80 * 1024 || P.nl_max > 2 * block || P.ed_max > 2 * block) {
     free_all(S);
     delete S;
     return fail(nullptr, DGSWE_E_MESH, "element chunks have halos too large for the LDS (" +
-                                           std::to_string(stage_lds_bytes(m)) + " bytes)");
+                                           std::to_string(lds) + " bytes)");
   }
   DevState &st = S->s;
-  for (int b = 0; b < 3; ++b) chk(dev_alloc(S, &st.buf[b], 9 * ne));
-  chk(dev_alloc(S, &st.wpp, 9 * ne));
+  const size_t sb = state_bytes(ne, S->precision);
+  for (int b = 0; b < 3; ++b) {
+    unsigned char *q = nullptr;
+    chk(dev_alloc(S, &q, sb));
+    st.buf[b] = q;
+  }
+  {
+    unsigned char *q = nullptr;
+    chk(dev_alloc(S, &q, sb));
+    st.wpp = q;
+  }
+  if (mixed) chk(dev_alloc(S, &S->rb, 9 * ne));
   chk(dev_alloc(S, &st.nodal, 3 * nn)); chk(dev_alloc(S, &st.partial, 3 * (size_t)diag_blocks(P.ne)));
   chk(dev_alloc(S, &st.ctrl, 1)); chk(dev_alloc(S, &S->d_diag, 4));
   if (!ok) {
@@ -244,9 +300,9 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
     return fail(nullptr, DGSWE_E_NOMEM, "device allocation or upload failed");
   }
   // zero state and forcing, dt of the zero state
-  chk(hipMemsetAsync(st.buf[0], 0, 9 * ne * sizeof(double), S->stream));
+  chk(hipMemsetAsync(st.buf[0], 0, sb, S->stream));
   chk(hipMemsetAsync(st.nodal, 0, 3 * nn * sizeof(double), S->stream));
-  chk(launch_init_state(m, st, pp, st.buf[0], 0.0, S->stream));
+  chk(launch_init_state(m, st, pp, st.buf[0], 0.0, S->precision, S->stream));
   chk(hipStreamSynchronize(S->stream));
   S->cur = 0;
   S->cur_is_pp = true;
@@ -263,19 +319,16 @@ dgswe_status dgswe_set_state(dgswe_solver *S, double t, const double *w, int32_t
   if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
   if (!w) return fail(S, DGSWE_E_INVALID, "state is NULL");
   if (!std::isfinite(t)) return fail(S, DGSWE_E_INVALID, "time is not finite");
-  const size_t ne = S->ne;
-  S->stage_buf.resize(9 * ne);
-  for (size_t j = 0; j < 9; ++j)
-    for (size_t i = 0; i < ne; ++i) S->stage_buf[j * ne + i] = w[j * ne + (size_t)S->perm[i]];
+  pack_state(S, w);
   // The stored state is post-processed by the first stage that reads it;
   // a state given without post-processing is marked as already done.
   S->cur = 0;
   S->cur_is_pp = postprocess == 0;
-  hipError_t e = hipMemcpyAsync(S->s.buf[0], S->stage_buf.data(), 9 * ne * sizeof(double), hipMemcpyHostToDevice,
+  hipError_t e = hipMemcpyAsync(S->s.buf[0], S->stage_raw.data(), S->stage_raw.size(), hipMemcpyHostToDevice,
                                 S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipMemcpyAsync");
   S->steps_enq = 0;
-  e = launch_init_state(S->m, S->s, S->prm, S->s.buf[0], t, S->stream);
+  e = launch_init_state(S->m, S->s, S->prm, S->s.buf[0], t, S->precision, S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "init kernel");
   e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
@@ -313,8 +366,20 @@ dgswe_status dgswe_set_forcing(dgswe_solver *S, const dgswe_forcing *f) {
     e = hipMemcpy(S->d_manning, tmp.data(), ne * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
     S->m.manning = S->d_manning;
+    if (S->precision == DGSWE_MIXED) {
+      if (!S->d_manningf) {
+        e = dev_alloc(S, &S->d_manningf, ne);
+        if (e != hipSuccess) return fail(S, DGSWE_E_NOMEM, "device allocation failed");
+      }
+      std::vector<float> tf(ne);
+      for (size_t i = 0; i < ne; ++i) tf[i] = (float)tmp[i];
+      e = hipMemcpy(S->d_manningf, tf.data(), ne * sizeof(float), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
+      S->m.manningf = S->d_manningf;
+    }
   } else {
     S->m.manning = nullptr;
+    S->m.manningf = nullptr;
   }
   S->forcing_dynamic = p.holland != 0;
   if (!p.holland) {
@@ -351,10 +416,10 @@ dgswe_status dgswe_step(dgswe_solver *S, int32_t n_steps) {
       Timed t(S, K_STAGE);
       if (stage == 0)
         e = launch_stage(m, st, p, st.buf[cur], nullptr, st.buf[s1], st.wpp, slot, 0, pp_cur, 0, S->block,
-                         S->stream);
+                         S->precision, S->stream);
       else
         e = launch_stage(m, st, p, st.buf[s1], st.wpp, st.buf[nx], nullptr, slot, 1, 1, want_dt, S->block,
-                         S->stream);
+                         S->precision, S->stream);
     }
     if (e != hipSuccess) return hip_fail(S, e, "kernel launch");
     S->cur = nx;
@@ -370,11 +435,12 @@ dgswe_status dgswe_read_state(dgswe_solver *S, double *w_out, dgswe_diag *d) {
   if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
   const size_t ne = S->ne;
   if (w_out) {
-    // the state at the boundary is post-processed
-    const double *src = S->s.buf[S->cur];
-    if (!S->cur_is_pp) {
-      double *tmp = S->s.buf[(S->cur + 1) % 3];
-      e = launch_post_only(S->m, S->s, S->prm, src, tmp, S->stream);
+    // the state at the boundary is post-processed FP64 [9][ne]; in FP64 a
+    // free state buffer takes the post-processed copy
+    const void *src = S->s.buf[S->cur];
+    if (!S->cur_is_pp || S->precision == DGSWE_MIXED) {
+      double *tmp = S->precision == DGSWE_MIXED ? S->rb : (double *)S->s.buf[(S->cur + 1) % 3];
+      e = launch_post_only(S->m, S->prm, src, S->cur_is_pp ? 0 : 1, tmp, S->precision, S->stream);
       if (e != hipSuccess) return hip_fail(S, e, "post-processing kernel");
       src = tmp;
     }

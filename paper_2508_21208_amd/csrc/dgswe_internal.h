@@ -48,6 +48,8 @@ struct DevMesh {
   const uint8_t *le_info;          // lp | lm << 2 | type << 4
   const double *le_nx, *le_ny, *le_hl, *le_hA, *le_hB;  // normal, half length, endpoint bathymetry
   const uint16_t *el_ledge, *nbl;
+  // FP32 copies for the mixed-precision path (nullptr in FP64)
+  const float *gx1f, *gy1f, *gx2f, *gy2f, *le_nxf, *le_nyf, *le_hlf, *manningf;
 };
 
 struct Params {
@@ -61,13 +63,14 @@ struct Params {
 };
 
 // Buffers of one solver touched by the step.  The state lives in three
-// rotating [9][ne] buffers (structure of arrays, so a wavefront reads and
-// writes 64 consecutive elements per array); each holds a stage result
-// BEFORE its limiter and wet/dry post-processing, which the next stage
-// applies on the fly.
+// rotating buffers (structure of arrays, so a wavefront reads and writes 64
+// consecutive elements per array): zeta modes [3][ne] FP64, then momentum
+// modes [6][ne] in FP64 or, in the mixed path, FP32.  Each holds a stage
+// result BEFORE its limiter and wet/dry post-processing, which the next
+// stage applies on the fly.
 struct DevState {
-  double *buf[3];
-  double *wpp;     // [9][ne] post-processed w^n of the current step (RK base)
+  void *buf[3];
+  void *wpp;       // post-processed w^n of the current step (RK base), same layout
   double *nodal;   // [3][nn] wind stress x, y and pressure at the nodes
   double *partial; // [3][nblk] diagnostics partial sums
   Ctrl *ctrl;
@@ -111,21 +114,24 @@ hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, 
 // gather, RK combination; writes the unlimited result to `wout`.  The first
 // stage (stage 0) also writes the post-processed input to `wpp`; the second
 // stage reads it back as the RK base `wbase`.
-hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const double *win,
-                        const double *wbase, double *wout, double *wpp, int slot, int stage, int pp_in,
-                        int want_dt, int block, hipStream_t st);
+// `precision` is DGSWE_FP64 or DGSWE_MIXED (state buffer layout and kernels).
+hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const void *win,
+                        const void *wbase, void *wout, void *wpp, int slot, int stage, int pp_in,
+                        int want_dt, int block, int precision, hipStream_t st);
 // thread-block sizes the stage kernel is built for
 constexpr int kStageBlocks[] = {256, 384};
-// Post-process a whole state (win -> wout), e.g. to read it back.
-hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p, const double *win,
-                            double *wout, hipStream_t st);
+// A whole state as FP64 [9][ne] (post-processed if pp), e.g. to read it back.
+hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, double *wout,
+                            int precision, hipStream_t st);
 // Reset the control block to time t and put the CFL candidates of `w`
 // into dtmin[0].
-hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const double *w,
-                             double t, hipStream_t st);
-hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const double *w,
+hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w,
+                             double t, int precision, hipStream_t st);
+// mass, volume and wet count of a state (its zeta block is read)
+hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w,
                        double *out4, hipStream_t st);
-size_t stage_lds_bytes(const DevMesh &m);
+size_t stage_lds_bytes(const DevMesh &m, int precision);
+size_t state_bytes(size_t ne, int precision);
 bool stage_block_ok(int block);
 int diag_blocks(int ne);
 

@@ -1,11 +1,13 @@
 // gfx950 kernels of one SSP-RK(2,2) discontinuous Galerkin shallow-water
-// step (arXiv 2508.21208, Sec. 2.2 and Sec. 5.2), FP64.
+// step (arXiv 2508.21208, Sec. 2.2 and Sec. 5.2).
 //
 // One fused kernel per RK stage.  A workgroup owns a chunk of C consecutive
 // elements (Hilbert order, so a compact patch of the mesh) and works in four
 // phases separated by barriers, all intermediates in LDS:
 //   L  load the chunk and its ring-1 halo (full state) and the ring-2 halo
-//      (means) of the previous stage's UNLIMITED result;
+//      (means) of the previous stage's UNLIMITED result, and issue the loads
+//      of the later phases (bathymetry, neighbour lists, edge records,
+//      geometry, nodal forcing, RK base) so they arrive while L completes;
 //   P  slope limiter + wet/dry of the chunk and ring 1 (the paper's SLOPELIM
 //      and WETDRY kernels), so every state the edges need is post-processed;
 //   E  each edge touching the chunk: traces of both sides at the three
@@ -22,6 +24,16 @@
 // momentum unchanged.  No floating-point atomics: results are deterministic.
 // k_forcing evaluates the Holland vortex once per mesh node and stage (the
 // paper's WIND node loops).
+//
+// Precision.  The kernels are templated on QT, the storage type of the
+// momentum modes and the arithmetic type of the flux, volume and source
+// terms; QT = double is the FP64 path.  QT = float is the mixed path (the
+// paper runs everything in FP32): zeta modes, bathymetry, element areas,
+// every limiter and wet/dry decision of the post-processing, the hydrostatic
+// term g/2 zeta (zeta + 2 h_b), the zeta jump of the numerical flux, the
+// zeta right-hand side and its RK update stay FP64.  Each FP32 edge mass
+// moment is added to one element and subtracted from the other in FP64, so
+// mass is conserved to FP64 rounding in both paths.
 #include "dgswe_internal.h"
 #include "../../include/dgswe.h"
 
@@ -42,11 +54,12 @@ HD unsigned long long double_to_bits(double d) {
   return x.u;
 }
 
-// Reciprocal, square root and cube root for the flux and source arithmetic:
-// the hardware estimates refined by Newton (reciprocal, square root) or
-// Halley (cube root) iterations, within about 1 ulp instead of the
-// correctly rounded library sequences.  Arguments are finite and in the
-// normal range (depths >= h0, lengths and areas of a mesh).
+// Reciprocal, square root and cube root for the flux and source arithmetic.
+// FP64: the hardware estimates refined by Newton (reciprocal, square root)
+// or Halley (cube root) iterations, within about 1 ulp instead of the
+// correctly rounded library sequences.  FP32: the hardware instructions
+// (about 1 ulp).  Arguments are finite and in the normal range (depths >=
+// h0, lengths and areas of a mesh).
 HD double rcp_nr(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
   double r = __builtin_amdgcn_rcp(x);
@@ -55,6 +68,13 @@ HD double rcp_nr(double x) {
   return r;
 #else
   return 1.0 / x;
+#endif
+}
+HD float rcp_nr(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
 #endif
 }
 
@@ -73,9 +93,16 @@ HD double sqrt_nr(double x) {
   return sqrt(x);
 #endif
 }
+HD float sqrt_nr(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return sqrtf(x);
+#endif
+}
 
-// cube root of x > 0: float estimate 2^(log2(x)/3), one Halley step
-// y <- y (y^3 + 2x) / (2y^3 + x) (cubic convergence)
+// cube root of x > 0: float estimate 2^(log2(x)/3); FP64 adds one Halley
+// step y <- y (y^3 + 2x) / (2y^3 + x) (cubic convergence)
 HD double cbrt_nr(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
   const float xf = (float)x;
@@ -85,6 +112,13 @@ HD double cbrt_nr(double x) {
   return y;
 #else
   return cbrt(x);
+#endif
+}
+HD float cbrt_nr(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
+#else
+  return cbrtf(x);
 #endif
 }
 
@@ -109,45 +143,50 @@ HD double tide_level(const Params &p, double t) {
   return z;
 }
 
-// hydrostatic flux g/2 (H^2 - h_b^2) written as g/2 zeta (zeta + 2 h_b)
+// hydrostatic flux g/2 (H^2 - h_b^2) written as g/2 zeta (zeta + 2 h_b), FP64
 HD double p_hydro(double g, double ze, double hb) { return 0.5 * g * ze * (ze + 2.0 * hb); }
 
-// normal physical flux F(w).n of one side; u = 0 on a dry side
-HD void flux_n(double g, double ze, double qx, double qy, double hb, bool wet, double nx, double ny,
-               double &un, double f[3]) {
-  const double H = ze + hb;
-  const double qn = qx * nx + qy * ny;
-  un = wet ? qn * rcp_nr(H) : 0.0;
-  const double p = p_hydro(g, ze, hb);
+// normal physical flux F(w).n of one side; u = 0 on a dry side.  zeta and
+// h_b FP64; momentum, normal and result in R.
+template <class R>
+HD void flux_n(double g, double ze, R qx, R qy, double hb, bool wet, R nx, R ny, R &un, R f[3]) {
+  const R H = (R)(ze + hb);
+  const R qn = qx * nx + qy * ny;
+  un = wet ? qn * rcp_nr(H) : (R)0;
+  const R p = (R)p_hydro(g, ze, hb);
   f[0] = qn;
   f[1] = qx * un + p * nx;
   f[2] = qy * un + p * ny;
 }
 
-// local Lax-Friedrichs flux from side L (normal n points from L to R)
-HD void llf(double g, const double wl[3], const double wr[3], double hb, double nx, double ny,
-            bool wetl, bool wetr, double out[3]) {
-  double unl, unr, fl[3], fr[3];
-  flux_n(g, wl[0], wl[1], wl[2], hb, wetl, nx, ny, unl, fl);
-  flux_n(g, wr[0], wr[1], wr[2], hb, wetr, nx, ny, unr, fr);
-  const double cl = sqrt_nr(g * fmax(wl[0] + hb, 0.0));
-  const double cr = sqrt_nr(g * fmax(wr[0] + hb, 0.0));
-  const double lam = fmax(fabs(unl) + cl, fabs(unr) + cr);
-  for (int m = 0; m < 3; ++m) out[m] = 0.5 * (fl[m] + fr[m]) - 0.5 * lam * (wr[m] - wl[m]);
+// local Lax-Friedrichs flux from side L (normal n points from L to R); the
+// zeta jump is formed in FP64
+template <class R>
+HD void llf(double g, double zl, R qlx, R qly, double zr, R qrx, R qry, double hb, R nx, R ny, bool wetl,
+            bool wetr, R out[3]) {
+  R unl, unr, fl[3], fr[3];
+  flux_n<R>(g, zl, qlx, qly, hb, wetl, nx, ny, unl, fl);
+  flux_n<R>(g, zr, qrx, qry, hb, wetr, nx, ny, unr, fr);
+  const R cl = sqrt_nr((R)(g * fmax(zl + hb, 0.0)));
+  const R cr = sqrt_nr((R)(g * fmax(zr + hb, 0.0)));
+  const R lam = fmax(fabs(unl) + cl, fabs(unr) + cr);
+  const R jump[3] = {(R)(zr - zl), qrx - qlx, qry - qly};
+  for (int m = 0; m < 3; ++m) out[m] = (R)0.5 * (fl[m] + fr[m]) - (R)0.5 * lam * jump[m];
 }
 
 // land wall: LLF against the mirror state, closed form, zero mass flux
-HD void wall(double g, const double w[3], double hb, double nx, double ny, bool wet, double out[3]) {
-  const double p = p_hydro(g, w[0], hb);
-  double f = p;
+template <class R>
+HD void wall(double g, double ze, R qx, R qy, double hb, R nx, R ny, bool wet, R out[3]) {
+  const R p = (R)p_hydro(g, ze, hb);
+  R f = p;
   if (wet) {
-    const double H = w[0] + hb;
-    const double iH = rcp_nr(H);
-    const double qn = w[1] * nx + w[2] * ny;
-    const double lam = fabs(qn) * iH + sqrt_nr(g * fmax(H, 0.0));
+    const double Hd = ze + hb;
+    const R iH = rcp_nr((R)Hd);
+    const R qn = qx * nx + qy * ny;
+    const R lam = fabs(qn) * iH + sqrt_nr((R)(g * fmax(Hd, 0.0)));
     f = qn * qn * iH + p + lam * qn;
   }
-  out[0] = 0.0;
+  out[0] = (R)0;
   out[1] = f * nx;
   out[2] = f * ny;
 }
@@ -187,10 +226,13 @@ HD void holland(const Params &f, double x, double y, double t, double out[3]) {
   out[2] = p;
 }
 
+HD double mean3(const double h[3]) { return (h[0] + h[1] + h[2]) / 3.0; }
+
 // ---------------------------------------------------------------- per-item math
-// Post-processing of one element (slope limiter, then wet/dry).  u[9] is the
-// unlimited state [var*3 + mode]; nbm[v][k] the unlimited mean of variable v
-// of neighbour k (has[k] false: no neighbour); h[3] the vertex bathymetry.
+// Post-processing of one element (slope limiter, then wet/dry), FP64 in
+// both paths.  u[9] is the unlimited state [var*3 + mode]; nbm[v][k] the
+// unlimited mean of variable v of neighbour k (has[k] false: no neighbour);
+// h[3] the vertex bathymetry.
 HD void postprocess(double u[9], const double nbm[3][3], const bool has[3], const double h[3],
                     double hmean, const Params &p) {
   if (p.limiter) {
@@ -241,34 +283,48 @@ HD void postprocess(double u[9], const double nbm[3][3], const bool has[3], cons
   }
 }
 
-// One pass over the three Gauss-Lobatto points s = -1, 0, 1 (weights 1/3,
-// 4/3, 1/3) of an edge in the e+ orientation, accumulating the flux moments
-// m0 = sum_g w_g F_g and m1 = sum_g w_g s_g F_g (before the factor len/2)
-// and the mass-flux integral.  kind 0: LLF between the two sides; 1: land
-// wall seen from e+ (wet flag wetp); 2: wall seen from e- (normal -n).
+// Trace coefficients, bathymetry and normal of one edge at its three
+// Gauss-Lobatto points s = -1, 0, 1 in the e+ orientation.
+template <class R>
 struct EdgeGeo {
   double cp1[3], cp2[3], cm1[3], cm2[3];  // trace coefficients per point, e+ and e-
   double hq[3];                           // bathymetry at the points
-  double nx, ny;
+  R nx, ny;
 };
 
-HD void edge_pass(int kind, const double up[9], const double um[9], bool ghost, double zb, bool wetp, bool wetm,
-                  const EdgeGeo &G, const Params &p, double m0[3], double m1[3], double &mflux) {
-  const double wq[3] = {1.0 / 3.0, 4.0 / 3.0, 1.0 / 3.0};
-  for (int v = 0; v < 3; ++v) { m0[v] = 0.0; m1[v] = 0.0; }
-  mflux = 0.0;
+// One pass over the three points (weights 1/3, 4/3, 1/3), accumulating the
+// flux moments m0 = sum_g w_g F_g and m1 = sum_g w_g s_g F_g (before the
+// factor len/2) and the mass-flux integral.  kind 0: LLF between the two
+// sides; 1: land wall seen from e+ (wet flag wetp); 2: wall seen from e-
+// (normal -n).  States: zeta modes (FP64) and momentum modes (R) of e+ and
+// e-; ghost: the e- trace is (zb, momentum of e+).
+template <class R>
+HD void edge_pass(int kind, const double zp[3], const R qp[6], const double zm[3], const R qm[6], bool ghost,
+                  double zb, bool wetp, bool wetm, const EdgeGeo<R> &G, const Params &p, R m0[3], R m1[3],
+                  R &mflux) {
+  const R wq[3] = {(R)(1.0 / 3.0), (R)(4.0 / 3.0), (R)(1.0 / 3.0)};
+  for (int v = 0; v < 3; ++v) { m0[v] = (R)0; m1[v] = (R)0; }
+  mflux = (R)0;
   for (int g = 0; g < 3; ++g) {
-    double wp[3], wm[3], F[3];
-    for (int v = 0; v < 3; ++v) wp[v] = up[3 * v] + G.cp1[g] * up[3 * v + 1] + G.cp2[g] * up[3 * v + 2];
+    const R c1 = (R)G.cp1[g], c2 = (R)G.cp2[g];
+    const double zpg = zp[0] + G.cp1[g] * zp[1] + G.cp2[g] * zp[2];
+    const R qxp = qp[0] + c1 * qp[1] + c2 * qp[2];
+    const R qyp = qp[3] + c1 * qp[4] + c2 * qp[5];
+    double zmg;
+    R qxm, qym;
     if (ghost) {
-      wm[0] = zb; wm[1] = wp[1]; wm[2] = wp[2];
+      zmg = zb; qxm = qxp; qym = qyp;
     } else {
-      for (int v = 0; v < 3; ++v) wm[v] = um[3 * v] + G.cm1[g] * um[3 * v + 1] + G.cm2[g] * um[3 * v + 2];
+      const R d1 = (R)G.cm1[g], d2 = (R)G.cm2[g];
+      zmg = zm[0] + G.cm1[g] * zm[1] + G.cm2[g] * zm[2];
+      qxm = qm[0] + d1 * qm[1] + d2 * qm[2];
+      qym = qm[3] + d1 * qm[4] + d2 * qm[5];
     }
-    if (kind == 0) llf(p.g, wp, wm, G.hq[g], G.nx, G.ny, wetp, wetm, F);
-    else if (kind == 1) wall(p.g, wp, G.hq[g], G.nx, G.ny, wetp, F);
-    else wall(p.g, wm, G.hq[g], -G.nx, -G.ny, true, F);
-    const double sg = (double)(g - 1);
+    R F[3];
+    if (kind == 0) llf<R>(p.g, zpg, qxp, qyp, zmg, qxm, qym, G.hq[g], G.nx, G.ny, wetp, wetm, F);
+    else if (kind == 1) wall<R>(p.g, zpg, qxp, qyp, G.hq[g], G.nx, G.ny, wetp, F);
+    else wall<R>(p.g, zmg, qxm, qym, G.hq[g], -G.nx, -G.ny, true, F);
+    const R sg = (R)(g - 1);
     for (int v = 0; v < 3; ++v) {
       m0[v] += wq[g] * F[v];
       m1[v] += (wq[g] * sg) * F[v];
@@ -284,10 +340,11 @@ HD void edge_pass(int kind, const double up[9], const double um[9], bool ghost, 
 // side dry -> LLF with u = 0 on the dry side if its mass flux runs into the
 // dry side, else a wall for the wet side and nothing for the dry side.
 // Ocean edges: ghost state (zeta_b, Q+), wet iff zeta_b + mean h_b > h0.
-HD int edge_flux(const double up[9], const double um[9], int lp, int lm, int type, bool wetp, bool wetm_in,
-                 double hA, double hB, double nx, double ny, double hl, double zb, const Params &p,
-                 double mom[6]) {
-  EdgeGeo G;
+template <class R>
+HD int edge_flux(const double zp[3], const R qp[6], const double zm[3], const R qm[6], int lp, int lm, int type,
+                 bool wetp, bool wetm_in, double hA, double hB, R nx, R ny, R hl, double zb, const Params &p,
+                 R mom[6]) {
+  EdgeGeo<R> G;
   const int va = lp == 2 ? 0 : lp + 1, vb = lp == 0 ? 2 : lp - 1;
   G.cp1[0] = c1v(va); G.cp2[0] = c2v(va);
   G.cp1[1] = c1m(lp); G.cp2[1] = c2m(lp);
@@ -301,28 +358,28 @@ HD int edge_flux(const double up[9], const double um[9], int lp, int lm, int typ
   G.nx = nx; G.ny = ny;
   const bool ghost = type != 0;
   const bool wetm = ghost ? (p.wetdry ? (zb + 0.5 * (hA + hB) > p.h0) : true) : wetm_in;
-  double m0[3], m1[3], mflux;
+  R m0[3], m1[3], mflux;
   int mode;
   bool minus = false;
   if (type == DGSWE_BC_LAND) {
-    edge_pass(1, up, um, true, zb, wetp, wetm, G, p, m0, m1, mflux);
+    edge_pass<R>(1, zp, qp, zm, qm, true, zb, wetp, wetm, G, p, m0, m1, mflux);
     mode = 1;
   } else if (!wetp && !wetm) {
-    for (int v = 0; v < 6; ++v) mom[v] = 0.0;
+    for (int v = 0; v < 6; ++v) mom[v] = (R)0;
     return 3;
   } else {
-    edge_pass(0, up, um, ghost, zb, wetp, wetm, G, p, m0, m1, mflux);
+    edge_pass<R>(0, zp, qp, zm, qm, ghost, zb, wetp, wetm, G, p, m0, m1, mflux);
     mode = ghost ? 1 : 0;
     if (!(wetp && wetm)) {
-      const bool flood = wetp ? (mflux > 0.0) : (mflux < 0.0);
+      const bool flood = wetp ? (mflux > (R)0) : (mflux < (R)0);
       if (!flood) {
         if (wetp) {
-          edge_pass(1, up, um, ghost, zb, true, wetm, G, p, m0, m1, mflux);
+          edge_pass<R>(1, zp, qp, zm, qm, ghost, zb, true, wetm, G, p, m0, m1, mflux);
           mode = 1;
         } else if (ghost) {
           mode = 3;
         } else {
-          edge_pass(2, up, um, false, zb, wetp, true, G, p, m0, m1, mflux);
+          edge_pass<R>(2, zp, qp, zm, qm, false, zb, wetp, true, G, p, m0, m1, mflux);
           mode = 2;
           minus = true;
         }
@@ -331,7 +388,7 @@ HD int edge_flux(const double up[9], const double um[9], int lp, int lm, int typ
   }
   // mode 2 holds the e- frame moments (P0, P1) with P1 along e-'s own
   // direction (-s); they are stored so that e- reads (-M0, M1) = (P0, P1)
-  const double sgn = minus ? -1.0 : 1.0;
+  const R sgn = minus ? (R)-1 : (R)1;
   for (int v = 0; v < 3; ++v) {
     mom[v] = sgn * hl * m0[v];
     mom[3 + v] = sgn * hl * m1[v];
@@ -339,46 +396,58 @@ HD int edge_flux(const double up[9], const double um[9], int lp, int lm, int typ
   return mode;
 }
 
-// Geometry and forcing of one element, as the area integrals need them.
-struct ElemIn {
-  double g1x, g1y, g2x, g2y, area;
+// Per-element inputs of the area integrals and of the RK update, loaded in
+// phase L and kept in registers: vertex bathymetry, wind stress at the
+// vertices, the pressure gradient modes, Manning n, 2 x inradius, the
+// chunk-local edges and (second stage) the post-processed RK base.
+template <class QT>
+struct ElemPre {
   double h[3];
-  double tx[3], ty[3], pa[3];
-  double manning;
+  QT tx[3], ty[3];
+  QT pm1, pm2;  // modes of grad p_a on grad phi_10, grad phi_01
+  double wbz[3];
+  QT wbq[6];
+  double inr2;
+  QT manning;
+  int ledge[3];
 };
 
-// Volume + source integrals of a post-processed state u; returns R_k / A
-// (area part) in r[9]:  (1/3) [grad phi_k . sum_q F(w_q) + sum_q phi_k(q) s(w_q)].
-HD void area_terms(const double u[9], bool wet, const ElemIn &E, const Params &p, double r[9]) {
+// Volume + source integrals of a post-processed state (zeta FP64, momentum
+// R); returns R_k / A (area part) (1/3) [grad phi_k . sum_q F(w_q) + sum_q
+// phi_k(q) s(w_q)] in rz[3] (FP64) and rq[6] (R).
+template <class R>
+HD void area_terms(const double z[3], const R q[6], bool wet, const ElemPre<R> &E, R g1x, R g1y, R g2x, R g2y,
+                   const Params &p, double rz[3], R rq[6]) {
   // gradient of a linear nodal field with vertex values f0, f1, f2: modes
   // (f1 - f0)/2 and (2 (f2 - f0) - (f1 - f0))/6 on grad phi_10, grad phi_01,
   // from vertex differences so a large common offset cancels exactly
   const double dh1 = E.h[1] - E.h[0], dh2 = E.h[2] - E.h[0];
-  const double hm1 = 0.5 * dh1, hm2 = (2.0 * dh2 - dh1) * (1.0 / 6.0);
-  const double dhx = hm1 * E.g1x + hm2 * E.g2x, dhy = hm1 * E.g1y + hm2 * E.g2y;
-  const double dp1 = E.pa[1] - E.pa[0], dp2 = E.pa[2] - E.pa[0];
-  const double pm1 = 0.5 * dp1, pm2 = (2.0 * dp2 - dp1) * (1.0 / 6.0);
-  const double dpx = pm1 * E.g1x + pm2 * E.g2x, dpy = pm1 * E.g1y + pm2 * E.g2y;
-  const double gn2 = p.g * E.manning * E.manning;
-  const double irho = 1.0 / p.rho0;
+  const R hm1 = (R)(0.5 * dh1), hm2 = (R)((2.0 * dh2 - dh1) * (1.0 / 6.0));
+  const R dhx = hm1 * g1x + hm2 * g2x, dhy = hm1 * g1y + hm2 * g2y;
+  const R dpx = E.pm1 * g1x + E.pm2 * g2x, dpy = E.pm1 * g1y + E.pm2 * g2y;
+  const R gr = (R)p.g;
+  const R gn2 = gr * E.manning * E.manning;
+  const R irho = (R)(1.0 / p.rho0);
+  const R h0 = (R)p.h0;
   // area points: barycentric (2/3,1/6,1/6) and permutations; basis values
   // phi_10 = (-1/2, 1/2, 0), phi_01 = (-1/2, -1/2, 1)
   const double C1[3] = {-0.5, 0.5, 0.0}, C2[3] = {-0.5, -0.5, 1.0};
   const double L0[3] = {2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0};
   const double L1[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
   const double L2[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
-  double sF[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-  double S0[3] = {0, 0, 0}, S1[3] = {0, 0, 0}, S2[3] = {0, 0, 0};
-  for (int q = 0; q < 3; ++q) {
-    const double ze = u[0] + C1[q] * u[1] + C2[q] * u[2];
-    const double qx = u[3] + C1[q] * u[4] + C2[q] * u[5];
-    const double qy = u[6] + C1[q] * u[7] + C2[q] * u[8];
-    const double hb = L0[q] * E.h[0] + L1[q] * E.h[1] + L2[q] * E.h[2];
-    const double H = ze + hb;
-    const double ph = p_hydro(p.g, ze, hb);
-    double uu = 0.0, vv = 0.0;
+  R sF[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  R S0[2] = {0, 0}, S1[2] = {0, 0}, S2[2] = {0, 0};
+  for (int qd = 0; qd < 3; ++qd) {
+    const R c1 = (R)C1[qd], c2 = (R)C2[qd], l0 = (R)L0[qd], l1 = (R)L1[qd], l2 = (R)L2[qd];
+    const double ze = z[0] + C1[qd] * z[1] + C2[qd] * z[2];
+    const R qx = q[0] + c1 * q[1] + c2 * q[2];
+    const R qy = q[3] + c1 * q[4] + c2 * q[5];
+    const double hb = L0[qd] * E.h[0] + L1[qd] * E.h[1] + L2[qd] * E.h[2];
+    const R H = (R)(ze + hb);
+    const R ph = (R)p_hydro(p.g, ze, hb);
+    R uu = (R)0, vv = (R)0;
     if (wet) {
-      const double iH = rcp_nr(H);
+      const R iH = rcp_nr(H);
       uu = qx * iH;
       vv = qy * iH;
     }
@@ -386,94 +455,131 @@ HD void area_terms(const double u[9], bool wet, const ElemIn &E, const Params &p
     sF[1][0] += qx * uu + ph;  sF[1][1] += qx * vv;
     sF[2][0] += qy * uu;       sF[2][1] += qy * vv + ph;
     if (wet) {
-      const double Hf = fmax(H, p.h0);
-      const double qm = sqrt_nr(qx * qx + qy * qy);
-      const double fr = gn2 * qm * rcp_nr(Hf * Hf * cbrt_nr(Hf));
-      const double txq = L0[q] * E.tx[0] + L1[q] * E.tx[1] + L2[q] * E.tx[2];
-      const double tyq = L0[q] * E.ty[0] + L1[q] * E.ty[1] + L2[q] * E.ty[2];
-      const double sx = p.g * ze * dhx - fr * qx + txq * irho - H * irho * dpx;
-      const double sy = p.g * ze * dhy - fr * qy + tyq * irho - H * irho * dpy;
-      S0[1] += sx;          S0[2] += sy;
-      S1[1] += C1[q] * sx;  S1[2] += C1[q] * sy;
-      S2[1] += C2[q] * sx;  S2[2] += C2[q] * sy;
+      const R Hf = fmax(H, h0);
+      const R qm = sqrt_nr(qx * qx + qy * qy);
+      const R fr = gn2 * qm * rcp_nr(Hf * Hf * cbrt_nr(Hf));
+      const R txq = l0 * E.tx[0] + l1 * E.tx[1] + l2 * E.tx[2];
+      const R tyq = l0 * E.ty[0] + l1 * E.ty[1] + l2 * E.ty[2];
+      const R gz = (R)(p.g * ze);
+      const R sx = gz * dhx - fr * qx + txq * irho - H * irho * dpx;
+      const R sy = gz * dhy - fr * qy + tyq * irho - H * irho * dpy;
+      S0[0] += sx;          S0[1] += sy;
+      S1[0] += c1 * sx;     S1[1] += c1 * sy;
+      S2[0] += c2 * sx;     S2[1] += c2 * sy;
     }
   }
-  for (int v = 0; v < 3; ++v) {
-    r[3 * v + 0] = S0[v] * (1.0 / 3.0);
-    r[3 * v + 1] = (E.g1x * sF[v][0] + E.g1y * sF[v][1] + S1[v]) * (1.0 / 3.0);
-    r[3 * v + 2] = (E.g2x * sF[v][0] + E.g2y * sF[v][1] + S2[v]) * (1.0 / 3.0);
+  const R third = (R)(1.0 / 3.0);
+  rz[0] = 0.0;  // no mass source
+  rz[1] = (double)((g1x * sF[0][0] + g1y * sF[0][1]) * third);
+  rz[2] = (double)((g2x * sF[0][0] + g2y * sF[0][1]) * third);
+  for (int v = 0; v < 2; ++v) {
+    rq[3 * v + 0] = S0[v] * third;
+    rq[3 * v + 1] = (g1x * sF[v + 1][0] + g1y * sF[v + 1][1] + S1[v]) * third;
+    rq[3 * v + 2] = (g2x * sF[v + 1][0] + g2y * sF[v + 1][1] + S2[v]) * third;
   }
 }
 
 // CFL candidate 2 r_e / (|Q_mean| / H_mean + sqrt(g H_mean)) of a state
 // (INFINITY when dry); unchanged by the post-processing.
-HD double cfl_candidate(const double u[9], double hmean, double inr2, const Params &p) {
-  const double Hm = u[0] + hmean;
+HD double cfl_candidate(double z0, double qx0, double qy0, double hmean, double inr2, const Params &p) {
+  const double Hm = z0 + hmean;
   const bool wet = p.wetdry ? (Hm > p.h0) : true;
   if (!wet) return INFINITY;
-  const double lam = sqrt(u[3] * u[3] + u[6] * u[6]) / Hm + sqrt(p.g * Hm);
+  const double lam = sqrt(qx0 * qx0 + qy0 * qy0) / Hm + sqrt(p.g * Hm);
   return inr2 / lam;
 }
 
-HD double mean3(const double h[3]) { return (h[0] + h[1] + h[2]) / 3.0; }
-
 // ---------------------------------------------------------------- global-memory views
-// Element e of a [9][ne] state, post-processed with neighbour means read
-// from the same array (used for the RK base and read-back).
-HD void load_pp_global(const DevMesh &m, const Params &p, const double *w, int e, bool pp, double u[9],
-                       double h[3]) {
+// A state buffer: zeta modes [3][ne] FP64, then momentum modes [6][ne] of
+// type QT (Qx modes 0-2, Qy modes 0-2), each mode contiguous.
+template <class QT>
+struct St {
+  double *z;
+  QT *q;
+};
+template <class QT>
+struct CSt {
+  const double *z;
+  const QT *q;
+};
+
+// element arrays stored in the precision of the flux arithmetic
+template <class QT>
+struct QMesh {
+  const QT *gx1, *gy1, *gx2, *gy2;  // physical gradients of phi_10, phi_01
+  const QT *nx, *ny, *hl;           // chunk-local edge normal and half length
+  const QT *manning;                // per-element Manning n or nullptr
+};
+HD QMesh<double> qmesh(const DevMesh &m, const double *) {
+  return {m.gx1, m.gy1, m.gx2, m.gy2, m.le_nx, m.le_ny, m.le_hl, m.manning};
+}
+HD QMesh<float> qmesh(const DevMesh &m, const float *) {
+  return {m.gx1f, m.gy1f, m.gx2f, m.gy2f, m.le_nxf, m.le_nyf, m.le_hlf, m.manningf};
+}
+template <class QT>
+HD QMesh<QT> qmesh(const DevMesh &m) {
+  return qmesh(m, (const QT *)nullptr);
+}
+
+// Element e of a state, post-processed with neighbour means read from the
+// same state if pp, as FP64 (read-back)
+template <class QT>
+HD void load_pp_global(const DevMesh &m, const Params &p, CSt<QT> w, int e, bool pp, double u[9]) {
   const size_t ne = (size_t)m.ne;
-  for (int j = 0; j < 9; ++j) u[j] = w[j * ne + e];
-  for (int k = 0; k < 3; ++k) h[k] = m.hbv[k * ne + e];
+  for (int k = 0; k < 3; ++k) u[k] = w.z[k * ne + e];
+  for (int k = 0; k < 6; ++k) u[3 + k] = (double)w.q[k * ne + e];
   if (!pp) return;
-  double nbm[3][3];
+  double h[3], nbm[3][3];
   bool has[3];
+  for (int k = 0; k < 3; ++k) h[k] = m.hbv[k * ne + e];
   for (int k = 0; k < 3; ++k) {
     const int f = m.el_nb[k * ne + e];
     has[k] = f >= 0;
-    for (int v = 0; v < 3; ++v) nbm[v][k] = has[k] ? w[(size_t)(3 * v) * ne + f] : 0.0;
+    nbm[0][k] = has[k] ? w.z[f] : 0.0;
+    nbm[1][k] = has[k] ? (double)w.q[f] : 0.0;
+    nbm[2][k] = has[k] ? (double)w.q[3 * ne + f] : 0.0;
   }
   postprocess(u, nbm, has, h, mean3(h), p);
 }
 
-HD void load_elem_in(const DevMesh &m, const DevState &s, const Params &p, int e, ElemIn &E) {
-  const size_t ne = (size_t)m.ne, nn = (size_t)m.nn;
-  E.g1x = m.gx1[e]; E.g1y = m.gy1[e]; E.g2x = m.gx2[e]; E.g2y = m.gy2[e];
-  E.area = m.area[e];
-  for (int k = 0; k < 3; ++k) {
-    E.h[k] = m.hbv[k * ne + e];
-    const int nd = m.el_node[k * ne + e];
-    E.tx[k] = s.nodal[nd];
-    E.ty[k] = s.nodal[nn + nd];
-    E.pa[k] = s.nodal[2 * nn + nd];
-  }
-  E.manning = m.manning ? m.manning[e] : p.manning_n;
-}
-
 // ---------------------------------------------------------------- fused stage phases
 // LDS layout of one chunk (sizes from the mesh maxima):
-//   S[9][nl_max]  states of chunk + ring 1 (post-processed in phase P)
-//   MQ[2][nm_max] unlimited Qx, Qy means of chunk + ring 1 + ring 2
-//   MZ[n2_max]    unlimited zeta means of ring 2 (the zeta mean of chunk and
-//                 ring 1 is S[0][i], which the post-processing never changes)
-//   EM[6][ed_max] edge moments
-//   GEO[5][C]     gradients of phi_10, phi_01 and area of the chunk elements
-//   EMODE[ed_max], WET[nl_max]
+//   SZ[3][nl_max] double, SQ[6][nl_max] QT: states of chunk + ring 1
+//                 (post-processed in phase P)
+//   MZ[n2_max]    double: unlimited zeta means of ring 2 (the zeta mean of
+//                 chunk and ring 1 is SZ[0][i], never changed by phase P)
+//   GA[C]         double: element areas
+//   MQ[2][nm_max] QT: unlimited Qx, Qy means of chunk + ring 1 + ring 2
+//   EM[6][ed_max] QT: edge moments
+//   GG[4][C]      QT: gradients of phi_10, phi_01 of the chunk elements
+//   EMODE[ed_max], WET[nl_max] bytes
+template <class QT>
 struct Lds {
-  double *S, *MQ, *MZ, *EM, *GEO;
+  double *SZ, *MZ, *GA;
+  QT *SQ, *MQ, *EM, *GG;
   unsigned char *EMODE, *WET;
   int nls, nms, eds, cs;  // strides
 };
 
-HD Lds lds_view(const DevMesh &m, void *base) {
-  Lds L;
+template <class QT>
+HD size_t lds_bytes(const DevMesh &m) {
+  return 8 * (3 * (size_t)m.nl_max + (size_t)m.n2_max + (size_t)m.C) +
+         sizeof(QT) * (6 * (size_t)m.nl_max + 2 * (size_t)m.nm_max + 6 * (size_t)m.ed_max + 4 * (size_t)m.C) +
+         (size_t)m.ed_max + (size_t)m.nl_max;
+}
+
+template <class QT>
+HD Lds<QT> lds_view(const DevMesh &m, void *base) {
+  Lds<QT> L;
   L.nls = m.nl_max; L.nms = m.nm_max; L.eds = m.ed_max; L.cs = m.C;
-  L.S = (double *)base;
-  L.MQ = L.S + 9 * (size_t)L.nls;
-  L.MZ = L.MQ + 2 * (size_t)L.nms;
-  L.EM = L.MZ + (size_t)m.n2_max;
-  L.GEO = L.EM + 6 * (size_t)L.eds;
-  L.EMODE = (unsigned char *)(L.GEO + 5 * (size_t)L.cs);
+  L.SZ = (double *)base;
+  L.MZ = L.SZ + 3 * (size_t)L.nls;
+  L.GA = L.MZ + (size_t)m.n2_max;
+  L.SQ = (QT *)(L.GA + (size_t)L.cs);
+  L.MQ = L.SQ + 6 * (size_t)L.nls;
+  L.EM = L.MQ + 2 * (size_t)L.nms;
+  L.GG = L.EM + 6 * (size_t)L.eds;
+  L.EMODE = (unsigned char *)(L.GG + 4 * (size_t)L.cs);
   L.WET = L.EMODE + L.eds;
   return L;
 }
@@ -496,16 +602,19 @@ HD ChunkInfo chunk_info(const DevMesh &m, int c) {
 }
 
 // one chunk-local edge record, loaded early and kept in registers
+template <class QT>
 struct EdgeRec {
   uint32_t pm;
   int info;
-  double nx, ny, hl, hA, hB;
+  QT nx, ny, hl;
+  double hA, hB;
 };
 
-HD void load_edge_rec(const DevMesh &m, const ChunkInfo &k, int j, EdgeRec &R) {
+template <class QT>
+HD void load_edge_rec(const DevMesh &m, const QMesh<QT> &Q, const ChunkInfo &k, int j, EdgeRec<QT> &R) {
   const size_t r = (size_t)(k.leo + j);
   R.pm = m.le_pm[r]; R.info = m.le_info[r];
-  R.nx = m.le_nx[r]; R.ny = m.le_ny[r]; R.hl = m.le_hl[r]; R.hA = m.le_hA[r]; R.hB = m.le_hB[r];
+  R.nx = Q.nx[r]; R.ny = Q.ny[r]; R.hl = Q.hl[r]; R.hA = m.le_hA[r]; R.hB = m.le_hB[r];
 }
 
 // vertex bathymetry of local element i (chunk: element arrays; ring 1:
@@ -521,50 +630,59 @@ HD void load_local_hb(const DevMesh &m, const ChunkInfo &k, int i, double h[3]) 
   }
 }
 
-// phase L for local element i of chunk + ring 1
-HD void phase_load_nl(const DevMesh &m, const ChunkInfo &k, const Lds &L, const double *win, int i) {
-  const size_t ne = (size_t)m.ne;
-  const int g = i < k.cc ? k.c0 + i : m.h1[k.h1o + i - k.cc];
-  double u[9];
-  for (int j = 0; j < 9; ++j) u[j] = win[j * ne + g];
-  for (int j = 0; j < 9; ++j) L.S[j * L.nls + i] = u[j];
-  L.MQ[i] = u[3];
-  L.MQ[L.nms + i] = u[6];
-}
-
-// phase L for ring-2 element j (means only)
-HD void phase_load_h2(const DevMesh &m, const ChunkInfo &k, const Lds &L, const double *win, int j) {
-  const size_t ne = (size_t)m.ne;
-  const int g = m.h2[k.h2o + j];
-  L.MZ[j] = win[g];
-  L.MQ[k.nl() + j] = win[3 * ne + g];
-  L.MQ[L.nms + k.nl() + j] = win[6 * ne + g];
-}
-
-// phase L: geometry of chunk element i into LDS
-HD void phase_load_geo(const DevMesh &m, const ChunkInfo &k, const Lds &L, int i) {
-  const int e = k.c0 + i;
-  L.GEO[i] = m.gx1[e];
-  L.GEO[L.cs + i] = m.gy1[e];
-  L.GEO[2 * L.cs + i] = m.gx2[e];
-  L.GEO[3 * L.cs + i] = m.gy2[e];
-  L.GEO[4 * L.cs + i] = m.area[e];
-}
-
-// phase P for local element i of chunk + ring 1 (h: its vertex bathymetry);
-// the post-processed state of a chunk element also goes to wpp if given
 // local neighbour indices of local element i (chunk + ring 1)
 HD void load_local_nb(const DevMesh &m, const ChunkInfo &k, int i, uint16_t nb[3]) {
   const int nl = k.nl();
   for (int q = 0; q < 3; ++q) nb[q] = m.nbl[k.nbo + q * nl + i];
 }
 
-HD void phase_post(const DevMesh &m, const Params &p, const ChunkInfo &k, const Lds &L, int pp_in, int i,
-                   const double h[3], const uint16_t nb[3], double *wpp) {
+// phase L for local element i of chunk + ring 1
+template <class QT>
+HD void phase_load_nl(const DevMesh &m, const ChunkInfo &k, const Lds<QT> &L, CSt<QT> win, int i) {
+  const size_t ne = (size_t)m.ne;
+  const int g = i < k.cc ? k.c0 + i : m.h1[k.h1o + i - k.cc];
+  double z[3];
+  QT q[6];
+  for (int j = 0; j < 3; ++j) z[j] = win.z[j * ne + g];
+  for (int j = 0; j < 6; ++j) q[j] = win.q[j * ne + g];
+  for (int j = 0; j < 3; ++j) L.SZ[j * L.nls + i] = z[j];
+  for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = q[j];
+  L.MQ[i] = q[0];
+  L.MQ[L.nms + i] = q[3];
+}
+
+// phase L for ring-2 element j (means only)
+template <class QT>
+HD void phase_load_h2(const DevMesh &m, const ChunkInfo &k, const Lds<QT> &L, CSt<QT> win, int j) {
+  const size_t ne = (size_t)m.ne;
+  const int g = m.h2[k.h2o + j];
+  L.MZ[j] = win.z[g];
+  L.MQ[k.nl() + j] = win.q[g];
+  L.MQ[L.nms + k.nl() + j] = win.q[3 * ne + g];
+}
+
+// phase L: geometry of chunk element i into LDS
+template <class QT>
+HD void phase_load_geo(const DevMesh &m, const QMesh<QT> &Q, const ChunkInfo &k, const Lds<QT> &L, int i) {
+  const int e = k.c0 + i;
+  L.GG[i] = Q.gx1[e];
+  L.GG[L.cs + i] = Q.gy1[e];
+  L.GG[2 * L.cs + i] = Q.gx2[e];
+  L.GG[3 * L.cs + i] = Q.gy2[e];
+  L.GA[i] = m.area[e];
+}
+
+// phase P for local element i of chunk + ring 1 (h: its vertex bathymetry,
+// nb: local neighbour indices); the post-processed state of a chunk element
+// also goes to wpp if given
+template <class QT>
+HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp_in, int i, const double h[3],
+                   const uint16_t nb[3], const St<QT> *wpp, size_t ne) {
   const int nl = k.nl();
   const double hmean = mean3(h);
   double u[9];
-  for (int j = 0; j < 9; ++j) u[j] = L.S[j * L.nls + i];
+  for (int j = 0; j < 3; ++j) u[j] = L.SZ[j * L.nls + i];
+  for (int j = 0; j < 6; ++j) u[3 + j] = (double)L.SQ[j * L.nls + i];
   if (pp_in) {
     double nbm[3][3];
     bool has[3];
@@ -572,52 +690,51 @@ HD void phase_post(const DevMesh &m, const Params &p, const ChunkInfo &k, const 
       const uint16_t f = nb[q];
       has[q] = f != kNone;
       const int fi = has[q] ? f : 0;
-      nbm[0][q] = fi < nl ? L.S[fi] : L.MZ[fi - nl];
-      nbm[1][q] = L.MQ[fi];
-      nbm[2][q] = L.MQ[L.nms + fi];
+      nbm[0][q] = fi < nl ? L.SZ[fi] : L.MZ[fi - nl];
+      nbm[1][q] = (double)L.MQ[fi];
+      nbm[2][q] = (double)L.MQ[L.nms + fi];
     }
     postprocess(u, nbm, has, h, hmean, p);
-    // the zeta mean S[0][i] is unchanged (neighbours read it concurrently)
-    for (int j = 1; j < 9; ++j) L.S[j * L.nls + i] = u[j];
+    // the zeta mean SZ[0][i] is unchanged (neighbours read it concurrently)
+    for (int j = 1; j < 3; ++j) L.SZ[j * L.nls + i] = u[j];
+    for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = (QT)u[3 + j];
   }
   L.WET[i] = (p.wetdry ? (u[0] + hmean > p.h0) : true) ? 1 : 0;
   if (wpp && i < k.cc) {
-    const size_t ne = (size_t)m.ne;
-    for (int j = 0; j < 9; ++j) wpp[j * ne + k.c0 + i] = u[j];
+    const size_t e = (size_t)(k.c0 + i);
+    for (int j = 0; j < 3; ++j) wpp->z[j * ne + e] = u[j];
+    for (int j = 0; j < 6; ++j) wpp->q[j * ne + e] = (QT)u[3 + j];
   }
 }
 
 // phase E for chunk-local edge j with its record
-HD void phase_edge(const Params &p, const Lds &L, double zb, int j, const EdgeRec &R) {
+template <class QT>
+HD void phase_edge(const Params &p, const Lds<QT> &L, double zb, int j, const EdgeRec<QT> &R) {
   const int lp = R.info & 3, lm = (R.info >> 2) & 3, type = R.info >> 4;
   const int ip = (int)(R.pm & 0xFFFFu), im = (int)(R.pm >> 16);
-  double up[9], um[9];
-  for (int q = 0; q < 9; ++q) up[q] = L.S[q * L.nls + ip];
+  double zp[3], zm[3];
+  QT qp[6], qm[6];
+  for (int q = 0; q < 3; ++q) zp[q] = L.SZ[q * L.nls + ip];
+  for (int q = 0; q < 6; ++q) qp[q] = L.SQ[q * L.nls + ip];
   bool wetm = false;
   if (type == 0) {
-    for (int q = 0; q < 9; ++q) um[q] = L.S[q * L.nls + im];
+    for (int q = 0; q < 3; ++q) zm[q] = L.SZ[q * L.nls + im];
+    for (int q = 0; q < 6; ++q) qm[q] = L.SQ[q * L.nls + im];
     wetm = L.WET[im] != 0;
   } else {
-    for (int q = 0; q < 9; ++q) um[q] = 0.0;
+    for (int q = 0; q < 3; ++q) zm[q] = 0.0;
+    for (int q = 0; q < 6; ++q) qm[q] = (QT)0;
   }
-  double mom[6];
-  const int mode = edge_flux(up, um, lp, lm, type, L.WET[ip] != 0, wetm, R.hA, R.hB, R.nx, R.ny, R.hl, zb, p, mom);
+  QT mom[6];
+  const int mode =
+      edge_flux<QT>(zp, qp, zm, qm, lp, lm, type, L.WET[ip] != 0, wetm, R.hA, R.hB, R.nx, R.ny, R.hl, zb, p, mom);
   for (int q = 0; q < 6; ++q) L.EM[q * L.eds + j] = mom[q];
   L.EMODE[j] = (unsigned char)mode;
 }
 
-// per-element inputs of phase A, loaded in phase L and kept in registers
-// (nodal forcing at the vertices, RK base on the second stage)
-struct ElemPre {
-  double h[3];
-  double tx[3], ty[3], pa[3];
-  double wb[9];
-  double inr2, manning;
-  int ledge[3];
-};
-
-HD void load_elem_pre(const DevMesh &m, const DevState &s, const Params &p, const ChunkInfo &k, int i,
-                      const double *wbase, ElemPre &P) {
+template <class QT>
+HD void load_elem_pre(const DevMesh &m, const QMesh<QT> &Q, const DevState &s, const Params &p,
+                      const ChunkInfo &k, int i, const CSt<QT> *wbase, ElemPre<QT> &P) {
   const size_t ne = (size_t)m.ne, nn = (size_t)m.nn;
   const int e = k.c0 + i;
   int node[3];
@@ -627,67 +744,84 @@ HD void load_elem_pre(const DevMesh &m, const DevState &s, const Params &p, cons
     P.ledge[q] = m.el_ledge[q * ne + e];
   }
   P.inr2 = m.inr2[e];
-  P.manning = m.manning ? m.manning[e] : p.manning_n;
+  P.manning = Q.manning ? Q.manning[e] : (QT)p.manning_n;
+  double pa[3];
   for (int q = 0; q < 3; ++q) {
-    P.tx[q] = s.nodal[node[q]];
-    P.ty[q] = s.nodal[nn + node[q]];
-    P.pa[q] = s.nodal[2 * nn + node[q]];
+    P.tx[q] = (QT)s.nodal[node[q]];
+    P.ty[q] = (QT)s.nodal[nn + node[q]];
+    pa[q] = s.nodal[2 * nn + node[q]];
   }
-  if (wbase)
-    for (int j = 0; j < 9; ++j) P.wb[j] = wbase[j * ne + e];
+  // pressure modes from vertex differences in FP64 (large common offset)
+  const double dp1 = pa[1] - pa[0], dp2 = pa[2] - pa[0];
+  P.pm1 = (QT)(0.5 * dp1);
+  P.pm2 = (QT)((2.0 * dp2 - dp1) * (1.0 / 6.0));
+  if (wbase) {
+    for (int j = 0; j < 3; ++j) P.wbz[j] = wbase->z[j * ne + e];
+    for (int j = 0; j < 6; ++j) P.wbq[j] = wbase->q[j * ne + e];
+  }
 }
 
 // phase A for chunk element i; returns the CFL candidate of the output when
 // want_dt, and sets bad on a non-finite output.  base: combine with the
-// post-processed RK base P.wb (second stage).
-HD double phase_area(const DevMesh &m, const Params &p, const ChunkInfo &k, const Lds &L, const ElemPre &P,
-                     bool base, double *wout, double dt, int want_dt, int i, bool &bad) {
-  const size_t ne = (size_t)m.ne;
-  const int e = k.c0 + i;
-  ElemIn E;
-  for (int q = 0; q < 3; ++q) {
-    E.h[q] = P.h[q];
-    E.tx[q] = P.tx[q];
-    E.ty[q] = P.ty[q];
-    E.pa[q] = P.pa[q];
-  }
-  E.manning = P.manning;
-  E.g1x = L.GEO[i]; E.g1y = L.GEO[L.cs + i]; E.g2x = L.GEO[2 * L.cs + i]; E.g2y = L.GEO[3 * L.cs + i];
-  E.area = L.GEO[4 * L.cs + i];
-  double u[9];
-  for (int j = 0; j < 9; ++j) u[j] = L.S[j * L.nls + i];
+// post-processed RK base held in P (second stage).
+template <class QT>
+HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, const ElemPre<QT> &P, bool base,
+                     St<QT> wout, size_t ne, double dt, int want_dt, int i, bool &bad) {
+  const size_t e = (size_t)(k.c0 + i);
+  double z[3];
+  QT q[6];
+  for (int j = 0; j < 3; ++j) z[j] = L.SZ[j * L.nls + i];
+  for (int j = 0; j < 6; ++j) q[j] = L.SQ[j * L.nls + i];
   const bool wet = L.WET[i] != 0;
-  double r[9];
-  area_terms(u, wet, E, p, r);
-  // fixed-order gather of the three edges: R_k / A -= edge_k / A
-  const double iA = rcp_nr(E.area);
+  double rz[3];
+  QT rq[6];
+  area_terms<QT>(z, q, wet, P, L.GG[i], L.GG[L.cs + i], L.GG[2 * L.cs + i], L.GG[3 * L.cs + i], p, rz, rq);
+  // fixed-order gather of the three edges: R_k / A -= edge_k / A (the zeta
+  // rows in FP64, so each edge's mass moment cancels between its sides)
+  const double iAd = rcp_nr(L.GA[i]);
+  const QT iA = (QT)iAd;
   for (int l = 0; l < 3; ++l) {
     const int code = P.ledge[l];
     const int j = code >> 1, side = code & 1;
     const int md = L.EMODE[j];
     if (md == 3 || md == 2 - side) continue;  // this side receives nothing
-    const double sg = side ? -iA : iA;
     const double a1 = ga1(l), b1 = gb1(l), a2 = ga2(l), b2 = gb2(l);
-    for (int v = 0; v < 3; ++v) {
-      const double P0 = sg * L.EM[v * L.eds + j];
-      const double P1 = iA * L.EM[(3 + v) * L.eds + j];
-      r[3 * v + 0] -= P0;
-      r[3 * v + 1] -= a1 * P0 + b1 * P1;
-      r[3 * v + 2] -= a2 * P0 + b2 * P1;
+    {
+      const double P0 = (side ? -iAd : iAd) * (double)L.EM[j];
+      const double P1 = iAd * (double)L.EM[3 * L.eds + j];
+      rz[0] -= P0;
+      rz[1] -= a1 * P0 + b1 * P1;
+      rz[2] -= a2 * P0 + b2 * P1;
+    }
+    const QT sg = side ? -iA : iA;
+    for (int v = 0; v < 2; ++v) {
+      const QT P0 = sg * L.EM[(v + 1) * L.eds + j];
+      const QT P1 = iA * L.EM[(v + 4) * L.eds + j];
+      rq[3 * v + 0] -= P0;
+      rq[3 * v + 1] -= (QT)a1 * P0 + (QT)b1 * P1;
+      rq[3 * v + 2] -= (QT)a2 * P0 + (QT)b2 * P1;
     }
   }
   const double imu[3] = {1.0, 6.0, 2.0};
   bool fin = true;
-  double out[9];
-  for (int j = 0; j < 9; ++j) {
-    double dw = r[j] * imu[j % 3];
-    if (!wet && j >= 3) dw = 0.0;
-    out[j] = base ? 0.5 * P.wb[j] + 0.5 * (u[j] + dt * dw) : u[j] + dt * dw;
-    wout[j * ne + e] = out[j];
-    fin = fin && __builtin_isfinite(out[j]);
+  double oz[3];
+  QT oq[6];
+  for (int j = 0; j < 3; ++j) {
+    const double dw = rz[j] * imu[j];
+    oz[j] = base ? 0.5 * P.wbz[j] + 0.5 * (z[j] + dt * dw) : z[j] + dt * dw;
+    wout.z[j * ne + e] = oz[j];
+    fin = fin && __builtin_isfinite(oz[j]);
+  }
+  const QT dtq = (QT)dt;
+  for (int j = 0; j < 6; ++j) {
+    QT dw = rq[j] * (QT)imu[j % 3];
+    if (!wet) dw = (QT)0;
+    oq[j] = base ? (QT)0.5 * P.wbq[j] + (QT)0.5 * (q[j] + dtq * dw) : q[j] + dtq * dw;
+    wout.q[j * ne + e] = oq[j];
+    fin = fin && __builtin_isfinite(oq[j]);
   }
   bad = !fin;
-  return want_dt ? cfl_candidate(out, mean3(E.h), P.inr2, p) : INFINITY;
+  return want_dt ? cfl_candidate(oz[0], (double)oq[0], (double)oq[3], mean3(P.h), P.inr2, p) : INFINITY;
 }
 
 #undef HD
@@ -734,15 +868,16 @@ __global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Param
 // C <= NT, chunk + ring 1 <= 2 NT, chunk-local edges <= 2 NT).  Stage 1
 // (stage == 0) also writes the post-processed w^n of its chunk to wpp, the
 // RK base that stage 2 reads.
-template <int NT, int WPE>
+template <int NT, int WPE, class QT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_stage(
-    DevMesh m, DevState s, Params p, const double *__restrict__ win, const double *__restrict__ wbase,
-    double *__restrict__ wout, double *__restrict__ wpp, int slot, int stage, int pp_in, int want_dt) {
+    DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase, St<QT> wout, St<QT> wpp, int slot, int stage,
+    int pp_in, int want_dt) {
   extern __shared__ double lds_raw[];
   __shared__ double red[NT / 64];
   __shared__ int s_active;
   Ctrl *ctl = s.ctrl;
   const int tid = threadIdx.x;
+  const size_t ne = (size_t)m.ne;
   double dt = 0.0;
   // the go/no-go decision is taken once per block, so every lane reaches the
   // same barriers
@@ -760,7 +895,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   const int c = chunk_of_block(blockIdx.x, m.nch);
   if (c < 0) return;
   const ChunkInfo k = chunk_info(m, c);
-  const Lds L = lds_view(m, lds_raw);
+  const Lds<QT> L = lds_view<QT>(m, lds_raw);
+  const QMesh<QT> Q = qmesh<QT>(m);
   const int nl = k.nl();
   if (stage == 0 && blockIdx.x == 0 && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
 
@@ -770,30 +906,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   uint16_t nb0[3], nb1[3];
   if (i0 < nl) { load_local_hb(m, k, i0, h0); load_local_nb(m, k, i0, nb0); }
   if (i1 < nl) { load_local_hb(m, k, i1, h1); load_local_nb(m, k, i1, nb1); }
-  EdgeRec r0, r1;
-  if (tid < k.ne_loc) load_edge_rec(m, k, tid, r0);
-  if (tid + NT < k.ne_loc) load_edge_rec(m, k, tid + NT, r1);
-  ElemPre pre;
+  EdgeRec<QT> r0, r1;
+  if (tid < k.ne_loc) load_edge_rec<QT>(m, Q, k, tid, r0);
+  if (tid + NT < k.ne_loc) load_edge_rec<QT>(m, Q, k, tid + NT, r1);
+  ElemPre<QT> pre;
   if (tid < k.cc) {
-    load_elem_pre(m, s, p, k, tid, stage ? wbase : nullptr, pre);
-    phase_load_geo(m, k, L, tid);
+    load_elem_pre<QT>(m, Q, s, p, k, tid, stage ? &wbase : nullptr, pre);
+    phase_load_geo<QT>(m, Q, k, L, tid);
   }
-  if (i0 < nl) phase_load_nl(m, k, L, win, i0);
-  if (i1 < nl) phase_load_nl(m, k, L, win, i1);
-  for (int j = tid; j < k.n2; j += NT) phase_load_h2(m, k, L, win, j);
+  if (i0 < nl) phase_load_nl<QT>(m, k, L, win, i0);
+  if (i1 < nl) phase_load_nl<QT>(m, k, L, win, i1);
+  for (int j = tid; j < k.n2; j += NT) phase_load_h2<QT>(m, k, L, win, j);
   __syncthreads();
-  double *wpp_out = stage == 0 ? wpp : nullptr;
-  if (i0 < nl) phase_post(m, p, k, L, pp_in, i0, h0, nb0, wpp_out);
-  if (i1 < nl) phase_post(m, p, k, L, pp_in, i1, h1, nb1, wpp_out);
+  const St<QT> *wpp_out = stage == 0 ? &wpp : nullptr;
+  if (i0 < nl) phase_post<QT>(p, k, L, pp_in, i0, h0, nb0, wpp_out, ne);
+  if (i1 < nl) phase_post<QT>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne);
   __syncthreads();
   const double ts = ctl->t[slot] + (stage ? dt : 0.0);
   const double zb = (p.n_tide > 0 || p.tide_offset != 0.0) ? tide_level(p, ts) : 0.0;
-  if (tid < k.ne_loc) phase_edge(p, L, zb, tid, r0);
-  if (tid + NT < k.ne_loc) phase_edge(p, L, zb, tid + NT, r1);
+  if (tid < k.ne_loc) phase_edge<QT>(p, L, zb, tid, r0);
+  if (tid + NT < k.ne_loc) phase_edge<QT>(p, L, zb, tid + NT, r1);
   __syncthreads();
   double cand = INFINITY;
   bool bad = false;
-  if (tid < k.cc) cand = phase_area(m, p, k, L, pre, stage != 0, wout, dt, want_dt, tid, bad);
+  if (tid < k.cc) cand = phase_area<QT>(p, k, L, pre, stage != 0, wout, ne, dt, want_dt, tid, bad);
   if (bad) atomicCAS(&ctl->status, 0, (int)DGSWE_E_NONFINITE);
   if (want_dt) {
     const double bm = block_min<NT>(cand, red);
@@ -806,13 +942,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   }
 }
 
-// post-processing of a whole state (win -> wout)
-__global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, const double *__restrict__ win,
+// a state (post-processed if pp) as FP64 [9][ne], for read-back
+template <class QT>
+__global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, CSt<QT> win, int pp,
                                                       double *__restrict__ wout) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= m.ne) return;
-  double u[9], h[3];
-  load_pp_global(m, p, win, e, true, u, h);
+  double u[9];
+  load_pp_global<QT>(m, p, win, e, pp != 0, u);
   for (int j = 0; j < 9; ++j) wout[(size_t)j * m.ne + e] = u[j];
 }
 
@@ -828,16 +965,15 @@ __global__ void k_ctrl_reset(Ctrl *c, double t) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_init(DevMesh m, DevState s, Params p, const double *__restrict__ w) {
+template <class QT>
+__global__ __launch_bounds__(kBlock) void k_init(DevMesh m, DevState s, Params p, CSt<QT> w) {
   __shared__ double red[kBlock / 64];
   const int e = blockIdx.x * kBlock + threadIdx.x;
   double cand = INFINITY;
   if (e < m.ne) {
     const size_t ne = (size_t)m.ne;
-    double u[9];
-    for (int j = 0; j < 9; ++j) u[j] = w[j * ne + e];
     const double h[3] = {m.hbv[e], m.hbv[ne + e], m.hbv[2 * ne + e]};
-    cand = cfl_candidate(u, mean3(h), m.inr2[e], p);
+    cand = cfl_candidate(w.z[e], (double)w.q[e], (double)w.q[3 * ne + e], mean3(h), m.inr2[e], p);
   }
   const double bm = block_min<kBlock>(cand, red);
   if (threadIdx.x == 0 && bm < INFINITY) atomicMin(&s.ctrl->dtmin[0], double_to_bits(bm));
@@ -846,8 +982,8 @@ __global__ __launch_bounds__(kBlock) void k_init(DevMesh m, DevState s, Params p
 // Diagnostics: per-block partial sums (mass, volume, wet count), then one
 // block adds the partials in a fixed order: deterministic.  Mean depth and
 // zeta mean are unchanged by the post-processing, so the unlimited state
-// gives the same values.
-__global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, DevState s, Params p, const double *__restrict__ w) {
+// gives the same values; z is the zeta block of a state buffer.
+__global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, DevState s, Params p, const double *__restrict__ z) {
   __shared__ double sm[3][kBlock];
   const int e = blockIdx.x * kBlock + threadIdx.x;
   const size_t ne = (size_t)m.ne;
@@ -855,10 +991,10 @@ __global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, DevState s, Params 
   if (e < m.ne) {
     const double h[3] = {m.hbv[e], m.hbv[ne + e], m.hbv[2 * ne + e]};
     const double hmean = mean3(h);
-    const double z = w[e];
-    a = m.area[e] * z;
-    b = m.area[e] * (z + hmean);
-    c = (p.wetdry ? (z + hmean > p.h0) : true) ? 1.0 : 0.0;
+    const double z0 = z[e];
+    a = m.area[e] * z0;
+    b = m.area[e] * (z0 + hmean);
+    c = (p.wetdry ? (z0 + hmean > p.h0) : true) ? 1.0 : 0.0;
   }
   sm[0][threadIdx.x] = a; sm[1][threadIdx.x] = b; sm[2][threadIdx.x] = c;
   __syncthreads();
@@ -900,10 +1036,12 @@ static inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / 
 
 int diag_blocks(int ne) { return (int)nblk(ne); }
 
-size_t stage_lds_bytes(const DevMesh &m) {
-  return 8 * (9 * (size_t)m.nl_max + 2 * (size_t)m.nm_max + (size_t)m.n2_max + 6 * (size_t)m.ed_max +
-              5 * (size_t)m.C) +
-         (size_t)m.ed_max + (size_t)m.nl_max;
+size_t stage_lds_bytes(const DevMesh &m, int precision) {
+  return precision == DGSWE_MIXED ? lds_bytes<float>(m) : lds_bytes<double>(m);
+}
+
+size_t state_bytes(size_t ne, int precision) {
+  return ne * (precision == DGSWE_MIXED ? 3 * sizeof(double) + 6 * sizeof(float) : 9 * sizeof(double));
 }
 
 bool stage_block_ok(int block) {
@@ -912,45 +1050,76 @@ bool stage_block_ok(int block) {
   return false;
 }
 
+// views of a state buffer: zeta modes first, then the momentum modes
+template <class QT>
+static St<QT> split(void *buf, size_t ne) {
+  return {(double *)buf, (QT *)((double *)buf + 3 * ne)};
+}
+template <class QT>
+static CSt<QT> csplit(const void *buf, size_t ne) {
+  return {(const double *)buf, (const QT *)((const double *)buf + 3 * ne)};
+}
+
 hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int slot, int stage,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_forcing, dim3(nblk(m.nn)), dim3(kBlock), 0, st, m, s, p, slot, stage);
   return hipGetLastError();
 }
 
-hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const double *win,
-                        const double *wbase, double *wout, double *wpp, int slot, int stage, int pp_in,
-                        int want_dt, int block, hipStream_t st) {
-  const size_t lds = stage_lds_bytes(m);
-#define DGSWE_STAGE(NT, W)                                                                                  \
-  hipLaunchKernelGGL((k_stage<NT, W>), dim3(m.nch), dim3(NT), lds, st, m, s, p, win, wbase, wout, wpp, slot, \
-                     stage, pp_in, want_dt)
-  switch (block) {
-    case 384: DGSWE_STAGE(384, 3); break;
-    default: DGSWE_STAGE(256, 2); break;
-  }
-#undef DGSWE_STAGE
+template <class QT>
+static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const void *win, const void *wbase,
+                     void *wout, void *wpp, int slot, int stage, int pp_in, int want_dt, int block, hipStream_t st) {
+  const size_t ne = (size_t)m.ne;
+  const size_t lds = lds_bytes<QT>(m);
+  const CSt<QT> a = csplit<QT>(win, ne);
+  const CSt<QT> b = wbase ? csplit<QT>(wbase, ne) : CSt<QT>{nullptr, nullptr};
+  const St<QT> o = split<QT>(wout, ne);
+  const St<QT> q = wpp ? split<QT>(wpp, ne) : St<QT>{nullptr, nullptr};
+  if (block == 384)
+    hipLaunchKernelGGL((k_stage<384, 3, QT>), dim3(m.nch), dim3(384), lds, st, m, s, p, a, b, o, q, slot, stage,
+                       pp_in, want_dt);
+  else
+    hipLaunchKernelGGL((k_stage<256, 2, QT>), dim3(m.nch), dim3(256), lds, st, m, s, p, a, b, o, q, slot, stage,
+                       pp_in, want_dt);
+}
+
+hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const void *win, const void *wbase,
+                        void *wout, void *wpp, int slot, int stage, int pp_in, int want_dt, int block, int precision,
+                        hipStream_t st) {
+  if (precision == DGSWE_MIXED)
+    stage_qt<float>(m, s, p, win, wbase, wout, wpp, slot, stage, pp_in, want_dt, block, st);
+  else
+    stage_qt<double>(m, s, p, win, wbase, wout, wpp, slot, stage, pp_in, want_dt, block, st);
   return hipGetLastError();
 }
 
-hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p, const double *win, double *wout,
+hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, double *wout, int precision,
                             hipStream_t st) {
-  (void)s;
-  hipLaunchKernelGGL(k_post_only, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, p, win, wout);
+  const size_t ne = (size_t)m.ne;
+  if (precision == DGSWE_MIXED)
+    hipLaunchKernelGGL(k_post_only<float>, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, p, csplit<float>(win, ne), pp,
+                       wout);
+  else
+    hipLaunchKernelGGL(k_post_only<double>, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, p, csplit<double>(win, ne),
+                       pp, wout);
   return hipGetLastError();
 }
 
-hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const double *w, double t,
-                             hipStream_t st) {
+hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w, double t,
+                             int precision, hipStream_t st) {
+  const size_t ne = (size_t)m.ne;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, s.ctrl, t);
-  hipLaunchKernelGGL(k_init, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, s, p, w);
+  if (precision == DGSWE_MIXED)
+    hipLaunchKernelGGL(k_init<float>, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, s, p, csplit<float>(w, ne));
+  else
+    hipLaunchKernelGGL(k_init<double>, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, s, p, csplit<double>(w, ne));
   return hipGetLastError();
 }
 
-hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const double *w, double *out4,
+hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w, double *out4,
                        hipStream_t st) {
   const int nb = (int)nblk(m.ne);
-  hipLaunchKernelGGL(k_diag1, dim3(nb), dim3(kBlock), 0, st, m, s, p, w);
+  hipLaunchKernelGGL(k_diag1, dim3(nb), dim3(kBlock), 0, st, m, s, p, (const double *)w);
   hipLaunchKernelGGL(k_diag2, dim3(1), dim3(kBlock), 0, st, s, nb, out4);
   return hipGetLastError();
 }

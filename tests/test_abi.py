@@ -99,3 +99,6 @@ def test_mesh_validation_before_device_work():
     with pytest.raises(D.DgsweError) as ei:
         _create(m, h0=-1.0)
     assert ei.value.status == 1
+    with pytest.raises(D.DgsweError) as ei:
+        _create(m, precision=2)
+    assert ei.value.status == 1
