@@ -30,8 +30,10 @@ struct dgswe_solver {
   std::vector<void *> allocs;
   DevMesh m{};
   DevState s{};
-  double *d_manning = nullptr;
+  double *d_manning = nullptr;   // per-element Manning n (internal order)
   float *d_manningf = nullptr;
+  double *d_manning1 = nullptr;  // one uniform Manning n
+  float *d_manning1f = nullptr;
   double *d_diag = nullptr;
   int precision = DGSWE_FP64;
   double *rb = nullptr;  // FP64 [9][ne] read-back buffer (mixed path)
@@ -241,8 +243,11 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   chk(upload(S, &m.el_nb, P.el_nb));
   chk(upload(S, &m.el_node, P.el_node));
   chk(upload(S, &m.node_x, P.node_x)); chk(upload(S, &m.node_y, P.node_y));
-  m.manning = nullptr;
-  m.manningf = nullptr;
+  chk(dev_alloc(S, &S->d_manning1, 1));
+  chk(dev_alloc(S, &S->d_manning1f, 1));
+  m.manning = S->d_manning1;
+  m.manningf = S->d_manning1f;
+  m.manning_step = 0;
   m.gx1f = m.gy1f = m.gx2f = m.gy2f = m.le_nxf = m.le_nyf = m.le_hlf = nullptr;
   if (mixed) {
     chk(upload_f32(S, &m.gx1f, P.gx1)); chk(upload_f32(S, &m.gy1f, P.gy1));
@@ -261,6 +266,7 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   build_chunks(P, chunk);
   m.C = P.C; m.nch = P.nch; m.nl_max = P.nl_max; m.nm_max = P.nm_max; m.ed_max = P.ed_max;
   m.n2_max = P.n2_max;
+  m.nh1 = P.nh1;
   chk(upload(S, &m.h1_off, P.h1_off)); chk(upload(S, &m.h1, P.h1)); chk(upload(S, &m.h1_hb, P.h1_hb));
   chk(upload(S, &m.h2_off, P.h2_off)); chk(upload(S, &m.h2, P.h2));
   chk(upload(S, &m.le_off, P.le_off)); chk(upload(S, &m.nb_off, P.nb_off));
@@ -302,6 +308,8 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   // zero state and forcing, dt of the zero state
   chk(hipMemsetAsync(st.buf[0], 0, sb, S->stream));
   chk(hipMemsetAsync(st.nodal, 0, 3 * nn * sizeof(double), S->stream));
+  chk(hipMemsetAsync(S->d_manning1, 0, sizeof(double), S->stream));
+  chk(hipMemsetAsync(S->d_manning1f, 0, sizeof(float), S->stream));
   chk(launch_init_state(m, st, pp, st.buf[0], 0.0, S->precision, S->stream));
   chk(hipStreamSynchronize(S->stream));
   S->cur = 0;
@@ -366,6 +374,7 @@ dgswe_status dgswe_set_forcing(dgswe_solver *S, const dgswe_forcing *f) {
     e = hipMemcpy(S->d_manning, tmp.data(), ne * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
     S->m.manning = S->d_manning;
+    S->m.manning_step = 1;
     if (S->precision == DGSWE_MIXED) {
       if (!S->d_manningf) {
         e = dev_alloc(S, &S->d_manningf, ne);
@@ -378,8 +387,13 @@ dgswe_status dgswe_set_forcing(dgswe_solver *S, const dgswe_forcing *f) {
       S->m.manningf = S->d_manningf;
     }
   } else {
-    S->m.manning = nullptr;
-    S->m.manningf = nullptr;
+    const float nf = (float)f->manning_n;
+    e = hipMemcpy(S->d_manning1, &f->manning_n, sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(S->d_manning1f, &nf, sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
+    S->m.manning = S->d_manning1;
+    S->m.manningf = S->d_manning1f;
+    S->m.manning_step = 0;
   }
   S->forcing_dynamic = p.holland != 0;
   if (!p.holland) {

@@ -37,18 +37,21 @@ struct DevMesh {
   const double *hbv;                    // [3][ne] bathymetry at the element's vertices
   const int *el_nb;                     // [3][ne] neighbour across local edge, -1 none
   const int *el_node;                   // [3][ne] node ids
-  const double *manning;                // [ne] or nullptr
+  const double *manning;                // Manning n of element e at manning[e * manning_step]
+  int manning_step;                     // 1: per element, 0: one uniform value
   // nodes
   const double *node_x, *node_y;
   // chunks (see build_chunks)
   int C, nch, nl_max, nm_max, ed_max, n2_max;
+  int nh1;                         // total ring-1 entries (stride of h1_hb)
   const int *h1_off, *h1, *h2_off, *h2, *le_off, *nb_off;  // per-chunk offsets and halo ids
   const double *h1_hb;             // [3][total ring-1 entries] vertex bathymetry of ring 1
   const uint32_t *le_pm;           // chunk-local edge: local e+ | local e- << 16 (0xFFFF: boundary)
   const uint8_t *le_info;          // lp | lm << 2 | type << 4
   const double *le_nx, *le_ny, *le_hl, *le_hA, *le_hB;  // normal, half length, endpoint bathymetry
   const uint16_t *el_ledge, *nbl;
-  // FP32 copies for the mixed-precision path (nullptr in FP64)
+  // FP32 copies for the mixed-precision path (nullptr in FP64; manningf
+  // follows manning_step)
   const float *gx1f, *gy1f, *gx2f, *gy2f, *le_nxf, *le_nyf, *le_hlf, *manningf;
 };
 
@@ -87,7 +90,7 @@ struct Prep {
   std::vector<double> ed_nx, ed_ny, ed_hlen;
   std::vector<double> node_x, node_y;
   // chunks of C consecutive elements with their halos (fused stage kernel)
-  int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
+  int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0, nh1 = 0;
   std::vector<int> h1_off, h1, h2_off, h2, le_off, le_gid, nb_off;
   std::vector<double> h1_hb;
   std::vector<uint32_t> le_pm;

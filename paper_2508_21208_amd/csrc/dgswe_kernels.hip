@@ -508,7 +508,7 @@ template <class QT>
 struct QMesh {
   const QT *gx1, *gy1, *gx2, *gy2;  // physical gradients of phi_10, phi_01
   const QT *nx, *ny, *hl;           // chunk-local edge normal and half length
-  const QT *manning;                // per-element Manning n or nullptr
+  const QT *manning;                // Manning n of element e at manning[e * manning_step]
 };
 HD QMesh<double> qmesh(const DevMesh &m, const double *) {
   return {m.gx1, m.gy1, m.gx2, m.gy2, m.le_nx, m.le_ny, m.le_hl, m.manning};
@@ -617,17 +617,14 @@ HD void load_edge_rec(const DevMesh &m, const QMesh<QT> &Q, const ChunkInfo &k, 
   R.nx = Q.nx[r]; R.ny = Q.ny[r]; R.hl = Q.hl[r]; R.hA = m.le_hA[r]; R.hB = m.le_hB[r];
 }
 
-// vertex bathymetry of local element i (chunk: element arrays; ring 1:
-// packed per chunk)
+// vertex bathymetry of local element i in [0, nl) (chunk: element arrays;
+// ring 1: packed per chunk); the source is selected, the loads are not
+// conditional
 HD void load_local_hb(const DevMesh &m, const ChunkInfo &k, int i, double h[3]) {
-  const size_t ne = (size_t)m.ne;
-  if (i < k.cc) {
-    for (int q = 0; q < 3; ++q) h[q] = m.hbv[q * ne + k.c0 + i];
-  } else {
-    const size_t nh1 = (size_t)m.h1_off[m.nch];
-    const size_t r = (size_t)(k.h1o + i - k.cc);
-    for (int q = 0; q < 3; ++q) h[q] = m.h1_hb[q * nh1 + r];
-  }
+  const bool in = i < k.cc;
+  const double *b = in ? m.hbv + (k.c0 + i) : m.h1_hb + (k.h1o + i - k.cc);
+  const size_t stride = in ? (size_t)m.ne : (size_t)m.nh1;
+  for (int q = 0; q < 3; ++q) h[q] = b[q * stride];
 }
 
 // local neighbour indices of local element i (chunk + ring 1)
@@ -636,40 +633,72 @@ HD void load_local_nb(const DevMesh &m, const ChunkInfo &k, int i, uint16_t nb[3
   for (int q = 0; q < 3; ++q) nb[q] = m.nbl[k.nbo + q * nl + i];
 }
 
-// phase L for local element i of chunk + ring 1
+// Phase L works in three rounds of loads so that each lane waits for
+// memory about twice instead of once per dependent gather: first the
+// indices later loads depend on (global id of a ring-1 element, of a
+// ring-2 element, node ids), then every load that needs no index, then the
+// gathers through the indices; LDS is written after all of them.
+
+// global element id of local element i in [0, nl) of chunk + ring 1; the
+// ring-1 list is read at a clamped position (the lists end with a sentinel)
+// so that the load is not conditional
+HD int local_to_global(const DevMesh &m, const ChunkInfo &k, int i) {
+  const int r = i - k.cc;
+  const int g = m.h1[k.h1o + (r < 0 ? 0 : r)];
+  return r < 0 ? k.c0 + i : g;
+}
+
+// full state of element g
 template <class QT>
-HD void phase_load_nl(const DevMesh &m, const ChunkInfo &k, const Lds<QT> &L, CSt<QT> win, int i) {
-  const size_t ne = (size_t)m.ne;
-  const int g = i < k.cc ? k.c0 + i : m.h1[k.h1o + i - k.cc];
+struct StateReg {
   double z[3];
   QT q[6];
-  for (int j = 0; j < 3; ++j) z[j] = win.z[j * ne + g];
-  for (int j = 0; j < 6; ++j) q[j] = win.q[j * ne + g];
-  for (int j = 0; j < 3; ++j) L.SZ[j * L.nls + i] = z[j];
-  for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = q[j];
-  L.MQ[i] = q[0];
-  L.MQ[L.nms + i] = q[3];
+};
+
+template <class QT>
+HD void load_state_reg(CSt<QT> w, size_t ne, int g, StateReg<QT> &S) {
+  for (int j = 0; j < 3; ++j) S.z[j] = w.z[j * ne + g];
+  for (int j = 0; j < 6; ++j) S.q[j] = w.q[j * ne + g];
 }
 
-// phase L for ring-2 element j (means only)
+// local element i of chunk + ring 1 into LDS (state, unlimited means)
 template <class QT>
-HD void phase_load_h2(const DevMesh &m, const ChunkInfo &k, const Lds<QT> &L, CSt<QT> win, int j) {
-  const size_t ne = (size_t)m.ne;
-  const int g = m.h2[k.h2o + j];
-  L.MZ[j] = win.z[g];
-  L.MQ[k.nl() + j] = win.q[g];
-  L.MQ[L.nms + k.nl() + j] = win.q[3 * ne + g];
+HD void store_state_lds(const Lds<QT> &L, int i, const StateReg<QT> &S) {
+  for (int j = 0; j < 3; ++j) L.SZ[j * L.nls + i] = S.z[j];
+  for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = S.q[j];
+  L.MQ[i] = S.q[0];
+  L.MQ[L.nms + i] = S.q[3];
 }
 
-// phase L: geometry of chunk element i into LDS
+// ring-2 element j of local index nl + j: unlimited means only
 template <class QT>
-HD void phase_load_geo(const DevMesh &m, const QMesh<QT> &Q, const ChunkInfo &k, const Lds<QT> &L, int i) {
+HD void load_h2_lds(const Lds<QT> &L, CSt<QT> w, size_t ne, int nl, int j, int g) {
+  L.MZ[j] = w.z[g];
+  L.MQ[nl + j] = w.q[g];
+  L.MQ[L.nms + nl + j] = w.q[3 * ne + g];
+}
+
+// geometry of a chunk element
+template <class QT>
+struct GeoReg {
+  QT g[4];
+  double area;
+};
+
+template <class QT>
+HD void load_geo(const DevMesh &m, const QMesh<QT> &Q, const ChunkInfo &k, int i, GeoReg<QT> &G) {
   const int e = k.c0 + i;
-  L.GG[i] = Q.gx1[e];
-  L.GG[L.cs + i] = Q.gy1[e];
-  L.GG[2 * L.cs + i] = Q.gx2[e];
-  L.GG[3 * L.cs + i] = Q.gy2[e];
-  L.GA[i] = m.area[e];
+  G.g[0] = Q.gx1[e];
+  G.g[1] = Q.gy1[e];
+  G.g[2] = Q.gx2[e];
+  G.g[3] = Q.gy2[e];
+  G.area = m.area[e];
+}
+
+template <class QT>
+HD void store_geo_lds(const Lds<QT> &L, int i, const GeoReg<QT> &G) {
+  for (int j = 0; j < 4; ++j) L.GG[j * L.cs + i] = G.g[j];
+  L.GA[i] = G.area;
 }
 
 // phase P for local element i of chunk + ring 1 (h: its vertex bathymetry,
@@ -732,19 +761,29 @@ HD void phase_edge(const Params &p, const Lds<QT> &L, double zb, int j, const Ed
   L.EMODE[j] = (unsigned char)mode;
 }
 
+// the parts of ElemPre that need no index: bathymetry, local edges, 2 r_e,
+// Manning n and (second stage) the RK base
 template <class QT>
-HD void load_elem_pre(const DevMesh &m, const QMesh<QT> &Q, const DevState &s, const Params &p,
-                      const ChunkInfo &k, int i, const CSt<QT> *wbase, ElemPre<QT> &P) {
-  const size_t ne = (size_t)m.ne, nn = (size_t)m.nn;
+HD void load_elem_pre(const DevMesh &m, const QMesh<QT> &Q, const Params &p, const ChunkInfo &k, int i,
+                      const CSt<QT> *wbase, ElemPre<QT> &P) {
+  const size_t ne = (size_t)m.ne;
   const int e = k.c0 + i;
-  int node[3];
   for (int q = 0; q < 3; ++q) {
     P.h[q] = m.hbv[q * ne + e];
-    node[q] = m.el_node[q * ne + e];
     P.ledge[q] = m.el_ledge[q * ne + e];
   }
   P.inr2 = m.inr2[e];
-  P.manning = Q.manning ? Q.manning[e] : (QT)p.manning_n;
+  P.manning = Q.manning[(size_t)e * m.manning_step];
+  if (wbase) {
+    for (int j = 0; j < 3; ++j) P.wbz[j] = wbase->z[j * ne + e];
+    for (int j = 0; j < 6; ++j) P.wbq[j] = wbase->q[j * ne + e];
+  }
+}
+
+// nodal forcing at the element's vertices (node: its node ids)
+template <class QT>
+HD void load_elem_forcing(const DevMesh &m, const DevState &s, const int node[3], ElemPre<QT> &P) {
+  const size_t nn = (size_t)m.nn;
   double pa[3];
   for (int q = 0; q < 3; ++q) {
     P.tx[q] = (QT)s.nodal[node[q]];
@@ -755,10 +794,6 @@ HD void load_elem_pre(const DevMesh &m, const QMesh<QT> &Q, const DevState &s, c
   const double dp1 = pa[1] - pa[0], dp2 = pa[2] - pa[0];
   P.pm1 = (QT)(0.5 * dp1);
   P.pm2 = (QT)((2.0 * dp2 - dp1) * (1.0 / 6.0));
-  if (wbase) {
-    for (int j = 0; j < 3; ++j) P.wbz[j] = wbase->z[j * ne + e];
-    for (int j = 0; j < 6; ++j) P.wbq[j] = wbase->q[j * ne + e];
-  }
 }
 
 // phase A for chunk element i; returns the CFL candidate of the output when
@@ -864,79 +899,111 @@ __global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Param
   s.nodal[2 * (size_t)m.nn + i] = out[2];
 }
 
-// One RK stage over one chunk per workgroup of NT lanes (chunk size
-// C <= NT, chunk + ring 1 <= 2 NT, chunk-local edges <= 2 NT).  Stage 1
-// (stage == 0) also writes the post-processed w^n of its chunk to wpp, the
-// RK base that stage 2 reads.
-template <int NT, int WPE, class QT>
+// One RK stage (STAGE 0 or 1) over one chunk per workgroup of NT lanes
+// (chunk size C <= NT, chunk + ring 1 <= 2 NT, chunk-local edges <= 2 NT).
+// The first stage also writes the post-processed w^n of its chunk to wpp,
+// the RK base that the second stage reads.
+template <int NT, int WPE, class QT, int STAGE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_stage(
-    DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase, St<QT> wout, St<QT> wpp, int slot, int stage,
-    int pp_in, int want_dt) {
+    DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase, St<QT> wout, St<QT> wpp, int slot, int pp_in,
+    int want_dt) {
   extern __shared__ double lds_raw[];
   __shared__ double red[NT / 64];
+  __shared__ double s_dt, s_t;
   __shared__ int s_active;
   Ctrl *ctl = s.ctrl;
   const int tid = threadIdx.x;
   const size_t ne = (size_t)m.ne;
-  double dt = 0.0;
-  // the go/no-go decision is taken once per block, so every lane reaches the
-  // same barriers
+  const int c = chunk_of_block(blockIdx.x, m.nch);
+  if (c < 0) return;  // the same for every lane of the block
+  const ChunkInfo k = chunk_info(m, c);
+  const Lds<QT> L = lds_view<QT>(m, lds_raw);
+  const QMesh<QT> Q = qmesh<QT>(m);
+  const int nl = k.nl();
+
+  // Phase L, round 1: the indices later loads depend on, for lane slots
+  // i0 = tid, i1 = tid + NT of chunk + ring 1, ring-2 slot tid and chunk
+  // element tid.  Inactive slots read clamped, valid positions; their values
+  // are never stored.
+  const int i0 = tid, i1 = tid + NT;
+  const bool a0 = i0 < nl, a1 = i1 < nl, ae = tid < k.cc, a2 = tid < k.n2;
+  const int c0i = a0 ? i0 : nl - 1, c1i = a1 ? i1 : nl - 1, cei = ae ? tid : k.cc - 1;
+  const int g0 = local_to_global(m, k, c0i);
+  const int g1 = local_to_global(m, k, c1i);
+  const int h2v = m.h2[k.h2o + (a2 ? tid : 0)];
+  int node[3];
+  for (int q = 0; q < 3; ++q) node[q] = m.el_node[q * ne + k.c0 + cei];
+
+  // the go/no-go decision and the step's dt and time are read once and
+  // broadcast, so every lane reaches the same barriers
   if (tid == 0) {
+    double dt = 0.0;
     int act = ctl->status == 0 ? 1 : 0;
     if (act && !step_dt(ctl, p, slot, dt)) {
       atomicCAS(&ctl->status, 0, (int)DGSWE_E_ALLDRY);
       act = 0;
     }
     s_active = act;
+    s_dt = dt;
+    s_t = ctl->t[slot];
   }
   __syncthreads();
   if (!s_active) return;
-  step_dt(ctl, p, slot, dt);
-  const int c = chunk_of_block(blockIdx.x, m.nch);
-  if (c < 0) return;
-  const ChunkInfo k = chunk_info(m, c);
-  const Lds<QT> L = lds_view<QT>(m, lds_raw);
-  const QMesh<QT> Q = qmesh<QT>(m);
-  const int nl = k.nl();
-  if (stage == 0 && blockIdx.x == 0 && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
+  const double dt = s_dt, t0 = s_t;
+  if (STAGE == 0 && blockIdx.x == 0 && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
 
-  // phase L, with the loads of the later phases issued early
-  const int i0 = tid, i1 = tid + NT;
+  // Round 2: loads that need no index.
   double h0[3], h1[3];
   uint16_t nb0[3], nb1[3];
-  if (i0 < nl) { load_local_hb(m, k, i0, h0); load_local_nb(m, k, i0, nb0); }
-  if (i1 < nl) { load_local_hb(m, k, i1, h1); load_local_nb(m, k, i1, nb1); }
+  load_local_hb(m, k, c0i, h0);
+  load_local_nb(m, k, c0i, nb0);
+  load_local_hb(m, k, c1i, h1);
+  load_local_nb(m, k, c1i, nb1);
   EdgeRec<QT> r0, r1;
-  if (tid < k.ne_loc) load_edge_rec<QT>(m, Q, k, tid, r0);
-  if (tid + NT < k.ne_loc) load_edge_rec<QT>(m, Q, k, tid + NT, r1);
+  const int j0 = tid < k.ne_loc ? tid : k.ne_loc - 1, j1 = tid + NT < k.ne_loc ? tid + NT : k.ne_loc - 1;
+  load_edge_rec<QT>(m, Q, k, j0, r0);
+  load_edge_rec<QT>(m, Q, k, j1, r1);
   ElemPre<QT> pre;
-  if (tid < k.cc) {
-    load_elem_pre<QT>(m, Q, s, p, k, tid, stage ? &wbase : nullptr, pre);
-    phase_load_geo<QT>(m, Q, k, L, tid);
+  GeoReg<QT> geo;
+  load_elem_pre<QT>(m, Q, p, k, cei, STAGE ? &wbase : nullptr, pre);
+  load_geo<QT>(m, Q, k, cei, geo);
+  // Round 3: gathers through the indices.
+  StateReg<QT> st0, st1;
+  load_state_reg<QT>(win, ne, g0, st0);
+  load_state_reg<QT>(win, ne, g1, st1);
+  load_elem_forcing<QT>(m, s, node, pre);
+  const int g2 = a2 ? h2v : k.c0;
+  const double mz2 = win.z[g2];
+  const QT mx2 = win.q[g2], my2 = win.q[3 * ne + g2];
+  for (int j = tid + NT; j < k.n2; j += NT) load_h2_lds<QT>(L, win, ne, nl, j, m.h2[k.h2o + j]);
+  if (a0) store_state_lds<QT>(L, i0, st0);
+  if (a1) store_state_lds<QT>(L, i1, st1);
+  if (ae) store_geo_lds<QT>(L, tid, geo);
+  if (a2) {
+    L.MZ[tid] = mz2;
+    L.MQ[nl + tid] = mx2;
+    L.MQ[L.nms + nl + tid] = my2;
   }
-  if (i0 < nl) phase_load_nl<QT>(m, k, L, win, i0);
-  if (i1 < nl) phase_load_nl<QT>(m, k, L, win, i1);
-  for (int j = tid; j < k.n2; j += NT) phase_load_h2<QT>(m, k, L, win, j);
   __syncthreads();
-  const St<QT> *wpp_out = stage == 0 ? &wpp : nullptr;
-  if (i0 < nl) phase_post<QT>(p, k, L, pp_in, i0, h0, nb0, wpp_out, ne);
-  if (i1 < nl) phase_post<QT>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne);
+  const St<QT> *wpp_out = STAGE == 0 ? &wpp : nullptr;
+  if (a0) phase_post<QT>(p, k, L, pp_in, i0, h0, nb0, wpp_out, ne);
+  if (a1) phase_post<QT>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne);
   __syncthreads();
-  const double ts = ctl->t[slot] + (stage ? dt : 0.0);
+  const double ts = t0 + (STAGE ? dt : 0.0);
   const double zb = (p.n_tide > 0 || p.tide_offset != 0.0) ? tide_level(p, ts) : 0.0;
   if (tid < k.ne_loc) phase_edge<QT>(p, L, zb, tid, r0);
   if (tid + NT < k.ne_loc) phase_edge<QT>(p, L, zb, tid + NT, r1);
   __syncthreads();
   double cand = INFINITY;
   bool bad = false;
-  if (tid < k.cc) cand = phase_area<QT>(p, k, L, pre, stage != 0, wout, ne, dt, want_dt, tid, bad);
+  if (ae) cand = phase_area<QT>(p, k, L, pre, STAGE != 0, wout, ne, dt, want_dt, tid, bad);
   if (bad) atomicCAS(&ctl->status, 0, (int)DGSWE_E_NONFINITE);
   if (want_dt) {
     const double bm = block_min<NT>(cand, red);
     if (tid == 0 && bm < INFINITY) atomicMin(&ctl->dtmin[slot ^ 1], double_to_bits(bm));
   }
-  if (stage == 1 && blockIdx.x == 0 && tid == 0) {
-    ctl->t[slot ^ 1] = ctl->t[slot] + dt;
+  if (STAGE == 1 && blockIdx.x == 0 && tid == 0) {
+    ctl->t[slot ^ 1] = t0 + dt;
     ctl->dt_last = dt;
     ctl->steps = ctl->steps + 1;
   }
@@ -1075,12 +1142,17 @@ static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const
   const CSt<QT> b = wbase ? csplit<QT>(wbase, ne) : CSt<QT>{nullptr, nullptr};
   const St<QT> o = split<QT>(wout, ne);
   const St<QT> q = wpp ? split<QT>(wpp, ne) : St<QT>{nullptr, nullptr};
-  if (block == 384)
-    hipLaunchKernelGGL((k_stage<384, 3, QT>), dim3(m.nch), dim3(384), lds, st, m, s, p, a, b, o, q, slot, stage,
-                       pp_in, want_dt);
-  else
-    hipLaunchKernelGGL((k_stage<256, 2, QT>), dim3(m.nch), dim3(256), lds, st, m, s, p, a, b, o, q, slot, stage,
-                       pp_in, want_dt);
+#define DGSWE_STAGE(NT, W, S)                                                                             \
+  hipLaunchKernelGGL((k_stage<NT, W, QT, S>), dim3(m.nch), dim3(NT), lds, st, m, s, p, a, b, o, q, slot, pp_in, \
+                     want_dt)
+  if (block == 384) {
+    if (stage) DGSWE_STAGE(384, 3, 1);
+    else DGSWE_STAGE(384, 3, 0);
+  } else {
+    if (stage) DGSWE_STAGE(256, 2, 1);
+    else DGSWE_STAGE(256, 2, 0);
+  }
+#undef DGSWE_STAGE
 }
 
 hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const void *win, const void *wbase,

@@ -324,6 +324,12 @@ void build_chunks(Prep &P, int C) {
   P.h2_off[P.nch] = (int)P.h2.size();
   P.le_off[P.nch] = (int)P.le_gid.size();
   P.nb_off[P.nch] = (int)P.nbl.size();
+  P.nh1 = (int)nh1;
+  // one sentinel entry past the end of the halo lists: the stage kernel
+  // reads a clamped halo index unconditionally (also for a chunk without
+  // ring 1 or ring 2) and discards it where it does not apply
+  P.h1.push_back(0);
+  P.h2.push_back(0);
 }
 
 }  // namespace dgswe
