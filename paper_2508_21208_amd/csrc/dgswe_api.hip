@@ -85,13 +85,6 @@ hipError_t upload(dgswe_solver *S, const T **dst, const std::vector<T> &v) {
   return e;
 }
 
-// FP32 copy of an FP64 array (mixed-precision path)
-hipError_t upload_f32(dgswe_solver *S, const float **dst, const std::vector<double> &v) {
-  std::vector<float> f(v.size());
-  for (size_t i = 0; i < v.size(); ++i) f[i] = (float)v[i];
-  return upload(S, dst, f);
-}
-
 // Host image of a caller-order FP64 [9][ne] state in the internal order and
 // the solver's buffer layout (zeta FP64, momentum FP64 or FP32).
 void pack_state(dgswe_solver *S, const double *w) {
@@ -236,23 +229,15 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   const size_t ne = P.ne, ned = P.ned, nn = P.nn;
   bool ok = true;
   auto chk = [&](hipError_t x) { if (x != hipSuccess) ok = false; };
-  chk(upload(S, &m.gx1, P.gx1)); chk(upload(S, &m.gy1, P.gy1));
-  chk(upload(S, &m.gx2, P.gx2)); chk(upload(S, &m.gy2, P.gy2));
   chk(upload(S, &m.area, P.area)); chk(upload(S, &m.inr2, P.inr2));
   chk(upload(S, &m.hbv, P.hbv));
   chk(upload(S, &m.el_nb, P.el_nb));
-  chk(upload(S, &m.el_node, P.el_node));
   chk(upload(S, &m.node_x, P.node_x)); chk(upload(S, &m.node_y, P.node_y));
   chk(dev_alloc(S, &S->d_manning1, 1));
   chk(dev_alloc(S, &S->d_manning1f, 1));
   m.manning = S->d_manning1;
   m.manningf = S->d_manning1f;
   m.manning_step = 0;
-  m.gx1f = m.gy1f = m.gx2f = m.gy2f = m.le_nxf = m.le_nyf = m.le_hlf = nullptr;
-  if (mixed) {
-    chk(upload_f32(S, &m.gx1f, P.gx1)); chk(upload_f32(S, &m.gy1f, P.gy1));
-    chk(upload_f32(S, &m.gx2f, P.gx2)); chk(upload_f32(S, &m.gy2f, P.gy2));
-  }
   // chunk size and workgroup size of the stage kernel
   int chunk = 256, block = 256;
   if (const char *ev = std::getenv("DGSWE_CHUNK")) chunk = std::atoi(ev);
@@ -266,17 +251,19 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   build_chunks(P, chunk);
   m.C = P.C; m.nch = P.nch; m.nl_max = P.nl_max; m.nm_max = P.nm_max; m.ed_max = P.ed_max;
   m.n2_max = P.n2_max;
-  m.nh1 = P.nh1;
-  chk(upload(S, &m.h1_off, P.h1_off)); chk(upload(S, &m.h1, P.h1)); chk(upload(S, &m.h1_hb, P.h1_hb));
+  chk(upload(S, &m.h1_off, P.h1_off)); chk(upload(S, &m.lgid, P.lgid));
   chk(upload(S, &m.h2_off, P.h2_off)); chk(upload(S, &m.h2, P.h2));
-  chk(upload(S, &m.le_off, P.le_off)); chk(upload(S, &m.nb_off, P.nb_off));
-  chk(upload(S, &m.le_pm, P.le_pm)); chk(upload(S, &m.le_info, P.le_info));
-  chk(upload(S, &m.le_nx, P.le_nx)); chk(upload(S, &m.le_ny, P.le_ny)); chk(upload(S, &m.le_hl, P.le_hl));
-  chk(upload(S, &m.le_hA, P.le_hA)); chk(upload(S, &m.le_hB, P.le_hB));
-  chk(upload(S, &m.el_ledge, P.el_ledge)); chk(upload(S, &m.nbl, P.nbl));
+  chk(upload(S, &m.le_off, P.le_off)); chk(upload(S, &m.lo_off, P.lo_off));
+  chk(upload(S, &m.eai, P.eai)); chk(upload(S, &m.enode, P.enode));
+  chk(upload(S, &m.lhb01, P.lhb01)); chk(upload(S, &m.lhb2, P.lhb2)); chk(upload(S, &m.lnb, P.lnb));
+  m.eg1 = m.eg2 = m.le_a = m.le_b = m.le_c = m.le_h = nullptr;
+  m.egf = m.le_f = nullptr;
   if (mixed) {
-    chk(upload_f32(S, &m.le_nxf, P.le_nx)); chk(upload_f32(S, &m.le_nyf, P.le_ny));
-    chk(upload_f32(S, &m.le_hlf, P.le_hl));
+    chk(upload(S, &m.egf, P.egf));
+    chk(upload(S, &m.le_f, P.le_f)); chk(upload(S, &m.le_h, P.le_h));
+  } else {
+    chk(upload(S, &m.eg1, P.eg1)); chk(upload(S, &m.eg2, P.eg2));
+    chk(upload(S, &m.le_a, P.le_a)); chk(upload(S, &m.le_b, P.le_b)); chk(upload(S, &m.le_c, P.le_c));
   }
   const size_t lds = stage_lds_bytes(m, S->precision);
   if (lds > 80 * 1024 || P.nl_max > 2 * block || P.ed_max > 2 * block) {
@@ -397,9 +384,10 @@ dgswe_status dgswe_set_forcing(dgswe_solver *S, const dgswe_forcing *f) {
   }
   S->forcing_dynamic = p.holland != 0;
   if (!p.holland) {
+    // (tau_x, tau_y) pairs per node, then p_a per node
     std::vector<double> tmp(3 * nn, 0.0);
     for (size_t i = 0; i < nn; ++i) {
-      if (f->wind_tau) { tmp[i] = f->wind_tau[2 * i]; tmp[nn + i] = f->wind_tau[2 * i + 1]; }
+      if (f->wind_tau) { tmp[2 * i] = f->wind_tau[2 * i]; tmp[2 * i + 1] = f->wind_tau[2 * i + 1]; }
       if (f->patm) tmp[2 * nn + i] = f->patm[i];
     }
     e = hipMemcpy(S->s.nodal, tmp.data(), 3 * nn * sizeof(double), hipMemcpyHostToDevice);

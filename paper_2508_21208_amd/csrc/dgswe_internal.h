@@ -27,32 +27,39 @@ struct Ctrl {
   int pad;
 };
 
-// Element-major structure-of-arrays mesh on the device (internal order).
+// Mesh on the device (internal order).  Arrays read by the stage kernel are
+// packed as 16-byte records in paired structure-of-arrays form (lane i reads
+// record i with one 16-byte load, a wavefront one contiguous 1 KiB block).
 struct DevMesh {
   int ne, nn, ned;
-  // elements
-  const double *gx1, *gy1, *gx2, *gy2;  // physical gradients of phi_10, phi_01
+  // elements, structure of arrays (initialisation, read-back, diagnostics)
   const double *area;                   // A_e
   const double *inr2;                   // 2 x inradius
   const double *hbv;                    // [3][ne] bathymetry at the element's vertices
   const int *el_nb;                     // [3][ne] neighbour across local edge, -1 none
-  const int *el_node;                   // [3][ne] node ids
   const double *manning;                // Manning n of element e at manning[e * manning_step]
+  const float *manningf;                // the same in FP32 (mixed path)
   int manning_step;                     // 1: per element, 0: one uniform value
   // nodes
   const double *node_x, *node_y;
-  // chunks (see build_chunks)
+  // chunks of the stage kernel (see build_chunks)
   int C, nch, nl_max, nm_max, ed_max, n2_max;
-  int nh1;                         // total ring-1 entries (stride of h1_hb)
-  const int *h1_off, *h1, *h2_off, *h2, *le_off, *nb_off;  // per-chunk offsets and halo ids
-  const double *h1_hb;             // [3][total ring-1 entries] vertex bathymetry of ring 1
-  const uint32_t *le_pm;           // chunk-local edge: local e+ | local e- << 16 (0xFFFF: boundary)
-  const uint8_t *le_info;          // lp | lm << 2 | type << 4
-  const double *le_nx, *le_ny, *le_hl, *le_hA, *le_hB;  // normal, half length, endpoint bathymetry
-  const uint16_t *el_ledge, *nbl;
-  // FP32 copies for the mixed-precision path (nullptr in FP64; manningf
-  // follows manning_step)
-  const float *gx1f, *gy1f, *gx2f, *gy2f, *le_nxf, *le_nyf, *le_hlf, *manningf;
+  const int *h1_off, *h2_off, *h2;       // per-chunk ring-1 counts, ring-2 element ids
+  const int *le_off, *lo_off;            // per-chunk offsets of local edges / local elements
+  // chunk elements
+  const double2 *eg1, *eg2;  // (d phi_10/dx, d phi_10/dy), (d phi_01/dx, d phi_01/dy), FP64 path
+  const float4 *egf;         // the four gradients in FP32, mixed path
+  const double2 *eai;        // (A_e, 2 x inradius)
+  const int4 *enode;         // node ids; w: local edge codes of the 3 local edges, 10 bits each
+  // local elements (chunk + ring 1) of each chunk
+  const int *lgid;           // global element id
+  const double2 *lhb01;      // vertex bathymetry 0, 1
+  const double *lhb2;        // vertex bathymetry 2
+  const unsigned long long *lnb;  // local neighbour index across local edge q in bits 16q (0xFFFF: none)
+  // local edges of each chunk; packed ids = e+ | e- << 12 | (lp | lm << 2 | type << 4) << 24
+  const double2 *le_a, *le_b, *le_c;  // FP64: (nx, ny), (len/2, h_b at s=-1), (h_b at s=+1, ids as bits)
+  const float4 *le_f;                 // mixed: (nx, ny, len/2, ids as bits)
+  const double2 *le_h;                // mixed: (h_b at s=-1, h_b at s=+1)
 };
 
 struct Params {
@@ -74,7 +81,7 @@ struct Params {
 struct DevState {
   void *buf[3];
   void *wpp;       // post-processed w^n of the current step (RK base), same layout
-  double *nodal;   // [3][nn] wind stress x, y and pressure at the nodes
+  double *nodal;   // wind stress (x, y) pairs [nn], then pressure [nn], at the nodes
   double *partial; // [3][nblk] diagnostics partial sums
   Ctrl *ctrl;
 };
@@ -90,20 +97,27 @@ struct Prep {
   std::vector<double> ed_nx, ed_ny, ed_hlen;
   std::vector<double> node_x, node_y;
   // chunks of C consecutive elements with their halos (fused stage kernel)
-  int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0, nh1 = 0;
-  std::vector<int> h1_off, h1, h2_off, h2, le_off, le_gid, nb_off;
-  std::vector<double> h1_hb;
-  std::vector<uint32_t> le_pm;
-  std::vector<uint8_t> le_info;
-  std::vector<double> le_nx, le_ny, le_hl, le_hA, le_hB;
-  std::vector<uint16_t> el_ledge, nbl;
+  int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
+  std::vector<int> h1_off, h1, h2_off, h2, le_off, le_gid, lo_off;
+  std::vector<double> le_nx, le_ny, le_hl, le_hA, le_hB;  // per local edge
+  std::vector<uint32_t> le_ids;                            // packed ids (see DevMesh)
+  std::vector<uint16_t> el_ledge;                          // [3][ne] local edge code per local edge
+  // packed records (see DevMesh)
+  std::vector<double2> eg1, eg2, eai, lhb01, le_a, le_b, le_c, le_h;
+  std::vector<float4> egf, le_f;
+  std::vector<int4> enode;
+  std::vector<int> lgid;
+  std::vector<double> lhb2;
+  std::vector<unsigned long long> lnb;
 };
 
 // Split the (Hilbert-ordered) elements into chunks of C and build, per chunk:
 // the ring-1 halo (neighbours outside the chunk), the ring-2 halo
 // (neighbours of ring 1 outside chunk and ring 1), the chunk-local edge list
-// and local neighbour / edge indices.  Local element index space of a chunk:
-// [0, Cc) chunk elements, then ring 1, then ring 2.
+// and local neighbour / edge indices, and the packed records of the stage
+// kernel.  Local element index space of a chunk: [0, Cc) chunk elements,
+// then ring 1, then ring 2.  Requires C <= 256 (12-bit local ids, 10-bit
+// local edge codes).
 void build_chunks(Prep &P, int C);
 
 // Returns 0 on success, else a DGSWE status code with a message in `err`.
@@ -122,7 +136,7 @@ hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, co
                         const void *wbase, void *wout, void *wpp, int slot, int stage, int pp_in,
                         int want_dt, int block, int precision, hipStream_t st);
 // thread-block sizes the stage kernel is built for
-constexpr int kStageBlocks[] = {256, 384};
+constexpr int kStageBlocks[] = {256};
 // A whole state as FP64 [9][ne] (post-processed if pp), e.g. to read it back.
 hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, double *wout,
                             int precision, hipStream_t st);

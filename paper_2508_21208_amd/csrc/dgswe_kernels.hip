@@ -122,11 +122,12 @@ HD float cbrt_nr(float x) {
 #endif
 }
 
-// dt of the current step: fixed, or cfl x the CFL minimum of w^n (capped).
-// Returns false when no wet element defines it and there is no cap.
-HD bool step_dt(const Ctrl *c, const Params &p, int slot, double &dt) {
+// dt of the current step: fixed, or cfl x the CFL minimum of w^n (capped),
+// from the bit pattern of that minimum.  Returns false when no wet element
+// defines it and there is no cap.
+HD bool dt_from_bits(const Params &p, unsigned long long bits, double &dt) {
   if (p.dt_fixed > 0.0) { dt = p.dt_fixed; return true; }
-  double raw = bits_to_double(c->dtmin[slot]);
+  double raw = bits_to_double(bits);
   if (raw == INFINITY) {
     if (p.dt_max > 0.0) { dt = p.dt_max; return true; }
     return false;
@@ -136,6 +137,7 @@ HD bool step_dt(const Ctrl *c, const Params &p, int slot, double &dt) {
   dt = d;
   return true;
 }
+HD bool step_dt(const Ctrl *c, const Params &p, int slot, double &dt) { return dt_from_bits(p, c->dtmin[slot], dt); }
 
 HD double tide_level(const Params &p, double t) {
   double z = p.tide_offset;
@@ -503,24 +505,6 @@ struct CSt {
   const QT *q;
 };
 
-// element arrays stored in the precision of the flux arithmetic
-template <class QT>
-struct QMesh {
-  const QT *gx1, *gy1, *gx2, *gy2;  // physical gradients of phi_10, phi_01
-  const QT *nx, *ny, *hl;           // chunk-local edge normal and half length
-  const QT *manning;                // Manning n of element e at manning[e * manning_step]
-};
-HD QMesh<double> qmesh(const DevMesh &m, const double *) {
-  return {m.gx1, m.gy1, m.gx2, m.gy2, m.le_nx, m.le_ny, m.le_hl, m.manning};
-}
-HD QMesh<float> qmesh(const DevMesh &m, const float *) {
-  return {m.gx1f, m.gy1f, m.gx2f, m.gy2f, m.le_nxf, m.le_nyf, m.le_hlf, m.manningf};
-}
-template <class QT>
-HD QMesh<QT> qmesh(const DevMesh &m) {
-  return qmesh(m, (const QT *)nullptr);
-}
-
 // Element e of a state, post-processed with neighbour means read from the
 // same state if pp, as FP64 (read-back)
 template <class QT>
@@ -585,7 +569,7 @@ HD Lds<QT> lds_view(const DevMesh &m, void *base) {
 }
 
 struct ChunkInfo {
-  int c, c0, cc, h1o, n1, h2o, n2, leo, ne_loc, nbo;
+  int c, c0, cc, h1o, n1, h2o, n2, leo, ne_loc, lo;
   HD int nl() const { return cc + n1; }
 };
 
@@ -597,40 +581,56 @@ HD ChunkInfo chunk_info(const DevMesh &m, int c) {
   k.h1o = m.h1_off[c]; k.n1 = m.h1_off[c + 1] - k.h1o;
   k.h2o = m.h2_off[c]; k.n2 = m.h2_off[c + 1] - k.h2o;
   k.leo = m.le_off[c]; k.ne_loc = m.le_off[c + 1] - k.leo;
-  k.nbo = m.nb_off[c];
+  k.lo = m.lo_off[c];
   return k;
+}
+
+// bit patterns of the packed ids stored in a double / float slot
+HD uint32_t ids_of(double v) {
+  union { double d; unsigned long long u; } x;
+  x.d = v;
+  return (uint32_t)x.u;
+}
+HD uint32_t ids_of(float v) {
+  union { float f; uint32_t u; } x;
+  x.f = v;
+  return x.u;
 }
 
 // one chunk-local edge record, loaded early and kept in registers
 template <class QT>
 struct EdgeRec {
-  uint32_t pm;
-  int info;
+  uint32_t ids;  // e+ | e- << 12 | (lp | lm << 2 | type << 4) << 24
   QT nx, ny, hl;
   double hA, hB;
 };
 
-template <class QT>
-HD void load_edge_rec(const DevMesh &m, const QMesh<QT> &Q, const ChunkInfo &k, int j, EdgeRec<QT> &R) {
+HD void load_edge_rec(const DevMesh &m, const ChunkInfo &k, int j, EdgeRec<double> &R) {
   const size_t r = (size_t)(k.leo + j);
-  R.pm = m.le_pm[r]; R.info = m.le_info[r];
-  R.nx = Q.nx[r]; R.ny = Q.ny[r]; R.hl = Q.hl[r]; R.hA = m.le_hA[r]; R.hB = m.le_hB[r];
+  const double2 a = m.le_a[r], b = m.le_b[r], c = m.le_c[r];
+  R.nx = a.x; R.ny = a.y; R.hl = b.x; R.hA = b.y; R.hB = c.x;
+  R.ids = ids_of(c.y);
+}
+HD void load_edge_rec(const DevMesh &m, const ChunkInfo &k, int j, EdgeRec<float> &R) {
+  const size_t r = (size_t)(k.leo + j);
+  const float4 a = m.le_f[r];
+  const double2 h = m.le_h[r];
+  R.nx = a.x; R.ny = a.y; R.hl = a.z; R.hA = h.x; R.hB = h.y;
+  R.ids = ids_of(a.w);
 }
 
-// vertex bathymetry of local element i in [0, nl) (chunk: element arrays;
-// ring 1: packed per chunk); the source is selected, the loads are not
-// conditional
+// vertex bathymetry of local element i in [0, nl) of chunk + ring 1
 HD void load_local_hb(const DevMesh &m, const ChunkInfo &k, int i, double h[3]) {
-  const bool in = i < k.cc;
-  const double *b = in ? m.hbv + (k.c0 + i) : m.h1_hb + (k.h1o + i - k.cc);
-  const size_t stride = in ? (size_t)m.ne : (size_t)m.nh1;
-  for (int q = 0; q < 3; ++q) h[q] = b[q * stride];
+  const double2 a = m.lhb01[k.lo + i];
+  h[0] = a.x;
+  h[1] = a.y;
+  h[2] = m.lhb2[k.lo + i];
 }
 
 // local neighbour indices of local element i (chunk + ring 1)
 HD void load_local_nb(const DevMesh &m, const ChunkInfo &k, int i, uint16_t nb[3]) {
-  const int nl = k.nl();
-  for (int q = 0; q < 3; ++q) nb[q] = m.nbl[k.nbo + q * nl + i];
+  const unsigned long long v = m.lnb[k.lo + i];
+  for (int q = 0; q < 3; ++q) nb[q] = (uint16_t)(v >> (16 * q));
 }
 
 // Phase L works in three rounds of loads so that each lane waits for
@@ -639,14 +639,8 @@ HD void load_local_nb(const DevMesh &m, const ChunkInfo &k, int i, uint16_t nb[3
 // ring-2 element, node ids), then every load that needs no index, then the
 // gathers through the indices; LDS is written after all of them.
 
-// global element id of local element i in [0, nl) of chunk + ring 1; the
-// ring-1 list is read at a clamped position (the lists end with a sentinel)
-// so that the load is not conditional
-HD int local_to_global(const DevMesh &m, const ChunkInfo &k, int i) {
-  const int r = i - k.cc;
-  const int g = m.h1[k.h1o + (r < 0 ? 0 : r)];
-  return r < 0 ? k.c0 + i : g;
-}
+// global element id of local element i in [0, nl) of chunk + ring 1
+HD int local_to_global(const DevMesh &m, const ChunkInfo &k, int i) { return m.lgid[k.lo + i]; }
 
 // full state of element g
 template <class QT>
@@ -685,15 +679,32 @@ struct GeoReg {
   double area;
 };
 
-template <class QT>
-HD void load_geo(const DevMesh &m, const QMesh<QT> &Q, const ChunkInfo &k, int i, GeoReg<QT> &G) {
+// gradients, area and 2 x inradius of chunk element i
+HD void load_geo(const DevMesh &m, const ChunkInfo &k, int i, GeoReg<double> &G, double &inr2) {
   const int e = k.c0 + i;
-  G.g[0] = Q.gx1[e];
-  G.g[1] = Q.gy1[e];
-  G.g[2] = Q.gx2[e];
-  G.g[3] = Q.gy2[e];
-  G.area = m.area[e];
+  const double2 a = m.eg1[e], b = m.eg2[e], c = m.eai[e];
+  G.g[0] = a.x; G.g[1] = a.y; G.g[2] = b.x; G.g[3] = b.y;
+  G.area = c.x;
+  inr2 = c.y;
 }
+HD void load_geo(const DevMesh &m, const ChunkInfo &k, int i, GeoReg<float> &G, double &inr2) {
+  const int e = k.c0 + i;
+  const float4 a = m.egf[e];
+  const double2 c = m.eai[e];
+  G.g[0] = a.x; G.g[1] = a.y; G.g[2] = a.z; G.g[3] = a.w;
+  G.area = c.x;
+  inr2 = c.y;
+}
+
+// node ids and local edge codes of chunk element i
+HD void load_elem_node(const DevMesh &m, const ChunkInfo &k, int i, int node[3], int ledge[3]) {
+  const int4 v = m.enode[k.c0 + i];
+  node[0] = v.x; node[1] = v.y; node[2] = v.z;
+  for (int q = 0; q < 3; ++q) ledge[q] = (v.w >> (10 * q)) & 0x3FF;
+}
+
+HD double manning_of(const DevMesh &m, int e, double) { return m.manning[(size_t)e * m.manning_step]; }
+HD float manning_of(const DevMesh &m, int e, float) { return m.manningf[(size_t)e * m.manning_step]; }
 
 template <class QT>
 HD void store_geo_lds(const Lds<QT> &L, int i, const GeoReg<QT> &G) {
@@ -739,8 +750,9 @@ HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp
 // phase E for chunk-local edge j with its record
 template <class QT>
 HD void phase_edge(const Params &p, const Lds<QT> &L, double zb, int j, const EdgeRec<QT> &R) {
-  const int lp = R.info & 3, lm = (R.info >> 2) & 3, type = R.info >> 4;
-  const int ip = (int)(R.pm & 0xFFFFu), im = (int)(R.pm >> 16);
+  const int info = (int)(R.ids >> 24);
+  const int lp = info & 3, lm = (info >> 2) & 3, type = info >> 4;
+  const int ip = (int)(R.ids & 0xFFFu), im = (int)((R.ids >> 12) & 0xFFFu);
   double zp[3], zm[3];
   QT qp[6], qm[6];
   for (int q = 0; q < 3; ++q) zp[q] = L.SZ[q * L.nls + ip];
@@ -761,33 +773,30 @@ HD void phase_edge(const Params &p, const Lds<QT> &L, double zb, int j, const Ed
   L.EMODE[j] = (unsigned char)mode;
 }
 
-// the parts of ElemPre that need no index: bathymetry, local edges, 2 r_e,
-// Manning n and (second stage) the RK base
+// the parts of ElemPre that need no index: Manning n and (second stage)
+// the RK base
 template <class QT>
-HD void load_elem_pre(const DevMesh &m, const QMesh<QT> &Q, const Params &p, const ChunkInfo &k, int i,
-                      const CSt<QT> *wbase, ElemPre<QT> &P) {
+HD void load_elem_pre(const DevMesh &m, const ChunkInfo &k, int i, const CSt<QT> *wbase, ElemPre<QT> &P) {
   const size_t ne = (size_t)m.ne;
   const int e = k.c0 + i;
-  for (int q = 0; q < 3; ++q) {
-    P.h[q] = m.hbv[q * ne + e];
-    P.ledge[q] = m.el_ledge[q * ne + e];
-  }
-  P.inr2 = m.inr2[e];
-  P.manning = Q.manning[(size_t)e * m.manning_step];
+  P.manning = manning_of(m, e, (QT)0);
   if (wbase) {
     for (int j = 0; j < 3; ++j) P.wbz[j] = wbase->z[j * ne + e];
     for (int j = 0; j < 6; ++j) P.wbq[j] = wbase->q[j * ne + e];
   }
 }
 
-// nodal forcing at the element's vertices (node: its node ids)
+// nodal forcing at the element's vertices (node: its node ids); the nodal
+// array holds (tau_x, tau_y) pairs [nn], then p_a [nn]
 template <class QT>
 HD void load_elem_forcing(const DevMesh &m, const DevState &s, const int node[3], ElemPre<QT> &P) {
   const size_t nn = (size_t)m.nn;
+  const double2 *tau = (const double2 *)s.nodal;
   double pa[3];
   for (int q = 0; q < 3; ++q) {
-    P.tx[q] = (QT)s.nodal[node[q]];
-    P.ty[q] = (QT)s.nodal[nn + node[q]];
+    const double2 t = tau[node[q]];
+    P.tx[q] = (QT)t.x;
+    P.ty[q] = (QT)t.y;
     pa[q] = s.nodal[2 * nn + node[q]];
   }
   // pressure modes from vertex differences in FP64 (large common offset)
@@ -894,8 +903,7 @@ __global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Param
   if (i >= m.nn) return;
   double out[3];
   holland(p, m.node_x[i], m.node_y[i], s.ctrl->t[slot] + (stage ? dt : 0.0), out);
-  s.nodal[i] = out[0];
-  s.nodal[(size_t)m.nn + i] = out[1];
+  ((double2 *)s.nodal)[i] = make_double2(out[0], out[1]);
   s.nodal[2 * (size_t)m.nn + i] = out[2];
 }
 
@@ -909,8 +917,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     int want_dt) {
   extern __shared__ double lds_raw[];
   __shared__ double red[NT / 64];
-  __shared__ double s_dt, s_t;
-  __shared__ int s_active;
   Ctrl *ctl = s.ctrl;
   const int tid = threadIdx.x;
   const size_t ne = (size_t)m.ne;
@@ -918,40 +924,28 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   if (c < 0) return;  // the same for every lane of the block
   const ChunkInfo k = chunk_info(m, c);
   const Lds<QT> L = lds_view<QT>(m, lds_raw);
-  const QMesh<QT> Q = qmesh<QT>(m);
   const int nl = k.nl();
 
   // Phase L, round 1: the indices later loads depend on, for lane slots
   // i0 = tid, i1 = tid + NT of chunk + ring 1, ring-2 slot tid and chunk
-  // element tid.  Inactive slots read clamped, valid positions; their values
-  // are never stored.
+  // element tid, and the control block.  Inactive slots read clamped, valid
+  // positions; their values are never stored.
   const int i0 = tid, i1 = tid + NT;
   const bool a0 = i0 < nl, a1 = i1 < nl, ae = tid < k.cc, a2 = tid < k.n2;
   const int c0i = a0 ? i0 : nl - 1, c1i = a1 ? i1 : nl - 1, cei = ae ? tid : k.cc - 1;
   const int g0 = local_to_global(m, k, c0i);
   const int g1 = local_to_global(m, k, c1i);
-  const int h2v = m.h2[k.h2o + (a2 ? tid : 0)];
+  // clamped: a chunk without ring 2 reads the sentinel after the list
+  const int g2 = m.h2[k.h2o + (a2 ? tid : (k.n2 > 0 ? k.n2 - 1 : 0))];
   int node[3];
-  for (int q = 0; q < 3; ++q) node[q] = m.el_node[q * ne + k.c0 + cei];
-
-  // the go/no-go decision and the step's dt and time are read once and
-  // broadcast, so every lane reaches the same barriers
-  if (tid == 0) {
-    double dt = 0.0;
-    int act = ctl->status == 0 ? 1 : 0;
-    if (act && !step_dt(ctl, p, slot, dt)) {
-      atomicCAS(&ctl->status, 0, (int)DGSWE_E_ALLDRY);
-      act = 0;
-    }
-    s_active = act;
-    s_dt = dt;
-    s_t = ctl->t[slot];
-  }
-  __syncthreads();
-  if (!s_active) return;
-  const double dt = s_dt, t0 = s_t;
-  if (STAGE == 0 && blockIdx.x == 0 && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
-
+  ElemPre<QT> pre;
+  load_elem_node(m, k, cei, node, pre.ledge);
+  // Every lane reads the status word and the step's dt and time.  No lane
+  // leaves early, so the barriers stay matched even if another workgroup
+  // changes the status meanwhile; an inactive workgroup only stores nothing.
+  const int status = ctl->status;
+  const unsigned long long dtbits = ctl->dtmin[slot];
+  const double t0 = ctl->t[slot];
   // Round 2: loads that need no index.
   double h0[3], h1[3];
   uint16_t nb0[3], nb1[3];
@@ -961,21 +955,32 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   load_local_nb(m, k, c1i, nb1);
   EdgeRec<QT> r0, r1;
   const int j0 = tid < k.ne_loc ? tid : k.ne_loc - 1, j1 = tid + NT < k.ne_loc ? tid + NT : k.ne_loc - 1;
-  load_edge_rec<QT>(m, Q, k, j0, r0);
-  load_edge_rec<QT>(m, Q, k, j1, r1);
-  ElemPre<QT> pre;
+  load_edge_rec(m, k, j0, r0);
+  load_edge_rec(m, k, j1, r1);
   GeoReg<QT> geo;
-  load_elem_pre<QT>(m, Q, p, k, cei, STAGE ? &wbase : nullptr, pre);
-  load_geo<QT>(m, Q, k, cei, geo);
-  // Round 3: gathers through the indices.
+  load_geo(m, k, cei, geo, pre.inr2);
+  load_elem_pre<QT>(m, k, cei, STAGE ? &wbase : nullptr, pre);
+  // Round 3: gathers through the indices (kept after round 2 in the
+  // instruction stream, so the index loads return while round 2 is issued).
+#ifdef __HIP_DEVICE_COMPILE__
+  __builtin_amdgcn_sched_barrier(0);
+#endif
   StateReg<QT> st0, st1;
   load_state_reg<QT>(win, ne, g0, st0);
   load_state_reg<QT>(win, ne, g1, st1);
   load_elem_forcing<QT>(m, s, node, pre);
-  const int g2 = a2 ? h2v : k.c0;
   const double mz2 = win.z[g2];
   const QT mx2 = win.q[g2], my2 = win.q[3 * ne + g2];
   for (int j = tid + NT; j < k.n2; j += NT) load_h2_lds<QT>(L, win, ne, nl, j, m.h2[k.h2o + j]);
+  // the go/no-go decision (uniform unless the status changes while the
+  // workgroup reads it)
+  double dt = 0.0;
+  bool active = status == 0;
+  if (!dt_from_bits(p, dtbits, dt)) {
+    if (active && tid == 0) atomicCAS(&ctl->status, 0, (int)DGSWE_E_ALLDRY);
+    active = false;
+  }
+  if (STAGE == 0 && active && blockIdx.x == 0 && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
   if (a0) store_state_lds<QT>(L, i0, st0);
   if (a1) store_state_lds<QT>(L, i1, st1);
   if (ae) store_geo_lds<QT>(L, tid, geo);
@@ -984,8 +989,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     L.MQ[nl + tid] = mx2;
     L.MQ[L.nms + nl + tid] = my2;
   }
+  for (int q = 0; q < 3; ++q) pre.h[q] = h0[q];
   __syncthreads();
-  const St<QT> *wpp_out = STAGE == 0 ? &wpp : nullptr;
+  const St<QT> *wpp_out = (STAGE == 0 && active) ? &wpp : nullptr;
   if (a0) phase_post<QT>(p, k, L, pp_in, i0, h0, nb0, wpp_out, ne);
   if (a1) phase_post<QT>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne);
   __syncthreads();
@@ -996,13 +1002,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   __syncthreads();
   double cand = INFINITY;
   bool bad = false;
-  if (ae) cand = phase_area<QT>(p, k, L, pre, STAGE != 0, wout, ne, dt, want_dt, tid, bad);
+  if (ae && active) cand = phase_area<QT>(p, k, L, pre, STAGE != 0, wout, ne, dt, want_dt, tid, bad);
   if (bad) atomicCAS(&ctl->status, 0, (int)DGSWE_E_NONFINITE);
   if (want_dt) {
     const double bm = block_min<NT>(cand, red);
     if (tid == 0 && bm < INFINITY) atomicMin(&ctl->dtmin[slot ^ 1], double_to_bits(bm));
   }
-  if (STAGE == 1 && blockIdx.x == 0 && tid == 0) {
+  if (STAGE == 1 && active && blockIdx.x == 0 && tid == 0) {
     ctl->t[slot ^ 1] = t0 + dt;
     ctl->dt_last = dt;
     ctl->steps = ctl->steps + 1;
@@ -1145,13 +1151,9 @@ static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const
 #define DGSWE_STAGE(NT, W, S)                                                                             \
   hipLaunchKernelGGL((k_stage<NT, W, QT, S>), dim3(m.nch), dim3(NT), lds, st, m, s, p, a, b, o, q, slot, pp_in, \
                      want_dt)
-  if (block == 384) {
-    if (stage) DGSWE_STAGE(384, 3, 1);
-    else DGSWE_STAGE(384, 3, 0);
-  } else {
-    if (stage) DGSWE_STAGE(256, 2, 1);
-    else DGSWE_STAGE(256, 2, 0);
-  }
+  (void)block;  // 256 lanes (the local ids and edge codes are packed for it)
+  if (stage) DGSWE_STAGE(256, 2, 1);
+  else DGSWE_STAGE(256, 2, 0);
 #undef DGSWE_STAGE
 }
 

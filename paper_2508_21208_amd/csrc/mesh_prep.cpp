@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <numeric>
 
 #include "dgswe_internal.h"
@@ -227,6 +228,20 @@ int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *
   return DGSWE_OK;
 }
 
+namespace {
+double bits_as_double(uint32_t v) {
+  const uint64_t u = v;
+  double d;
+  std::memcpy(&d, &u, sizeof d);
+  return d;
+}
+float bits_as_float(uint32_t v) {
+  float f;
+  std::memcpy(&f, &v, sizeof f);
+  return f;
+}
+}  // namespace
+
 void build_chunks(Prep &P, int C) {
   const int ne = P.ne;
   const size_t nes = (size_t)ne;
@@ -235,10 +250,10 @@ void build_chunks(Prep &P, int C) {
   P.h1_off.assign(P.nch + 1, 0);
   P.h2_off.assign(P.nch + 1, 0);
   P.le_off.assign(P.nch + 1, 0);
-  P.nb_off.assign(P.nch + 1, 0);
-  P.h1.clear(); P.h2.clear(); P.le_gid.clear(); P.nbl.clear();
-  P.le_pm.clear(); P.le_info.clear();
+  P.lo_off.assign(P.nch + 1, 0);
+  P.h1.clear(); P.h2.clear(); P.le_gid.clear(); P.le_ids.clear();
   P.le_nx.clear(); P.le_ny.clear(); P.le_hl.clear(); P.le_hA.clear(); P.le_hB.clear();
+  P.lhb01.clear(); P.lhb2.clear(); P.lnb.clear(); P.lgid.clear();
   P.el_ledge.assign(3 * nes, 0);
   P.nl_max = P.nm_max = P.ed_max = P.n2_max = 0;
   std::vector<int> loc(nes, -1);       // global element -> local index in the current chunk
@@ -265,14 +280,21 @@ void build_chunks(Prep &P, int C) {
     std::sort(h2.begin(), h2.end());
     for (size_t k = 0; k < h2.size(); ++k) loc[h2[k]] = nl + (int)k;
     const int nm = nl + (int)h2.size();
-    // local neighbour table of chunk + ring 1, layout [l][i]
-    P.nb_off[c] = (int)P.nbl.size();
-    for (int l = 0; l < 3; ++l)
-      for (int i = 0; i < nl; ++i) {
-        int g = i < cc ? c0 + i : h1[i - cc];
-        int f = P.el_nb[(size_t)l * nes + g];
-        P.nbl.push_back(f < 0 ? (uint16_t)0xFFFF : (uint16_t)loc[f]);
+    // local elements (chunk + ring 1): vertex bathymetry and local neighbours
+    P.lo_off[c] = (int)P.lnb.size();
+    for (int i = 0; i < nl; ++i) {
+      const int g = i < cc ? c0 + i : h1[i - cc];
+      P.lgid.push_back(g);
+      P.lhb01.push_back(make_double2(P.hbv[g], P.hbv[nes + g]));
+      P.lhb2.push_back(P.hbv[2 * nes + g]);
+      unsigned long long nbw = 0;
+      for (int l = 0; l < 3; ++l) {
+        const int f = P.el_nb[(size_t)l * nes + g];
+        const unsigned long long v = f < 0 ? 0xFFFFull : (unsigned long long)loc[f];
+        nbw |= v << (16 * l);
       }
+      P.lnb.push_back(nbw);
+    }
     // chunk-local edges: every edge of a chunk element, once
     edges.clear();
     for (int i = 0; i < cc; ++i)
@@ -287,9 +309,8 @@ void build_chunks(Prep &P, int C) {
       eloc[d] = (int)k;
       P.le_gid.push_back(d);
       const uint32_t ip = (uint32_t)loc[P.ed_ep[d]];
-      const uint32_t im = P.ed_em[d] < 0 ? 0xFFFFu : (uint32_t)loc[P.ed_em[d]];
-      P.le_pm.push_back(ip | (im << 16));
-      P.le_info.push_back((uint8_t)P.ed_info[d]);
+      const uint32_t im = P.ed_em[d] < 0 ? 0u : (uint32_t)loc[P.ed_em[d]];
+      P.le_ids.push_back(ip | (im << 12) | ((uint32_t)P.ed_info[d] << 24));
       P.le_nx.push_back(P.ed_nx[d]);
       P.le_ny.push_back(P.ed_ny[d]);
       P.le_hl.push_back(P.ed_hlen[d]);
@@ -316,20 +337,33 @@ void build_chunks(Prep &P, int C) {
     for (int g : h2) loc[g] = -1;
     for (int d : edges) eloc[d] = -1;
   }
-  const size_t nh1 = P.h1.size();
-  P.h1_hb.resize(3 * nh1);
-  for (size_t k = 0; k < nh1; ++k)
-    for (int q = 0; q < 3; ++q) P.h1_hb[q * nh1 + k] = P.hbv[(size_t)q * nes + P.h1[k]];
   P.h1_off[P.nch] = (int)P.h1.size();
   P.h2_off[P.nch] = (int)P.h2.size();
   P.le_off[P.nch] = (int)P.le_gid.size();
-  P.nb_off[P.nch] = (int)P.nbl.size();
-  P.nh1 = (int)nh1;
-  // one sentinel entry past the end of the halo lists: the stage kernel
-  // reads a clamped halo index unconditionally (also for a chunk without
-  // ring 1 or ring 2) and discards it where it does not apply
-  P.h1.push_back(0);
+  P.lo_off[P.nch] = (int)P.lnb.size();
+  // one sentinel entry (element 0) past the end of the ring-2 list: the
+  // stage kernel reads a clamped ring-2 position unconditionally, also for a
+  // chunk without ring 2, and stores only the entries that exist
   P.h2.push_back(0);
+  // packed records of the stage kernel
+  const size_t nle = P.le_gid.size();
+  P.le_a.resize(nle); P.le_b.resize(nle); P.le_c.resize(nle); P.le_f.resize(nle); P.le_h.resize(nle);
+  for (size_t r = 0; r < nle; ++r) {
+    P.le_a[r] = make_double2(P.le_nx[r], P.le_ny[r]);
+    P.le_b[r] = make_double2(P.le_hl[r], P.le_hA[r]);
+    P.le_c[r] = make_double2(P.le_hB[r], bits_as_double(P.le_ids[r]));
+    P.le_f[r] = make_float4((float)P.le_nx[r], (float)P.le_ny[r], (float)P.le_hl[r], bits_as_float(P.le_ids[r]));
+    P.le_h[r] = make_double2(P.le_hA[r], P.le_hB[r]);
+  }
+  P.eg1.resize(nes); P.eg2.resize(nes); P.egf.resize(nes); P.eai.resize(nes); P.enode.resize(nes);
+  for (size_t e = 0; e < nes; ++e) {
+    P.eg1[e] = make_double2(P.gx1[e], P.gy1[e]);
+    P.eg2[e] = make_double2(P.gx2[e], P.gy2[e]);
+    P.egf[e] = make_float4((float)P.gx1[e], (float)P.gy1[e], (float)P.gx2[e], (float)P.gy2[e]);
+    P.eai[e] = make_double2(P.area[e], P.inr2[e]);
+    const int codes = (int)P.el_ledge[e] | ((int)P.el_ledge[nes + e] << 10) | ((int)P.el_ledge[2 * nes + e] << 20);
+    P.enode[e] = make_int4(P.el_node[e], P.el_node[nes + e], P.el_node[2 * nes + e], codes);
+  }
 }
 
 }  // namespace dgswe
