@@ -18,6 +18,8 @@ cores.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +32,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "elem-stage updates/s @4M tri p=1, FP64 vs mixed/batched; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_hbm_traffic_hurricane_4M.json")
+KERNEL_SOURCES = ("paper_2508_21208_amd/csrc/dgswe_kernels.hip", "paper_2508_21208_amd/csrc/dgswe_internal.h",
+                  "paper_2508_21208_amd/csrc/mesh_prep.cpp", "paper_2508_21208_amd/csrc/dgswe_api.hip")
 
 
 def log(msg):
@@ -59,6 +64,120 @@ def algorithmic_bytes(kernel: str, ne: int, ned: int, nn: int, precision: str = 
     if kernel == "k_forcing":
         return 40.0 * nn
     raise KeyError(kernel)
+
+
+def source_hash() -> str:
+    """sha256 over the kernel, data-layout and launch sources: measured
+    traffic belongs to exactly this code."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(precision: str):
+    """HBM bytes per k_stage launch measured with rocprofv3 counters for the
+    current sources, or None (no record, or the kernel changed since)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_hash():
+        return None
+    k = rec.get("k_stage", {}).get(precision)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def stage_kernel_precision(name: str):
+    """'double' / 'float' for a k_stage<NT, WPE, T, STAGE> kernel name, else None."""
+    if "k_stage<" not in name:
+        return None
+    args = name.split("k_stage<", 1)[1].split(">", 1)[0].split(",")
+    return args[2].strip() if len(args) >= 3 else None
+
+
+def summarize_pmc(pmc_dir: str, stats_csv: str | None, out_md: str | None):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
+    dispatch) of `bench.py --copy-probe` into HBM bytes per k_stage launch.
+    Each counter is scaled by what it reads for the 2 GiB device copy in the
+    same run (bytes moved / counter reading)."""
+    def load(tag):
+        with open(os.path.join(pmc_dir, tag, "run_counter_collection.csv")) as fh:
+            return list(csv.DictReader(fh))
+    copy_bytes = 2 * 1024 ** 3
+    res = {"source_sha256": source_hash(), "k_stage": {}, "calibration": {}}
+    vals = {}
+    for tag in ("FETCH_SIZE", "WRITE_SIZE"):
+        rows = load(tag)
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        big = max(copies)
+        scale = copy_bytes / (big * 1024.0)
+        res["calibration"][tag] = {"copy_KiB": big, "bytes_per_KiB": round(scale * 1024.0, 1), "factor": round(scale, 3)}
+        for prec, key in (("fp64", "double"), ("mixed", "float")):
+            v = [float(r["Counter_Value"]) for r in rows if stage_kernel_precision(r["Kernel_Name"]) == key]
+            if v:
+                vals.setdefault(prec, {})[tag] = (sum(v) / len(v), len(v), scale)
+    for prec, d in vals.items():
+        if len(d) < 2:
+            continue
+        fk, fn, fs = d["FETCH_SIZE"]
+        wk, wn, ws = d["WRITE_SIZE"]
+        b = fk * 1024.0 * fs + wk * 1024.0 * ws
+        res["k_stage"][prec] = {"fetch_KiB": round(fk, 1), "write_KiB": round(wk, 1), "dispatches": [fn, wn],
+                                "bytes_per_launch": round(b)}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
+    if out_md:
+        lines = ["# k_stage on the 4M-triangle hurricane workload: kernel times and HBM traffic", "",
+                 "Commands, on one MI355X, with REPO = the repository root and OUT = an output folder:", "",
+                 "```",
+                 "cd /tmp && export TMPDIR=/tmp",
+                 "rocprofv3 --kernel-trace --stats -d $OUT/prof -o bench --output-format csv -- "
+                 "python3 $REPO/bench.py --steps 50 --warmup 5 --no-cpu-baseline --no-profile",
+                 "rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc/FETCH_SIZE -o run --output-format csv -- "
+                 "python3 $REPO/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-profile --copy-probe",
+                 "rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc/WRITE_SIZE -o run --output-format csv -- "
+                 "python3 $REPO/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-profile --copy-probe",
+                 "cd $REPO && python3 bench.py --summarize-pmc $OUT/pmc --kernel-stats "
+                 "$OUT/prof/bench_kernel_stats.csv --summary-md profiles/k_stage_hurricane_4M.md",
+                 "```", "", "The bench runs the FP64 headline and then the mixed-precision variant in the same "
+                 "process, so both precisions appear below.", "",
+                 f"Kernel sources sha256 (bench.py reports this traffic only for these sources): "
+                 f"`{res['source_sha256']}`", ""]
+        if stats_csv:
+            with open(stats_csv) as fh:
+                rows = list(csv.DictReader(fh))
+            lines += ["## Kernel trace (`--kernel-trace --stats`, 50 timed + 5 warm-up steps per precision)", "",
+                      "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
+            for r in rows[:10]:
+                nm = r["Name"].split("(")[0].replace("dgswe::", "")
+                lines.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                             f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                             f"{float(r['Percentage']):.1f} |")
+            lines.append("")
+            for key, prec in (("double", "fp64"), ("float", "mixed")):
+                sel = [r for r in rows if stage_kernel_precision(r["Name"]) == key]
+                if sel:
+                    n = sum(int(r["Calls"]) for r in sel)
+                    tot = sum(float(r["TotalDurationNs"]) for r in sel)
+                    lines.append(f"k_stage {prec}, both RK stages: {n} launches, average {tot / n / 1e3:.1f} us "
+                                 f"(bench.py reports the HIP-event average over the same two kernels).")
+            lines.append("")
+        lines += ["## HBM traffic per k_stage launch (mean over both RK stages)", "",
+                  "| precision | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch (calibrated) |",
+                  "|---|---|---|---|"]
+        for prec, d in res["k_stage"].items():
+            lines.append(f"| {prec} | {d['fetch_KiB']:.0f} | {d['write_KiB']:.0f} | {d['bytes_per_launch'] / 1e9:.3f} GB |")
+        c = res["calibration"]
+        lines += ["", "Calibration: a 2 GiB device copy in the same runs reads "
+                  f"{c['FETCH_SIZE']['copy_KiB']:.0f} KiB FETCH_SIZE and {c['WRITE_SIZE']['copy_KiB']:.0f} KiB "
+                  f"WRITE_SIZE, so fetched bytes = FETCH_SIZE x {c['FETCH_SIZE']['bytes_per_KiB']} B and written "
+                  f"bytes = WRITE_SIZE x {c['WRITE_SIZE']['bytes_per_KiB']} B.", ""]
+        with open(out_md, "w") as fh:
+            fh.write("\n".join(lines))
 
 
 def cpu_baseline(wl, target_s=12.0):
@@ -127,8 +246,9 @@ def roofline(kernels, ne, ned, nn, precision):
     for k in kernels:
         kb = algorithmic_bytes(k, ne, ned, nn, precision)
         kernels[k]["alg_GBs"] = round(kb / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
+    traffic = stored_traffic(precision) if dom == "k_stage" else None
     return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": int(b), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
 
 
@@ -145,7 +265,14 @@ def main():
                     help="precision of the headline run (fp64 is the metric's)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of 2 GiB (3 times) to calibrate HBM counters")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="no GPU run: turn rocprofv3 FETCH_SIZE/WRITE_SIZE runs under DIR into the traffic record")
+    ap.add_argument("--kernel-stats", help="with --summarize-pmc: rocprofv3 kernel_stats.csv to tabulate")
+    ap.add_argument("--summary-md", help="with --summarize-pmc: write a markdown summary here")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.kernel_stats, args.summary_md)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; a multi-GPU run (domain "
                                    "decomposition with a per-stage halo exchange) is not implemented",
