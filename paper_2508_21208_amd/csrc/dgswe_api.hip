@@ -256,14 +256,14 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
   chk(upload(S, &m.le_off, P.le_off)); chk(upload(S, &m.lo_off, P.lo_off));
   chk(upload(S, &m.eai, P.eai)); chk(upload(S, &m.enode, P.enode));
   chk(upload(S, &m.lhb01, P.lhb01)); chk(upload(S, &m.lhb2, P.lhb2)); chk(upload(S, &m.lnb, P.lnb));
-  m.eg1 = m.eg2 = m.le_a = m.le_b = m.le_c = m.le_h = nullptr;
+  m.eg1 = m.eg2 = m.le_a = m.le_b = nullptr;
   m.egf = m.le_f = nullptr;
   if (mixed) {
     chk(upload(S, &m.egf, P.egf));
-    chk(upload(S, &m.le_f, P.le_f)); chk(upload(S, &m.le_h, P.le_h));
+    chk(upload(S, &m.le_f, P.le_f));
   } else {
     chk(upload(S, &m.eg1, P.eg1)); chk(upload(S, &m.eg2, P.eg2));
-    chk(upload(S, &m.le_a, P.le_a)); chk(upload(S, &m.le_b, P.le_b)); chk(upload(S, &m.le_c, P.le_c));
+    chk(upload(S, &m.le_a, P.le_a)); chk(upload(S, &m.le_b, P.le_b));
   }
   const size_t lds = stage_lds_bytes(m, S->precision);
   if (lds > 80 * 1024 || P.nl_max > 2 * block || P.ed_max > 2 * block) {

@@ -57,9 +57,9 @@ struct DevMesh {
   const double *lhb2;        // vertex bathymetry 2
   const unsigned long long *lnb;  // local neighbour index across local edge q in bits 16q (0xFFFF: none)
   // local edges of each chunk; packed ids = e+ | e- << 12 | (lp | lm << 2 | type << 4) << 24
-  const double2 *le_a, *le_b, *le_c;  // FP64: (nx, ny), (len/2, h_b at s=-1), (h_b at s=+1, ids as bits)
-  const float4 *le_f;                 // mixed: (nx, ny, len/2, ids as bits)
-  const double2 *le_h;                // mixed: (h_b at s=-1, h_b at s=+1)
+  // (the bathymetry at the edge ends is the e+ element's, read from LDS)
+  const double2 *le_a, *le_b;  // FP64: (nx, ny), (len/2, ids as bits)
+  const float4 *le_f;          // mixed: (nx, ny, len/2, ids as bits)
 };
 
 struct Params {
@@ -99,11 +99,11 @@ struct Prep {
   // chunks of C consecutive elements with their halos (fused stage kernel)
   int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
   std::vector<int> h1_off, h1, h2_off, h2, le_off, le_gid, lo_off;
-  std::vector<double> le_nx, le_ny, le_hl, le_hA, le_hB;  // per local edge
+  std::vector<double> le_nx, le_ny, le_hl;                // per local edge
   std::vector<uint32_t> le_ids;                            // packed ids (see DevMesh)
   std::vector<uint16_t> el_ledge;                          // [3][ne] local edge code per local edge
   // packed records (see DevMesh)
-  std::vector<double2> eg1, eg2, eai, lhb01, le_a, le_b, le_c, le_h;
+  std::vector<double2> eg1, eg2, eai, lhb01, le_a, le_b;
   std::vector<float4> egf, le_f;
   std::vector<int4> enode;
   std::vector<int> lgid;

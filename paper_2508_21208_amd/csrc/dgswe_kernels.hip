@@ -533,13 +533,14 @@ HD void load_pp_global(const DevMesh &m, const Params &p, CSt<QT> w, int e, bool
 //   MZ[n2_max]    double: unlimited zeta means of ring 2 (the zeta mean of
 //                 chunk and ring 1 is SZ[0][i], never changed by phase P)
 //   GA[C]         double: element areas
+//   LH[3][nl_max] double: vertex bathymetry of chunk + ring 1
 //   MQ[2][nm_max] QT: unlimited Qx, Qy means of chunk + ring 1 + ring 2
 //   EM[6][ed_max] QT: edge moments
 //   GG[4][C]      QT: gradients of phi_10, phi_01 of the chunk elements
 //   EMODE[ed_max], WET[nl_max] bytes
 template <class QT>
 struct Lds {
-  double *SZ, *MZ, *GA;
+  double *SZ, *MZ, *GA, *LH;
   QT *SQ, *MQ, *EM, *GG;
   unsigned char *EMODE, *WET;
   int nls, nms, eds, cs;  // strides
@@ -547,7 +548,7 @@ struct Lds {
 
 template <class QT>
 HD size_t lds_bytes(const DevMesh &m) {
-  return 8 * (3 * (size_t)m.nl_max + (size_t)m.n2_max + (size_t)m.C) +
+  return 8 * (6 * (size_t)m.nl_max + (size_t)m.n2_max + (size_t)m.C) +
          sizeof(QT) * (6 * (size_t)m.nl_max + 2 * (size_t)m.nm_max + 6 * (size_t)m.ed_max + 4 * (size_t)m.C) +
          (size_t)m.ed_max + (size_t)m.nl_max;
 }
@@ -559,7 +560,8 @@ HD Lds<QT> lds_view(const DevMesh &m, void *base) {
   L.SZ = (double *)base;
   L.MZ = L.SZ + 3 * (size_t)L.nls;
   L.GA = L.MZ + (size_t)m.n2_max;
-  L.SQ = (QT *)(L.GA + (size_t)L.cs);
+  L.LH = L.GA + (size_t)L.cs;
+  L.SQ = (QT *)(L.LH + 3 * (size_t)L.nls);
   L.MQ = L.SQ + 6 * (size_t)L.nls;
   L.EM = L.MQ + 2 * (size_t)L.nms;
   L.GG = L.EM + 6 * (size_t)L.eds;
@@ -602,20 +604,18 @@ template <class QT>
 struct EdgeRec {
   uint32_t ids;  // e+ | e- << 12 | (lp | lm << 2 | type << 4) << 24
   QT nx, ny, hl;
-  double hA, hB;
 };
 
 HD void load_edge_rec(const DevMesh &m, const ChunkInfo &k, int j, EdgeRec<double> &R) {
   const size_t r = (size_t)(k.leo + j);
-  const double2 a = m.le_a[r], b = m.le_b[r], c = m.le_c[r];
-  R.nx = a.x; R.ny = a.y; R.hl = b.x; R.hA = b.y; R.hB = c.x;
-  R.ids = ids_of(c.y);
+  const double2 a = m.le_a[r], b = m.le_b[r];
+  R.nx = a.x; R.ny = a.y; R.hl = b.x;
+  R.ids = ids_of(b.y);
 }
 HD void load_edge_rec(const DevMesh &m, const ChunkInfo &k, int j, EdgeRec<float> &R) {
   const size_t r = (size_t)(k.leo + j);
   const float4 a = m.le_f[r];
-  const double2 h = m.le_h[r];
-  R.nx = a.x; R.ny = a.y; R.hl = a.z; R.hA = h.x; R.hB = h.y;
+  R.nx = a.x; R.ny = a.y; R.hl = a.z;
   R.ids = ids_of(a.w);
 }
 
@@ -766,9 +766,12 @@ HD void phase_edge(const Params &p, const Lds<QT> &L, double zb, int j, const Ed
     for (int q = 0; q < 3; ++q) zm[q] = 0.0;
     for (int q = 0; q < 6; ++q) qm[q] = (QT)0;
   }
+  // bathymetry at the edge ends: vertices lp+1 (s = -1) and lp+2 (s = +1) of e+
+  const int va = lp == 2 ? 0 : lp + 1, vb = lp == 0 ? 2 : lp - 1;
+  const double hA = L.LH[va * L.nls + ip], hB = L.LH[vb * L.nls + ip];
   QT mom[6];
   const int mode =
-      edge_flux<QT>(zp, qp, zm, qm, lp, lm, type, L.WET[ip] != 0, wetm, R.hA, R.hB, R.nx, R.ny, R.hl, zb, p, mom);
+      edge_flux<QT>(zp, qp, zm, qm, lp, lm, type, L.WET[ip] != 0, wetm, hA, hB, R.nx, R.ny, R.hl, zb, p, mom);
   for (int q = 0; q < 6; ++q) L.EM[q * L.eds + j] = mom[q];
   L.EMODE[j] = (unsigned char)mode;
 }
@@ -981,8 +984,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     active = false;
   }
   if (STAGE == 0 && active && blockIdx.x == 0 && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
-  if (a0) store_state_lds<QT>(L, i0, st0);
-  if (a1) store_state_lds<QT>(L, i1, st1);
+  if (a0) {
+    store_state_lds<QT>(L, i0, st0);
+    for (int q = 0; q < 3; ++q) L.LH[q * L.nls + i0] = h0[q];
+  }
+  if (a1) {
+    store_state_lds<QT>(L, i1, st1);
+    for (int q = 0; q < 3; ++q) L.LH[q * L.nls + i1] = h1[q];
+  }
   if (ae) store_geo_lds<QT>(L, tid, geo);
   if (a2) {
     L.MZ[tid] = mz2;

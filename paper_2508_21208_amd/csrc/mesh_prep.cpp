@@ -252,7 +252,7 @@ void build_chunks(Prep &P, int C) {
   P.le_off.assign(P.nch + 1, 0);
   P.lo_off.assign(P.nch + 1, 0);
   P.h1.clear(); P.h2.clear(); P.le_gid.clear(); P.le_ids.clear();
-  P.le_nx.clear(); P.le_ny.clear(); P.le_hl.clear(); P.le_hA.clear(); P.le_hB.clear();
+  P.le_nx.clear(); P.le_ny.clear(); P.le_hl.clear();
   P.lhb01.clear(); P.lhb2.clear(); P.lnb.clear(); P.lgid.clear();
   P.el_ledge.assign(3 * nes, 0);
   P.nl_max = P.nm_max = P.ed_max = P.n2_max = 0;
@@ -314,9 +314,6 @@ void build_chunks(Prep &P, int C) {
       P.le_nx.push_back(P.ed_nx[d]);
       P.le_ny.push_back(P.ed_ny[d]);
       P.le_hl.push_back(P.ed_hlen[d]);
-      const int lp = P.ed_info[d] & 3, ep = P.ed_ep[d];
-      P.le_hA.push_back(P.hbv[(size_t)((lp + 1) % 3) * nes + ep]);
-      P.le_hB.push_back(P.hbv[(size_t)((lp + 2) % 3) * nes + ep]);
     }
     for (int i = 0; i < cc; ++i)
       for (int l = 0; l < 3; ++l) {
@@ -347,13 +344,11 @@ void build_chunks(Prep &P, int C) {
   P.h2.push_back(0);
   // packed records of the stage kernel
   const size_t nle = P.le_gid.size();
-  P.le_a.resize(nle); P.le_b.resize(nle); P.le_c.resize(nle); P.le_f.resize(nle); P.le_h.resize(nle);
+  P.le_a.resize(nle); P.le_b.resize(nle); P.le_f.resize(nle);
   for (size_t r = 0; r < nle; ++r) {
     P.le_a[r] = make_double2(P.le_nx[r], P.le_ny[r]);
-    P.le_b[r] = make_double2(P.le_hl[r], P.le_hA[r]);
-    P.le_c[r] = make_double2(P.le_hB[r], bits_as_double(P.le_ids[r]));
+    P.le_b[r] = make_double2(P.le_hl[r], bits_as_double(P.le_ids[r]));
     P.le_f[r] = make_float4((float)P.le_nx[r], (float)P.le_ny[r], (float)P.le_hl[r], bits_as_float(P.le_ids[r]));
-    P.le_h[r] = make_double2(P.le_hA[r], P.le_hB[r]);
   }
   P.eg1.resize(nes); P.eg2.resize(nes); P.egf.resize(nes); P.eai.resize(nes); P.enode.resize(nes);
   for (size_t e = 0; e < nes; ++e) {
