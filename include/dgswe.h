@@ -113,6 +113,37 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
                                const int32_t *bnd_nodes, const int32_t *bnd_type,
                                const dgswe_params *prm, void *hip_stream, dgswe_solver **out);
 
+/* One mesh of a batch: the arguments of dgswe_create_mesh. */
+typedef struct {
+  int32_t n_nodes;
+  const double *node_xy;
+  const double *node_hb;
+  int32_t n_elems;
+  const int32_t *tri;
+  int32_t n_bnd;
+  const int32_t *bnd_nodes;
+  const int32_t *bnd_type;
+} dgswe_mesh;
+
+/* A batch: n_meshes independent instances of the same step (an ensemble of
+ * storm tracks, a queue of requests), advanced together by dgswe_step with
+ * one kernel launch per stage for all of them.  The paper runs one mesh;
+ * a member of a batch follows exactly the same arithmetic as that mesh
+ * alone (same results, bitwise), with its own forcing, time, dt (its own
+ * CFL minimum), step count and error status.  Parameters (prm, including
+ * the precision) are shared.  Each mesh is validated as in
+ * dgswe_create_mesh (errors name the mesh); at most 2^31 - 1 elements in
+ * total.  A handle made by dgswe_create_mesh is a batch of one.  The
+ * single-mesh calls (dgswe_set_state, dgswe_set_forcing, dgswe_read_state)
+ * return DGSWE_E_INVALID on a batch of several meshes; use the member calls
+ * below, whose `member` is the index into `meshes` (out of range ->
+ * DGSWE_E_INVALID). */
+dgswe_status dgswe_create_batch(int32_t n_meshes, const dgswe_mesh *meshes, const dgswe_params *prm,
+                                void *hip_stream, dgswe_solver **out);
+
+/* Number of meshes in the batch (0 for NULL). */
+int32_t dgswe_member_count(const dgswe_solver *s);
+
 /* Replace the modal state (layout above, caller's element order) and set the
  * time to t; resets the step counter.  `w` is copied before the call returns.
  * Every stage of the step starts from a post-processed state (slope limiter,
@@ -122,6 +153,12 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
  * from a state returned by dgswe_read_state: the continuation is then
  * bitwise identical to an uninterrupted run). */
 dgswe_status dgswe_set_state(dgswe_solver *s, double t, const double *w, int32_t postprocess);
+
+/* dgswe_set_state for one member of a batch (w: that mesh's elements).
+ * The other members are not touched; the member's time, dt and step count
+ * restart from t. */
+dgswe_status dgswe_member_set_state(dgswe_solver *s, int32_t member, double t, const double *w,
+                                    int32_t postprocess);
 
 /* Forcing (Sec. 2.1: bottom friction tau_b, sources F_x, F_y; Sec. 6.1:
  * tidal elevation on the open boundary).
@@ -152,13 +189,17 @@ typedef struct {
 
 dgswe_status dgswe_set_forcing(dgswe_solver *s, const dgswe_forcing *f);
 
-/* Enqueue n_steps SSP-RK(2,2) steps on the solver's stream and return
- * without waiting (Sec. 2.2, Eq. RKSSP; Sec. 5.2, Algorithms 1-3).  Each
- * step computes its dt on the device: dt_fixed if > 0, otherwise
- * cfl * min over wet elements of 2 r_e / (|Q_mean|/H_mean + sqrt(g H_mean))
- * (r_e the inradius), capped by dt_max if > 0.  Errors detected by the
- * kernels (DGSWE_E_NONFINITE, DGSWE_E_ALLDRY) stop all further steps and
- * are reported by the next dgswe_read_state. */
+/* dgswe_set_forcing for one member of a batch (arrays sized for its mesh). */
+dgswe_status dgswe_member_set_forcing(dgswe_solver *s, int32_t member, const dgswe_forcing *f);
+
+/* Enqueue n_steps SSP-RK(2,2) steps of every member on the solver's stream
+ * and return without waiting (Sec. 2.2, Eq. RKSSP; Sec. 5.2, Algorithms
+ * 1-3).  Each step computes its dt on the device, per member: dt_fixed if
+ * > 0, otherwise cfl * min over the member's wet elements of
+ * 2 r_e / (|Q_mean|/H_mean + sqrt(g H_mean)) (r_e the inradius), capped by
+ * dt_max if > 0.  Errors detected by the kernels (DGSWE_E_NONFINITE,
+ * DGSWE_E_ALLDRY) stop all further steps of that member and are reported
+ * by its next read. */
 dgswe_status dgswe_step(dgswe_solver *s, int32_t n_steps);
 
 typedef struct {
@@ -174,6 +215,10 @@ typedef struct {
  * layout as dgswe_set_state) and the diagnostics (if d != NULL).  Returns
  * the first kernel-detected error, if any (the data are still copied). */
 dgswe_status dgswe_read_state(dgswe_solver *s, double *w_out, dgswe_diag *d);
+
+/* dgswe_read_state for one member of a batch (its own diagnostics and
+ * error status). */
+dgswe_status dgswe_member_read_state(dgswe_solver *s, int32_t member, double *w_out, dgswe_diag *d);
 
 /* Release the solver and its device memory (NULL is ignored). */
 void dgswe_destroy(dgswe_solver *s);
@@ -194,8 +239,11 @@ dgswe_status dgswe_profile_read(dgswe_solver *s, int32_t max_kernels, char *name
                                 int64_t *launches, int32_t *n_out);
 
 /* Sizes after preprocessing: out[0] = nodes, out[1] = elements,
- * out[2] = edges, out[3] = boundary edges. */
+ * out[2] = edges, out[3] = boundary edges (the sums over a batch). */
 dgswe_status dgswe_mesh_info(const dgswe_solver *s, int64_t out[4]);
+
+/* The same sizes for one member of a batch. */
+dgswe_status dgswe_member_info(const dgswe_solver *s, int32_t member, int64_t out[4]);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ def build(verbose: bool = True, jobs: int = 4) -> str:
     if any(rc):
         raise RuntimeError(f"hipcc failed: {rc}")
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

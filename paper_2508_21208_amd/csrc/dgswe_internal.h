@@ -12,19 +12,36 @@ namespace dgswe {
 
 constexpr int kMaxTide = 8;
 constexpr int kBlock = 256;
+// One chunk record: first element, element count, ring-1 offset and count,
+// ring-2 offset and count, local-edge offset and count, local-element
+// offset, member, 1 if first chunk of its member, Manning index base and
+// stride (element i of the chunk reads man[base + i * stride]), padding
+// (64 bytes, one scalar load).
+constexpr int kChunkRec = 16;
 
-// Device control block: one per solver, read by every kernel of a step.
-// Step n (counted from dgswe_set_state) reads t[n & 1] and dtmin[n & 1];
-// its last kernel writes t[(n + 1) & 1] and the CFL candidates of step n + 1
-// into dtmin[(n + 1) & 1], so no kernel writes a value another block of the
-// same kernel reads.
+// Device control block: one per member of a batch, read by every kernel of
+// a step.  Step n of the batch reads t[n & 1] and dtmin[n & 1]; its last
+// kernel writes t[(n + 1) & 1] and the CFL candidates of step n + 1 into
+// dtmin[(n + 1) & 1], so no kernel writes a value another block of the same
+// kernel reads.
 struct Ctrl {
   double t[2];                   // model time at the start of a step, per parity
   double dt_last;                // dt of the last completed step
   unsigned long long dtmin[2];   // bit pattern of the raw CFL minimum, per parity
-  long long steps;               // completed steps
+  long long steps;               // completed steps since the member's state was set
   int status;                    // first error detected on the device (0 = none)
-  int pad;
+  int pp_in;                     // the stored state still needs post-processing
+};
+
+// Forcing and bookkeeping of one member of a batch (device copy).  Members
+// occupy disjoint, contiguous ranges of the batch's element, node and chunk
+// arrays; every chunk belongs to one member.
+struct Member {
+  int e0, ne, n0, nn;            // element and node ranges
+  int chunk0, nchunk;            // chunk range
+  int holland, n_tide;
+  double tide_amp[kMaxTide], tide_omega[kMaxTide], tide_phase[kMaxTide], tide_offset;
+  double x0, y0, vx, vy, dp, pn, rmax, B, rho_air, coriolis_f, wind_factor;
 };
 
 // Mesh on the device (internal order).  Arrays read by the stage kernel are
@@ -37,15 +54,20 @@ struct DevMesh {
   const double *inr2;                   // 2 x inradius
   const double *hbv;                    // [3][ne] bathymetry at the element's vertices
   const int *el_nb;                     // [3][ne] neighbour across local edge, -1 none
-  const double *manning;                // Manning n of element e at manning[e * manning_step]
-  const float *manningf;                // the same in FP32 (mixed path)
-  int manning_step;                     // 1: per element, 0: one uniform value
   // nodes
   const double *node_x, *node_y;
+  // members of the batch
+  int nmem;
+  const Member *mem;
+  const int *fblk_off;                  // [nmem + 1] first forcing block of each member
+  // Manning n: per element [ne], then one uniform value per member [nmem];
+  // the chunk records say which applies
+  const double *man;
+  const float *manf;                    // the same in FP32 (mixed path)
   // chunks of the stage kernel (see build_chunks)
   int C, nch, nl_max, nm_max, ed_max, n2_max;
-  const int *h1_off, *h2_off, *h2;       // per-chunk ring-1 counts, ring-2 element ids
-  const int *le_off, *lo_off;            // per-chunk offsets of local edges / local elements
+  const int *chunk_rec;                  // [nch][kChunkRec] chunk records (see chunk_records)
+  const int *h2;                         // ring-2 element ids
   // chunk elements
   const double2 *eg1, *eg2;  // (d phi_10/dx, d phi_10/dy), (d phi_01/dx, d phi_01/dy), FP64 path
   const float4 *egf;         // the four gradients in FP32, mixed path
@@ -62,14 +84,10 @@ struct DevMesh {
   const float4 *le_f;          // mixed: (nx, ny, len/2, ids as bits)
 };
 
+// Parameters shared by all members of a batch.
 struct Params {
   double g, rho0, h0, cfl, dt_fixed, dt_max;
   int limiter, wetdry;
-  double manning_n;
-  int n_tide;
-  double tide_amp[kMaxTide], tide_omega[kMaxTide], tide_phase[kMaxTide], tide_offset;
-  int holland;
-  double x0, y0, vx, vy, dp, pn, rmax, B, rho_air, coriolis_f, wind_factor;
 };
 
 // Buffers of one solver touched by the step.  The state lives in three
@@ -83,7 +101,7 @@ struct DevState {
   void *wpp;       // post-processed w^n of the current step (RK base), same layout
   double *nodal;   // wind stress (x, y) pairs [nn], then pressure [nn], at the nodes
   double *partial; // [3][nblk] diagnostics partial sums
-  Ctrl *ctrl;
+  Ctrl *ctrl;      // [nmem]
 };
 
 // Host-side preprocessing result (internal element order).
@@ -98,7 +116,7 @@ struct Prep {
   std::vector<double> node_x, node_y;
   // chunks of C consecutive elements with their halos (fused stage kernel)
   int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
-  std::vector<int> h1_off, h1, h2_off, h2, le_off, le_gid, lo_off;
+  std::vector<int> ch_off, h1_off, h1, h2_off, h2, le_off, le_gid, lo_off;
   std::vector<double> le_nx, le_ny, le_hl;                // per local edge
   std::vector<uint32_t> le_ids;                            // packed ids (see DevMesh)
   std::vector<uint16_t> el_ledge;                          // [3][ne] local edge code per local edge
@@ -110,6 +128,17 @@ struct Prep {
   std::vector<double> lhb2;
   std::vector<unsigned long long> lnb;
 };
+
+// The per-chunk records of the stage kernel from a (merged) mesh and the
+// member of each chunk.
+void chunk_records(const Prep &P, const std::vector<int> &chunk_member, std::vector<int> &rec);
+
+// Concatenate the preprocessed meshes of a batch (each after build_chunks
+// with the same C) into one: element, node, chunk, local-element and
+// local-edge ranges follow each other in member order and every stored id
+// is shifted into the batch's index space.  Per-mesh element permutations
+// stay with the parts.
+void merge_meshes(const std::vector<Prep> &parts, Prep &out);
 
 // Split the (Hilbert-ordered) elements into chunks of C and build, per chunk:
 // the ring-1 halo (neighbours outside the chunk), the ring-2 halo
@@ -125,27 +154,33 @@ int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *
                  const int *bnd, const int *btype, Prep &out, std::string &err);
 
 // Kernel launchers (dgswe_kernels.hip).  Each returns hipGetLastError().
-hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int slot, int stage,
+// Holland forcing at the stage time for the nodes of every member with a
+// moving vortex (nfblk = the total number of forcing blocks).
+hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int nfblk, int slot, int stage,
                           hipStream_t st);
-// One RK stage: post-process `win` (if pp_in), edge fluxes, area integrals,
-// gather, RK combination; writes the unlimited result to `wout`.  The first
-// stage (stage 0) also writes the post-processed input to `wpp`; the second
-// stage reads it back as the RK base `wbase`.
-// `precision` is DGSWE_FP64 or DGSWE_MIXED (state buffer layout and kernels).
+// One RK stage of every member: post-process `win` (where the member's
+// control block asks for it), edge fluxes, area integrals, gather, RK
+// combination; writes the unlimited result to `wout`.  The first stage
+// (stage 0) also writes the post-processed input to `wpp`; the second stage
+// reads it back as the RK base `wbase`.  `precision` is DGSWE_FP64 or
+// DGSWE_MIXED (state buffer layout and kernels).
 hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const void *win,
-                        const void *wbase, void *wout, void *wpp, int slot, int stage, int pp_in,
-                        int want_dt, int block, int precision, hipStream_t st);
+                        const void *wbase, void *wout, void *wpp, int slot, int stage, int want_dt, int block,
+                        int precision, hipStream_t st);
 // thread-block sizes the stage kernel is built for
 constexpr int kStageBlocks[] = {256};
-// A whole state as FP64 [9][ne] (post-processed if pp), e.g. to read it back.
-hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, double *wout,
-                            int precision, hipStream_t st);
-// Reset the control block to time t and put the CFL candidates of `w`
-// into dtmin[0].
-hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w,
-                             double t, int precision, hipStream_t st);
-// mass, volume and wet count of a state (its zeta block is read)
-hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w,
+// Elements [e0, e0 + count) of a state as FP64 [9][count] (post-processed if
+// pp), e.g. to read a member back.
+hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
+                            double *wout, int precision, hipStream_t st);
+// Reset member `mb`'s control block to time t (both parities; pp_in: the
+// stored state still needs post-processing) and put the CFL candidates of
+// its elements [e0, e0 + count) in `w` into dtmin[slot].
+hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w, int mb, int e0,
+                             int count, double t, int slot, int pp_in, int precision, hipStream_t st);
+// mass, volume and wet count of elements [e0, e0 + count) of a state (its
+// zeta block is read)
+hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w, int e0, int count,
                        double *out4, hipStream_t st);
 size_t stage_lds_bytes(const DevMesh &m, int precision);
 size_t state_bytes(size_t ne, int precision);

@@ -139,9 +139,9 @@ HD bool dt_from_bits(const Params &p, unsigned long long bits, double &dt) {
 }
 HD bool step_dt(const Ctrl *c, const Params &p, int slot, double &dt) { return dt_from_bits(p, c->dtmin[slot], dt); }
 
-HD double tide_level(const Params &p, double t) {
-  double z = p.tide_offset;
-  for (int i = 0; i < p.n_tide; ++i) z += p.tide_amp[i] * cos(p.tide_omega[i] * t + p.tide_phase[i]);
+HD double tide_level(const Member &f, double t) {
+  double z = f.tide_offset;
+  for (int i = 0; i < f.n_tide; ++i) z += f.tide_amp[i] * cos(f.tide_omega[i] * t + f.tide_phase[i]);
   return z;
 }
 
@@ -207,7 +207,7 @@ HD double gb1(int l) { return l == 2 ? 1.0 : -0.5; }
 HD double ga2(int l) { return l == 2 ? -1.0 : 0.5; }
 HD double gb2(int l) { return l == 0 ? 1.5 : (l == 1 ? -1.5 : 0.0); }
 
-HD void holland(const Params &f, double x, double y, double t, double out[3]) {
+HD void holland(const Member &f, double x, double y, double t, double out[3]) {
   double cx = f.x0 + f.vx * t, cy = f.y0 + f.vy * t;
   double dx = x - cx, dy = y - cy;
   double r = sqrt(dx * dx + dy * dy);
@@ -571,19 +571,23 @@ HD Lds<QT> lds_view(const DevMesh &m, void *base) {
 }
 
 struct ChunkInfo {
-  int c, c0, cc, h1o, n1, h2o, n2, leo, ne_loc, lo;
+  int c, c0, cc, h1o, n1, h2o, n2, leo, ne_loc, lo, member, first, man_base, man_step;
   HD int nl() const { return cc + n1; }
 };
 
 HD ChunkInfo chunk_info(const DevMesh &m, int c) {
+  const int *r = m.chunk_rec + (size_t)c * kChunkRec;
   ChunkInfo k;
   k.c = c;
-  k.c0 = c * m.C;
-  k.cc = m.ne - k.c0 < m.C ? m.ne - k.c0 : m.C;
-  k.h1o = m.h1_off[c]; k.n1 = m.h1_off[c + 1] - k.h1o;
-  k.h2o = m.h2_off[c]; k.n2 = m.h2_off[c + 1] - k.h2o;
-  k.leo = m.le_off[c]; k.ne_loc = m.le_off[c + 1] - k.leo;
-  k.lo = m.lo_off[c];
+  k.c0 = r[0]; k.cc = r[1];
+  k.h1o = r[2]; k.n1 = r[3];
+  k.h2o = r[4]; k.n2 = r[5];
+  k.leo = r[6]; k.ne_loc = r[7];
+  k.lo = r[8];
+  k.member = r[9];
+  k.first = r[10];
+  k.man_base = r[11];
+  k.man_step = r[12];
   return k;
 }
 
@@ -703,8 +707,13 @@ HD void load_elem_node(const DevMesh &m, const ChunkInfo &k, int i, int node[3],
   for (int q = 0; q < 3; ++q) ledge[q] = (v.w >> (10 * q)) & 0x3FF;
 }
 
-HD double manning_of(const DevMesh &m, int e, double) { return m.manning[(size_t)e * m.manning_step]; }
-HD float manning_of(const DevMesh &m, int e, float) { return m.manningf[(size_t)e * m.manning_step]; }
+// Manning n of element i of a chunk
+HD double manning_of(const DevMesh &m, const ChunkInfo &k, int i, double) {
+  return m.man[(size_t)k.man_base + (size_t)i * k.man_step];
+}
+HD float manning_of(const DevMesh &m, const ChunkInfo &k, int i, float) {
+  return m.manf[(size_t)k.man_base + (size_t)i * k.man_step];
+}
 
 template <class QT>
 HD void store_geo_lds(const Lds<QT> &L, int i, const GeoReg<QT> &G) {
@@ -782,7 +791,6 @@ template <class QT>
 HD void load_elem_pre(const DevMesh &m, const ChunkInfo &k, int i, const CSt<QT> *wbase, ElemPre<QT> &P) {
   const size_t ne = (size_t)m.ne;
   const int e = k.c0 + i;
-  P.manning = manning_of(m, e, (QT)0);
   if (wbase) {
     for (int j = 0; j < 3; ++j) P.wbz[j] = wbase->z[j * ne + e];
     for (int j = 0; j < 6; ++j) P.wbq[j] = wbase->q[j * ne + e];
@@ -898,34 +906,48 @@ __device__ __forceinline__ int chunk_of_block(int b, int nch) {
   return -1;
 }
 
+// Forcing blocks are numbered member by member (members without a moving
+// vortex have none); block b finds its member by bisection of fblk_off.
 __global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Params p, int slot, int stage) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (s.ctrl->status) return;
+  const int b = blockIdx.x;
+  int lo = 0, hi = m.nmem;  // fblk_off[lo] <= b < fblk_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (m.fblk_off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const Member &f = m.mem[lo];
+  const Ctrl *ctl = s.ctrl + lo;
+  const int i = (b - m.fblk_off[lo]) * kBlock + threadIdx.x;
+  if (i >= f.nn || ctl->status) return;
   double dt;
-  if (!step_dt(s.ctrl, p, slot, dt)) return;
-  if (i >= m.nn) return;
+  if (!step_dt(ctl, p, slot, dt)) return;
+  const int n = f.n0 + i;
   double out[3];
-  holland(p, m.node_x[i], m.node_y[i], s.ctrl->t[slot] + (stage ? dt : 0.0), out);
-  ((double2 *)s.nodal)[i] = make_double2(out[0], out[1]);
-  s.nodal[2 * (size_t)m.nn + i] = out[2];
+  holland(f, m.node_x[n], m.node_y[n], ctl->t[slot] + (stage ? dt : 0.0), out);
+  ((double2 *)s.nodal)[n] = make_double2(out[0], out[1]);
+  s.nodal[2 * (size_t)m.nn + n] = out[2];
 }
 
 // One RK stage (STAGE 0 or 1) over one chunk per workgroup of NT lanes
 // (chunk size C <= NT, chunk + ring 1 <= 2 NT, chunk-local edges <= 2 NT).
-// The first stage also writes the post-processed w^n of its chunk to wpp,
-// the RK base that the second stage reads.
+// The chunks of all members of a batch form one grid; each workgroup reads
+// its member's forcing and control block.  The first stage also writes the
+// post-processed w^n of its chunk to wpp, the RK base that the second stage
+// reads.
 template <int NT, int WPE, class QT, int STAGE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_stage(
-    DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase, St<QT> wout, St<QT> wpp, int slot, int pp_in,
-    int want_dt) {
+    DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase, St<QT> wout, St<QT> wpp, int slot, int want_dt) {
   extern __shared__ double lds_raw[];
   __shared__ double red[NT / 64];
-  Ctrl *ctl = s.ctrl;
   const int tid = threadIdx.x;
   const size_t ne = (size_t)m.ne;
   const int c = chunk_of_block(blockIdx.x, m.nch);
   if (c < 0) return;  // the same for every lane of the block
   const ChunkInfo k = chunk_info(m, c);
+  const int mb = k.member;
+  const Member &F = m.mem[mb];
+  Ctrl *ctl = s.ctrl + mb;
   const Lds<QT> L = lds_view<QT>(m, lds_raw);
   const int nl = k.nl();
 
@@ -943,12 +965,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   int node[3];
   ElemPre<QT> pre;
   load_elem_node(m, k, cei, node, pre.ledge);
-  // Every lane reads the status word and the step's dt and time.  No lane
-  // leaves early, so the barriers stay matched even if another workgroup
-  // changes the status meanwhile; an inactive workgroup only stores nothing.
-  const int status = ctl->status;
-  const unsigned long long dtbits = ctl->dtmin[slot];
-  const double t0 = ctl->t[slot];
   // Round 2: loads that need no index.
   double h0[3], h1[3];
   uint16_t nb0[3], nb1[3];
@@ -963,6 +979,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   GeoReg<QT> geo;
   load_geo(m, k, cei, geo, pre.inr2);
   load_elem_pre<QT>(m, k, cei, STAGE ? &wbase : nullptr, pre);
+  pre.manning = manning_of(m, k, cei, (QT)0);
   // Round 3: gathers through the indices (kept after round 2 in the
   // instruction stream, so the index loads return while round 2 is issued).
 #ifdef __HIP_DEVICE_COMPILE__
@@ -974,6 +991,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   load_elem_forcing<QT>(m, s, node, pre);
   const double mz2 = win.z[g2];
   const QT mx2 = win.q[g2], my2 = win.q[3 * ne + g2];
+  // Every lane reads its member's status word, dt, time and post-processing
+  // flag (issued after the vector loads, whose addresses must not wait for
+  // these scalar loads).  No lane leaves early, so the barriers stay
+  // matched even if another workgroup changes the status meanwhile; an
+  // inactive workgroup only stores nothing.
+  const int status = ctl->status;
+  const unsigned long long dtbits = ctl->dtmin[slot];
+  const double t0 = ctl->t[slot];
+  const int pp_in = STAGE == 0 ? ctl->pp_in : 1;
+  const bool tide = F.n_tide > 0 || F.tide_offset != 0.0;
   for (int j = tid + NT; j < k.n2; j += NT) load_h2_lds<QT>(L, win, ne, nl, j, m.h2[k.h2o + j]);
   // the go/no-go decision (uniform unless the status changes while the
   // workgroup reads it)
@@ -983,7 +1010,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     if (active && tid == 0) atomicCAS(&ctl->status, 0, (int)DGSWE_E_ALLDRY);
     active = false;
   }
-  if (STAGE == 0 && active && blockIdx.x == 0 && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
+  if (STAGE == 0 && active && k.first && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
   if (a0) {
     store_state_lds<QT>(L, i0, st0);
     for (int q = 0; q < 3; ++q) L.LH[q * L.nls + i0] = h0[q];
@@ -1005,7 +1032,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   if (a1) phase_post<QT>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne);
   __syncthreads();
   const double ts = t0 + (STAGE ? dt : 0.0);
-  const double zb = (p.n_tide > 0 || p.tide_offset != 0.0) ? tide_level(p, ts) : 0.0;
+  const double zb = tide ? tide_level(F, ts) : 0.0;
   if (tid < k.ne_loc) phase_edge<QT>(p, L, zb, tid, r0);
   if (tid + NT < k.ne_loc) phase_edge<QT>(p, L, zb, tid + NT, r1);
   __syncthreads();
@@ -1017,25 +1044,27 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const double bm = block_min<NT>(cand, red);
     if (tid == 0 && bm < INFINITY) atomicMin(&ctl->dtmin[slot ^ 1], double_to_bits(bm));
   }
-  if (STAGE == 1 && active && blockIdx.x == 0 && tid == 0) {
+  if (STAGE == 1 && active && k.first && tid == 0) {
     ctl->t[slot ^ 1] = t0 + dt;
     ctl->dt_last = dt;
     ctl->steps = ctl->steps + 1;
+    ctl->pp_in = 1;  // the stored result is unlimited
   }
 }
 
-// a state (post-processed if pp) as FP64 [9][ne], for read-back
+// elements [e0, e0 + count) of a state (post-processed if pp) as FP64
+// [9][count], for read-back
 template <class QT>
-__global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, CSt<QT> win, int pp,
+__global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, CSt<QT> win, int pp, int e0, int count,
                                                       double *__restrict__ wout) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= m.ne) return;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= count) return;
   double u[9];
-  load_pp_global<QT>(m, p, win, e, pp != 0, u);
-  for (int j = 0; j < 9; ++j) wout[(size_t)j * m.ne + e] = u[j];
+  load_pp_global<QT>(m, p, win, e0 + i, pp != 0, u);
+  for (int j = 0; j < 9; ++j) wout[(size_t)j * count + i] = u[j];
 }
 
-__global__ void k_ctrl_reset(Ctrl *c, double t) {
+__global__ void k_ctrl_reset(Ctrl *c, double t, int pp_in) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->t[0] = t;
     c->t[1] = t;
@@ -1044,33 +1073,39 @@ __global__ void k_ctrl_reset(Ctrl *c, double t) {
     c->dtmin[1] = double_to_bits(INFINITY);
     c->steps = 0;
     c->status = 0;
+    c->pp_in = pp_in;
   }
 }
 
+// CFL candidates of elements [e0, e0 + count) into ctl->dtmin[slot]
 template <class QT>
-__global__ __launch_bounds__(kBlock) void k_init(DevMesh m, DevState s, Params p, CSt<QT> w) {
+__global__ __launch_bounds__(kBlock) void k_init(DevMesh m, Ctrl *ctl, Params p, CSt<QT> w, int e0, int count,
+                                                 int slot) {
   __shared__ double red[kBlock / 64];
-  const int e = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
   double cand = INFINITY;
-  if (e < m.ne) {
+  if (i < count) {
     const size_t ne = (size_t)m.ne;
+    const int e = e0 + i;
     const double h[3] = {m.hbv[e], m.hbv[ne + e], m.hbv[2 * ne + e]};
     cand = cfl_candidate(w.z[e], (double)w.q[e], (double)w.q[3 * ne + e], mean3(h), m.inr2[e], p);
   }
   const double bm = block_min<kBlock>(cand, red);
-  if (threadIdx.x == 0 && bm < INFINITY) atomicMin(&s.ctrl->dtmin[0], double_to_bits(bm));
+  if (threadIdx.x == 0 && bm < INFINITY) atomicMin(&ctl->dtmin[slot], double_to_bits(bm));
 }
 
 // Diagnostics: per-block partial sums (mass, volume, wet count), then one
 // block adds the partials in a fixed order: deterministic.  Mean depth and
 // zeta mean are unchanged by the post-processing, so the unlimited state
 // gives the same values; z is the zeta block of a state buffer.
-__global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, DevState s, Params p, const double *__restrict__ z) {
+__global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, DevState s, Params p, const double *__restrict__ z,
+                                                  int e0, int count) {
   __shared__ double sm[3][kBlock];
-  const int e = blockIdx.x * kBlock + threadIdx.x;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int e = e0 + i;
   const size_t ne = (size_t)m.ne;
   double a = 0.0, b = 0.0, c = 0.0;
-  if (e < m.ne) {
+  if (i < count) {
     const double h[3] = {m.hbv[e], m.hbv[ne + e], m.hbv[2 * ne + e]};
     const double hmean = mean3(h);
     const double z0 = z[e];
@@ -1142,15 +1177,15 @@ static CSt<QT> csplit(const void *buf, size_t ne) {
   return {(const double *)buf, (const QT *)((const double *)buf + 3 * ne)};
 }
 
-hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int slot, int stage,
+hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int nfblk, int slot, int stage,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_forcing, dim3(nblk(m.nn)), dim3(kBlock), 0, st, m, s, p, slot, stage);
+  if (nfblk > 0) hipLaunchKernelGGL(k_forcing, dim3(nfblk), dim3(kBlock), 0, st, m, s, p, slot, stage);
   return hipGetLastError();
 }
 
 template <class QT>
 static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const void *win, const void *wbase,
-                     void *wout, void *wpp, int slot, int stage, int pp_in, int want_dt, int block, hipStream_t st) {
+                     void *wout, void *wpp, int slot, int stage, int want_dt, int block, hipStream_t st) {
   const size_t ne = (size_t)m.ne;
   const size_t lds = lds_bytes<QT>(m);
   const CSt<QT> a = csplit<QT>(win, ne);
@@ -1158,8 +1193,7 @@ static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const
   const St<QT> o = split<QT>(wout, ne);
   const St<QT> q = wpp ? split<QT>(wpp, ne) : St<QT>{nullptr, nullptr};
 #define DGSWE_STAGE(NT, W, S)                                                                             \
-  hipLaunchKernelGGL((k_stage<NT, W, QT, S>), dim3(m.nch), dim3(NT), lds, st, m, s, p, a, b, o, q, slot, pp_in, \
-                     want_dt)
+  hipLaunchKernelGGL((k_stage<NT, W, QT, S>), dim3(m.nch), dim3(NT), lds, st, m, s, p, a, b, o, q, slot, want_dt)
   (void)block;  // 256 lanes (the local ids and edge codes are packed for it)
   if (stage) DGSWE_STAGE(256, 2, 1);
   else DGSWE_STAGE(256, 2, 0);
@@ -1167,42 +1201,47 @@ static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const
 }
 
 hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const void *win, const void *wbase,
-                        void *wout, void *wpp, int slot, int stage, int pp_in, int want_dt, int block, int precision,
+                        void *wout, void *wpp, int slot, int stage, int want_dt, int block, int precision,
                         hipStream_t st) {
   if (precision == DGSWE_MIXED)
-    stage_qt<float>(m, s, p, win, wbase, wout, wpp, slot, stage, pp_in, want_dt, block, st);
+    stage_qt<float>(m, s, p, win, wbase, wout, wpp, slot, stage, want_dt, block, st);
   else
-    stage_qt<double>(m, s, p, win, wbase, wout, wpp, slot, stage, pp_in, want_dt, block, st);
+    stage_qt<double>(m, s, p, win, wbase, wout, wpp, slot, stage, want_dt, block, st);
   return hipGetLastError();
 }
 
-hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, double *wout, int precision,
-                            hipStream_t st) {
+hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
+                            double *wout, int precision, hipStream_t st) {
   const size_t ne = (size_t)m.ne;
+  if (count <= 0) return hipSuccess;
   if (precision == DGSWE_MIXED)
-    hipLaunchKernelGGL(k_post_only<float>, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, p, csplit<float>(win, ne), pp,
-                       wout);
+    hipLaunchKernelGGL(k_post_only<float>, dim3(nblk(count)), dim3(kBlock), 0, st, m, p, csplit<float>(win, ne), pp,
+                       e0, count, wout);
   else
-    hipLaunchKernelGGL(k_post_only<double>, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, p, csplit<double>(win, ne),
-                       pp, wout);
+    hipLaunchKernelGGL(k_post_only<double>, dim3(nblk(count)), dim3(kBlock), 0, st, m, p, csplit<double>(win, ne),
+                       pp, e0, count, wout);
   return hipGetLastError();
 }
 
-hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w, double t,
-                             int precision, hipStream_t st) {
+hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w, int mb, int e0,
+                             int count, double t, int slot, int pp_in, int precision, hipStream_t st) {
   const size_t ne = (size_t)m.ne;
-  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, s.ctrl, t);
+  Ctrl *ctl = s.ctrl + mb;
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, ctl, t, pp_in);
+  if (count <= 0) return hipGetLastError();
   if (precision == DGSWE_MIXED)
-    hipLaunchKernelGGL(k_init<float>, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, s, p, csplit<float>(w, ne));
+    hipLaunchKernelGGL(k_init<float>, dim3(nblk(count)), dim3(kBlock), 0, st, m, ctl, p, csplit<float>(w, ne), e0,
+                       count, slot);
   else
-    hipLaunchKernelGGL(k_init<double>, dim3(nblk(m.ne)), dim3(kBlock), 0, st, m, s, p, csplit<double>(w, ne));
+    hipLaunchKernelGGL(k_init<double>, dim3(nblk(count)), dim3(kBlock), 0, st, m, ctl, p, csplit<double>(w, ne), e0,
+                       count, slot);
   return hipGetLastError();
 }
 
-hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w, double *out4,
-                       hipStream_t st) {
-  const int nb = (int)nblk(m.ne);
-  hipLaunchKernelGGL(k_diag1, dim3(nb), dim3(kBlock), 0, st, m, s, p, (const double *)w);
+hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w, int e0, int count,
+                       double *out4, hipStream_t st) {
+  const int nb = (int)nblk(count > 0 ? count : 1);
+  hipLaunchKernelGGL(k_diag1, dim3(nb), dim3(kBlock), 0, st, m, s, p, (const double *)w, e0, count);
   hipLaunchKernelGGL(k_diag2, dim3(1), dim3(kBlock), 0, st, s, nb, out4);
   return hipGetLastError();
 }

@@ -22,7 +22,9 @@ DGSWE_MIXED = 1
 
 EXPORTED = ("dgswe_default_params", "dgswe_create_mesh", "dgswe_set_state", "dgswe_set_forcing",
             "dgswe_step", "dgswe_read_state", "dgswe_destroy", "dgswe_last_error", "dgswe_profile",
-            "dgswe_profile_read", "dgswe_mesh_info")
+            "dgswe_profile_read", "dgswe_mesh_info", "dgswe_create_batch", "dgswe_member_count",
+            "dgswe_member_set_state", "dgswe_member_set_forcing", "dgswe_member_read_state",
+            "dgswe_member_info")
 
 
 class dgswe_params(C.Structure):
@@ -41,6 +43,12 @@ class dgswe_forcing(C.Structure):
                 ("x0", C.c_double), ("y0", C.c_double), ("vx", C.c_double), ("vy", C.c_double),
                 ("dp", C.c_double), ("pn", C.c_double), ("rmax", C.c_double), ("B", C.c_double),
                 ("rho_air", C.c_double), ("coriolis_f", C.c_double), ("wind_factor", C.c_double)]
+
+
+class dgswe_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("node_xy", _dp), ("node_hb", _dp), ("n_elems", C.c_int32),
+                ("tri", C.POINTER(C.c_int32)), ("n_bnd", C.c_int32), ("bnd_nodes", C.POINTER(C.c_int32)),
+                ("bnd_type", C.POINTER(C.c_int32))]
 
 
 class dgswe_diag(C.Structure):
@@ -92,6 +100,18 @@ def load_library(path: str = LIB_PATH):
     L.dgswe_profile_read.restype = C.c_int
     L.dgswe_mesh_info.argtypes = [vp, C.POINTER(C.c_int64)]
     L.dgswe_mesh_info.restype = C.c_int
+    L.dgswe_create_batch.argtypes = [C.c_int32, C.POINTER(dgswe_mesh), C.POINTER(dgswe_params), vp, C.POINTER(vp)]
+    L.dgswe_create_batch.restype = C.c_int
+    L.dgswe_member_count.argtypes = [vp]
+    L.dgswe_member_count.restype = C.c_int32
+    L.dgswe_member_set_state.argtypes = [vp, C.c_int32, C.c_double, _dp, C.c_int32]
+    L.dgswe_member_set_state.restype = C.c_int
+    L.dgswe_member_set_forcing.argtypes = [vp, C.c_int32, C.POINTER(dgswe_forcing)]
+    L.dgswe_member_set_forcing.restype = C.c_int
+    L.dgswe_member_read_state.argtypes = [vp, C.c_int32, _dp, C.POINTER(dgswe_diag)]
+    L.dgswe_member_read_state.restype = C.c_int
+    L.dgswe_member_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
+    L.dgswe_member_info.restype = C.c_int
     _lib = L
     return L
 
@@ -130,20 +150,47 @@ def dgswe_create_mesh(xy, hb, tri, bnd, bnd_type, prm: dgswe_params, hip_stream=
     return h
 
 
+def dgswe_create_batch(meshes, prm: dgswe_params, hip_stream=None):
+    """meshes: objects with xy, hb, tri, bnd, bnd_type (e.g. workloads.Mesh)."""
+    L = load_library()
+    keep = []
+    descs = (dgswe_mesh * len(meshes))()
+    ip = C.POINTER(C.c_int32)
+    for i, m in enumerate(meshes):
+        xy = np.ascontiguousarray(m.xy, dtype=np.float64)
+        hb = np.ascontiguousarray(m.hb, dtype=np.float64)
+        tri = np.ascontiguousarray(m.tri, dtype=np.int32)
+        bnd = np.ascontiguousarray(m.bnd, dtype=np.int32).reshape(-1, 2)
+        bt = np.ascontiguousarray(m.bnd_type, dtype=np.int32)
+        keep += [xy, hb, tri, bnd, bt]
+        descs[i] = dgswe_mesh(xy.shape[0], _d(xy), _d(hb), tri.shape[0], tri.ctypes.data_as(ip), bnd.shape[0],
+                              bnd.ctypes.data_as(ip), bt.ctypes.data_as(ip))
+    h = C.c_void_p()
+    st = L.dgswe_create_batch(len(meshes), descs, C.byref(prm), C.c_void_p(hip_stream) if hip_stream else None,
+                              C.byref(h))
+    if st != DGSWE_OK:
+        raise DgsweError(st, L.dgswe_last_error(None).decode())
+    return h
+
+
 def _check(h, st):
     if st != DGSWE_OK:
         raise DgsweError(st, load_library().dgswe_last_error(h).decode())
 
 
-def dgswe_set_state(h, t, w, postprocess=False):
+def dgswe_set_state(h, t, w, postprocess=False, member=None):
     w = np.ascontiguousarray(w, dtype=np.float64)
-    _check(h, load_library().dgswe_set_state(h, float(t), _d(w), int(bool(postprocess))))
+    L = load_library()
+    if member is None:
+        _check(h, L.dgswe_set_state(h, float(t), _d(w), int(bool(postprocess))))
+    else:
+        _check(h, L.dgswe_member_set_state(h, int(member), float(t), _d(w), int(bool(postprocess))))
 
 
 HOLLAND_KEYS = ("x0", "y0", "vx", "vy", "dp", "pn", "rmax", "B", "rho_air", "coriolis_f", "wind_factor")
 
 
-def dgswe_set_forcing(h, f: dict, n_elems: int | None = None, n_nodes: int | None = None):
+def dgswe_set_forcing(h, f: dict, n_elems: int | None = None, n_nodes: int | None = None, member=None):
     keep = []
 
     def arr(x, n=None):
@@ -169,16 +216,23 @@ def dgswe_set_forcing(h, f: dict, n_elems: int | None = None, n_nodes: int | Non
     fs.holland = int(f.get("holland", 0))
     for k in HOLLAND_KEYS:
         setattr(fs, k, float(f.get(k, 0.0)))
-    _check(h, load_library().dgswe_set_forcing(h, C.byref(fs)))
+    L = load_library()
+    if member is None:
+        _check(h, L.dgswe_set_forcing(h, C.byref(fs)))
+    else:
+        _check(h, L.dgswe_member_set_forcing(h, int(member), C.byref(fs)))
 
 
 def dgswe_step(h, n_steps):
     _check(h, load_library().dgswe_step(h, int(n_steps)))
 
 
-def dgswe_read_state(h, w_out=None, diag=True):
+def dgswe_read_state(h, w_out=None, diag=True, member=None):
     d = dgswe_diag()
-    st = load_library().dgswe_read_state(h, None if w_out is None else _d(w_out), C.byref(d) if diag else None)
+    L = load_library()
+    wp = None if w_out is None else _d(w_out)
+    dd = C.byref(d) if diag else None
+    st = L.dgswe_read_state(h, wp, dd) if member is None else L.dgswe_member_read_state(h, int(member), wp, dd)
     _check(h, st)
     return d
 
@@ -206,9 +260,11 @@ def dgswe_profile_read(h, max_kernels=16):
     return out
 
 
-def dgswe_mesh_info(h):
+def dgswe_mesh_info(h, member=None):
     out = (C.c_int64 * 4)()
-    _check(h, load_library().dgswe_mesh_info(h, out))
+    L = load_library()
+    st = L.dgswe_mesh_info(h, out) if member is None else L.dgswe_member_info(h, int(member), out)
+    _check(h, st)
     return dict(n_nodes=out[0], n_elems=out[1], n_edges=out[2], n_boundary=out[3])
 
 
@@ -256,6 +312,58 @@ class Solver:
 
     def info(self):
         return dgswe_mesh_info(self.h)
+
+    def close(self):
+        if self.h:
+            dgswe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several independent meshes advanced together (one stage launch for
+    all); member i is meshes[i]."""
+
+    def __init__(self, meshes, params: dict | None = None, forcings=None, hip_stream=None):
+        self.h = None
+        self.meshes = list(meshes)
+        self.h = dgswe_create_batch(self.meshes, params_from_dict(params or {}), hip_stream)
+        for i, f in enumerate(forcings or []):
+            if f:
+                self.set_forcing(i, f)
+
+    def __len__(self):
+        return len(self.meshes)
+
+    def set_forcing(self, i, f: dict):
+        m = self.meshes[i]
+        dgswe_set_forcing(self.h, f, int(m.tri.shape[0]), int(m.xy.shape[0]), member=i)
+
+    def set_state(self, i, w, t=0.0, postprocess=False):
+        ne = int(self.meshes[i].tri.shape[0])
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, ne)
+        dgswe_set_state(self.h, t, w, postprocess, member=i)
+
+    def step(self, n=1):
+        dgswe_step(self.h, n)
+
+    def state(self, i):
+        w = np.empty((3, 3, int(self.meshes[i].tri.shape[0])), dtype=np.float64)
+        dgswe_read_state(self.h, w, True, member=i)
+        return w
+
+    def diagnostics(self, i):
+        d = dgswe_read_state(self.h, None, True, member=i)
+        return dict(t=d.t, dt_last=d.dt_last, mass=d.mass, volume=d.volume, steps=d.steps,
+                    n_wet=d.n_wet, n_dry=d.n_dry)
+
+    def info(self, i=None):
+        return dgswe_mesh_info(self.h, i)
 
     def close(self):
         if self.h:

@@ -102,3 +102,21 @@ def test_mesh_validation_before_device_work():
     with pytest.raises(D.DgsweError) as ei:
         _create(m, precision=2)
     assert ei.value.status == 1
+
+
+def test_batch_validation_before_device_work():
+    m = W.rect_mesh(3, 2, 3.0, 2.0)
+    bad = W.Mesh(m.xy, m.hb, m.tri[:, [0, 2, 1]].copy(), m.bnd, m.bnd_type)
+    with pytest.raises(D.DgsweError) as ei:
+        D.dgswe_create_batch([m, bad], D.dgswe_default_params())
+    assert ei.value.status == 2 and "mesh 1" in str(ei.value)
+    with pytest.raises(D.DgsweError) as ei:
+        D.dgswe_create_batch([], D.dgswe_default_params())
+    assert ei.value.status == 1
+    with pytest.raises(D.DgsweError) as ei:
+        D.dgswe_create_batch([m, m], D.params_from_dict(dict(p=2)))
+    assert ei.value.status == 1
+    L = D.load_library()
+    assert L.dgswe_member_count(None) == 0
+    out = (C.c_int64 * 4)()
+    assert L.dgswe_member_info(None, 0, out) == 1
