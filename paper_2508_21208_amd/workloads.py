@@ -361,24 +361,31 @@ def cfg_hurricane(n_target=4_000_000, steps=1000, seed=BASE_SEED + 3) -> Workloa
 def cfg_ensemble(n_members=64, n_meshes=8, min_elems=50_000, max_elems=500_000, steps=500,
                  seed=BASE_SEED + 1000) -> list:
     """Storm-surge ensemble: n_members independent coastal solves, each with
-    its own Holland track (heading uniform in +-45 degrees about onshore,
-    speed 3-8 m/s, start 60-140 km offshore at y 150-450 km) and Manning n
-    uniform in [0.015, 0.035], M2 tide.  Mesh sizes are uniform in
-    [min_elems, max_elems]; to keep generation time bounded the members
-    share n_meshes distinct meshes (member i uses mesh i mod n_meshes)."""
+    its own Holland track (heading uniform in +-30 degrees about onshore,
+    speed 3-8 m/s, start 100-160 km offshore at y 200-400 km, like the
+    single hurricane case: a vortex starting over the shallow shelf drives
+    1 cm-deep cells through the explicit friction term's stability limit)
+    and Manning n uniform in [0.015, 0.035], M2 tide.  The step is capped at
+    0.3 s (the paper's fixed step for its hurricane run): on these coarser
+    meshes the CFL step reaches 1.8 s, at which the explicit Manning term of
+    centimetre-deep cells under hurricane winds exceeds its stability limit
+    (g n^2 |Q| dt / H^(7/3) > 2) and the state diverges, in the FP64 oracle
+    as on the GPU.  Mesh sizes are uniform in [min_elems, max_elems]; to
+    keep generation time bounded the members share n_meshes distinct meshes
+    (member i uses mesh i mod n_meshes)."""
     rng = np.random.default_rng(seed)
     sizes = rng.integers(min_elems, max_elems + 1, size=n_meshes)
     meshes = [coastal_mesh(int(n), seed + 1 + k, hmin=50.0 if n > 200_000 else 100.0) for k, n in enumerate(sizes)]
     out = []
     for i in range(n_members):
         m = meshes[i % n_meshes]
-        heading = float(rng.uniform(-0.25 * np.pi, 0.25 * np.pi))
+        heading = float(rng.uniform(-np.pi / 6.0, np.pi / 6.0))
         speed = float(rng.uniform(3.0, 8.0))
-        offshore = float(rng.uniform(60e3, 140e3))
-        y0 = float(rng.uniform(150e3, 450e3))
+        offshore = float(rng.uniform(100e3, 160e3))
+        y0 = float(rng.uniform(200e3, 400e3))
         n = float(rng.uniform(0.015, 0.035))
         f = default_forcing(manning_n=n, **m2_tide(1.0),
                             **holland_track(m, speed=speed, heading=heading, offshore=offshore, y0=y0))
-        out.append(Workload(f"ensemble_{i}_{m.n_elems}", m, coastal_initial_state(m), default_params(), f, steps,
-                            True))
+        out.append(Workload(f"ensemble_{i}_{m.n_elems}", m, coastal_initial_state(m), default_params(dt_max=0.3), f,
+                            steps, True))
     return out
