@@ -14,7 +14,10 @@
  *     (the volume term enters with a plus sign: integration by parts of
  *      (div F, v) gives -(grad v, F) on the left, i.e. +(grad v, F) on the
  *      right; the AREA algorithm also adds it)
- *   - Dubiner modal basis, p = 1 ................ Sec. 2.2, Eq. (dubiner)
+ *   - Dubiner modal basis, p = 1 and p = 2 ...... Sec. 2.2, Eq. (dubiner)
+ *     (the paper implements p = 1 and states that higher orders are
+ *      supported; p = 2 follows the same definitions with the readings
+ *      marked P2 below)
  *   - semi-discrete ODE and SSP Runge-Kutta ..... Sec. 2.2, Eq. (RKSSP)
  *   - AREA / EDGE / GATHER structure ............ Sec. 5.2, Algorithms 1-3:
  *     every edge flux is evaluated once and written into per-element,
@@ -96,6 +99,9 @@ typedef struct or_mesh {
   or_forcing frc;
   double t, dt_last;
   int64_t steps;
+  int32_t nm;       /* modes per variable: 3 (p = 1) or 6 (p = 2) */
+  int32_t nq;       /* area quadrature points per element */
+  double *jit;      /* p = 2: [ne][4] J^{-T} = [[a, b], [c, d]] (grad = J^{-T} grad_ref) */
   double *w, *w1, *wt, *dw, *slot, *nodal, *extra;
   or_source_fn src_fn;
   void *src_ctx;
@@ -282,7 +288,7 @@ void or_destroy(or_mesh *M) {
   free(M->xy); free(M->hb); free(M->tri);
   free(M->ed_el); free(M->ed_loc); free(M->ed_type); free(M->ed_n); free(M->ed_len);
   free(M->el_edge); free(M->el_nb); free(M->area); free(M->inr2); free(M->gphi); free(M->glam);
-  free(M->qxy);
+  free(M->qxy); free(M->jit);
   free(M->w); free(M->w1); free(M->wt); free(M->dw); free(M->slot); free(M->nodal); free(M->extra);
   free(M->frc.manning_elem); free(M->frc.wind_tau); free(M->frc.patm);
   free(M);
@@ -408,6 +414,7 @@ or_mesh *or_create(int32_t nn, const double *xy, const double *hb, int32_t ne, c
   M->nodal = calloc(1, sizeof(double) * 3 * (size_t)nn);
   M->extra = NULL;
   if (!M->w || !M->w1 || !M->wt || !M->dw || !M->slot || !M->nodal) { or_destroy(M); *status = OR_E_NOMEM; return NULL; }
+  M->nm = 3; M->nq = 3;
   M->prm.g = 9.81; M->prm.rho0 = 1000.0; M->prm.h0 = 0.01; M->prm.cfl = 0.2;
   M->prm.dt_fixed = 0.0; M->prm.dt_max = 0.0; M->prm.limiter = 1; M->prm.wetdry = 1;
   M->frc.pn = 101300.0;
@@ -456,17 +463,17 @@ int32_t or_set_forcing(or_mesh *M, double manning_n, const double *manning_elem,
 void or_set_extra_source(or_mesh *M, or_source_fn fn, void *ctx) {
   M->src_fn = fn; M->src_ctx = ctx;
   free(M->extra); M->extra = NULL;
-  if (fn) M->extra = calloc(1, sizeof(double) * 9 * (size_t)M->ne);
+  if (fn) M->extra = calloc(1, sizeof(double) * 3 * M->nq * (size_t)M->ne);
 }
 
 int32_t or_set_state(or_mesh *M, double t, const double *w) {
-  memcpy(M->w, w, sizeof(double) * 9 * (size_t)M->ne);
+  memcpy(M->w, w, sizeof(double) * 3 * M->nm * (size_t)M->ne);
   M->t = t; M->steps = 0; M->dt_last = 0.0;
   return OR_OK;
 }
 
 void or_get_state(const or_mesh *M, double *w, double *t, double *dt_last, int64_t *steps) {
-  if (w) memcpy(w, M->w, sizeof(double) * 9 * (size_t)M->ne);
+  if (w) memcpy(w, M->w, sizeof(double) * 3 * M->nm * (size_t)M->ne);
   if (t) *t = M->t;
   if (dt_last) *dt_last = M->dt_last;
   if (steps) *steps = M->steps;
@@ -483,7 +490,7 @@ void or_geometry(const or_mesh *M, double *area, double *inr2, int32_t *el_nb, i
   if (ed_type) memcpy(ed_type, M->ed_type, sizeof(int32_t) * M->ned);
   if (ed_len) memcpy(ed_len, M->ed_len, sizeof(double) * M->ned);
   if (ed_n) memcpy(ed_n, M->ed_n, sizeof(double) * 2 * M->ned);
-  if (qxy) memcpy(qxy, M->qxy, sizeof(double) * 6 * M->ne);
+  if (qxy) memcpy(qxy, M->qxy, sizeof(double) * 2 * M->nq * M->ne);
 }
 
 /* ------------------------------------------------------------------ */
@@ -703,11 +710,20 @@ static void element_rhs(or_mesh *M, const double *w, double t, double *dw) {
   }
 }
 
+static void edge_integrals2(or_mesh *M, const double *w, double t);
+static void element_rhs2(or_mesh *M, const double *w, double t, double *dw);
+static int32_t postprocess2(or_mesh *M, const double *wt, double *out);
+
 /* L_h(w) of Eq. (RKSSP) at time t */
 int32_t or_rhs(or_mesh *M, const double *w, double t, double *dw) {
   forcing_at_nodes(M, t);
-  edge_integrals(M, w, t);
-  element_rhs(M, w, t, dw);
+  if (M->nm == 6) {
+    edge_integrals2(M, w, t);
+    element_rhs2(M, w, t, dw);
+  } else {
+    edge_integrals(M, w, t);
+    element_rhs(M, w, t, dw);
+  }
   return OR_OK;
 }
 
@@ -735,6 +751,7 @@ static void to_vertices(double u0, double u1, double u2, double v[3]) {
  *                     (flat at Hm if rounding leaves nothing to take from);
  *   otherwise      -> unchanged. */
 int32_t or_postprocess(or_mesh *M, const double *wt, double *out) {
+  if (M->nm == 6) return postprocess2(M, wt, out);
   const int32_t ne = M->ne;
   const double h0 = M->prm.h0;
 #pragma omp parallel for schedule(static)
@@ -820,8 +837,8 @@ double or_dt_raw(const or_mesh *M, const double *w) {
 #pragma omp parallel for reduction(min : mn) schedule(static)
   for (int32_t e = 0; e < ne; ++e) {
     if (!is_wet(M, w, e)) continue;
-    double H = W(w, 0, 0, e, ne) + hb_mean(M, e);
-    double qx = W(w, 1, 0, e, ne), qy = W(w, 2, 0, e, ne);
+    double H = w[e] + hb_mean(M, e);
+    double qx = w[(size_t)M->nm * ne + e], qy = w[2 * (size_t)M->nm * ne + e];
     double lam = sqrt(qx * qx + qy * qy) / H + sqrt(g * H);
     double c = M->inr2[e] / lam;
     if (c < mn) mn = c;
@@ -849,7 +866,7 @@ static int32_t pick_dt(const or_mesh *M, const double *w, double *dt) {
  *   w^{n+1} = PP(1/2 w^n + 1/2 (w1 + dt L(w1, t^n + dt))) */
 int32_t or_step(or_mesh *M, int32_t nsteps) {
   const int32_t ne = M->ne;
-  const size_t n9 = 9 * (size_t)ne;
+  const size_t n9 = 3 * (size_t)M->nm * ne;
   for (int32_t s = 0; s < nsteps; ++s) {
     double dt;
     int32_t st = pick_dt(M, M->w, &dt);
@@ -878,8 +895,8 @@ void or_diagnostics(const or_mesh *M, const double *w, double out[4]) {
   double mass = 0.0, vol = 0.0;
   int64_t nwet = 0;
   for (int32_t e = 0; e < ne; ++e) {
-    mass += M->area[e] * W(w, 0, 0, e, ne);
-    vol += M->area[e] * (W(w, 0, 0, e, ne) + hb_mean(M, e));
+    mass += M->area[e] * w[e];
+    vol += M->area[e] * (w[e] + hb_mean(M, e));
     nwet += is_wet(M, w, e);
   }
   out[0] = mass; out[1] = vol; out[2] = (double)nwet; out[3] = (double)(ne - nwet);
@@ -894,4 +911,388 @@ void or_holland_at(const double hp[11], double x, double y, double t, double out
   f.x0 = hp[0]; f.y0 = hp[1]; f.vx = hp[2]; f.vy = hp[3]; f.dp = hp[4]; f.pn = hp[5];
   f.rmax = hp[6]; f.B = hp[7]; f.rho_air = hp[8]; f.coriolis_f = hp[9]; f.wind_factor = hp[10];
   or_holland(&f, x, y, t, out);
+}
+
+/* ------------------------------------------------------------------ */
+/* p = 2 (six modes per variable)                                       */
+/* ------------------------------------------------------------------ */
+
+/* Dubiner p = 2, order [phi_00, phi_10, phi_01, phi_20, phi_11, phi_02]:
+ * phi_ij = P_i(a) ((1-b)/2)^i P_j^{(2i+1,0)}(b), a = 2(1+xi)/(1-eta) - 1,
+ * b = eta.  With A = a (1-b)/2 = (1 + 2 xi + eta)/2 and B = (1-b)/2:
+ *   phi_20 = P_2(a) B^2 = (3 A^2 - B^2)/2,
+ *   phi_11 = A P_1^{(3,0)}(eta) = A (3 + 5 eta)/2,
+ *   phi_02 = P_2^{(1,0)}(eta) = (5 eta^2 + 2 eta - 1)/2. */
+void or_basis2(double xi, double eta, double phi[6], double dphi[6][2]) {
+  const double A = 0.5 * (1.0 + 2.0 * xi + eta), B = 0.5 * (1.0 - eta);
+  phi[0] = 1.0;
+  phi[1] = A;
+  phi[2] = 0.5 * (1.0 + 3.0 * eta);
+  phi[3] = 0.5 * (3.0 * A * A - B * B);
+  phi[4] = 0.5 * A * (3.0 + 5.0 * eta);
+  phi[5] = 0.5 * (5.0 * eta * eta + 2.0 * eta - 1.0);
+  if (dphi) {
+    dphi[0][0] = 0.0; dphi[0][1] = 0.0;
+    dphi[1][0] = 1.0; dphi[1][1] = 0.5;
+    dphi[2][0] = 0.0; dphi[2][1] = 1.5;
+    dphi[3][0] = 3.0 * A; dphi[3][1] = 0.5 * (3.0 * A + B);
+    dphi[4][0] = 0.5 * (3.0 + 5.0 * eta); dphi[4][1] = 0.25 * (3.0 + 5.0 * eta) + 2.5 * A;
+    dphi[5][0] = 0.0; dphi[5][1] = 5.0 * eta + 1.0;
+  }
+}
+
+/* P2 READING: area rule of degree 4 with 6 points (Dunavant): two orbits of
+ * barycentric points (a, b, b) with their permutations; edge rule: 4-point
+ * Gauss-Lobatto (s = -1, -1/sqrt5, 1/sqrt5, 1; weights 1/6, 5/6, 5/6, 1/6),
+ * exact to degree 5 = 2p + 1. */
+static const double D4_A1 = 0.10810301816807022736, D4_B1 = 0.44594849091596488632, D4_W1 = 0.22338158967801146570;
+static const double D4_A2 = 0.81684757298045851308, D4_B2 = 0.09157621350977074346, D4_W2 = 0.10995174365532186764;
+static double AREA2_BARY[6][3], AREA2_W[6], EDGE2_S[4], EDGE2_W[4];
+static int tables2_ready = 0;
+
+static void tables2(void) {
+  if (tables2_ready) return;
+  const double orb[2][3] = {{D4_A1, D4_B1, D4_W1}, {D4_A2, D4_B2, D4_W2}};
+  for (int o = 0; o < 2; ++o)
+    for (int r = 0; r < 3; ++r) {
+      int q = 3 * o + r;
+      for (int v = 0; v < 3; ++v) AREA2_BARY[q][v] = (v == r) ? orb[o][0] : orb[o][1];
+      AREA2_W[q] = orb[o][2];
+    }
+  const double r5 = 1.0 / sqrt(5.0);
+  EDGE2_S[0] = -1.0; EDGE2_S[1] = -r5; EDGE2_S[2] = r5; EDGE2_S[3] = 1.0;
+  EDGE2_W[0] = 1.0 / 6.0; EDGE2_W[1] = 5.0 / 6.0; EDGE2_W[2] = 5.0 / 6.0; EDGE2_W[3] = 1.0 / 6.0;
+  tables2_ready = 1;
+}
+
+void or_area_rule2(double bary[18], double wfrac[6]) {
+  tables2();
+  for (int q = 0; q < 6; ++q) {
+    for (int v = 0; v < 3; ++v) bary[q * 3 + v] = AREA2_BARY[q][v];
+    wfrac[q] = AREA2_W[q];
+  }
+}
+
+void or_edge_rule2(double s[4], double w[4]) {
+  tables2();
+  for (int g = 0; g < 4; ++g) { s[g] = EDGE2_S[g]; w[g] = EDGE2_W[g]; }
+}
+
+/* diagonal of the physical mass matrix divided by the area: the reference
+ * norms 2 / ((2i+1)(i+j+1)) over the reference area 2 */
+static const double MU2[6] = {1.0, 1.0 / 6.0, 1.0 / 2.0, 1.0 / 15.0, 1.0 / 9.0, 1.0 / 3.0};
+
+void or_mass2(double mu[6]) { for (int k = 0; k < 6; ++k) mu[k] = MU2[k]; }
+
+static void edge_basis2(int l, double s, double phi[6]) {
+  static const double V[3][2] = {{-1.0, -1.0}, {1.0, -1.0}, {-1.0, 1.0}};
+  int a = (l + 1) % 3, b = (l + 2) % 3;
+  double xi = V[a][0] * 0.5 * (1.0 - s) + V[b][0] * 0.5 * (1.0 + s);
+  double eta = V[a][1] * 0.5 * (1.0 - s) + V[b][1] * 0.5 * (1.0 + s);
+  or_basis2(xi, eta, phi, NULL);
+}
+
+#define W6(w, m, k, e, ne) (w)[((size_t)((m) * 6 + (k))) * (ne) + (e)]
+
+static void eval_state2(const double *w, int32_t e, int32_t ne, const double phi[6], double out[3]) {
+  for (int m = 0; m < 3; ++m) {
+    double s = 0.0;
+    for (int k = 0; k < 6; ++k) s += W6(w, m, k, e, ne) * phi[k];
+    out[m] = s;
+  }
+}
+
+/* switch a mesh to p = 2 (before its state is set); the state becomes
+ * [3][6][ne] and the area quadrature has 6 points per element */
+int32_t or_set_order(or_mesh *M, int32_t p) {
+  if (p != 1 && p != 2) return OR_E_INVALID;
+  const int32_t ne = M->ne;
+  int32_t nm = p == 2 ? 6 : 3, nq = p == 2 ? 6 : 3;
+  tables2();
+  size_t sw = sizeof(double) * 3 * (size_t)nm * ne;
+  free(M->w); free(M->w1); free(M->wt); free(M->dw); free(M->slot); free(M->qxy); free(M->jit); free(M->extra);
+  M->extra = NULL; M->src_fn = NULL;
+  M->w = calloc(1, sw); M->w1 = calloc(1, sw); M->wt = calloc(1, sw); M->dw = calloc(1, sw);
+  M->slot = calloc(1, sizeof(double) * 9 * (size_t)nm * ne);
+  M->qxy = malloc(sizeof(double) * 2 * (size_t)nq * ne);
+  M->jit = malloc(sizeof(double) * 4 * (size_t)ne);
+  if (!M->w || !M->w1 || !M->wt || !M->dw || !M->slot || !M->qxy || !M->jit) return OR_E_NOMEM;
+  M->nm = nm; M->nq = nq;
+  for (int32_t e = 0; e < ne; ++e) {
+    const int32_t *v = M->tri + 3 * e;
+    double x1 = M->xy[2 * v[0]], y1 = M->xy[2 * v[0] + 1];
+    double x2 = M->xy[2 * v[1]], y2 = M->xy[2 * v[1] + 1];
+    double x3 = M->xy[2 * v[2]], y3 = M->xy[2 * v[2] + 1];
+    double J11 = 0.5 * (x2 - x1), J12 = 0.5 * (x3 - x1), J21 = 0.5 * (y2 - y1), J22 = 0.5 * (y3 - y1);
+    double det = J11 * J22 - J12 * J21;
+    /* J^{-T} = 1/det [[J22, -J21], [-J12, J11]] */
+    M->jit[4 * e] = J22 / det; M->jit[4 * e + 1] = -J21 / det;
+    M->jit[4 * e + 2] = -J12 / det; M->jit[4 * e + 3] = J11 / det;
+    for (int q = 0; q < nq; ++q) {
+      const double *L = p == 2 ? AREA2_BARY[q] : AREA_BARY[q];
+      M->qxy[2 * ((size_t)nq * e + q)] = L[0] * x1 + L[1] * x2 + L[2] * x3;
+      M->qxy[2 * ((size_t)nq * e + q) + 1] = L[0] * y1 + L[1] * y2 + L[2] * y3;
+    }
+  }
+  return OR_OK;
+}
+
+/* EDGE for p = 2: as edge_integrals with the 4-point rule and the six-mode
+ * traces; slot[e][l][k][m] (54 values per element) */
+static void edge_integrals2(or_mesh *M, const double *w, double t) {
+  const double g = M->prm.g, h0 = M->prm.h0;
+  const int32_t ne = M->ne, ned = M->ned;
+  const double zb = tide_level(&M->frc, t);
+#pragma omp parallel for schedule(static)
+  for (int32_t d = 0; d < ned; ++d) {
+    int32_t ep = M->ed_el[2 * d], em = M->ed_el[2 * d + 1];
+    int lp = M->ed_loc[2 * d], lm = M->ed_loc[2 * d + 1];
+    int type = M->ed_type[d];
+    double nx = M->ed_n[2 * d], ny = M->ed_n[2 * d + 1], len = M->ed_len[d];
+    int32_t na = M->tri[3 * ep + (lp + 1) % 3], nb = M->tri[3 * ep + (lp + 2) % 3];
+    double Fp[4][3], Fm[4][3], php[4][6], phm[4][6], wp[4][3], wm[4][3], hbq[4];
+    int wetp = is_wet(M, w, ep), wetm = 0;
+    for (int gq = 0; gq < 4; ++gq) {
+      double s = EDGE2_S[gq];
+      edge_basis2(lp, s, php[gq]);
+      eval_state2(w, ep, ne, php[gq], wp[gq]);
+      hbq[gq] = M->hb[na] * 0.5 * (1.0 - s) + M->hb[nb] * 0.5 * (1.0 + s);
+      if (type == 0) {
+        edge_basis2(lm, -s, phm[gq]);
+        eval_state2(w, em, ne, phm[gq], wm[gq]);
+      } else {
+        wm[gq][0] = zb; wm[gq][1] = wp[gq][1]; wm[gq][2] = wp[gq][2];
+      }
+    }
+    if (type == 0) wetm = is_wet(M, w, em);
+    else if (type == BC_OCEAN) wetm = M->prm.wetdry ? (zb + 0.5 * (M->hb[na] + M->hb[nb]) > h0) : 1;
+    if (type == BC_LAND) {
+      for (int gq = 0; gq < 4; ++gq) {
+        or_wall(g, wp[gq], hbq[gq], nx, ny, wetp, Fp[gq]);
+        for (int m = 0; m < 3; ++m) Fm[gq][m] = 0.0;
+      }
+    } else if (!wetp && !wetm) {
+      for (int gq = 0; gq < 4; ++gq)
+        for (int m = 0; m < 3; ++m) { Fp[gq][m] = 0.0; Fm[gq][m] = 0.0; }
+    } else {
+      double F[4][3];
+      for (int gq = 0; gq < 4; ++gq) or_llf(g, wp[gq], wm[gq], hbq[gq], nx, ny, wetp, wetm, F[gq]);
+      int flood = 1;
+      if (!(wetp && wetm)) {
+        double mflux = 0.0;
+        for (int gq = 0; gq < 4; ++gq) mflux += EDGE2_W[gq] * F[gq][0];
+        flood = wetp ? (mflux > 0.0) : (mflux < 0.0);
+      }
+      if (flood) {
+        for (int gq = 0; gq < 4; ++gq)
+          for (int m = 0; m < 3; ++m) { Fp[gq][m] = F[gq][m]; Fm[gq][m] = -F[gq][m]; }
+      } else if (wetp) {
+        for (int gq = 0; gq < 4; ++gq) {
+          or_wall(g, wp[gq], hbq[gq], nx, ny, 1, Fp[gq]);
+          for (int m = 0; m < 3; ++m) Fm[gq][m] = 0.0;
+        }
+      } else {
+        for (int gq = 0; gq < 4; ++gq) {
+          or_wall(g, wm[gq], hbq[gq], -nx, -ny, 1, Fm[gq]);
+          for (int m = 0; m < 3; ++m) Fp[gq][m] = 0.0;
+        }
+      }
+    }
+    double *sp = M->slot + 54 * (size_t)ep + 18 * lp;
+    for (int k = 0; k < 6; ++k)
+      for (int m = 0; m < 3; ++m) {
+        double s = 0.0;
+        for (int gq = 0; gq < 4; ++gq) s += 0.5 * len * EDGE2_W[gq] * php[gq][k] * Fp[gq][m];
+        sp[3 * k + m] = s;
+      }
+    if (type == 0) {
+      double *sm = M->slot + 54 * (size_t)em + 18 * lm;
+      for (int k = 0; k < 6; ++k)
+        for (int m = 0; m < 3; ++m) {
+          double s = 0.0;
+          for (int gq = 0; gq < 4; ++gq) s += 0.5 * len * EDGE2_W[gq] * phm[gq][k] * Fm[gq][m];
+          sm[3 * k + m] = s;
+        }
+    }
+  }
+}
+
+/* AREA + GATHER for p = 2: 6-point rule; the basis gradients vary over the
+ * element: grad phi_k(x_q) = J^{-T} grad_ref phi_k(xi_q, eta_q) */
+static void element_rhs2(or_mesh *M, const double *w, double t, double *dw) {
+  const double g = M->prm.g, h0 = M->prm.h0, rho0 = M->prm.rho0;
+  const int32_t ne = M->ne;
+  if (M->src_fn) M->src_fn(t, 6 * ne, M->qxy, M->extra, M->src_ctx);
+#pragma omp parallel for schedule(static)
+  for (int32_t e = 0; e < ne; ++e) {
+    const int32_t *v = M->tri + 3 * e;
+    double A = M->area[e];
+    const double *jt = M->jit + 4 * e;
+    const double *gl = M->glam + 6 * e;
+    double hbv[3], tx[3], ty[3], pa[3];
+    for (int i = 0; i < 3; ++i) {
+      hbv[i] = M->hb[v[i]];
+      tx[i] = M->nodal[3 * v[i]]; ty[i] = M->nodal[3 * v[i] + 1]; pa[i] = M->nodal[3 * v[i] + 2];
+    }
+    double dhx = 0.0, dhy = 0.0, dpx = 0.0, dpy = 0.0;
+    for (int i = 1; i < 3; ++i) {
+      dhx += (hbv[i] - hbv[0]) * gl[2 * i]; dhy += (hbv[i] - hbv[0]) * gl[2 * i + 1];
+      dpx += (pa[i] - pa[0]) * gl[2 * i]; dpy += (pa[i] - pa[0]) * gl[2 * i + 1];
+    }
+    double n = M->frc.manning_elem ? M->frc.manning_elem[e] : M->frc.manning_n;
+    int wet = is_wet(M, w, e);
+    double R[3][6];
+    for (int m = 0; m < 3; ++m)
+      for (int k = 0; k < 6; ++k) R[m][k] = 0.0;
+    for (int q = 0; q < 6; ++q) {
+      double xi, eta, phq[6], dref[6][2], wq[3];
+      ref_point(AREA2_BARY[q], &xi, &eta);
+      or_basis2(xi, eta, phq, dref);
+      eval_state2(w, e, ne, phq, wq);
+      double hq = AREA2_BARY[q][0] * hbv[0] + AREA2_BARY[q][1] * hbv[1] + AREA2_BARY[q][2] * hbv[2];
+      double wA = AREA2_W[q] * A;
+      /* volume term */
+      double F[3][2];
+      phys_flux(g, wq[0], wq[1], wq[2], hq, wet, F);
+      for (int k = 1; k < 6; ++k) {
+        double gx = jt[0] * dref[k][0] + jt[1] * dref[k][1];
+        double gy = jt[2] * dref[k][0] + jt[3] * dref[k][1];
+        for (int m = 0; m < 3; ++m) R[m][k] += wA * (gx * F[m][0] + gy * F[m][1]);
+      }
+      /* source term */
+      double ze = wq[0], qx = wq[1], qy = wq[2];
+      double H = ze + hq;
+      double S[3] = {0.0, 0.0, 0.0};
+      if (wet) {
+        double Hf = fmax(H, h0);
+        double qm = sqrt(qx * qx + qy * qy);
+        double fr = g * n * n * qm / pow(Hf, 7.0 / 3.0);
+        double txq = AREA2_BARY[q][0] * tx[0] + AREA2_BARY[q][1] * tx[1] + AREA2_BARY[q][2] * tx[2];
+        double tyq = AREA2_BARY[q][0] * ty[0] + AREA2_BARY[q][1] * ty[1] + AREA2_BARY[q][2] * ty[2];
+        S[1] = g * ze * dhx - fr * qx + txq / rho0 - H / rho0 * dpx;
+        S[2] = g * ze * dhy - fr * qy + tyq / rho0 - H / rho0 * dpy;
+      }
+      if (M->extra)
+        for (int m = 0; m < 3; ++m) S[m] += M->extra[(size_t)m * 6 * ne + 6 * (size_t)e + q];
+      for (int m = 0; m < 3; ++m)
+        for (int k = 0; k < 6; ++k) R[m][k] += wA * phq[k] * S[m];
+    }
+    const double *sl = M->slot + 54 * (size_t)e;
+    for (int l = 0; l < 3; ++l)
+      for (int k = 0; k < 6; ++k)
+        for (int m = 0; m < 3; ++m) R[m][k] -= sl[18 * l + 3 * k + m];
+    if (!wet)
+      for (int k = 0; k < 6; ++k) { R[1][k] = 0.0; R[2][k] = 0.0; }
+    for (int m = 0; m < 3; ++m)
+      for (int k = 0; k < 6; ++k) W6(dw, m, k, e, ne) = R[m][k] / (A * MU2[k]);
+  }
+}
+
+/* values of a six-mode field at the vertices (0..2) and the edge midpoints
+ * (3..5: local edges 0, 1, 2) */
+static void to_points2(const double u[6], double v[6]) {
+  static const double P[6][2] = {{-1.0, -1.0}, {1.0, -1.0}, {-1.0, 1.0}, {0.0, 0.0}, {-1.0, 0.0}, {0.0, -1.0}};
+  for (int i = 0; i < 6; ++i) {
+    double phi[6];
+    or_basis2(P[i][0], P[i][1], phi, NULL);
+    double s = 0.0;
+    for (int k = 0; k < 6; ++k) s += u[k] * phi[k];
+    v[i] = s;
+  }
+}
+
+/* Post-processing for p = 2 (P2 READINGS), both leave the means unchanged.
+ * Limiter, per variable (troubled-cell, hierarchical): with [lo, hi] the
+ * range of the element and face-neighbour means and alpha the p = 1
+ * Barth-Jespersen factor of the linear part (modes 0-2), the element is
+ * troubled when alpha < 1 or the full field leaves [lo, hi] at a vertex or
+ * an edge midpoint; a troubled element drops its quadratic modes and scales
+ * its linear modes by alpha, i.e. it is limited as a p = 1 element.
+ * Wet/dry: a dry element (mean depth <= H0) is flat at its mean depth with
+ * zero momentum; an element whose depth falls below H0 at a vertex or an
+ * edge midpoint drops the quadratic modes of all variables and gets the
+ * p = 1 vertex correction of its linear part; otherwise it is unchanged. */
+static int32_t postprocess2(or_mesh *M, const double *wt, double *out) {
+  const int32_t ne = M->ne;
+  const double h0 = M->prm.h0;
+#pragma omp parallel for schedule(static)
+  for (int32_t e = 0; e < ne; ++e) {
+    double u[3][6];
+    for (int m = 0; m < 3; ++m)
+      for (int k = 0; k < 6; ++k) u[m][k] = W6(wt, m, k, e, ne);
+    if (M->prm.limiter) {
+      for (int m = 0; m < 3; ++m) {
+        double mean = u[m][0], hi = mean, lo = mean;
+        for (int l = 0; l < 3; ++l) {
+          int32_t f = M->el_nb[3 * e + l];
+          if (f < 0) continue;
+          double nbm = W6(wt, m, 0, f, ne);
+          if (nbm > hi) hi = nbm;
+          if (nbm < lo) lo = nbm;
+        }
+        double vv[3];
+        to_vertices(u[m][0], u[m][1], u[m][2], vv);
+        double alpha = 1.0;
+        for (int i = 0; i < 3; ++i) {
+          double a = 1.0;
+          if (vv[i] > mean) a = fmin(1.0, (hi - mean) / (vv[i] - mean));
+          else if (vv[i] < mean) a = fmin(1.0, (lo - mean) / (vv[i] - mean));
+          if (a < alpha) alpha = a;
+        }
+        double pv[6];
+        to_points2(u[m], pv);
+        int troubled = alpha < 1.0;
+        for (int i = 0; i < 6; ++i)
+          if (pv[i] > hi || pv[i] < lo) troubled = 1;
+        if (troubled) {
+          u[m][1] *= alpha; u[m][2] *= alpha;
+          u[m][3] = 0.0; u[m][4] = 0.0; u[m][5] = 0.0;
+        }
+      }
+    }
+    if (M->prm.wetdry) {
+      const int32_t *vt = M->tri + 3 * e;
+      double hbv[3] = {M->hb[vt[0]], M->hb[vt[1]], M->hb[vt[2]]};
+      double hbp[6] = {hbv[0], hbv[1], hbv[2], 0.5 * (hbv[1] + hbv[2]), 0.5 * (hbv[2] + hbv[0]),
+                       0.5 * (hbv[0] + hbv[1])};
+      double Hm = u[0][0] + hb_mean(M, e);
+      double zp[6];
+      to_points2(u[0], zp);
+      int reduce = Hm <= h0;
+      for (int i = 0; i < 6 && !reduce; ++i)
+        if (zp[i] + hbp[i] < h0) reduce = 1;
+      if (reduce) {
+        for (int m = 0; m < 3; ++m) { u[m][3] = 0.0; u[m][4] = 0.0; u[m][5] = 0.0; }
+        double zv[3], Hv[3];
+        to_vertices(u[0][0], u[0][1], u[0][2], zv);
+        for (int i = 0; i < 3; ++i) Hv[i] = zv[i] + hbv[i];
+        int changed = 0;
+        if (Hm <= h0) {
+          for (int i = 0; i < 3; ++i) Hv[i] = Hm;
+          for (int k = 0; k < 6; ++k) { u[1][k] = 0.0; u[2][k] = 0.0; }
+          changed = 1;
+        } else if (fmin(Hv[0], fmin(Hv[1], Hv[2])) < h0) {
+          double D = 0.0, S = 0.0;
+          for (int i = 0; i < 3; ++i) {
+            if (Hv[i] < h0) D += h0 - Hv[i];
+            else S += Hv[i] - h0;
+          }
+          if (S > D) {
+            for (int i = 0; i < 3; ++i) Hv[i] = (Hv[i] < h0) ? h0 : Hv[i] - D * (Hv[i] - h0) / S;
+          } else {
+            for (int i = 0; i < 3; ++i) Hv[i] = Hm;
+          }
+          changed = 1;
+        }
+        if (changed) {
+          for (int i = 0; i < 3; ++i) zv[i] = Hv[i] - hbv[i];
+          u[0][1] = 0.5 * (zv[1] - zv[0]);
+          u[0][2] = 0.5 * (zv[2] - u[0][0]);
+        }
+      }
+    }
+    for (int m = 0; m < 3; ++m)
+      for (int k = 0; k < 6; ++k) W6(out, m, k, e, ne) = u[m][k];
+  }
+  return OR_OK;
 }

@@ -70,6 +70,12 @@ def load_oracle():
     L.or_llf.argtypes = [C.c_double, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int32,
                          C.c_int32, _dp]
     L.or_wall.argtypes = [C.c_double, _dp, C.c_double, C.c_double, C.c_double, C.c_int32, _dp]
+    L.or_set_order.argtypes = [C.c_void_p, C.c_int32]
+    L.or_set_order.restype = C.c_int32
+    L.or_basis2.argtypes = [C.c_double, C.c_double, _dp, _dp]
+    L.or_area_rule2.argtypes = [_dp, _dp]
+    L.or_edge_rule2.argtypes = [_dp, _dp]
+    L.or_mass2.argtypes = [_dp]
     _lib = L
     return L
 
@@ -92,7 +98,9 @@ HOLLAND_KEYS = ("x0", "y0", "vx", "vy", "dp", "pn", "rmax", "B", "rho_air", "cor
 class Oracle:
     """One mesh + state, stepped by the plain C oracle."""
 
-    def __init__(self, mesh, params: dict | None = None, forcing: dict | None = None):
+    def __init__(self, mesh, params: dict | None = None, forcing: dict | None = None, order: int = 1):
+        """order: polynomial degree p (1 or 2); the state is (3, nm, ne) with
+        nm = 3 (p = 1) or 6 (p = 2) modes per variable."""
         L = load_oracle()
         self.L = L
         self.mesh = mesh
@@ -114,6 +122,12 @@ class Oracle:
         info = np.zeros(4, dtype=np.int32)
         L.or_info(h, _i(info))
         self.ned = int(info[2])
+        self.order = int(order)
+        self.nm = 6 if self.order == 2 else 3
+        if self.order != 1:
+            r = L.or_set_order(h, self.order)
+            if r:
+                raise OracleError(f"or_set_order: {r}")
         if params:
             self.set_params(params)
         if forcing:
@@ -168,13 +182,13 @@ class Oracle:
     def set_state(self, w, t=0.0, postprocess=False):
         """postprocess=True applies the stage post-processing (limiter, then
         wet/dry) once to `w` before it becomes the state."""
-        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, self.ne)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, self.nm, self.ne)
         if postprocess:
             w = self.postprocess(w)
         self.L.or_set_state(self.h, float(t), _d(w))
 
     def state(self):
-        w = np.empty((3, 3, self.ne), dtype=np.float64)
+        w = np.empty((3, self.nm, self.ne), dtype=np.float64)
         t = C.c_double(0); dtl = C.c_double(0); s = C.c_int64(0)
         self.L.or_get_state(self.h, _d(w), C.byref(t), C.byref(dtl), C.byref(s))
         self.t, self.dt_last, self.steps = t.value, dtl.value, s.value
@@ -186,25 +200,25 @@ class Oracle:
             raise OracleError(f"or_step: status {r}")
 
     def rhs(self, w, t=0.0):
-        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, self.ne)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, self.nm, self.ne)
         dw = np.empty_like(w)
         self.L.or_rhs(self.h, _d(w), float(t), _d(dw))
         return dw
 
     def postprocess(self, w):
-        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, self.ne)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, self.nm, self.ne)
         out = np.empty_like(w)
         self.L.or_postprocess(self.h, _d(w), _d(out))
         return out
 
     def dt_raw(self, w):
-        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, self.ne)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, self.nm, self.ne)
         return float(self.L.or_dt_raw(self.h, _d(w)))
 
     def diagnostics(self, w=None):
         if w is None:
             w = self.state()
-        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, self.ne)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, self.nm, self.ne)
         out = np.zeros(4)
         self.L.or_diagnostics(self.h, _d(w), _d(out))
         return dict(mass=out[0], volume=out[1], n_wet=int(out[2]), n_dry=int(out[3]))
@@ -213,7 +227,7 @@ class Oracle:
         ne, ned = self.ne, self.ned
         area = np.empty(ne); inr2 = np.empty(ne); nb = np.empty((ne, 3), np.int32)
         ed_el = np.empty((ned, 2), np.int32); ed_type = np.empty(ned, np.int32)
-        ed_len = np.empty(ned); ed_n = np.empty((ned, 2)); qxy = np.empty((ne, 3, 2))
+        ed_len = np.empty(ned); ed_n = np.empty((ned, 2)); qxy = np.empty((ne, 6 if self.order == 2 else 3, 2))
         self.L.or_geometry(self.h, _d(area), _d(inr2), _i(nb), _i(ed_el), _i(ed_type), _d(ed_len),
                            _d(ed_n), _d(qxy))
         return dict(area=area, inr2=inr2, el_nb=nb, ed_el=ed_el, ed_type=ed_type, ed_len=ed_len,
@@ -264,3 +278,32 @@ def holland(params: dict, x, y, t=0.0):
     out = np.zeros(3)
     L.or_holland_at(_d(hp), float(x), float(y), float(t), _d(out))
     return out
+
+
+def basis2(xi, eta):
+    """p = 2 Dubiner basis values (6,) and reference gradients (6, 2)."""
+    L = load_oracle()
+    phi = np.zeros(6); dphi = np.zeros(12)
+    L.or_basis2(float(xi), float(eta), _d(phi), _d(dphi))
+    return phi, dphi.reshape(6, 2)
+
+
+def area_rule2():
+    L = load_oracle()
+    b = np.zeros(18); w = np.zeros(6)
+    L.or_area_rule2(_d(b), _d(w))
+    return b.reshape(6, 3), w
+
+
+def edge_rule2():
+    L = load_oracle()
+    s = np.zeros(4); w = np.zeros(4)
+    L.or_edge_rule2(_d(s), _d(w))
+    return s, w
+
+
+def mass2():
+    L = load_oracle()
+    mu = np.zeros(6)
+    L.or_mass2(_d(mu))
+    return mu
