@@ -18,8 +18,8 @@ using namespace dgswe;
 namespace {
 thread_local std::string g_create_error = "no error";
 
-enum KernelId { K_FORCING = 0, K_STAGE, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage"};
+enum KernelId { K_FORCING = 0, K_STAGE, K_PP2, K_RHS2, K_COUNT };
+const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage", "k_pp2", "k_rhs2"};
 
 // Host view of one member of a batch.
 struct MemberHost {
@@ -50,11 +50,13 @@ struct dgswe_solver {
   DevMesh m{};
   DevState s{};
   double *d_diag = nullptr;
-  double *rb = nullptr;         // FP64 [9][largest member] read-back buffer
+  double *rb = nullptr;         // FP64 [3 nm][largest member] read-back buffer
   long long steps_enq = 0;
   int block = 256;              // workgroup size of the stage kernel
   int cur = 0;                  // buffer holding w^n
   int precision = DGSWE_FP64;
+  int order = 1;                // polynomial degree p
+  int nm = 3;                   // modes per variable
   std::string err = "no error";
   std::vector<double> stage_buf;
   std::vector<unsigned char> stage_raw;
@@ -63,8 +65,8 @@ struct dgswe_solver {
   struct Rec { int k; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
-  double prof_ms[K_COUNT] = {0, 0};
-  long long prof_n[K_COUNT] = {0, 0};
+  double prof_ms[K_COUNT] = {};
+  long long prof_n[K_COUNT] = {};
 };
 
 namespace {
@@ -112,7 +114,7 @@ void free_all(dgswe_solver *S) {
 bool validate_params(const dgswe_params *p, std::string &msg) {
   // (shared by every member of a batch)
   if (!p) { msg = "params is NULL"; return false; }
-  if (p->p != 1) { msg = "only p = 1 is supported"; return false; }
+  if (p->p != 1 && p->p != 2) { msg = "p must be 1 or 2"; return false; }
   if (p->precision != DGSWE_FP64 && p->precision != DGSWE_MIXED) {
     msg = "precision must be DGSWE_FP64 or DGSWE_MIXED";
     return false;
@@ -218,7 +220,8 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
                               parts[i], msgs[i]);
         if (rcs[i] != DGSWE_OK) continue;
         build_chunks(parts[i], chunk);
-        if (parts[i].nl_max > 2 * block || parts[i].ed_max > 2 * block) {
+        // (the p = 2 kernels use only the chunk ranges, not the halos)
+        if (prm->p == 1 && (parts[i].nl_max > 2 * block || parts[i].ed_max > 2 * block)) {
           rcs[i] = DGSWE_E_MESH;
           msgs[i] = "element chunks have halos too large for the stage kernel";
         }
@@ -236,6 +239,7 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
     }
   Prep P;
   merge_meshes(parts, P);
+  if (prm->p == 2) p2_records(P);
 
   dgswe_solver *S = new (std::nothrow) dgswe_solver();
   if (!S) return fail(nullptr, DGSWE_E_NOMEM, "host allocation failed");
@@ -250,6 +254,8 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
   }
   S->uprm = *prm;
   S->precision = prm->precision;
+  S->order = prm->p;
+  S->nm = prm->p == 2 ? 6 : 3;
   S->block = block;
   const bool mixed = S->precision == DGSWE_MIXED;
   S->nn = P.nn; S->ne = P.ne; S->ned = P.ned; S->nbnd = P.nbnd;
@@ -309,20 +315,28 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
     chk(upload(S, &m.eg1, P.eg1)); chk(upload(S, &m.eg2, P.eg2));
     chk(upload(S, &m.le_a, P.le_a)); chk(upload(S, &m.le_b, P.le_b));
   }
+  m.e2edge = nullptr;
+  m.ed2a = m.ed2b = nullptr;
+  m.hmean = nullptr;
+  if (S->order == 2) {
+    chk(upload(S, &m.e2edge, P.el_edge));
+    chk(upload(S, &m.ed2a, P.ed2a)); chk(upload(S, &m.ed2b, P.ed2b));
+    chk(upload(S, &m.hmean, P.hmean));
+  }
   m.nmem = n_members;
   chk(dev_alloc(S, &S->d_mem, (size_t)n_members));
   chk(dev_alloc(S, &S->d_fblk_off, (size_t)n_members + 1));
   m.mem = S->d_mem;
   m.fblk_off = S->d_fblk_off;
   const size_t lds = stage_lds_bytes(m, S->precision);
-  if (lds > 80 * 1024) {
+  if (S->order == 1 && lds > 80 * 1024) {
     free_all(S);
     delete S;
     return fail(nullptr, DGSWE_E_MESH, "element chunks have halos too large for the LDS (" +
                                            std::to_string(lds) + " bytes)");
   }
   DevState &st = S->s;
-  const size_t sb = state_bytes(ne, S->precision);
+  const size_t sb = state_bytes(ne, S->precision, S->order);
   for (int b = 0; b < 3; ++b) {
     unsigned char *q = nullptr;
     chk(dev_alloc(S, &q, sb));
@@ -333,7 +347,7 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
     chk(dev_alloc(S, &q, sb));
     st.wpp = q;
   }
-  chk(dev_alloc(S, &S->rb, 9 * (size_t)big));
+  chk(dev_alloc(S, &S->rb, 3 * (size_t)S->nm * (size_t)big));
   chk(dev_alloc(S, &st.nodal, 3 * nn)); chk(dev_alloc(S, &st.partial, 3 * (size_t)diag_blocks(big)));
   chk(dev_alloc(S, &st.ctrl, (size_t)n_members)); chk(dev_alloc(S, &S->d_diag, 4));
   if (!ok) {
@@ -348,7 +362,7 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
   chk(hipMemsetAsync(S->d_manf, 0, (ne + (size_t)n_members) * sizeof(float), S->stream));
   for (int32_t i = 0; i < n_members; ++i) {
     chk(launch_init_state(m, st, pp, st.buf[0], i, S->mem[i].e0, S->mem[i].ne, 0.0, 0, 0, S->precision,
-                          S->stream));
+                          S->order, S->stream));
   }
   chk(hipStreamSynchronize(S->stream));
   if (ok && sync_members(S) != DGSWE_OK) ok = false;
@@ -369,32 +383,32 @@ dgswe_status set_state_impl(dgswe_solver *S, int32_t member, double t, const dou
   if (!std::isfinite(t)) return fail(S, DGSWE_E_INVALID, "time is not finite");
   MemberHost &h = S->mh[member];
   const Member &f = S->mem[member];
-  const size_t ne = (size_t)h.ne, NE = (size_t)S->ne;
+  const size_t ne = (size_t)h.ne, NE = (size_t)S->ne, nm = (size_t)S->nm;
   const bool mixed = S->precision == DGSWE_MIXED;
   // member-order image: zeta modes FP64, momentum modes FP64 or FP32
-  S->stage_raw.resize(state_bytes(ne, S->precision));
+  S->stage_raw.resize(state_bytes(ne, S->precision, S->order));
   double *z = (double *)S->stage_raw.data();
-  for (size_t j = 0; j < 3; ++j)
+  for (size_t j = 0; j < nm; ++j)
     for (size_t i = 0; i < ne; ++i) z[j * ne + i] = w[j * ne + (size_t)h.perm[i]];
   if (mixed) {
-    float *q = (float *)(z + 3 * ne);
-    for (size_t j = 0; j < 6; ++j)
-      for (size_t i = 0; i < ne; ++i) q[j * ne + i] = (float)w[(3 + j) * ne + (size_t)h.perm[i]];
+    float *q = (float *)(z + nm * ne);
+    for (size_t j = 0; j < 2 * nm; ++j)
+      for (size_t i = 0; i < ne; ++i) q[j * ne + i] = (float)w[(nm + j) * ne + (size_t)h.perm[i]];
   } else {
-    double *q = z + 3 * ne;
-    for (size_t j = 0; j < 6; ++j)
-      for (size_t i = 0; i < ne; ++i) q[j * ne + i] = w[(3 + j) * ne + (size_t)h.perm[i]];
+    double *q = z + nm * ne;
+    for (size_t j = 0; j < 2 * nm; ++j)
+      for (size_t i = 0; i < ne; ++i) q[j * ne + i] = w[(nm + j) * ne + (size_t)h.perm[i]];
   }
   // into the member's range of every mode array of the current buffer
   unsigned char *base = (unsigned char *)S->s.buf[S->cur];
   const size_t qs = mixed ? sizeof(float) : sizeof(double);
   hipError_t e = hipSuccess;
-  for (size_t j = 0; j < 3 && e == hipSuccess; ++j)
+  for (size_t j = 0; j < nm && e == hipSuccess; ++j)
     e = hipMemcpyAsync(base + (j * NE + (size_t)f.e0) * sizeof(double), z + j * ne, ne * sizeof(double),
                        hipMemcpyHostToDevice, S->stream);
-  const unsigned char *qsrc = (const unsigned char *)(z + 3 * ne);
-  unsigned char *qdst = base + 3 * NE * sizeof(double);
-  for (size_t j = 0; j < 6 && e == hipSuccess; ++j)
+  const unsigned char *qsrc = (const unsigned char *)(z + nm * ne);
+  unsigned char *qdst = base + nm * NE * sizeof(double);
+  for (size_t j = 0; j < 2 * nm && e == hipSuccess; ++j)
     e = hipMemcpyAsync(qdst + (j * NE + (size_t)f.e0) * qs, qsrc + j * ne * qs, ne * qs, hipMemcpyHostToDevice,
                        S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipMemcpyAsync");
@@ -402,7 +416,7 @@ dgswe_status set_state_impl(dgswe_solver *S, int32_t member, double t, const dou
   // state given without post-processing is marked as already done.
   h.cur_is_pp = postprocess == 0;
   e = launch_init_state(S->m, S->s, S->prm, S->s.buf[S->cur], member, f.e0, f.ne, t, (int)(S->steps_enq & 1),
-                        postprocess ? 1 : 0, S->precision, S->stream);
+                        postprocess ? 1 : 0, S->precision, S->order, S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "init kernel");
   e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
@@ -487,14 +501,19 @@ dgswe_status read_state_impl(dgswe_solver *S, int32_t member, double *w_out, dgs
   const size_t ne = (size_t)h.ne;
   if (w_out) {
     // the state at the boundary is post-processed, FP64
-    e = launch_post_only(S->m, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
-                         S->stream);
+    const size_t nv = 3 * (size_t)S->nm;
+    if (S->order == 2)
+      e = launch_post_only2(S->m, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
+                            S->stream);
+    else
+      e = launch_post_only(S->m, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
+                           S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "post-processing kernel");
-    S->stage_buf.resize(9 * ne);
-    e = hipMemcpyAsync(S->stage_buf.data(), S->rb, 9 * ne * sizeof(double), hipMemcpyDeviceToHost, S->stream);
+    S->stage_buf.resize(nv * ne);
+    e = hipMemcpyAsync(S->stage_buf.data(), S->rb, nv * ne * sizeof(double), hipMemcpyDeviceToHost, S->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
-    for (size_t j = 0; j < 9; ++j)
+    for (size_t j = 0; j < nv; ++j)
       for (size_t i = 0; i < ne; ++i) w_out[j * ne + (size_t)h.perm[i]] = S->stage_buf[j * ne + i];
   }
   Ctrl c{};
@@ -597,6 +616,21 @@ dgswe_status dgswe_step(dgswe_solver *S, int32_t n_steps) {
         e = launch_forcing(m, st, p, S->nfblk, slot, stage, S->stream);
       }
       if (e != hipSuccess) break;
+      if (S->order == 2) {
+        // records of the stage input: w^n's go to wpp (the RK base of the
+        // second stage), the first stage result's to the buffer of w^n,
+        // which is no longer read
+        void *rec = stage == 0 ? st.wpp : st.buf[cur];
+        {
+          Timed t(S, K_PP2);
+          e = launch_pp2(m, st, p, stage == 0 ? st.buf[cur] : st.buf[s1], rec, slot, stage, S->precision, S->stream);
+        }
+        if (e != hipSuccess) break;
+        Timed t(S, K_RHS2);
+        e = launch_rhs2(m, st, p, rec, stage == 0 ? nullptr : st.wpp, stage == 0 ? st.buf[s1] : st.buf[nx], slot,
+                        stage, stage == 0 ? 0 : want_dt, S->precision, S->stream);
+        continue;
+      }
       Timed t(S, K_STAGE);
       if (stage == 0)
         e = launch_stage(m, st, p, st.buf[cur], nullptr, st.buf[s1], st.wpp, slot, 0, 0, S->block, S->precision,

@@ -82,6 +82,13 @@ struct DevMesh {
   // (the bathymetry at the edge ends is the e+ element's, read from LDS)
   const double2 *le_a, *le_b;  // FP64: (nx, ny), (len/2, ids as bits)
   const float4 *le_f;          // mixed: (nx, ny, len/2, ids as bits)
+  // p = 2 kernels (element-centric): edge of local edge l of element e as
+  // (edge << 1 | 1 if e is the edge's e- side) [3][ne]; per edge (nx, ny)
+  // from e+ to e- and (len/2, lp | lm << 2 | type << 4 as bits); mean
+  // bathymetry per element
+  const int *e2edge;
+  const double2 *ed2a, *ed2b;
+  const double *hmean;
 };
 
 // Parameters shared by all members of a batch.
@@ -118,6 +125,9 @@ struct Prep {
   int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
   std::vector<int> ch_off, h1_off, h1, h2_off, h2, le_off, le_gid, lo_off;
   std::vector<double> le_nx, le_ny, le_hl;                // per local edge
+  // element-centric edge records of the p = 2 kernels (see DevMesh)
+  std::vector<double2> ed2a, ed2b;
+  std::vector<double> hmean;
   std::vector<uint32_t> le_ids;                            // packed ids (see DevMesh)
   std::vector<uint16_t> el_ledge;                          // [3][ne] local edge code per local edge
   // packed records (see DevMesh)
@@ -149,6 +159,9 @@ void merge_meshes(const std::vector<Prep> &parts, Prep &out);
 // local edge codes).
 void build_chunks(Prep &P, int C);
 
+// The p = 2 records (ed2a, ed2b, hmean) of a (merged) mesh from its edges.
+void p2_records(Prep &P);
+
 // Returns 0 on success, else a DGSWE status code with a message in `err`.
 int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *tri, int nbnd,
                  const int *bnd, const int *btype, Prep &out, std::string &err);
@@ -177,13 +190,26 @@ hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, 
 // stored state still needs post-processing) and put the CFL candidates of
 // its elements [e0, e0 + count) in `w` into dtmin[slot].
 hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w, int mb, int e0,
-                             int count, double t, int slot, int pp_in, int precision, hipStream_t st);
+                             int count, double t, int slot, int pp_in, int precision, int order, hipStream_t st);
 // mass, volume and wet count of elements [e0, e0 + count) of a state (its
 // zeta block is read)
 hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w, int e0, int count,
                        double *out4, hipStream_t st);
+// p = 2: post-processing of a stage input (raw state, structure of arrays)
+// into element records (the first stage also checks the time step and resets
+// the next CFL minimum), then the RK stage from those records (and, in the
+// second stage, the first stage's records as the RK base).
+hipError_t launch_pp2(const DevMesh &m, const DevState &s, const Params &p, const void *win, void *rec, int slot,
+                      int stage, int precision, hipStream_t st);
+hipError_t launch_rhs2(const DevMesh &m, const DevState &s, const Params &p, const void *rec, const void *rbase,
+                       void *wout, int slot, int stage, int want_dt, int precision, hipStream_t st);
+// p = 2 read-back: elements [e0, e0 + count) as FP64 [18][count]
+hipError_t launch_post_only2(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
+                             double *wout, int precision, hipStream_t st);
 size_t stage_lds_bytes(const DevMesh &m, int precision);
-size_t state_bytes(size_t ne, int precision);
+// bytes of one state buffer: (3 zeta modes FP64 + 6 momentum modes) per
+// element at p = 1, (6 + 12) at p = 2
+size_t state_bytes(size_t ne, int precision, int order);
 bool stage_block_ok(int block);
 int diag_blocks(int ne);
 

@@ -34,201 +34,10 @@
 // zeta right-hand side and its RK update stay FP64.  Each FP32 edge mass
 // moment is added to one element and subtracted from the other in FP64, so
 // mass is conserved to FP64 rounding in both paths.
-#include "dgswe_internal.h"
-#include "../../include/dgswe.h"
+#include "dgswe_device.h"
 
 namespace dgswe {
 
-#define HD __host__ __device__ __forceinline__
-constexpr uint16_t kNone = 0xFFFF;
-
-// ---------------------------------------------------------------- helpers
-HD double bits_to_double(unsigned long long b) {
-  union { unsigned long long u; double d; } x;
-  x.u = b;
-  return x.d;
-}
-HD unsigned long long double_to_bits(double d) {
-  union { unsigned long long u; double d; } x;
-  x.d = d;
-  return x.u;
-}
-
-// Reciprocal, square root and cube root for the flux and source arithmetic.
-// FP64: the hardware estimates refined by Newton (reciprocal, square root)
-// or Halley (cube root) iterations, within about 1 ulp instead of the
-// correctly rounded library sequences.  FP32: the hardware instructions
-// (about 1 ulp).  Arguments are finite and in the normal range (depths >=
-// h0, lengths and areas of a mesh).
-HD double rcp_nr(double x) {
-#ifdef __HIP_DEVICE_COMPILE__
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return r;
-#else
-  return 1.0 / x;
-#endif
-}
-HD float rcp_nr(float x) {
-#ifdef __HIP_DEVICE_COMPILE__
-  return __builtin_amdgcn_rcpf(x);
-#else
-  return 1.0f / x;
-#endif
-}
-
-// sqrt(x) for x >= 0 (0 for x == 0)
-HD double sqrt_nr(double x) {
-#ifdef __HIP_DEVICE_COMPILE__
-  const double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
-  const double r = fma(-g, h, 0.5);
-  g = fma(g, r, g);
-  h = fma(h, r, h);
-  const double d = fma(-g, g, x);
-  g = fma(d, h, g);
-  return x > 0.0 ? g : 0.0;
-#else
-  return sqrt(x);
-#endif
-}
-HD float sqrt_nr(float x) {
-#ifdef __HIP_DEVICE_COMPILE__
-  return __builtin_amdgcn_sqrtf(x);
-#else
-  return sqrtf(x);
-#endif
-}
-
-// cube root of x > 0: float estimate 2^(log2(x)/3); FP64 adds one Halley
-// step y <- y (y^3 + 2x) / (2y^3 + x) (cubic convergence)
-HD double cbrt_nr(double x) {
-#ifdef __HIP_DEVICE_COMPILE__
-  const float xf = (float)x;
-  double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(xf) * (1.0f / 3.0f));
-  const double y3 = y * y * y;
-  y = y * (y3 + 2.0 * x) * rcp_nr(2.0 * y3 + x);
-  return y;
-#else
-  return cbrt(x);
-#endif
-}
-HD float cbrt_nr(float x) {
-#ifdef __HIP_DEVICE_COMPILE__
-  return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
-#else
-  return cbrtf(x);
-#endif
-}
-
-// dt of the current step: fixed, or cfl x the CFL minimum of w^n (capped),
-// from the bit pattern of that minimum.  Returns false when no wet element
-// defines it and there is no cap.
-HD bool dt_from_bits(const Params &p, unsigned long long bits, double &dt) {
-  if (p.dt_fixed > 0.0) { dt = p.dt_fixed; return true; }
-  double raw = bits_to_double(bits);
-  if (raw == INFINITY) {
-    if (p.dt_max > 0.0) { dt = p.dt_max; return true; }
-    return false;
-  }
-  double d = p.cfl * raw;
-  if (p.dt_max > 0.0 && d > p.dt_max) d = p.dt_max;
-  dt = d;
-  return true;
-}
-HD bool step_dt(const Ctrl *c, const Params &p, int slot, double &dt) { return dt_from_bits(p, c->dtmin[slot], dt); }
-
-HD double tide_level(const Member &f, double t) {
-  double z = f.tide_offset;
-  for (int i = 0; i < f.n_tide; ++i) z += f.tide_amp[i] * cos(f.tide_omega[i] * t + f.tide_phase[i]);
-  return z;
-}
-
-// hydrostatic flux g/2 (H^2 - h_b^2) written as g/2 zeta (zeta + 2 h_b), FP64
-HD double p_hydro(double g, double ze, double hb) { return 0.5 * g * ze * (ze + 2.0 * hb); }
-
-// normal physical flux F(w).n of one side; u = 0 on a dry side.  zeta and
-// h_b FP64; momentum, normal and result in R.
-template <class R>
-HD void flux_n(double g, double ze, R qx, R qy, double hb, bool wet, R nx, R ny, R &un, R f[3]) {
-  const R H = (R)(ze + hb);
-  const R qn = qx * nx + qy * ny;
-  un = wet ? qn * rcp_nr(H) : (R)0;
-  const R p = (R)p_hydro(g, ze, hb);
-  f[0] = qn;
-  f[1] = qx * un + p * nx;
-  f[2] = qy * un + p * ny;
-}
-
-// local Lax-Friedrichs flux from side L (normal n points from L to R); the
-// zeta jump is formed in FP64
-template <class R>
-HD void llf(double g, double zl, R qlx, R qly, double zr, R qrx, R qry, double hb, R nx, R ny, bool wetl,
-            bool wetr, R out[3]) {
-  R unl, unr, fl[3], fr[3];
-  flux_n<R>(g, zl, qlx, qly, hb, wetl, nx, ny, unl, fl);
-  flux_n<R>(g, zr, qrx, qry, hb, wetr, nx, ny, unr, fr);
-  const R cl = sqrt_nr((R)(g * fmax(zl + hb, 0.0)));
-  const R cr = sqrt_nr((R)(g * fmax(zr + hb, 0.0)));
-  const R lam = fmax(fabs(unl) + cl, fabs(unr) + cr);
-  const R jump[3] = {(R)(zr - zl), qrx - qlx, qry - qly};
-  for (int m = 0; m < 3; ++m) out[m] = (R)0.5 * (fl[m] + fr[m]) - (R)0.5 * lam * jump[m];
-}
-
-// land wall: LLF against the mirror state, closed form, zero mass flux
-template <class R>
-HD void wall(double g, double ze, R qx, R qy, double hb, R nx, R ny, bool wet, R out[3]) {
-  const R p = (R)p_hydro(g, ze, hb);
-  R f = p;
-  if (wet) {
-    const double Hd = ze + hb;
-    const R iH = rcp_nr((R)Hd);
-    const R qn = qx * nx + qy * ny;
-    const R lam = fabs(qn) * iH + sqrt_nr((R)(g * fmax(Hd, 0.0)));
-    f = qn * qn * iH + p + lam * qn;
-  }
-  out[0] = (R)0;
-  out[1] = f * nx;
-  out[2] = f * ny;
-}
-
-// p=1 vertex coefficients: value at vertex v = u0 + C1[v] u1 + C2[v] u2
-HD double c1v(int v) { return v == 0 ? -1.0 : (v == 1 ? 1.0 : 0.0); }
-HD double c2v(int v) { return v == 2 ? 2.0 : -1.0; }
-// midpoint of local edge l (between vertices l+1 and l+2)
-HD double c1m(int l) { return l == 0 ? 0.5 : (l == 1 ? -0.5 : 0.0); }
-HD double c2m(int l) { return l == 2 ? -1.0 : 0.5; }
-
-// gather weights: contribution to mode k of an element from the moments
-// (P0, P1) of its local edge l is P0 (k=0), a1 P0 + b1 P1, a2 P0 + b2 P1
-HD double ga1(int l) { return l == 0 ? 0.5 : (l == 1 ? -0.5 : 0.0); }
-HD double gb1(int l) { return l == 2 ? 1.0 : -0.5; }
-HD double ga2(int l) { return l == 2 ? -1.0 : 0.5; }
-HD double gb2(int l) { return l == 0 ? 1.5 : (l == 1 ? -1.5 : 0.0); }
-
-HD void holland(const Member &f, double x, double y, double t, double out[3]) {
-  double cx = f.x0 + f.vx * t, cy = f.y0 + f.vy * t;
-  double dx = x - cx, dy = y - cy;
-  double r = sqrt(dx * dx + dy * dy);
-  double pc = f.pn - f.dp;
-  if (r <= 0.0) { out[0] = 0.0; out[1] = 0.0; out[2] = pc; return; }
-  double a = pow(f.rmax / r, f.B);
-  double e = exp(-a);
-  double p = pc + f.dp * e;
-  double rf2 = 0.5 * r * f.coriolis_f;
-  double vg = sqrt(f.B * f.dp / f.rho_air * a * e + rf2 * rf2) - fabs(rf2);
-  double ws = f.wind_factor * vg;
-  double sgn = (f.coriolis_f < 0.0) ? -1.0 : 1.0;
-  double wx = -sgn * ws * dy / r, wy = sgn * ws * dx / r;
-  double cd = (0.75 + 0.067 * ws) * 1.0e-3;
-  if (cd > 3.5e-3) cd = 3.5e-3;
-  out[0] = f.rho_air * cd * ws * wx;
-  out[1] = f.rho_air * cd * ws * wy;
-  out[2] = p;
-}
-
-HD double mean3(const double h[3]) { return (h[0] + h[1] + h[2]) / 3.0; }
 
 // ---------------------------------------------------------------- per-item math
 // Post-processing of one element (slope limiter, then wet/dry), FP64 in
@@ -481,29 +290,7 @@ HD void area_terms(const double z[3], const R q[6], bool wet, const ElemPre<R> &
   }
 }
 
-// CFL candidate 2 r_e / (|Q_mean| / H_mean + sqrt(g H_mean)) of a state
-// (INFINITY when dry); unchanged by the post-processing.
-HD double cfl_candidate(double z0, double qx0, double qy0, double hmean, double inr2, const Params &p) {
-  const double Hm = z0 + hmean;
-  const bool wet = p.wetdry ? (Hm > p.h0) : true;
-  if (!wet) return INFINITY;
-  const double lam = sqrt(qx0 * qx0 + qy0 * qy0) / Hm + sqrt(p.g * Hm);
-  return inr2 / lam;
-}
 
-// ---------------------------------------------------------------- global-memory views
-// A state buffer: zeta modes [3][ne] FP64, then momentum modes [6][ne] of
-// type QT (Qx modes 0-2, Qy modes 0-2), each mode contiguous.
-template <class QT>
-struct St {
-  double *z;
-  QT *q;
-};
-template <class QT>
-struct CSt {
-  const double *z;
-  const QT *q;
-};
 
 // Element e of a state, post-processed with neighbour means read from the
 // same state if pp, as FP64 (read-back)
@@ -570,26 +357,6 @@ HD Lds<QT> lds_view(const DevMesh &m, void *base) {
   return L;
 }
 
-struct ChunkInfo {
-  int c, c0, cc, h1o, n1, h2o, n2, leo, ne_loc, lo, member, first, man_base, man_step;
-  HD int nl() const { return cc + n1; }
-};
-
-HD ChunkInfo chunk_info(const DevMesh &m, int c) {
-  const int *r = m.chunk_rec + (size_t)c * kChunkRec;
-  ChunkInfo k;
-  k.c = c;
-  k.c0 = r[0]; k.cc = r[1];
-  k.h1o = r[2]; k.n1 = r[3];
-  k.h2o = r[4]; k.n2 = r[5];
-  k.leo = r[6]; k.ne_loc = r[7];
-  k.lo = r[8];
-  k.member = r[9];
-  k.first = r[10];
-  k.man_base = r[11];
-  k.man_step = r[12];
-  return k;
-}
 
 // bit patterns of the packed ids stored in a double / float slot
 HD uint32_t ids_of(double v) {
@@ -707,13 +474,6 @@ HD void load_elem_node(const DevMesh &m, const ChunkInfo &k, int i, int node[3],
   for (int q = 0; q < 3; ++q) ledge[q] = (v.w >> (10 * q)) & 0x3FF;
 }
 
-// Manning n of element i of a chunk
-HD double manning_of(const DevMesh &m, const ChunkInfo &k, int i, double) {
-  return m.man[(size_t)k.man_base + (size_t)i * k.man_step];
-}
-HD float manning_of(const DevMesh &m, const ChunkInfo &k, int i, float) {
-  return m.manf[(size_t)k.man_base + (size_t)i * k.man_step];
-}
 
 template <class QT>
 HD void store_geo_lds(const Lds<QT> &L, int i, const GeoReg<QT> &G) {
@@ -882,29 +642,6 @@ HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, cons
 #undef HD
 
 // ---------------------------------------------------------------- kernels
-template <int NT>
-__device__ __forceinline__ double block_min(double v, double *red) {
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) red[wv] = v;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int i = 1; i < NT / 64; ++i) v = fmin(v, red[i]);
-  return v;  // valid in thread 0
-}
-
-// XCD-aware chunk order: consecutive workgroups land on different XCDs
-// (round robin over 8), so XCD x processes the contiguous chunk range
-// [x * nch / 8, (x + 1) * nch / 8) and neighbouring chunks share its L2.
-__device__ __forceinline__ int chunk_of_block(int b, int nch) {
-  const int nx = 8;
-  const int per = nch / nx, rem = nch % nx;
-  const int x = b % nx, r = b / nx;
-  const int start = x * per + (x < rem ? x : rem);
-  const int len = per + (x < rem ? 1 : 0);
-  if (r < len) return start + r;
-  return -1;
-}
 
 // Forcing blocks are numbered member by member (members without a moving
 // vortex have none); block b finds its member by bisection of fblk_off.
@@ -1080,7 +817,7 @@ __global__ void k_ctrl_reset(Ctrl *c, double t, int pp_in) {
 // CFL candidates of elements [e0, e0 + count) into ctl->dtmin[slot]
 template <class QT>
 __global__ __launch_bounds__(kBlock) void k_init(DevMesh m, Ctrl *ctl, Params p, CSt<QT> w, int e0, int count,
-                                                 int slot) {
+                                                 int slot, int nm) {
   __shared__ double red[kBlock / 64];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   double cand = INFINITY;
@@ -1088,7 +825,7 @@ __global__ __launch_bounds__(kBlock) void k_init(DevMesh m, Ctrl *ctl, Params p,
     const size_t ne = (size_t)m.ne;
     const int e = e0 + i;
     const double h[3] = {m.hbv[e], m.hbv[ne + e], m.hbv[2 * ne + e]};
-    cand = cfl_candidate(w.z[e], (double)w.q[e], (double)w.q[3 * ne + e], mean3(h), m.inr2[e], p);
+    cand = cfl_candidate(w.z[e], (double)w.q[e], (double)w.q[(size_t)nm * ne + e], mean3(h), m.inr2[e], p);
   }
   const double bm = block_min<kBlock>(cand, red);
   if (threadIdx.x == 0 && bm < INFINITY) atomicMin(&ctl->dtmin[slot], double_to_bits(bm));
@@ -1157,8 +894,9 @@ size_t stage_lds_bytes(const DevMesh &m, int precision) {
   return precision == DGSWE_MIXED ? lds_bytes<float>(m) : lds_bytes<double>(m);
 }
 
-size_t state_bytes(size_t ne, int precision) {
-  return ne * (precision == DGSWE_MIXED ? 3 * sizeof(double) + 6 * sizeof(float) : 9 * sizeof(double));
+size_t state_bytes(size_t ne, int precision, int order) {
+  const size_t nm = order == 2 ? 6 : 3;
+  return ne * nm * (precision == DGSWE_MIXED ? sizeof(double) + 2 * sizeof(float) : 3 * sizeof(double));
 }
 
 bool stage_block_ok(int block) {
@@ -1167,15 +905,6 @@ bool stage_block_ok(int block) {
   return false;
 }
 
-// views of a state buffer: zeta modes first, then the momentum modes
-template <class QT>
-static St<QT> split(void *buf, size_t ne) {
-  return {(double *)buf, (QT *)((double *)buf + 3 * ne)};
-}
-template <class QT>
-static CSt<QT> csplit(const void *buf, size_t ne) {
-  return {(const double *)buf, (const QT *)((const double *)buf + 3 * ne)};
-}
 
 hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int nfblk, int slot, int stage,
                           hipStream_t st) {
@@ -1224,17 +953,18 @@ hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, 
 }
 
 hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w, int mb, int e0,
-                             int count, double t, int slot, int pp_in, int precision, hipStream_t st) {
+                             int count, double t, int slot, int pp_in, int precision, int order, hipStream_t st) {
   const size_t ne = (size_t)m.ne;
   Ctrl *ctl = s.ctrl + mb;
+  const int nm = order == 2 ? 6 : 3;
   hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, ctl, t, pp_in);
   if (count <= 0) return hipGetLastError();
   if (precision == DGSWE_MIXED)
-    hipLaunchKernelGGL(k_init<float>, dim3(nblk(count)), dim3(kBlock), 0, st, m, ctl, p, csplit<float>(w, ne), e0,
-                       count, slot);
+    hipLaunchKernelGGL(k_init<float>, dim3(nblk(count)), dim3(kBlock), 0, st, m, ctl, p, CSt<float>{(const double *)w, (const float *)((const double *)w + nm * ne)},
+                       e0, count, slot, nm);
   else
-    hipLaunchKernelGGL(k_init<double>, dim3(nblk(count)), dim3(kBlock), 0, st, m, ctl, p, csplit<double>(w, ne), e0,
-                       count, slot);
+    hipLaunchKernelGGL(k_init<double>, dim3(nblk(count)), dim3(kBlock), 0, st, m, ctl, p, CSt<double>{(const double *)w, (const double *)w + nm * ne},
+                       e0, count, slot, nm);
   return hipGetLastError();
 }
 

@@ -1,0 +1,638 @@
+// gfx950 kernels of the p = 2 DG step (six modes per variable): the same
+// SSP-RK(2,2) scheme, fluxes and source terms as the p = 1 path (arXiv
+// 2508.21208, Sec. 2.2), with the Dubiner basis carried to degree 2 and the
+// quadratures raised to match (degree-4 area rule, 4-point Gauss-Lobatto
+// edges).
+//
+// Two kernels per RK stage, one workgroup per chunk of 256 consecutive
+// (Hilbert-ordered) elements, one lane per element, no LDS:
+//   k_pp2   slope limiter + wet/dry of the stage input (raw state, structure
+//           of arrays) into a post-processed copy, one 16-byte-aligned record
+//           per element (144 B in FP64), so a neighbour's state is a few
+//           contiguous 16-byte loads;
+//   k_rhs2  volume and source integrals at the six area points, the three
+//           edges of the element at four Gauss-Lobatto points each, inverse
+//           mass diagonal and the Shu-Osher RK combination, written raw.
+// An interior edge is evaluated by both of its elements, each in the edge's
+// own orientation (its e+ side first) with the same arithmetic, so both get
+// bitwise the same flux and each takes its side: no edge buffer, no atomics,
+// mass conserved to rounding.  The post-processed stage-1 input (the RK base
+// of stage 2) is kept as the first stage's record buffer.
+//
+// Precision as in the p = 1 path: QT is the storage type of the momentum
+// modes and the arithmetic type of flux, volume and source terms; zeta,
+// bathymetry, the post-processing and the zeta update stay FP64.
+#include "dgswe_device.h"
+
+namespace dgswe {
+
+// ---------------------------------------------------------------- basis
+// Dubiner p = 2 in the order [phi00, phi10, phi01, phi20, phi11, phi02] with
+// A = (1 + 2 xi + eta)/2, B = (1 - eta)/2: phi10 = A, phi01 = (1 + 3 eta)/2,
+// phi20 = (3 A^2 - B^2)/2, phi11 = A (3 + 5 eta)/2, phi02 = (5 eta^2 + 2 eta - 1)/2.
+HD void basis2(double xi, double eta, double f[6]) {
+  const double A = 0.5 * (1.0 + 2.0 * xi + eta), B = 0.5 * (1.0 - eta);
+  f[0] = 1.0;
+  f[1] = A;
+  f[2] = 0.5 * (1.0 + 3.0 * eta);
+  f[3] = 0.5 * (3.0 * A * A - B * B);
+  f[4] = 0.5 * A * (3.0 + 5.0 * eta);
+  f[5] = 0.5 * (5.0 * eta * eta + 2.0 * eta - 1.0);
+}
+// reference gradients (d/dxi, d/deta)
+HD void basis2_grad(double xi, double eta, double d[6][2]) {
+  const double A = 0.5 * (1.0 + 2.0 * xi + eta), B = 0.5 * (1.0 - eta);
+  d[0][0] = 0.0; d[0][1] = 0.0;
+  d[1][0] = 1.0; d[1][1] = 0.5;
+  d[2][0] = 0.0; d[2][1] = 1.5;
+  d[3][0] = 3.0 * A; d[3][1] = 0.5 * (3.0 * A + B);
+  d[4][0] = 0.5 * (3.0 + 5.0 * eta); d[4][1] = 0.25 * (3.0 + 5.0 * eta) + 2.5 * A;
+  d[5][0] = 0.0; d[5][1] = 5.0 * eta + 1.0;
+}
+
+// mass diagonal / area and its inverse
+constexpr double kMu2Inv[6] = {1.0, 6.0, 2.0, 15.0, 9.0, 3.0};
+
+// values of the six modes at the vertices V0 (-1,-1), V1 (1,-1), V2 (-1,1)
+// and at the midpoints of local edges 0, 1, 2 (opposite V0, V1, V2)
+constexpr double kPt6[6][6] = {
+    {1.0, -1.0, -1.0, 1.0, 1.0, 1.0},   {1.0, 1.0, -1.0, 1.0, -1.0, 1.0},   {1.0, 0.0, 2.0, 0.0, 0.0, 3.0},
+    {1.0, 0.5, 0.5, 0.25, 0.75, -0.5}, {1.0, -0.5, 0.5, 0.25, -0.75, -0.5}, {1.0, 0.0, -1.0, -0.5, 0.0, 1.0}};
+
+// degree-4 symmetric area rule: barycentric (a, b, b) and permutations,
+// weights as fractions of the area
+constexpr double kD4A1 = 0.10810301816807022736, kD4B1 = 0.44594849091596488632, kD4W1 = 0.22338158967801146570;
+constexpr double kD4A2 = 0.81684757298045851308, kD4B2 = 0.09157621350977074346, kD4W2 = 0.10995174365532186764;
+HD void area_point2(int q, double L[3], double &w) {
+  const bool o1 = q < 3;
+  const int r = o1 ? q : q - 3;
+  const double a = o1 ? kD4A1 : kD4A2, b = o1 ? kD4B1 : kD4B2;
+  for (int v = 0; v < 3; ++v) L[v] = v == r ? a : b;
+  w = o1 ? kD4W1 : kD4W2;
+}
+
+// 4-point Gauss-Lobatto rule on [-1, 1]: nodes -1, -1/sqrt5, 1/sqrt5, 1,
+// weights 1/6, 5/6, 5/6, 1/6
+constexpr double kGL4S = 0.44721359549995793928;
+HD double gl4_s(int g) { return g == 0 ? -1.0 : (g == 1 ? -kGL4S : (g == 2 ? kGL4S : 1.0)); }
+HD double gl4_w(int g) { return (g == 0 || g == 3) ? (1.0 / 6.0) : (5.0 / 6.0); }
+
+// reference point at parameter s of local edge l (from vertex l+1 at s = -1
+// to vertex l+2 at s = +1)
+HD void edge_point2(int l, double s, double &xi, double &eta) {
+  const int a = l == 2 ? 0 : l + 1, b = l == 0 ? 2 : l - 1;
+  const double ax = a == 1 ? 1.0 : -1.0, ay = a == 2 ? 1.0 : -1.0;
+  const double bx = b == 1 ? 1.0 : -1.0, by = b == 2 ? 1.0 : -1.0;
+  xi = ax * 0.5 * (1.0 - s) + bx * 0.5 * (1.0 + s);
+  eta = ay * 0.5 * (1.0 - s) + by * 0.5 * (1.0 + s);
+}
+
+// packed edge info (lp | lm << 2 | type << 4) stored in the low bits of a double
+HD uint32_t info_bits(double v) {
+  union { double d; unsigned long long u; } x;
+  x.d = v;
+  return (uint32_t)x.u;
+}
+
+// ---------------------------------------------------------------- records
+// post-processed state of one element: zeta modes (FP64), Qx modes, Qy modes
+template <class QT>
+struct alignas(16) Rec2 {
+  double z[6];
+  QT q[12];
+};
+static_assert(sizeof(Rec2<double>) == 144, "FP64 record");
+static_assert(sizeof(Rec2<float>) == 96, "mixed record");
+
+template <class QT>
+HD void load_rec(const Rec2<QT> *__restrict__ r, int e, double z[6], QT q[12]) {
+  const double2 *d = (const double2 *)(r + e);
+  for (int j = 0; j < 3; ++j) {
+    const double2 v = d[j];
+    z[2 * j] = v.x;
+    z[2 * j + 1] = v.y;
+  }
+  if constexpr (sizeof(QT) == 8) {
+    for (int j = 0; j < 6; ++j) {
+      const double2 v = d[3 + j];
+      q[2 * j] = (QT)v.x;
+      q[2 * j + 1] = (QT)v.y;
+    }
+  } else {
+    const float4 *f = (const float4 *)(d + 3);
+    for (int j = 0; j < 3; ++j) {
+      const float4 v = f[j];
+      q[4 * j] = (QT)v.x; q[4 * j + 1] = (QT)v.y; q[4 * j + 2] = (QT)v.z; q[4 * j + 3] = (QT)v.w;
+    }
+  }
+}
+
+template <class QT>
+HD void store_rec(Rec2<QT> *__restrict__ r, int e, const double u[18]) {
+  double2 *d = (double2 *)(r + e);
+  for (int j = 0; j < 3; ++j) d[j] = make_double2(u[2 * j], u[2 * j + 1]);
+  if constexpr (sizeof(QT) == 8) {
+    for (int j = 0; j < 6; ++j) d[3 + j] = make_double2(u[6 + 2 * j], u[7 + 2 * j]);
+  } else {
+    float4 *f = (float4 *)(d + 3);
+    for (int j = 0; j < 3; ++j)
+      f[j] = make_float4((float)u[6 + 4 * j], (float)u[7 + 4 * j], (float)u[8 + 4 * j], (float)u[9 + 4 * j]);
+  }
+}
+
+// ---------------------------------------------------------------- post-processing
+// Post-processing of one element, FP64: u[18] = zeta, Qx, Qy modes
+// [var * 6 + mode] of the raw state; nbm[v][k] the raw mean of variable v of
+// neighbour k.
+//   Limiter, per variable: alpha is the p = 1 Barth-Jespersen factor of the
+//   linear part against the range of the element and neighbour means; the
+//   element is troubled when alpha < 1 or the full field leaves the range at
+//   a vertex or an edge midpoint, and then keeps only its linear part scaled
+//   by alpha.
+//   Wet/dry: mean depth <= H0 -> flat at the mean depth, momentum 0; a depth
+//   below H0 at a vertex or an edge midpoint -> the quadratic modes of all
+//   variables are dropped and the p = 1 vertex correction is applied to the
+//   linear part; otherwise unchanged.
+HD void postprocess2(double u[18], const double nbm[3][3], const bool has[3], const double h[3], double hmean,
+                     const Params &p) {
+  if (p.limiter) {
+    for (int v = 0; v < 3; ++v) {
+      double *w = u + 6 * v;
+      const double mean = w[0];
+      double hi = mean, lo = mean;
+      for (int k = 0; k < 3; ++k)
+        if (has[k]) { hi = fmax(hi, nbm[v][k]); lo = fmin(lo, nbm[v][k]); }
+      const double a = w[1], b = w[2];
+      const double d0 = (mean - a - b) - mean, d1 = (mean + a - b) - mean, d2 = (mean + 2.0 * b) - mean;
+      const double dmax = fmax(d0, fmax(d1, d2)), dmin = fmin(d0, fmin(d1, d2));
+      double alpha = 1.0;
+      if (dmax > 0.0 && hi - mean < dmax) alpha = fmin(alpha, (hi - mean) / dmax);
+      if (dmin < 0.0 && lo - mean > dmin) alpha = fmin(alpha, (lo - mean) / dmin);
+      bool troubled = alpha < 1.0;
+      for (int i = 0; i < 6; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < 6; ++k) s += w[k] * kPt6[i][k];
+        troubled = troubled || s > hi || s < lo;
+      }
+      if (troubled) {
+        w[1] = a * alpha;
+        w[2] = b * alpha;
+        w[3] = 0.0; w[4] = 0.0; w[5] = 0.0;
+      }
+    }
+  }
+  if (p.wetdry) {
+    const double Hm = u[0] + hmean;
+    const double hp[6] = {h[0], h[1], h[2], 0.5 * (h[1] + h[2]), 0.5 * (h[2] + h[0]), 0.5 * (h[0] + h[1])};
+    bool reduce = Hm <= p.h0;
+    for (int i = 0; i < 6; ++i) {
+      double s = 0.0;
+      for (int k = 0; k < 6; ++k) s += u[k] * kPt6[i][k];
+      reduce = reduce || s + hp[i] < p.h0;
+    }
+    if (reduce) {
+      for (int v = 0; v < 3; ++v) { u[6 * v + 3] = 0.0; u[6 * v + 4] = 0.0; u[6 * v + 5] = 0.0; }
+      const double z0 = u[0] - u[1] - u[2], z1 = u[0] + u[1] - u[2], z2 = u[0] + 2.0 * u[2];
+      double H[3] = {z0 + h[0], z1 + h[1], z2 + h[2]};
+      bool changed = false;
+      if (Hm <= p.h0) {
+        H[0] = H[1] = H[2] = Hm;
+        for (int j = 6; j < 18; ++j) u[j] = 0.0;
+        changed = true;
+      } else if (fmin(H[0], fmin(H[1], H[2])) < p.h0) {
+        double D = 0.0, S = 0.0;
+        for (int i = 0; i < 3; ++i) {
+          if (H[i] < p.h0) D += p.h0 - H[i];
+          else S += H[i] - p.h0;
+        }
+        if (S > D) {
+          for (int i = 0; i < 3; ++i) H[i] = (H[i] < p.h0) ? p.h0 : H[i] - D * (H[i] - p.h0) / S;
+        } else {
+          H[0] = H[1] = H[2] = Hm;
+        }
+        changed = true;
+      }
+      if (changed) {
+        const double y0 = H[0] - h[0], y1 = H[1] - h[1], y2 = H[2] - h[2];
+        u[1] = 0.5 * (y1 - y0);
+        u[2] = 0.5 * (y2 - u[0]);
+      }
+    }
+  }
+}
+
+// raw element e of a state (structure of arrays: zeta [6][ne], Qx [6][ne],
+// Qy [6][ne]) as FP64 u[18], post-processed if pp with raw neighbour means
+template <class QT>
+HD void load_pp2(const DevMesh &m, const Params &p, CSt<QT> w, int e, bool pp, double u[18]) {
+  const size_t ne = (size_t)m.ne;
+  for (int k = 0; k < 6; ++k) u[k] = w.z[k * ne + e];
+  for (int k = 0; k < 12; ++k) u[6 + k] = (double)w.q[k * ne + e];
+  if (!pp) return;
+  double h[3], nbm[3][3];
+  bool has[3];
+  for (int k = 0; k < 3; ++k) h[k] = m.hbv[k * ne + e];
+  for (int k = 0; k < 3; ++k) {
+    const int f = m.el_nb[k * ne + e];
+    has[k] = f >= 0;
+    const int fi = has[k] ? f : e;
+    nbm[0][k] = w.z[fi];
+    nbm[1][k] = (double)w.q[fi];
+    nbm[2][k] = (double)w.q[6 * ne + fi];
+  }
+  postprocess2(u, nbm, has, h, mean3(h), p);
+}
+
+// ---------------------------------------------------------------- edge
+// Trace at parameter s of local edge l of the state (zb, qb) if pick_b,
+// else (za, qa).
+template <class R>
+HD void trace_sel(bool pick_b, const double za[6], const R qa[12], const double zb[6], const R qb[12], int l,
+                  double s, double &tz, R &tx, R &ty) {
+  double xi, eta, f[6];
+  edge_point2(l, s, xi, eta);
+  basis2(xi, eta, f);
+  double sz = 0.0;
+  R sx = (R)0, sy = (R)0;
+  for (int k = 0; k < 6; ++k) {
+    const R fk = (R)f[k];
+    sz += (pick_b ? zb[k] : za[k]) * f[k];
+    sx += (pick_b ? qb[k] : qa[k]) * fk;
+    sy += (pick_b ? qb[6 + k] : qa[6 + k]) * fk;
+  }
+  tz = sz; tx = sx; ty = sy;
+}
+
+// bathymetry at point g of an edge with end values hA (s = -1), hB (s = +1)
+HD double edge_hb(double hA, double hB, int g) {
+  return hA * 0.5 * (1.0 - gl4_s(g)) + hB * 0.5 * (1.0 + gl4_s(g));
+}
+
+// Flux kinds of an edge (wet/dry rules as for p = 1): LLF to both sides (e+
+// gets F, e- gets -F), LLF to e+ only (ocean ghost), land or no-flood wall
+// of e+, no-flood wall of e- (normal -n), nothing.
+enum EdgeKind { EK_LLF = 0, EK_LLF_P, EK_WALL_P, EK_WALL_M, EK_NONE };
+
+// ---------------------------------------------------------------- kernels
+// Post-processing of one stage input into records.  The first stage also
+// does the step's bookkeeping: ALLDRY when no time step is defined, and the
+// reset of the next step's CFL minimum.
+template <class QT, int STAGE>
+__global__ __launch_bounds__(kBlock) void k_pp2(DevMesh m, DevState s, Params p, CSt<QT> win,
+                                                Rec2<QT> *__restrict__ out, int slot) {
+  const int c = chunk_of_block(blockIdx.x, m.nch);
+  if (c < 0) return;
+  const ChunkInfo k = chunk_info(m, c);
+  Ctrl *ctl = s.ctrl + k.member;
+  const int i = threadIdx.x;
+  const int status = ctl->status;
+  const unsigned long long dtbits = ctl->dtmin[slot];
+  const int pp_in = STAGE == 0 ? ctl->pp_in : 1;
+  double dt;
+  if (status != 0) return;
+  if (!dt_from_bits(p, dtbits, dt)) {
+    if (STAGE == 0 && k.first && i == 0) atomicCAS(&ctl->status, 0, (int)DGSWE_E_ALLDRY);
+    return;
+  }
+  if (STAGE == 0 && k.first && i == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
+  if (i >= k.cc) return;
+  const int e = k.c0 + i;
+  double u[18];
+  load_pp2<QT>(m, p, win, e, pp_in != 0, u);
+  store_rec<QT>(out, e, u);
+}
+
+// One RK stage of chunk element i from the post-processed records u (and,
+// in the second stage, the RK base records): out = u + dt L(u), or
+// 1/2 base + 1/2 (u + dt L(u)); zeta modes in out, momentum modes in oqv,
+// the CFL candidate of the result in cand.  Returns false on a non-finite
+// result.
+template <class QT, int STAGE>
+HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const ChunkInfo &k, const Member &F,
+                     const Rec2<QT> *__restrict__ u, const Rec2<QT> *__restrict__ base, int i, double t0, double dt,
+                     double out[6], QT oqv[12], double &cand) {
+  using R = QT;
+  const size_t ne = (size_t)m.ne;
+  const int e = k.c0 + i;
+
+  double z[6];
+  R q[12];
+  load_rec<QT>(u, e, z, q);
+  double h[3];
+  for (int j = 0; j < 3; ++j) h[j] = m.hbv[j * ne + e];
+  const double hm = mean3(h);
+  const bool wet = p.wetdry ? (z[0] + hm > p.h0) : true;
+  const double2 ai = m.eai[e];
+  const double iA = rcp_nr(ai.x);
+
+  // physical gradients of the reference coordinates from those of phi_10
+  // and phi_01: J^-T e1 = g1 - g2/3, J^-T e2 = 2/3 g2
+  R g1x, g1y, g2x, g2y;
+  if constexpr (sizeof(QT) == 8) {
+    const double2 a = m.eg1[e], b = m.eg2[e];
+    g1x = a.x; g1y = a.y; g2x = b.x; g2y = b.y;
+  } else {
+    const float4 a = m.egf[e];
+    g1x = a.x; g1y = a.y; g2x = a.z; g2y = a.w;
+  }
+  const R c1x = g1x - g2x * (R)(1.0 / 3.0), c1y = g1y - g2y * (R)(1.0 / 3.0);
+  const R c2x = g2x * (R)(2.0 / 3.0), c2y = g2y * (R)(2.0 / 3.0);
+
+  // nodal forcing: wind stress at the vertices, pressure gradient from
+  // vertex differences (FP64, large common offset)
+  const int4 nd = m.enode[e];
+  const int node[3] = {nd.x, nd.y, nd.z};
+  R tx[3], ty[3];
+  double pa[3];
+  {
+    const double2 *tau = (const double2 *)s.nodal;
+    for (int j = 0; j < 3; ++j) {
+      const double2 t = tau[node[j]];
+      tx[j] = (R)t.x;
+      ty[j] = (R)t.y;
+      pa[j] = s.nodal[2 * (size_t)m.nn + node[j]];
+    }
+  }
+  const double dh1 = h[1] - h[0], dh2 = h[2] - h[0];
+  const R hm1 = (R)(0.5 * dh1), hm2 = (R)((2.0 * dh2 - dh1) * (1.0 / 6.0));
+  const R dhx = hm1 * g1x + hm2 * g2x, dhy = hm1 * g1y + hm2 * g2y;
+  const double dp1 = pa[1] - pa[0], dp2 = pa[2] - pa[0];
+  const R pm1 = (R)(0.5 * dp1), pm2 = (R)((2.0 * dp2 - dp1) * (1.0 / 6.0));
+  const R dpx = pm1 * g1x + pm2 * g2x, dpy = pm1 * g1y + pm2 * g2y;
+  const R man = manning_of(m, k, i, (QT)0);
+
+  // area part: rz[k] = (1/A) sum_q w_q A grad phi_k . F_zeta (FP64 sums of
+  // R terms), rq[v][k] likewise for the momentum rows with the sources
+  double rz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  R rq[12];
+  for (int j = 0; j < 12; ++j) rq[j] = (R)0;
+  {
+    const R gr = (R)p.g, gn2 = gr * man * man, irho = (R)(1.0 / p.rho0), h0 = (R)p.h0;
+    for (int qd = 0; qd < 6; ++qd) {
+      double L[3], wq;
+      area_point2(qd, L, wq);
+      const double xi = -L[0] + L[1] - L[2], eta = -L[0] - L[1] + L[2];
+      double f[6], d[6][2];
+      basis2(xi, eta, f);
+      basis2_grad(xi, eta, d);
+      double ze = 0.0;
+      R qx = (R)0, qy = (R)0;
+      for (int j = 0; j < 6; ++j) {
+        ze += z[j] * f[j];
+        qx += q[j] * (R)f[j];
+        qy += q[6 + j] * (R)f[j];
+      }
+      const double hb = L[0] * h[0] + L[1] * h[1] + L[2] * h[2];
+      const R H = (R)(ze + hb);
+      const R ph = (R)p_hydro(p.g, ze, hb);
+      R uu = (R)0, vv = (R)0;
+      if (wet) {
+        const R iH = rcp_nr(H);
+        uu = qx * iH;
+        vv = qy * iH;
+      }
+      const R w = (R)wq;
+      const R Fz[2] = {qx * w, qy * w};
+      const R Fx[2] = {(qx * uu + ph) * w, qx * vv * w};
+      const R Fy[2] = {qy * uu * w, (qy * vv + ph) * w};
+      for (int j = 1; j < 6; ++j) {
+        const R gx = (R)d[j][0] * c1x + (R)d[j][1] * c2x;
+        const R gy = (R)d[j][0] * c1y + (R)d[j][1] * c2y;
+        rz[j] += (double)(gx * Fz[0] + gy * Fz[1]);
+        rq[j] += gx * Fx[0] + gy * Fx[1];
+        rq[6 + j] += gx * Fy[0] + gy * Fy[1];
+      }
+      if (wet) {
+        const R Hf = fmax(H, h0);
+        const R qm = sqrt_nr(qx * qx + qy * qy);
+        const R fr = gn2 * qm * rcp_nr(Hf * Hf * cbrt_nr(Hf));
+        const R txq = (R)L[0] * tx[0] + (R)L[1] * tx[1] + (R)L[2] * tx[2];
+        const R tyq = (R)L[0] * ty[0] + (R)L[1] * ty[1] + (R)L[2] * ty[2];
+        const R gz = (R)(p.g * ze);
+        const R sx = (gz * dhx - fr * qx + txq * irho - H * irho * dpx) * w;
+        const R sy = (gz * dhy - fr * qy + tyq * irho - H * irho * dpy) * w;
+        for (int j = 0; j < 6; ++j) {
+          rq[j] += (R)f[j] * sx;
+          rq[6 + j] += (R)f[j] * sy;
+        }
+      }
+    }
+  }
+
+  // edges: each evaluated in its own orientation with both sides' traces
+  const double ts = t0 + (STAGE ? dt : 0.0);
+  const bool tide = F.n_tide > 0 || F.tide_offset != 0.0;
+  const double zb = tide ? tide_level(F, ts) : 0.0;
+#pragma unroll 1
+  for (int l = 0; l < 3; ++l) {
+    const int code = m.e2edge[(size_t)l * ne + e];
+    const int d = code >> 1;
+    const bool minus = (code & 1) != 0;
+    const double2 en = m.ed2a[d], eb = m.ed2b[d];
+    const uint32_t info = info_bits(eb.y);
+    const int lp = info & 3, lm = (info >> 2) & 3, type = (int)(info >> 4) & 3;
+    const int f = m.el_nb[(size_t)l * ne + e];
+    // the other element (itself on a boundary edge, which has no e- side)
+    const int o = f >= 0 ? f : e;
+    double oz[6];
+    R oq[12];
+    load_rec<QT>(u, o, oz, oq);
+    const bool owet = p.wetdry ? (oz[0] + m.hmean[o] > p.h0) : true;
+    // bathymetry at the edge ends (s = -1: vertex lp+1 of e+, which is
+    // vertex lm+2 of e-; s = +1: vertex lp+2 of e+, vertex lm+1 of e-)
+    const int va = minus ? (lm == 0 ? 2 : lm - 1) : (lp == 2 ? 0 : lp + 1);
+    const int vb = minus ? (lm == 2 ? 0 : lm + 1) : (lp == 0 ? 2 : lp - 1);
+    const double hA = h[va], hB = h[vb];
+    const R nx = (R)en.x, ny = (R)en.y;
+    const bool ghost = type != 0;
+    const bool wetp = minus ? owet : wet;
+    const bool wetm = ghost ? (p.wetdry ? (zb + 0.5 * (hA + hB) > p.h0) : true) : (minus ? wet : owet);
+    // e+ / e- trace at point g, both elements running the same instructions
+    // on the same operands (the states are selected, not the code)
+    auto tr = [&](int g, double &pz, R &px, R &py, double &mz, R &mx, R &my) {
+      trace_sel<R>(minus, z, q, oz, oq, lp, gl4_s(g), pz, px, py);
+      if (ghost) {
+        mz = zb; mx = px; my = py;
+      } else {
+        trace_sel<R>(!minus, z, q, oz, oq, lm, -gl4_s(g), mz, mx, my);
+      }
+    };
+    int kind;
+    if (type == DGSWE_BC_LAND) kind = EK_WALL_P;
+    else if (!wetp && !wetm) kind = EK_NONE;
+    else if (wetp && wetm) kind = ghost ? EK_LLF_P : EK_LLF;
+    else {
+      // one side dry: the sign of the LLF mass flux decides
+      R mf = (R)0;
+#pragma unroll 1
+      for (int g = 0; g < 4; ++g) {
+        double pz, mz;
+        R px, py, mx, my, Fg[3];
+        tr(g, pz, px, py, mz, mx, my);
+        llf<R>(p.g, pz, px, py, mz, mx, my, edge_hb(hA, hB, g), nx, ny, wetp, wetm, Fg);
+        mf += (R)gl4_w(g) * Fg[0];
+      }
+      const bool flood = wetp ? (mf > (R)0) : (mf < (R)0);
+      kind = flood ? (ghost ? EK_LLF_P : EK_LLF) : (wetp ? EK_WALL_P : (ghost ? EK_NONE : EK_WALL_M));
+    }
+    const bool take = minus ? (kind == EK_LLF || kind == EK_WALL_M) : (kind == EK_LLF || kind == EK_LLF_P || kind == EK_WALL_P);
+    if (!take) continue;
+    const R sg = (minus && kind == EK_LLF) ? (R)-1 : (R)1;
+    const double hlA = eb.x * iA;
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+      double pz, mz;
+      R px, py, mx, my, Fg[3];
+      tr(g, pz, px, py, mz, mx, my);
+      const double hq = edge_hb(hA, hB, g);
+      if (kind == EK_WALL_P) wall<R>(p.g, pz, px, py, hq, nx, ny, wetp, Fg);
+      else if (kind == EK_WALL_M) wall<R>(p.g, mz, mx, my, hq, -nx, -ny, wetm, Fg);
+      else llf<R>(p.g, pz, px, py, mz, mx, my, hq, nx, ny, wetp, wetm, Fg);
+      // own basis at the point (e- runs the edge backwards)
+      double xi, eta, fb[6];
+      edge_point2(l, minus ? -gl4_s(g) : gl4_s(g), xi, eta);
+      basis2(xi, eta, fb);
+      const double wg = hlA * gl4_w(g);
+      const double fz = (double)(sg * Fg[0]) * wg;
+      const R fx = sg * Fg[1] * (R)wg, fy = sg * Fg[2] * (R)wg;
+      for (int j = 0; j < 6; ++j) {
+        rz[j] -= fz * fb[j];
+        rq[j] -= fx * (R)fb[j];
+        rq[6 + j] -= fy * (R)fb[j];
+      }
+    }
+  }
+
+  // inverse mass diagonal and the RK combination
+  double bz[6];
+  R bq[12];
+  if (STAGE) load_rec<QT>(base, e, bz, bq);
+  else {
+    for (int j = 0; j < 6; ++j) bz[j] = 0.0;
+    for (int j = 0; j < 12; ++j) bq[j] = (R)0;
+  }
+  bool fin = true;
+  for (int j = 0; j < 6; ++j) {
+    const double dw = rz[j] * kMu2Inv[j];
+    out[j] = STAGE ? 0.5 * bz[j] + 0.5 * (z[j] + dt * dw) : z[j] + dt * dw;
+    fin = fin && __builtin_isfinite(out[j]);
+  }
+  const R dtq = (R)dt;
+  for (int j = 0; j < 12; ++j) {
+    R dw = rq[j] * (R)kMu2Inv[j % 6];
+    if (!wet) dw = (R)0;
+    oqv[j] = STAGE ? (R)0.5 * bq[j] + (R)0.5 * (q[j] + dtq * dw) : q[j] + dtq * dw;
+    fin = fin && __builtin_isfinite(oqv[j]);
+  }
+  cand = cfl_candidate(out[0], (double)oqv[0], (double)oqv[6], hm, ai.y, p);
+  return fin;
+}
+
+template <class QT, int STAGE>
+__global__ __launch_bounds__(kBlock) void k_rhs2(DevMesh m, DevState s, Params p, const Rec2<QT> *__restrict__ u,
+                                                 const Rec2<QT> *__restrict__ base, St<QT> wout, int slot,
+                                                 int want_dt) {
+  __shared__ double red[kBlock / 64];
+  const int c = chunk_of_block(blockIdx.x, m.nch);
+  if (c < 0) return;
+  const ChunkInfo k = chunk_info(m, c);
+  const Member &F = m.mem[k.member];
+  Ctrl *ctl = s.ctrl + k.member;
+  const int tid = threadIdx.x;
+  const size_t ne = (size_t)m.ne;
+  const int status = ctl->status;
+  const unsigned long long dtbits = ctl->dtmin[slot];
+  const double t0 = ctl->t[slot];
+  double dt = 0.0;
+  // No lane leaves early (the CFL reduction has barriers): an inactive
+  // workgroup computes and stores nothing.
+  const bool active = status == 0 && dt_from_bits(p, dtbits, dt);
+  const bool act = active && tid < k.cc;
+  double out[6], cand = INFINITY;
+  QT oqv[12];
+  const bool fin = rhs2_element<QT, STAGE>(m, s, p, k, F, u, base, act ? tid : k.cc - 1, t0, dt, out, oqv, cand);
+  const int e = k.c0 + tid;
+  if (act) {
+    for (int j = 0; j < 6; ++j) wout.z[j * ne + e] = out[j];
+    for (int j = 0; j < 12; ++j) wout.q[j * ne + e] = oqv[j];
+    if (!fin) atomicCAS(&ctl->status, 0, (int)DGSWE_E_NONFINITE);
+  }
+  if (want_dt) {
+    const double bm = block_min<kBlock>(act ? cand : (double)INFINITY, red);
+    if (tid == 0 && bm < INFINITY) atomicMin(&ctl->dtmin[slot ^ 1], double_to_bits(bm));
+  }
+  if (STAGE == 1 && active && k.first && tid == 0) {
+    ctl->t[slot ^ 1] = t0 + dt;
+    ctl->dt_last = dt;
+    ctl->steps = ctl->steps + 1;
+    ctl->pp_in = 1;
+  }
+}
+
+// elements [e0, e0 + count) of a state (post-processed if pp) as FP64
+// [18][count], for read-back
+template <class QT>
+__global__ __launch_bounds__(kBlock) void k_post_only2(DevMesh m, Params p, CSt<QT> win, int pp, int e0, int count,
+                                                       double *__restrict__ wout) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= count) return;
+  double u[18];
+  load_pp2<QT>(m, p, win, e0 + i, pp != 0, u);
+  for (int j = 0; j < 18; ++j) wout[(size_t)j * count + i] = u[j];
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned nblk2(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <class QT>
+static void stage2_qt(const DevMesh &m, const DevState &s, const Params &p, const void *win, void *rec,
+                      const void *rbase, void *wout, int slot, int stage, int want_dt, hipStream_t st, bool pp_only,
+                      bool rhs_only) {
+  const size_t ne = (size_t)m.ne;
+  const CSt<QT> a = {(const double *)win, (const QT *)((const double *)win + 6 * ne)};
+  const St<QT> o = {(double *)wout, (QT *)((double *)wout + 6 * ne)};
+  Rec2<QT> *r = (Rec2<QT> *)rec;
+  const Rec2<QT> *b = (const Rec2<QT> *)rbase;
+  if (!rhs_only) {
+    if (stage) hipLaunchKernelGGL((k_pp2<QT, 1>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, a, r, slot);
+    else hipLaunchKernelGGL((k_pp2<QT, 0>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, a, r, slot);
+  }
+  if (!pp_only) {
+    if (stage) hipLaunchKernelGGL((k_rhs2<QT, 1>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, slot, want_dt);
+    else hipLaunchKernelGGL((k_rhs2<QT, 0>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, slot, want_dt);
+  }
+}
+
+hipError_t launch_pp2(const DevMesh &m, const DevState &s, const Params &p, const void *win, void *rec, int slot,
+                      int stage, int precision, hipStream_t st) {
+  if (precision == DGSWE_MIXED)
+    stage2_qt<float>(m, s, p, win, rec, nullptr, nullptr, slot, stage, 0, st, true, false);
+  else
+    stage2_qt<double>(m, s, p, win, rec, nullptr, nullptr, slot, stage, 0, st, true, false);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs2(const DevMesh &m, const DevState &s, const Params &p, const void *rec, const void *rbase,
+                       void *wout, int slot, int stage, int want_dt, int precision, hipStream_t st) {
+  if (precision == DGSWE_MIXED)
+    stage2_qt<float>(m, s, p, nullptr, (void *)rec, rbase, wout, slot, stage, want_dt, st, false, true);
+  else
+    stage2_qt<double>(m, s, p, nullptr, (void *)rec, rbase, wout, slot, stage, want_dt, st, false, true);
+  return hipGetLastError();
+}
+
+hipError_t launch_post_only2(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
+                             double *wout, int precision, hipStream_t st) {
+  const size_t ne = (size_t)m.ne;
+  if (count <= 0) return hipSuccess;
+  if (precision == DGSWE_MIXED)
+    hipLaunchKernelGGL(k_post_only2<float>, dim3(nblk2(count)), dim3(kBlock), 0, st, m, p,
+                       CSt<float>{(const double *)win, (const float *)((const double *)win + 6 * ne)}, pp, e0, count,
+                       wout);
+  else
+    hipLaunchKernelGGL(k_post_only2<double>, dim3(nblk2(count)), dim3(kBlock), 0, st, m, p,
+                       CSt<double>{(const double *)win, (const double *)win + 6 * ne}, pp, e0, count, wout);
+  return hipGetLastError();
+}
+
+}  // namespace dgswe

@@ -391,10 +391,24 @@ void merge_meshes(const std::vector<Prep> &parts, Prep &out) {
   out.el_nb.assign(3 * ne, -1);
   out.node_x.reserve(nn); out.node_y.reserve(nn);
   out.eg1.reserve(ne); out.eg2.reserve(ne); out.egf.reserve(ne); out.eai.reserve(ne); out.enode.reserve(ne);
+  out.el_edge.assign(3 * ne, -1);
+  out.ed_info.reserve((size_t)out.ned);
+  out.ed_nx.reserve((size_t)out.ned); out.ed_ny.reserve((size_t)out.ned); out.ed_hlen.reserve((size_t)out.ned);
   out.ch_off.reserve(nch + 1); out.h1_off.reserve(nch + 1); out.h2_off.reserve(nch + 1); out.le_off.reserve(nch + 1); out.lo_off.reserve(nch + 1);
-  int e0 = 0, n0 = 0, h1o = 0, h2o = 0, leo = 0, loo = 0;
+  int e0 = 0, n0 = 0, h1o = 0, h2o = 0, leo = 0, loo = 0, d0 = 0;
   for (const Prep &q : parts) {
     const size_t qne = (size_t)q.ne;
+    // edges (p = 2 records): ids shifted by the edges of earlier parts
+    for (int k = 0; k < 3; ++k)
+      for (size_t e = 0; e < qne; ++e) {
+        const int code = q.el_edge[(size_t)k * qne + e];
+        out.el_edge[(size_t)k * ne + e0 + e] = (((code >> 1) + d0) << 1) | (code & 1);
+      }
+    out.ed_info.insert(out.ed_info.end(), q.ed_info.begin(), q.ed_info.end());
+    out.ed_nx.insert(out.ed_nx.end(), q.ed_nx.begin(), q.ed_nx.end());
+    out.ed_ny.insert(out.ed_ny.end(), q.ed_ny.begin(), q.ed_ny.end());
+    out.ed_hlen.insert(out.ed_hlen.end(), q.ed_hlen.begin(), q.ed_hlen.end());
+    d0 += q.ned;
     out.area.insert(out.area.end(), q.area.begin(), q.area.end());
     out.inr2.insert(out.inr2.end(), q.inr2.begin(), q.inr2.end());
     for (int k = 0; k < 3; ++k)
@@ -444,6 +458,20 @@ void merge_meshes(const std::vector<Prep> &parts, Prep &out) {
 }  // namespace dgswe
 
 namespace dgswe {
+
+void p2_records(Prep &P) {
+  const size_t ne = (size_t)P.ne, ned = (size_t)P.ned;
+  P.ed2a.resize(ned);
+  P.ed2b.resize(ned);
+  for (size_t d = 0; d < ned; ++d) {
+    union { double v; unsigned long long u; } x;
+    x.u = (unsigned long long)(uint32_t)P.ed_info[d];
+    P.ed2a[d] = make_double2(P.ed_nx[d], P.ed_ny[d]);
+    P.ed2b[d] = make_double2(P.ed_hlen[d], x.v);
+  }
+  P.hmean.resize(ne);
+  for (size_t e = 0; e < ne; ++e) P.hmean[e] = (P.hbv[e] + P.hbv[ne + e] + P.hbv[2 * ne + e]) / 3.0;
+}
 
 void chunk_records(const Prep &P, const std::vector<int> &chunk_member, std::vector<int> &rec) {
   rec.assign((size_t)P.nch * kChunkRec, 0);

@@ -277,14 +277,21 @@ def params_from_dict(p: dict) -> dgswe_params:
     return prm
 
 
+def modes_per_variable(params: dict | None) -> int:
+    """3 modes per variable at p = 1, 6 at p = 2"""
+    return 6 if int((params or {}).get("p", 1)) == 2 else 3
+
+
 class Solver:
-    """One mesh and its device-resident state."""
+    """One mesh and its device-resident state (shape (3, nm, ne): zeta, Qx,
+    Qy, each with nm = 3 (p = 1) or 6 (p = 2) modes)."""
 
     def __init__(self, mesh, params: dict | None = None, forcing: dict | None = None, hip_stream=None):
         self.h = None
         self.mesh = mesh
         self.ne = int(mesh.tri.shape[0])
         self.nn = int(mesh.xy.shape[0])
+        self.nm = modes_per_variable(params)
         self.h = dgswe_create_mesh(mesh.xy, mesh.hb, mesh.tri, mesh.bnd, mesh.bnd_type,
                                    params_from_dict(params or {}), hip_stream)
         if forcing:
@@ -294,14 +301,14 @@ class Solver:
         dgswe_set_forcing(self.h, f, self.ne, self.nn)
 
     def set_state(self, w, t=0.0, postprocess=False):
-        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, self.ne)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, self.nm, self.ne)
         dgswe_set_state(self.h, t, w, postprocess)
 
     def step(self, n=1):
         dgswe_step(self.h, n)
 
     def state(self):
-        w = np.empty((3, 3, self.ne), dtype=np.float64)
+        w = np.empty((3, self.nm, self.ne), dtype=np.float64)
         self.diag = dgswe_read_state(self.h, w)
         return w
 
@@ -332,6 +339,7 @@ class Batch:
     def __init__(self, meshes, params: dict | None = None, forcings=None, hip_stream=None):
         self.h = None
         self.meshes = list(meshes)
+        self.nm = modes_per_variable(params)
         self.h = dgswe_create_batch(self.meshes, params_from_dict(params or {}), hip_stream)
         for i, f in enumerate(forcings or []):
             if f:
@@ -346,14 +354,14 @@ class Batch:
 
     def set_state(self, i, w, t=0.0, postprocess=False):
         ne = int(self.meshes[i].tri.shape[0])
-        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, 3, ne)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, self.nm, ne)
         dgswe_set_state(self.h, t, w, postprocess, member=i)
 
     def step(self, n=1):
         dgswe_step(self.h, n)
 
     def state(self, i):
-        w = np.empty((3, 3, int(self.meshes[i].tri.shape[0])), dtype=np.float64)
+        w = np.empty((3, self.nm, int(self.meshes[i].tri.shape[0])), dtype=np.float64)
         dgswe_read_state(self.h, w, True, member=i)
         return w
 

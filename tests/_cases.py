@@ -1,5 +1,6 @@
 """Shared seeded workloads and comparison helpers for the parity tests."""
 import functools
+import math
 import sys
 
 import numpy as np
@@ -38,3 +39,10 @@ def rel_l2(a, b):
         num = np.linalg.norm(a[v] - b[v])
         out.append(num / den if den > 0 else num)
     return out
+
+
+def exact_mass(o, w):
+    """sum of A_e zeta_0 over the oracle's elements, correctly rounded (the
+    oracle's own diagnostic adds in element order, whose rounding error on a
+    4M-element sum of mixed-sign terms reaches ~1e-11 relative)"""
+    return math.fsum((o.geometry()["area"] * w[0, 0]).tolist())

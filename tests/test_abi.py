@@ -93,9 +93,10 @@ def test_mesh_validation_before_device_work():
     with pytest.raises(D.DgsweError) as ei:
         _create(W.Mesh(m.xy, m.hb, t3, m.bnd, m.bnd_type))
     assert ei.value.status == 2
-    with pytest.raises(D.DgsweError) as ei:
-        _create(m, p=2)
-    assert ei.value.status == 1
+    for bad_p in (0, 3):
+        with pytest.raises(D.DgsweError) as ei:
+            _create(m, p=bad_p)
+        assert ei.value.status == 1
     with pytest.raises(D.DgsweError) as ei:
         _create(m, h0=-1.0)
     assert ei.value.status == 1
@@ -114,7 +115,7 @@ def test_batch_validation_before_device_work():
         D.dgswe_create_batch([], D.dgswe_default_params())
     assert ei.value.status == 1
     with pytest.raises(D.DgsweError) as ei:
-        D.dgswe_create_batch([m, m], D.params_from_dict(dict(p=2)))
+        D.dgswe_create_batch([m, m], D.params_from_dict(dict(p=3)))
     assert ei.value.status == 1
     L = D.load_library()
     assert L.dgswe_member_count(None) == 0
