@@ -14,8 +14,9 @@ against 8 TB/s), under "variants" the same workload in mixed precision
 (FP32 momentum and flux arithmetic, FP64 elevation and wet/dry) and a
 batched storm-surge ensemble (64 coastal meshes of 50k-500k triangles,
 19.5M in total, each with its own hurricane track and Manning n, mixed
-precision, one launch per stage for all members), and the FP64 CPU oracle
-timed on a bounded sample of the same workload on the host cores.
+precision, one launch per stage for all members), the same 4M workload at
+p = 2 (six modes per variable) in FP64 and mixed precision, and the FP64
+CPU oracle timed on a bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -56,13 +57,27 @@ B_ALG_FP64 = 315.0
 B_ALG_MIXED = 217.0
 
 
+# p = 2, per element and launch (averaged over the two stages), every array
+# loaded once.  k_pp2: raw state in 144 (mixed 96) + vertex bathymetry 24 +
+# neighbour ids 12 + post-processed record out 144 (96).  k_rhs2: record in
+# 144 (96) + RK base (second stage only) 72 (48) + vertex bathymetry 24 +
+# area and inradius 16 + basis gradients 32 (16) + node ids 16 + edge ids 12
+# + neighbour ids 12 + edge normal, length and orientation 48 (1.5 edges per
+# element) + mean bathymetry 8 + Manning n 8 (4) + nodal forcing 12 (0.5
+# nodes per element) + state out 144 (96).
+B_ALG_P2 = {("k_pp2", "fp64"): 324.0, ("k_rhs2", "fp64"): 548.0,
+            ("k_pp2", "mixed"): 228.0, ("k_rhs2", "mixed"): 408.0}
+
+
 def algorithmic_bytes(kernel: str, ne: int, ned: int, nn: int, precision: str = "fp64") -> float:
-    """Algorithmic bytes of one launch: k_stage carries the whole stage
-    (B_ALG_FP64 or B_ALG_MIXED per element); k_forcing reads node
-    coordinates and writes the nodal wind stress and pressure (40 B per
-    node)."""
+    """Algorithmic bytes of one launch: k_stage carries the whole p = 1
+    stage (B_ALG_FP64 or B_ALG_MIXED per element), k_pp2 and k_rhs2 the
+    p = 2 stage (B_ALG_P2); k_forcing reads node coordinates and writes the
+    nodal wind stress and pressure (40 B per node)."""
     if kernel == "k_stage":
         return (B_ALG_MIXED if precision == "mixed" else B_ALG_FP64) * ne
+    if (kernel, precision) in B_ALG_P2:
+        return B_ALG_P2[(kernel, precision)] * ne
     if kernel == "k_forcing":
         return 40.0 * nn
     raise KeyError(kernel)
@@ -203,16 +218,22 @@ def cpu_baseline(wl, target_s=12.0):
                       f"{secs:.1f} s, OpenMP threads={threads}"}
 
 
-def measure(wl, precision, steps, warmup, stream, profile):
+def measure(wl, precision, steps, warmup, stream, profile, order=1):
     """Create the solver on `stream`, warm up, time `steps` steps with the
     stream synchronised on both sides; returns (elapsed s, solver info,
-    per-kernel HIP-event times, diagnostics)."""
+    per-kernel HIP-event times, diagnostics).  order 2: p = 2 with CFL 0.1,
+    starting from the p = 1 initial state with zero quadratic modes."""
     import torch
     from paper_2508_21208_amd.dgswe import DGSWE_FP64, DGSWE_MIXED, Solver, dgswe_profile, dgswe_profile_read
     prm = dict(wl.params, precision=DGSWE_MIXED if precision == "mixed" else DGSWE_FP64)
+    w0 = wl.w0
+    if order == 2:
+        prm.update(p=2, cfl=0.1)
+        w0 = np.zeros((3, 6, wl.w0.shape[2]))
+        w0[:, :3] = wl.w0
     s = Solver(wl.mesh, prm, wl.forcing, hip_stream=stream.cuda_stream)
     info = s.info()
-    s.set_state(wl.w0, 0.0, wl.postprocess_initial)
+    s.set_state(w0, 0.0, wl.postprocess_initial)
     log(f"{precision}: solver ready: {info['n_elems']} elements, {info['n_edges']} edges")
     s.step(warmup)
     s.diagnostics()
@@ -298,6 +319,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble variant")
+    ap.add_argument("--no-p2", action="store_true", help="skip the p = 2 variants")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline run (fp64 is the metric's)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -341,6 +363,15 @@ def main():
                            "kernels": k2, "t_end": d2["t"]}
         if k2:
             log(f"{other} kernels: " + json.dumps(k2))
+    if not args.no_p2:
+        for prec in ("fp64", "mixed"):
+            el4, _, k4, d4 = measure(wl, prec, args.steps, args.warmup, stream, profile, order=2)
+            variants["p2_" + prec] = {"value": ne * 2 * args.steps / el4, "unit": "elem-stage/s", "p": 2,
+                                      "precision": prec, "ms_per_step": 1e3 * el4 / args.steps,
+                                      "roofline": roofline(k4, ne, ned, nn, prec, with_traffic=False),
+                                      "kernels": k4, "t_end": d4["t"]}
+            if k4:
+                log(f"p2 {prec} kernels: " + json.dumps(k4))
     if not args.no_batched:
         el3, ne3, nm3, k3 = measure_batched(args.steps, args.warmup, stream, profile)
         variants["batched"] = {"value": ne3 * 2 * args.steps / el3, "unit": "elem-stage/s",

@@ -24,10 +24,12 @@
  *   - Element vertices are counter-clockwise; local edge l of an element lies
  *     opposite its vertex l.  The reference triangle has vertices (-1,-1),
  *     (1,-1), (-1,1) mapped to the element's vertices 0, 1, 2.
- *   - State layout w[(var*3 + mode)*n_elems + e] in FP64, var in
- *     {zeta [m], Qx [m^2/s], Qy [m^2/s]}, modes in the order
- *     [phi_00 = 1, phi_10 = (1 + 2 xi + eta)/2, phi_01 = (1 + 3 eta)/2],
- *     elements in the caller's order.  The library reorders elements
+ *   - State layout w[(var*nm + mode)*n_elems + e] in FP64, var in
+ *     {zeta [m], Qx [m^2/s], Qy [m^2/s]}, nm = 3 modes per variable at
+ *     p = 1 and 6 at p = 2, in the order of the Dubiner basis (Sec. 2.2)
+ *     [phi_00 = 1, phi_10 = A, phi_01 = (1 + 3 eta)/2, phi_20 = (3 A^2 - B^2)/2,
+ *     phi_11 = A (3 + 5 eta)/2, phi_02 = (5 eta^2 + 2 eta - 1)/2] with
+ *     A = (1 + 2 xi + eta)/2, B = (1 - eta)/2, elements in the caller's order.  The library reorders elements
  *     internally; this is never visible at the boundary.
  *   - Every pointer argument is HOST memory, read only during the call; the
  *     caller keeps ownership and may free it when the call returns.  Output
@@ -65,7 +67,7 @@ enum { DGSWE_BC_LAND = 1, DGSWE_BC_OCEAN = 2, DGSWE_BC_RIVER = 3 /* reserved: re
 enum { DGSWE_FP64 = 0, DGSWE_MIXED = 1 };
 
 typedef struct {
-  int32_t p;         /* polynomial degree: 1 */
+  int32_t p;         /* polynomial degree: 1 or 2 (all members of a batch) */
   int32_t precision; /* DGSWE_FP64, or DGSWE_MIXED (see below) */
   double g;          /* gravity [m/s^2], e.g. 9.81 */
   double rho0;       /* water density [kg/m^3], e.g. 1000 */
@@ -86,7 +88,17 @@ typedef struct {
  * in FP32.  Each edge's mass flux is added to one element and subtracted
  * from the other in FP64, so the total mass is conserved to FP64 rounding
  * in both modes.  States cross this interface as FP64 in both modes (the
- * momentum rounded to FP32 on dgswe_set_state). */
+ * momentum rounded to FP32 on dgswe_set_state).
+ *
+ * Degree p = 2 (the paper builds p = 1 and states that the formulation
+ * extends to higher degrees, Sec. 2.2): six modes per variable, a degree-4
+ * six-point area rule and four-point Gauss-Lobatto edges; the limiter keeps
+ * an element's quadratic modes unless the p = 1 limiter would act on its
+ * linear part or the full field leaves the neighbour-mean range at a vertex
+ * or an edge midpoint (then the element is limited as a p = 1 element); the
+ * wet/dry step drops the quadratic modes of an element whose depth falls
+ * below H0 at a vertex or an edge midpoint and then applies the p = 1 rule.
+ * The CFL number should be smaller than at p = 1 (about 0.1). */
 
 /* Fill `p` with the defaults: p=1, FP64, g=9.81, rho0=1000, h0=0.01,
  * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1. */
@@ -106,8 +118,8 @@ void dgswe_default_params(dgswe_params *p);
  *   out: receives the handle (NULL on error).
  * Validation: indices in range, positive (counter-clockwise) area, no edge
  * shared by more than two triangles, every boundary edge typed exactly
- * once -> otherwise DGSWE_E_MESH; DGSWE_BC_RIVER, p != 1 or an unsupported
- * precision -> DGSWE_E_INVALID.  The initial state is zero at t = 0. */
+ * once -> otherwise DGSWE_E_MESH; DGSWE_BC_RIVER, p not 1 or 2, or an
+ * unsupported precision -> DGSWE_E_INVALID.  The initial state is zero at t = 0. */
 dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const double *node_hb,
                                int32_t n_elems, const int32_t *tri, int32_t n_bnd,
                                const int32_t *bnd_nodes, const int32_t *bnd_type,

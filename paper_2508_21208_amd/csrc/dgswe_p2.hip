@@ -22,6 +22,8 @@
 // Precision as in the p = 1 path: QT is the storage type of the momentum
 // modes and the arithmetic type of flux, volume and source terms; zeta,
 // bathymetry, the post-processing and the zeta update stay FP64.
+#include <cstdlib>
+
 #include "dgswe_device.h"
 
 namespace dgswe {
@@ -244,23 +246,29 @@ HD void load_pp2(const DevMesh &m, const Params &p, CSt<QT> w, int e, bool pp, d
 }
 
 // ---------------------------------------------------------------- edge
-// Trace at parameter s of local edge l of the state (zb, qb) if pick_b,
-// else (za, qa).
-template <class R>
-HD void trace_sel(bool pick_b, const double za[6], const R qa[12], const double zb[6], const R qb[12], int l,
-                  double s, double &tz, R &tx, R &ty) {
-  double xi, eta, f[6];
-  edge_point2(l, s, xi, eta);
-  basis2(xi, eta, f);
-  double sz = 0.0;
-  R sx = (R)0, sy = (R)0;
-  for (int k = 0; k < 6; ++k) {
-    const R fk = (R)f[k];
-    sz += (pick_b ? zb[k] : za[k]) * f[k];
-    sx += (pick_b ? qb[k] : qa[k]) * fk;
-    sy += (pick_b ? qb[6 + k] : qa[6 + k]) * fk;
+// Traces of record r (element id) at the four points of its local edge l;
+// rev: the points in the opposite direction (the e- side of an edge).  The
+// record is read here (from cache: it was read before), so only the traces
+// stay in registers.
+template <class QT>
+HD void traces_of(const Rec2<QT> *__restrict__ u, int r, int l, bool rev, double tz[4], QT tx[4], QT ty[4]) {
+  double z[6];
+  QT q[12];
+  load_rec<QT>(u, r, z, q);
+  for (int g = 0; g < 4; ++g) {
+    double xi, eta, f[6];
+    edge_point2(l, rev ? -gl4_s(g) : gl4_s(g), xi, eta);
+    basis2(xi, eta, f);
+    double sz = 0.0;
+    QT sx = (QT)0, sy = (QT)0;
+    for (int k = 0; k < 6; ++k) {
+      const QT fk = (QT)f[k];
+      sz += z[k] * f[k];
+      sx += q[k] * fk;
+      sy += q[6 + k] * fk;
+    }
+    tz[g] = sz; tx[g] = sx; ty[g] = sy;
   }
-  tz = sz; tx = sx; ty = sy;
 }
 
 // bathymetry at point g of an edge with end values hA (s = -1), hB (s = +1)
@@ -315,13 +323,10 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   const size_t ne = (size_t)m.ne;
   const int e = k.c0 + i;
 
-  double z[6];
-  R q[12];
-  load_rec<QT>(u, e, z, q);
   double h[3];
   for (int j = 0; j < 3; ++j) h[j] = m.hbv[j * ne + e];
   const double hm = mean3(h);
-  const bool wet = p.wetdry ? (z[0] + hm > p.h0) : true;
+  const bool wet = p.wetdry ? (u[e].z[0] + hm > p.h0) : true;
   const double2 ai = m.eai[e];
   const double iA = rcp_nr(ai.x);
 
@@ -367,7 +372,12 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   R rq[12];
   for (int j = 0; j < 12; ++j) rq[j] = (R)0;
   {
+    // the element's own record, live during the area integrals only
+    double z[6];
+    R q[12];
+    load_rec<QT>(u, e, z, q);
     const R gr = (R)p.g, gn2 = gr * man * man, irho = (R)(1.0 / p.rho0), h0 = (R)p.h0;
+#pragma unroll 1
     for (int qd = 0; qd < 6; ++qd) {
       double L[3], wq;
       area_point2(qd, L, wq);
@@ -395,12 +405,16 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
       const R Fz[2] = {qx * w, qy * w};
       const R Fx[2] = {(qx * uu + ph) * w, qx * vv * w};
       const R Fy[2] = {qy * uu * w, (qy * vv + ph) * w};
+      // grad phi_j . F = d_j0 (J^-T e1 . F) + d_j1 (J^-T e2 . F): the flux in
+      // reference components, then the reference gradients
+      const R Gz1 = c1x * Fz[0] + c1y * Fz[1], Gz2 = c2x * Fz[0] + c2y * Fz[1];
+      const R Gx1 = c1x * Fx[0] + c1y * Fx[1], Gx2 = c2x * Fx[0] + c2y * Fx[1];
+      const R Gy1 = c1x * Fy[0] + c1y * Fy[1], Gy2 = c2x * Fy[0] + c2y * Fy[1];
       for (int j = 1; j < 6; ++j) {
-        const R gx = (R)d[j][0] * c1x + (R)d[j][1] * c2x;
-        const R gy = (R)d[j][0] * c1y + (R)d[j][1] * c2y;
-        rz[j] += (double)(gx * Fz[0] + gy * Fz[1]);
-        rq[j] += gx * Fx[0] + gy * Fx[1];
-        rq[6 + j] += gx * Fy[0] + gy * Fy[1];
+        const R d0 = (R)d[j][0], d1 = (R)d[j][1];
+        rz[j] += (double)(d0 * Gz1 + d1 * Gz2);
+        rq[j] += d0 * Gx1 + d1 * Gx2;
+        rq[6 + j] += d0 * Gy1 + d1 * Gy2;
       }
       if (wet) {
         const R Hf = fmax(H, h0);
@@ -434,10 +448,7 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
     const int f = m.el_nb[(size_t)l * ne + e];
     // the other element (itself on a boundary edge, which has no e- side)
     const int o = f >= 0 ? f : e;
-    double oz[6];
-    R oq[12];
-    load_rec<QT>(u, o, oz, oq);
-    const bool owet = p.wetdry ? (oz[0] + m.hmean[o] > p.h0) : true;
+    const bool owet = p.wetdry ? (u[o].z[0] + m.hmean[o] > p.h0) : true;
     // bathymetry at the edge ends (s = -1: vertex lp+1 of e+, which is
     // vertex lm+2 of e-; s = +1: vertex lp+2 of e+, vertex lm+1 of e-)
     const int va = minus ? (lm == 0 ? 2 : lm - 1) : (lp == 2 ? 0 : lp + 1);
@@ -447,16 +458,17 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
     const bool ghost = type != 0;
     const bool wetp = minus ? owet : wet;
     const bool wetm = ghost ? (p.wetdry ? (zb + 0.5 * (hA + hB) > p.h0) : true) : (minus ? wet : owet);
-    // e+ / e- trace at point g, both elements running the same instructions
-    // on the same operands (the states are selected, not the code)
-    auto tr = [&](int g, double &pz, R &px, R &py, double &mz, R &mx, R &my) {
-      trace_sel<R>(minus, z, q, oz, oq, lp, gl4_s(g), pz, px, py);
-      if (ghost) {
-        mz = zb; mx = px; my = py;
-      } else {
-        trace_sel<R>(!minus, z, q, oz, oq, lm, -gl4_s(g), mz, mx, my);
-      }
-    };
+    // e+ and e- traces, both elements of the edge running the same
+    // instructions on the same records (the records are selected, not the
+    // code); a ghost e- side is (zeta_b, momentum of e+)
+    double pz[4], mz[4];
+    R px[4], py[4], mx[4], my[4];
+    traces_of<QT>(u, minus ? o : e, lp, false, pz, px, py);
+    if (ghost) {
+      for (int g = 0; g < 4; ++g) { mz[g] = zb; mx[g] = px[g]; my[g] = py[g]; }
+    } else {
+      traces_of<QT>(u, minus ? e : o, lm, true, mz, mx, my);
+    }
     int kind;
     if (type == DGSWE_BC_LAND) kind = EK_WALL_P;
     else if (!wetp && !wetm) kind = EK_NONE;
@@ -464,12 +476,9 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
     else {
       // one side dry: the sign of the LLF mass flux decides
       R mf = (R)0;
-#pragma unroll 1
       for (int g = 0; g < 4; ++g) {
-        double pz, mz;
-        R px, py, mx, my, Fg[3];
-        tr(g, pz, px, py, mz, mx, my);
-        llf<R>(p.g, pz, px, py, mz, mx, my, edge_hb(hA, hB, g), nx, ny, wetp, wetm, Fg);
+        R Fg[3];
+        llf<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], edge_hb(hA, hB, g), nx, ny, wetp, wetm, Fg);
         mf += (R)gl4_w(g) * Fg[0];
       }
       const bool flood = wetp ? (mf > (R)0) : (mf < (R)0);
@@ -481,13 +490,11 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
     const double hlA = eb.x * iA;
 #pragma unroll 1
     for (int g = 0; g < 4; ++g) {
-      double pz, mz;
-      R px, py, mx, my, Fg[3];
-      tr(g, pz, px, py, mz, mx, my);
+      R Fg[3];
       const double hq = edge_hb(hA, hB, g);
-      if (kind == EK_WALL_P) wall<R>(p.g, pz, px, py, hq, nx, ny, wetp, Fg);
-      else if (kind == EK_WALL_M) wall<R>(p.g, mz, mx, my, hq, -nx, -ny, wetm, Fg);
-      else llf<R>(p.g, pz, px, py, mz, mx, my, hq, nx, ny, wetp, wetm, Fg);
+      if (kind == EK_WALL_P) wall<R>(p.g, pz[g], px[g], py[g], hq, nx, ny, wetp, Fg);
+      else if (kind == EK_WALL_M) wall<R>(p.g, mz[g], mx[g], my[g], hq, -nx, -ny, wetm, Fg);
+      else llf<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], hq, nx, ny, wetp, wetm, Fg);
       // own basis at the point (e- runs the edge backwards)
       double xi, eta, fb[6];
       edge_point2(l, minus ? -gl4_s(g) : gl4_s(g), xi, eta);
@@ -504,6 +511,9 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   }
 
   // inverse mass diagonal and the RK combination
+  double z[6];
+  R q[12];
+  load_rec<QT>(u, e, z, q);
   double bz[6];
   R bq[12];
   if (STAGE) load_rec<QT>(base, e, bz, bq);
@@ -528,8 +538,10 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   return fin;
 }
 
-template <class QT, int STAGE>
-__global__ __launch_bounds__(kBlock) void k_rhs2(DevMesh m, DevState s, Params p, const Rec2<QT> *__restrict__ u,
+// WPE: minimum waves per SIMD the register allocation is held to
+template <class QT, int STAGE, int WPE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_rhs2(
+    DevMesh m, DevState s, Params p, const Rec2<QT> *__restrict__ u,
                                                  const Rec2<QT> *__restrict__ base, St<QT> wout, int slot,
                                                  int want_dt) {
   __shared__ double red[kBlock / 64];
@@ -582,6 +594,10 @@ __global__ __launch_bounds__(kBlock) void k_post_only2(DevMesh m, Params p, CSt<
 }
 
 // ---------------------------------------------------------------- launchers
+// register budget of k_rhs2 (waves per SIMD), overridable with the
+// environment variable DGSWE_RHS2_WPE = 1..4
+constexpr int kRhs2WpeFp64 = 2, kRhs2WpeMixed = 2;
+
 static inline unsigned nblk2(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <class QT>
@@ -598,8 +614,24 @@ static void stage2_qt(const DevMesh &m, const DevState &s, const Params &p, cons
     else hipLaunchKernelGGL((k_pp2<QT, 0>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, a, r, slot);
   }
   if (!pp_only) {
-    if (stage) hipLaunchKernelGGL((k_rhs2<QT, 1>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, slot, want_dt);
-    else hipLaunchKernelGGL((k_rhs2<QT, 0>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, slot, want_dt);
+    static const int wpe = [] {
+      const char *ev = std::getenv("DGSWE_RHS2_WPE");
+      const int w = ev ? std::atoi(ev) : 0;
+      return (w >= 1 && w <= 4) ? w : (sizeof(QT) == 8 ? kRhs2WpeFp64 : kRhs2WpeMixed);
+    }();
+#define DGSWE_RHS2(S, W) \
+  hipLaunchKernelGGL((k_rhs2<QT, S, W>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, slot, want_dt)
+#define DGSWE_RHS2_W(S)                \
+  switch (wpe) {                       \
+    case 1: DGSWE_RHS2(S, 1); break;   \
+    case 2: DGSWE_RHS2(S, 2); break;   \
+    case 3: DGSWE_RHS2(S, 3); break;   \
+    default: DGSWE_RHS2(S, 4); break;  \
+  }
+    if (stage) { DGSWE_RHS2_W(1) }
+    else { DGSWE_RHS2_W(0) }
+#undef DGSWE_RHS2_W
+#undef DGSWE_RHS2
   }
 }
 
