@@ -153,8 +153,53 @@ typedef struct {
 dgswe_status dgswe_create_batch(int32_t n_meshes, const dgswe_mesh *meshes, const dgswe_params *prm,
                                 void *hip_stream, dgswe_solver **out);
 
-/* Number of meshes in the batch (0 for NULL). */
+/* Number of member slots (meshes of a batch, capacity of a pool; 0 for
+ * NULL). */
 int32_t dgswe_member_count(const dgswe_solver *s);
+
+/* A serving pool: an empty batch whose members join and leave between
+ * dgswe_step calls (continuous batching; the spec serving loop).  The
+ * device memory is reserved here once: room for max_elems elements in total
+ * (with the matching node, halo and edge storage) and max_members member
+ * slots.  A joining mesh takes a contiguous range of each store (first
+ * fit); a leaving one gives it back.  Every step advances all members
+ * present, each with its own forcing, time, dt and status, with one kernel
+ * launch per stage over exactly the present members' work; a member's
+ * results do not depend on what else is in the pool (bitwise).  Members
+ * are addressed by slot (the member calls above).  Capacity out of range
+ * (max_elems in [1, 2^30 - 1], max_members in [1, 65536]) or invalid
+ * params -> DGSWE_E_INVALID; device memory exhausted -> DGSWE_E_NOMEM. */
+dgswe_status dgswe_create_pool(int64_t max_elems, int32_t max_members, const dgswe_params *prm, void *hip_stream,
+                               dgswe_solver **out);
+
+/* A mesh after host-only preprocessing (validation, element ordering, halo
+ * and edge tables) for the order and precision of `prm`: thread safe, no
+ * device work, so a serving loop can prepare arriving requests while the
+ * device steps.  Errors as dgswe_create_mesh. */
+typedef struct dgswe_prepared dgswe_prepared;
+dgswe_status dgswe_prepare_mesh(const dgswe_mesh *mesh, const dgswe_params *prm, dgswe_prepared **out);
+void dgswe_prepared_free(dgswe_prepared *p);
+int64_t dgswe_prepared_elems(const dgswe_prepared *p);
+
+/* Admit a prepared mesh into a free slot of a pool (state zero at t = 0, no
+ * forcing; then dgswe_member_set_forcing / dgswe_member_set_state).  On
+ * success the pool owns `p` (do not free it) and *member receives the slot.
+ * Admission is by memory: no free slot or no contiguous room in some store
+ * -> DGSWE_E_NOMEM and the pool is unchanged (the caller keeps `p`); `p`
+ * prepared for another order p, or `s` not a pool -> DGSWE_E_INVALID.
+ * Waits for the stream (the step tables are rewritten). */
+dgswe_status dgswe_member_add_prepared(dgswe_solver *s, dgswe_prepared *p, int32_t *member);
+
+/* dgswe_prepare_mesh + dgswe_member_add_prepared in one call. */
+dgswe_status dgswe_member_add(dgswe_solver *s, const dgswe_mesh *mesh, int32_t *member);
+
+/* Release a member's slot and storage (waits for the stream; read its state
+ * first).  Empty slot or not a pool -> DGSWE_E_INVALID. */
+dgswe_status dgswe_member_remove(dgswe_solver *s, int32_t member);
+
+/* Pool occupancy: out[0] elements in use, out[1] element capacity,
+ * out[2] members present, out[3] slots, out[4] device bytes held. */
+dgswe_status dgswe_pool_usage(const dgswe_solver *s, int64_t out[5]);
 
 /* Replace the modal state (layout above, caller's element order) and set the
  * time to t; resets the step counter.  `w` is copied before the call returns.

@@ -1,11 +1,22 @@
 // C ABI of the gfx950 DG shallow-water step: solver lifetime for a batch
-// of independent meshes (a single mesh is a batch of one), host<->device
-// transfers (with each mesh's internal element permutation), the per-step
-// launch sequence and HIP-event kernel timing.
+// of independent meshes (a single mesh is a batch of one) or a serving pool
+// whose members join and leave between steps, host<->device transfers (with
+// each mesh's internal element permutation), the per-step launch sequence
+// and HIP-event kernel timing.
+//
+// Device memory layout.  Every per-element, per-node, per-local-element,
+// per-local-edge, ring-2 and per-edge array of the kernels is one arena of
+// fixed capacity; a member occupies one contiguous range of each arena
+// (first fit, freed ranges coalesce), with every stored id shifted into the
+// arena's index space.  Structure-of-arrays rows have the arena capacity as
+// their stride.  The chunk records list the chunks of the active members
+// only and are rebuilt when a member joins or leaves, so a step launches one
+// grid over exactly the active work.  A batch is a pool sized to its meshes.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <thread>
 #include <vector>
@@ -21,14 +32,79 @@ thread_local std::string g_create_error = "no error";
 enum KernelId { K_FORCING = 0, K_STAGE, K_PP2, K_RHS2, K_COUNT };
 const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage", "k_pp2", "k_rhs2"};
 
-// Host view of one member of a batch.
+// First-fit allocator over [0, cap) with coalescing of freed ranges.
+class Arena {
+ public:
+  void init(long long cap) {
+    cap_ = cap;
+    free_.clear();
+    if (cap > 0) free_[0] = cap;
+  }
+  bool take(long long n, long long &off) {
+    if (n <= 0) { off = 0; return true; }
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      off = it->first;
+      const long long rest = it->second - n;
+      free_.erase(it);
+      if (rest > 0) free_[off + n] = rest;
+      return true;
+    }
+    return false;
+  }
+  void give(long long off, long long n) {
+    if (n <= 0) return;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  long long cap() const { return cap_; }
+  long long free_total() const {
+    long long t = 0;
+    for (auto &kv : free_) t += kv.second;
+    return t;
+  }
+
+ private:
+  long long cap_ = 0;
+  std::map<long long, long long> free_;
+};
+
+// arenas: elements, nodes, local elements (chunk + ring 1 of each chunk),
+// chunk-local edges, ring-2 entries (+1 sentinel per member), edges (p = 2)
+enum ArenaId { A_ELEM = 0, A_NODE, A_LOC, A_LEDGE, A_RING2, A_EDGE, A_COUNT };
+
+// Host view of one member (slot).
 struct MemberHost {
+  bool active = false;
   std::vector<int> perm;   // internal (member-local) -> caller element
   int ne = 0, nn = 0, ned = 0, nbnd = 0;
   bool cur_is_pp = true;   // its stored state is already post-processed
   bool holland = false;    // moving vortex (nodal forcing recomputed per stage)
+  bool man_elem = false;   // per-element Manning n (else the member's uniform slot)
+  long long off[A_COUNT] = {}, len[A_COUNT] = {};
+  // chunks relative to the member's ranges: c0, cc, n1, h2o, n2, leo, ne_loc, lo
+  std::vector<int> chunks;
+  int nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
 };
+constexpr int kChunkHost = 8;
 }  // namespace
+
+// A mesh after host preprocessing, not yet on the device.
+struct dgswe_prepared {
+  dgswe::Prep P;
+  int order = 1;
+};
 
 struct dgswe_solver {
   dgswe_params uprm{};
@@ -36,7 +112,11 @@ struct dgswe_solver {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int device = 0;
-  int nn = 0, ne = 0, ned = 0, nbnd = 0;
+  int nn = 0, ne = 0, ned = 0, nbnd = 0;   // sums over the active members
+  Arena arena[A_COUNT];
+  int chunk_cap = 0;            // capacity of the chunk-record array
+  bool is_pool = false;         // members may join and leave
+  size_t dev_bytes = 0;         // device memory held
   std::vector<MemberHost> mh;
   std::vector<Member> mem;      // host mirror of the device member table
   Member *d_mem = nullptr;
@@ -50,7 +130,8 @@ struct dgswe_solver {
   DevMesh m{};
   DevState s{};
   double *d_diag = nullptr;
-  double *rb = nullptr;         // FP64 [3 nm][largest member] read-back buffer
+  double *rb = nullptr;         // FP64 [3 nm][rb_elems] read-back buffer (grown on demand)
+  size_t rb_elems = 0;
   long long steps_enq = 0;
   int block = 256;              // workgroup size of the stage kernel
   int cur = 0;                  // buffer holding w^n
@@ -85,7 +166,10 @@ template <class T>
 hipError_t dev_alloc(dgswe_solver *S, T **p, size_t n) {
   void *q = nullptr;
   hipError_t e = hipMalloc(&q, n * sizeof(T) + 16);
-  if (e == hipSuccess) S->allocs.push_back(q);
+  if (e == hipSuccess) {
+    S->allocs.push_back(q);
+    S->dev_bytes += n * sizeof(T) + 16;
+  }
   *p = (T *)q;
   return e;
 }
@@ -103,6 +187,9 @@ hipError_t upload(dgswe_solver *S, const T **dst, const std::vector<T> &v) {
 void free_all(dgswe_solver *S) {
   for (void *p : S->allocs) (void)hipFree(p);
   S->allocs.clear();
+  if (S->rb) (void)hipFree(S->rb);
+  S->rb = nullptr;
+  S->rb_elems = 0;
   for (auto &r : S->recs) { S->pool.push_back(r.a); S->pool.push_back(r.b); }
   S->recs.clear();
   for (hipEvent_t ev : S->pool) (void)hipEventDestroy(ev);
@@ -186,61 +273,46 @@ dgswe_status sync_members(dgswe_solver *S) {
 dgswe_status check_member(dgswe_solver *S, int32_t member) {
   if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
   if (member < 0 || member >= (int32_t)S->mh.size()) return fail(S, DGSWE_E_INVALID, "member out of range");
+  if (!S->mh[(size_t)member].active) return fail(S, DGSWE_E_INVALID, "member slot is empty");
   return DGSWE_OK;
 }
 
-dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgswe_params *prm, void *hip_stream,
-                         dgswe_solver **out) {
-  if (!out) return fail(nullptr, DGSWE_E_INVALID, "out is NULL");
-  *out = nullptr;
-  if (n_members < 1 || !meshes) return fail(nullptr, DGSWE_E_INVALID, "a batch needs at least one mesh");
-  std::string msg;
-  if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
-  // chunk size and workgroup size of the stage kernel
-  int chunk = 256, block = 256;
+// Host preprocessing of one mesh for the solver's order and chunking.
+int prep_one(const dgswe_mesh &d, int order, int chunk, int block, Prep &P, std::string &msg) {
+  int rc = prepare_mesh(d.n_nodes, d.node_xy, d.node_hb, d.n_elems, d.tri, d.n_bnd, d.bnd_nodes, d.bnd_type, P, msg);
+  if (rc != DGSWE_OK) return rc;
+  build_chunks(P, chunk);
+  // (the p = 2 kernels use only the chunk ranges, not the halos)
+  if (order == 1 && (P.nl_max > 2 * block || P.ed_max > 2 * block)) {
+    msg = "element chunks have halos too large for the stage kernel";
+    return DGSWE_E_MESH;
+  }
+  if (order == 2) p2_records(P);
+  return DGSWE_OK;
+}
+
+// entries each arena needs for a prepared mesh
+void arena_need(const Prep &q, int order, long long need[A_COUNT]) {
+  need[A_ELEM] = q.ne;
+  need[A_NODE] = q.nn;
+  need[A_LOC] = q.lo_off[q.nch];
+  need[A_LEDGE] = q.le_off[q.nch];
+  need[A_RING2] = (long long)q.h2_off[q.nch] + 1;
+  need[A_EDGE] = order == 2 ? q.ned : 0;
+}
+
+bool chunk_config(int &chunk, int &block) {
+  chunk = 256;
+  block = 256;
   if (const char *ev = std::getenv("DGSWE_CHUNK")) chunk = std::atoi(ev);
   if (const char *ev = std::getenv("DGSWE_BLOCK")) block = std::atoi(ev);
-  if (!stage_block_ok(block) || chunk < 64 || chunk > block)
-    return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
-  std::vector<Prep> parts((size_t)n_members);
-  long long ne_total = 0;
-  for (int32_t i = 0; i < n_members; ++i) ne_total += meshes[i].n_elems > 0 ? meshes[i].n_elems : 0;
-  if (ne_total > 0x7fffffffLL) return fail(nullptr, DGSWE_E_INVALID, "more than 2^31 - 1 elements in the batch");
-  // host preprocessing of the meshes, several at a time (each thread owns
-  // whole meshes; the first failing mesh in order is reported)
-  std::vector<int> rcs((size_t)n_members, DGSWE_OK);
-  std::vector<std::string> msgs((size_t)n_members);
-  {
-    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    const int nt = (int)std::min<unsigned>(hw, (unsigned)n_members);
-    auto work = [&](int t0) {
-      for (int i = t0; i < n_members; i += nt) {
-        const dgswe_mesh &d = meshes[i];
-        rcs[i] = prepare_mesh(d.n_nodes, d.node_xy, d.node_hb, d.n_elems, d.tri, d.n_bnd, d.bnd_nodes, d.bnd_type,
-                              parts[i], msgs[i]);
-        if (rcs[i] != DGSWE_OK) continue;
-        build_chunks(parts[i], chunk);
-        // (the p = 2 kernels use only the chunk ranges, not the halos)
-        if (prm->p == 1 && (parts[i].nl_max > 2 * block || parts[i].ed_max > 2 * block)) {
-          rcs[i] = DGSWE_E_MESH;
-          msgs[i] = "element chunks have halos too large for the stage kernel";
-        }
-      }
-    };
-    std::vector<std::thread> th;
-    for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
-    work(0);
-    for (auto &x : th) x.join();
-  }
-  for (int32_t i = 0; i < n_members; ++i)
-    if (rcs[i] != DGSWE_OK) {
-      msg = n_members > 1 ? "mesh " + std::to_string(i) + ": " + msgs[i] : msgs[i];
-      return fail(nullptr, (dgswe_status)rcs[i], msg);
-    }
-  Prep P;
-  merge_meshes(parts, P);
-  if (prm->p == 2) p2_records(P);
+  return stage_block_ok(block) && chunk >= 64 && chunk <= block;
+}
 
+// Device arrays for the given arena capacities, `slots` members and
+// `chunk_cap` chunk records.
+dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long cap[A_COUNT], int chunk_cap, int slots,
+                          void *hip_stream, dgswe_solver **out) {
   dgswe_solver *S = new (std::nothrow) dgswe_solver();
   if (!S) return fail(nullptr, DGSWE_E_NOMEM, "host allocation failed");
   hipError_t e = hipGetDevice(&S->device);
@@ -258,85 +330,52 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
   S->nm = prm->p == 2 ? 6 : 3;
   S->block = block;
   const bool mixed = S->precision == DGSWE_MIXED;
-  S->nn = P.nn; S->ne = P.ne; S->ned = P.ned; S->nbnd = P.nbnd;
   Params &pp = S->prm;
   pp.g = prm->g; pp.rho0 = prm->rho0; pp.h0 = prm->h0; pp.cfl = prm->cfl;
   pp.dt_fixed = prm->dt_fixed; pp.dt_max = prm->dt_max;
   pp.limiter = prm->limiter ? 1 : 0; pp.wetdry = prm->wetdry ? 1 : 0;
+  for (int a = 0; a < A_COUNT; ++a) S->arena[a].init(cap[a]);
+  S->chunk_cap = chunk_cap;
+  S->mh.resize((size_t)slots);
+  S->mem.assign((size_t)slots, Member{});
+  for (Member &f : S->mem) f.pn = 101300.0;
 
   bool ok = true;
   auto chk = [&](hipError_t x) { if (x != hipSuccess) ok = false; };
-  // members
-  S->mh.resize((size_t)n_members);
-  S->mem.resize((size_t)n_members);
-  std::vector<int> chunk_member;
-  chunk_member.reserve((size_t)P.nch);
-  int e0 = 0, n0 = 0, c0 = 0, big = 0;
-  for (int32_t i = 0; i < n_members; ++i) {
-    MemberHost &h = S->mh[i];
-    const Prep &q = parts[i];
-    h.perm = q.perm;
-    h.ne = q.ne; h.nn = q.nn; h.ned = q.ned; h.nbnd = q.nbnd;
-    big = std::max(big, q.ne);
-    Member f{};
-    f.e0 = e0; f.ne = q.ne; f.n0 = n0; f.nn = q.nn; f.chunk0 = c0; f.nchunk = q.nch;
-    f.holland = 0; f.n_tide = 0; f.tide_offset = 0.0; f.pn = 101300.0;
-    S->mem[i] = f;
-    for (int c = 0; c < q.nch; ++c) chunk_member.push_back(i);
-    e0 += q.ne; n0 += q.nn; c0 += q.nch;
-  }
-  parts.clear();
+  const size_t E = (size_t)std::max(1LL, cap[A_ELEM]), N = (size_t)std::max(1LL, cap[A_NODE]);
+  const size_t L = (size_t)std::max(1LL, cap[A_LOC]), LE = (size_t)std::max(1LL, cap[A_LEDGE]);
+  const size_t R2 = (size_t)std::max(1LL, cap[A_RING2]), D = (size_t)std::max(1LL, cap[A_EDGE]);
   DevMesh &m = S->m;
-  m.ne = P.ne; m.nn = P.nn; m.ned = P.ned;
-  const size_t ne = P.ne, nn = P.nn;
-  chk(upload(S, &m.area, P.area)); chk(upload(S, &m.inr2, P.inr2));
-  chk(upload(S, &m.hbv, P.hbv));
-  chk(upload(S, &m.el_nb, P.el_nb));
-  chk(upload(S, &m.node_x, P.node_x)); chk(upload(S, &m.node_y, P.node_y));
-  m.C = P.C; m.nch = P.nch; m.nl_max = P.nl_max; m.nm_max = P.nm_max; m.ed_max = P.ed_max;
-  m.n2_max = P.n2_max;
-  chunk_records(P, chunk_member, S->chunk_rec);
-  chk(dev_alloc(S, &S->d_chunk_rec, S->chunk_rec.size()));
-  chk(hipMemcpy(S->d_chunk_rec, S->chunk_rec.data(), S->chunk_rec.size() * sizeof(int), hipMemcpyHostToDevice));
+  m = DevMesh{};
+  m.ne = (int)E; m.nn = (int)N; m.ned = 0;
+  auto al = [&](auto **ptr, size_t n) {
+    using T = std::remove_const_t<std::remove_pointer_t<std::remove_reference_t<decltype(*ptr)>>>;
+    T *q = nullptr;
+    chk(dev_alloc(S, &q, n));
+    *ptr = q;
+  };
+  al(&m.area, E); al(&m.inr2, E); al(&m.hbv, 3 * E); al(&m.el_nb, 3 * E);
+  al(&m.node_x, N); al(&m.node_y, N);
+  al(&m.eai, E); al(&m.enode, E);
+  if (mixed) { al(&m.egf, E); al(&m.le_f, LE); }
+  else { al(&m.eg1, E); al(&m.eg2, E); al(&m.le_a, LE); al(&m.le_b, LE); }
+  al(&m.lgid, L); al(&m.lhb01, L); al(&m.lhb2, L); al(&m.lnb, L);
+  al(&m.h2, R2);
+  if (S->order == 2) { al(&m.e2edge, 3 * E); al(&m.hmean, E); al(&m.ed2a, D); al(&m.ed2b, D); }
+  chk(dev_alloc(S, &S->d_chunk_rec, (size_t)std::max(1, chunk_cap) * kChunkRec));
   m.chunk_rec = S->d_chunk_rec;
-  chk(dev_alloc(S, &S->d_man, ne + (size_t)n_members));
-  chk(dev_alloc(S, &S->d_manf, ne + (size_t)n_members));
+  chk(dev_alloc(S, &S->d_man, E + (size_t)slots));
+  chk(dev_alloc(S, &S->d_manf, E + (size_t)slots));
   m.man = S->d_man;
   m.manf = S->d_manf;
-  chk(upload(S, &m.lgid, P.lgid)); chk(upload(S, &m.h2, P.h2));
-  chk(upload(S, &m.eai, P.eai)); chk(upload(S, &m.enode, P.enode));
-  chk(upload(S, &m.lhb01, P.lhb01)); chk(upload(S, &m.lhb2, P.lhb2)); chk(upload(S, &m.lnb, P.lnb));
-  m.eg1 = m.eg2 = m.le_a = m.le_b = nullptr;
-  m.egf = m.le_f = nullptr;
-  if (mixed) {
-    chk(upload(S, &m.egf, P.egf));
-    chk(upload(S, &m.le_f, P.le_f));
-  } else {
-    chk(upload(S, &m.eg1, P.eg1)); chk(upload(S, &m.eg2, P.eg2));
-    chk(upload(S, &m.le_a, P.le_a)); chk(upload(S, &m.le_b, P.le_b));
-  }
-  m.e2edge = nullptr;
-  m.ed2a = m.ed2b = nullptr;
-  m.hmean = nullptr;
-  if (S->order == 2) {
-    chk(upload(S, &m.e2edge, P.el_edge));
-    chk(upload(S, &m.ed2a, P.ed2a)); chk(upload(S, &m.ed2b, P.ed2b));
-    chk(upload(S, &m.hmean, P.hmean));
-  }
-  m.nmem = n_members;
-  chk(dev_alloc(S, &S->d_mem, (size_t)n_members));
-  chk(dev_alloc(S, &S->d_fblk_off, (size_t)n_members + 1));
+  m.C = 0; m.nch = 0; m.nl_max = m.nm_max = m.ed_max = m.n2_max = 1;
+  m.nmem = slots;
+  chk(dev_alloc(S, &S->d_mem, (size_t)slots));
+  chk(dev_alloc(S, &S->d_fblk_off, (size_t)slots + 1));
   m.mem = S->d_mem;
   m.fblk_off = S->d_fblk_off;
-  const size_t lds = stage_lds_bytes(m, S->precision);
-  if (S->order == 1 && lds > 80 * 1024) {
-    free_all(S);
-    delete S;
-    return fail(nullptr, DGSWE_E_MESH, "element chunks have halos too large for the LDS (" +
-                                           std::to_string(lds) + " bytes)");
-  }
   DevState &st = S->s;
-  const size_t sb = state_bytes(ne, S->precision, S->order);
+  const size_t sb = state_bytes(E, S->precision, S->order);
   for (int b = 0; b < 3; ++b) {
     unsigned char *q = nullptr;
     chk(dev_alloc(S, &q, sb));
@@ -347,30 +386,284 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
     chk(dev_alloc(S, &q, sb));
     st.wpp = q;
   }
-  chk(dev_alloc(S, &S->rb, 3 * (size_t)S->nm * (size_t)big));
-  chk(dev_alloc(S, &st.nodal, 3 * nn)); chk(dev_alloc(S, &st.partial, 3 * (size_t)diag_blocks(big)));
-  chk(dev_alloc(S, &st.ctrl, (size_t)n_members)); chk(dev_alloc(S, &S->d_diag, 4));
+  chk(dev_alloc(S, &st.nodal, 3 * N)); chk(dev_alloc(S, &st.partial, 3 * (size_t)diag_blocks((int)E)));
+  chk(dev_alloc(S, &st.ctrl, (size_t)slots)); chk(dev_alloc(S, &S->d_diag, 4));
+  if (ok) {
+    // ring-2 entries are read clamped, so every entry is a valid element id
+    chk(hipMemset((void *)m.h2, 0, R2 * sizeof(int)));
+    chk(hipMemset(S->d_man, 0, (E + (size_t)slots) * sizeof(double)));
+    chk(hipMemset(S->d_manf, 0, (E + (size_t)slots) * sizeof(float)));
+  }
   if (!ok) {
     free_all(S);
     delete S;
-    return fail(nullptr, DGSWE_E_NOMEM, "device allocation or upload failed");
+    return fail(nullptr, DGSWE_E_NOMEM, "device allocation failed");
   }
-  // zero state and forcing, dt of the zero state
-  chk(hipMemsetAsync(st.buf[0], 0, sb, S->stream));
-  chk(hipMemsetAsync(st.nodal, 0, 3 * nn * sizeof(double), S->stream));
-  chk(hipMemsetAsync(S->d_man, 0, (ne + (size_t)n_members) * sizeof(double), S->stream));
-  chk(hipMemsetAsync(S->d_manf, 0, (ne + (size_t)n_members) * sizeof(float), S->stream));
-  for (int32_t i = 0; i < n_members; ++i) {
-    chk(launch_init_state(m, st, pp, st.buf[0], i, S->mem[i].e0, S->mem[i].ne, 0.0, 0, 0, S->precision,
-                          S->order, S->stream));
-  }
-  chk(hipStreamSynchronize(S->stream));
-  if (ok && sync_members(S) != DGSWE_OK) ok = false;
   S->cur = 0;
-  if (!ok) {
+  *out = S;
+  return DGSWE_OK;
+}
+
+template <class T>
+hipError_t put(const T *dst, size_t off, const T *src, size_t n) {
+  if (n == 0) return hipSuccess;
+  return hipMemcpy((T *)dst + off, src, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Place a prepared mesh into free ranges of every arena as member `slot`
+// (state zero at t = 0, no forcing).  DGSWE_E_NOMEM when some arena has no
+// room; the solver is then unchanged.
+dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
+  long long need[A_COUNT], off[A_COUNT];
+  arena_need(q, S->order, need);
+  for (int a = 0; a < A_COUNT; ++a) {
+    if (!S->arena[a].take(need[a], off[a])) {
+      for (int b = 0; b < a; ++b) S->arena[b].give(off[b], need[b]);
+      return fail(S, DGSWE_E_NOMEM, "no room for a mesh of " + std::to_string(q.ne) + " elements (" +
+                                        std::to_string(S->arena[A_ELEM].free_total()) + " elements free)");
+    }
+  }
+  if (S->order == 1) {
+    DevMesh t = S->m;
+    t.nl_max = std::max(t.nl_max, q.nl_max); t.nm_max = std::max(t.nm_max, q.nm_max);
+    t.ed_max = std::max(t.ed_max, q.ed_max); t.n2_max = std::max(t.n2_max, q.n2_max);
+    t.C = q.C;
+    if (stage_lds_bytes(t, S->precision) > 80 * 1024) {
+      for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(off[a], need[a]);
+      return fail(S, DGSWE_E_MESH, "element chunks have halos too large for the LDS");
+    }
+  }
+  const bool mixed = S->precision == DGSWE_MIXED;
+  const DevMesh &m = S->m;
+  const size_t E = (size_t)m.ne, N = (size_t)m.nn, ne = (size_t)q.ne, nn = (size_t)q.nn;
+  const int e0 = (int)off[A_ELEM], n0 = (int)off[A_NODE];
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  chk(put(m.area, e0, q.area.data(), ne));
+  chk(put(m.inr2, e0, q.inr2.data(), ne));
+  {
+    std::vector<int> nb(ne);
+    for (size_t k = 0; k < 3; ++k) {
+      chk(put(m.hbv, k * E + e0, q.hbv.data() + k * ne, ne));
+      for (size_t i = 0; i < ne; ++i) {
+        const int f = q.el_nb[k * ne + i];
+        nb[i] = f < 0 ? -1 : f + e0;
+      }
+      chk(put(m.el_nb, k * E + e0, nb.data(), ne));
+    }
+  }
+  chk(put(m.node_x, n0, q.node_x.data(), nn));
+  chk(put(m.node_y, n0, q.node_y.data(), nn));
+  chk(put(m.eai, e0, q.eai.data(), ne));
+  {
+    std::vector<int4> en(q.enode);
+    for (int4 &v : en) { v.x += n0; v.y += n0; v.z += n0; }
+    chk(put(m.enode, e0, en.data(), ne));
+  }
+  if (mixed) {
+    chk(put(m.egf, e0, q.egf.data(), ne));
+    chk(put(m.le_f, (size_t)off[A_LEDGE], q.le_f.data(), (size_t)need[A_LEDGE]));
+  } else {
+    chk(put(m.eg1, e0, q.eg1.data(), ne));
+    chk(put(m.eg2, e0, q.eg2.data(), ne));
+    chk(put(m.le_a, (size_t)off[A_LEDGE], q.le_a.data(), (size_t)need[A_LEDGE]));
+    chk(put(m.le_b, (size_t)off[A_LEDGE], q.le_b.data(), (size_t)need[A_LEDGE]));
+  }
+  {
+    std::vector<int> g(q.lgid.begin(), q.lgid.begin() + need[A_LOC]);
+    for (int &x : g) x += e0;
+    chk(put(m.lgid, (size_t)off[A_LOC], g.data(), g.size()));
+    chk(put(m.lhb01, (size_t)off[A_LOC], q.lhb01.data(), (size_t)need[A_LOC]));
+    chk(put(m.lhb2, (size_t)off[A_LOC], q.lhb2.data(), (size_t)need[A_LOC]));
+    chk(put(m.lnb, (size_t)off[A_LOC], q.lnb.data(), (size_t)need[A_LOC]));
+    // ring-2 list and a sentinel (the member's first element)
+    std::vector<int> r2((size_t)need[A_RING2], e0);
+    for (int i = 0; i < q.h2_off[q.nch]; ++i) r2[(size_t)i] = q.h2[(size_t)i] + e0;
+    chk(put(m.h2, (size_t)off[A_RING2], r2.data(), r2.size()));
+  }
+  if (S->order == 2) {
+    const int d0 = (int)off[A_EDGE];
+    std::vector<int> code(ne);
+    for (size_t k = 0; k < 3; ++k) {
+      for (size_t i = 0; i < ne; ++i) {
+        const int c = q.el_edge[k * ne + i];
+        code[i] = (((c >> 1) + d0) << 1) | (c & 1);
+      }
+      chk(put(m.e2edge, k * E + e0, code.data(), ne));
+    }
+    chk(put(m.hmean, e0, q.hmean.data(), ne));
+    chk(put(m.ed2a, (size_t)d0, q.ed2a.data(), (size_t)q.ned));
+    chk(put(m.ed2b, (size_t)d0, q.ed2b.data(), (size_t)q.ned));
+  }
+  if (e != hipSuccess) {
+    for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(off[a], need[a]);
+    return hip_fail(S, e, "upload");
+  }
+  MemberHost &h = S->mh[(size_t)slot];
+  h = MemberHost{};
+  h.active = true;
+  h.perm = std::move(q.perm);
+  h.ne = q.ne; h.nn = q.nn; h.ned = q.ned; h.nbnd = q.nbnd;
+  for (int a = 0; a < A_COUNT; ++a) { h.off[a] = off[a]; h.len[a] = need[a]; }
+  h.chunks.resize((size_t)q.nch * kChunkHost);
+  for (int c = 0; c < q.nch; ++c) {
+    int *r = &h.chunks[(size_t)c * kChunkHost];
+    r[0] = q.ch_off[c]; r[1] = q.ch_off[c + 1] - q.ch_off[c];
+    r[2] = q.h1_off[c + 1] - q.h1_off[c];
+    r[3] = q.h2_off[c]; r[4] = q.h2_off[c + 1] - q.h2_off[c];
+    r[5] = q.le_off[c]; r[6] = q.le_off[c + 1] - q.le_off[c];
+    r[7] = q.lo_off[c];
+  }
+  h.nl_max = q.nl_max; h.nm_max = q.nm_max; h.ed_max = q.ed_max; h.n2_max = q.n2_max;
+  S->m.C = q.C;
+  Member f{};
+  f.e0 = e0; f.ne = q.ne; f.n0 = n0; f.nn = q.nn;
+  f.pn = 101300.0;
+  S->mem[(size_t)slot] = f;
+  // zero state (every mode row of the current buffer), forcing and Manning
+  const size_t nm = (size_t)S->nm, qs = mixed ? sizeof(float) : sizeof(double);
+  unsigned char *base = (unsigned char *)S->s.buf[S->cur];
+  for (size_t j = 0; j < nm && e == hipSuccess; ++j)
+    e = hipMemsetAsync(base + (j * E + e0) * sizeof(double), 0, ne * sizeof(double), S->stream);
+  for (size_t j = 0; j < 2 * nm && e == hipSuccess; ++j)
+    e = hipMemsetAsync(base + nm * E * sizeof(double) + (j * E + e0) * qs, 0, ne * qs, S->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(S->s.nodal + 2 * (size_t)n0, 0, 2 * nn * sizeof(double), S->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(S->s.nodal + 2 * N + n0, 0, nn * sizeof(double), S->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(S->d_man + E + slot, 0, sizeof(double), S->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(S->d_manf + E + slot, 0, sizeof(float), S->stream);
+  if (e == hipSuccess)
+    e = launch_init_state(S->m, S->s, S->prm, S->s.buf[S->cur], slot, e0, q.ne, 0.0, (int)(S->steps_enq & 1), 0,
+                          S->precision, S->order, S->stream);
+  if (e != hipSuccess) return hip_fail(S, e, "member initialisation");
+  return DGSWE_OK;
+}
+
+// Chunk records of the active members (slot order), member table, forcing
+// blocks and the mesh maxima; waits for the stream first (the kernels read
+// these tables).
+dgswe_status rebuild(dgswe_solver *S) {
+  hipError_t e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+  DevMesh &m = S->m;
+  const int E = m.ne;
+  S->chunk_rec.clear();
+  int nch = 0;
+  S->nn = S->ne = S->ned = S->nbnd = 0;
+  m.nl_max = m.nm_max = m.ed_max = m.n2_max = 1;
+  for (size_t i = 0; i < S->mh.size(); ++i) {
+    MemberHost &h = S->mh[i];
+    Member &f = S->mem[i];
+    if (!h.active) {
+      f = Member{};
+      f.pn = 101300.0;
+      continue;
+    }
+    const int nc = (int)(h.chunks.size() / kChunkHost);
+    f.chunk0 = nch;
+    f.nchunk = nc;
+    for (int c = 0; c < nc; ++c) {
+      const int *r = &h.chunks[(size_t)c * kChunkHost];
+      int rec[kChunkRec] = {};
+      rec[0] = f.e0 + r[0]; rec[1] = r[1];
+      rec[2] = 0; rec[3] = r[2];
+      rec[4] = (int)h.off[A_RING2] + r[3]; rec[5] = r[4];
+      rec[6] = (int)h.off[A_LEDGE] + r[5]; rec[7] = r[6];
+      rec[8] = (int)h.off[A_LOC] + r[7];
+      rec[9] = (int)i;
+      rec[10] = c == 0 ? 1 : 0;
+      rec[11] = h.man_elem ? f.e0 + r[0] : E + (int)i;
+      rec[12] = h.man_elem ? 1 : 0;
+      S->chunk_rec.insert(S->chunk_rec.end(), rec, rec + kChunkRec);
+      ++nch;
+    }
+    S->nn += h.nn; S->ne += h.ne; S->ned += h.ned; S->nbnd += h.nbnd;
+    m.nl_max = std::max(m.nl_max, h.nl_max); m.nm_max = std::max(m.nm_max, h.nm_max);
+    m.ed_max = std::max(m.ed_max, h.ed_max); m.n2_max = std::max(m.n2_max, h.n2_max);
+  }
+  if (nch > S->chunk_cap) return fail(S, DGSWE_E_NOMEM, "chunk table full");
+  m.nch = nch;
+  m.ned = S->ned;
+  if (nch > 0) {
+    e = hipMemcpy(S->d_chunk_rec, S->chunk_rec.data(), S->chunk_rec.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
+  }
+  return sync_members(S);
+}
+
+// capacities of the arenas for a pool of max_elems elements and `slots` members
+void pool_caps(long long max_elems, int slots, int order, long long cap[A_COUNT], int &chunk_cap) {
+  const long long E = max_elems, M = slots;
+  cap[A_ELEM] = E;
+  cap[A_NODE] = E + 3 * M;
+  cap[A_LOC] = 2 * E + 512 * M;
+  cap[A_LEDGE] = 2 * E + 512 * M;
+  cap[A_RING2] = E + 256 * M;
+  cap[A_EDGE] = order == 2 ? 2 * E + 3 * M : 0;
+  chunk_cap = (int)(E / 64 + 2 * M + 1);
+}
+
+dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgswe_params *prm, void *hip_stream,
+                         dgswe_solver **out) {
+  if (!out) return fail(nullptr, DGSWE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n_members < 1 || !meshes) return fail(nullptr, DGSWE_E_INVALID, "a batch needs at least one mesh");
+  std::string msg;
+  if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
+  int chunk, block;
+  if (!chunk_config(chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+  long long ne_total = 0;
+  for (int32_t i = 0; i < n_members; ++i) ne_total += meshes[i].n_elems > 0 ? meshes[i].n_elems : 0;
+  if (ne_total > 0x7fffffffLL) return fail(nullptr, DGSWE_E_INVALID, "more than 2^31 - 1 elements in the batch");
+  std::vector<Prep> parts((size_t)n_members);
+  // host preprocessing of the meshes, several at a time (each thread owns
+  // whole meshes; the first failing mesh in order is reported)
+  std::vector<int> rcs((size_t)n_members, DGSWE_OK);
+  std::vector<std::string> msgs((size_t)n_members);
+  {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int nt = (int)std::min<unsigned>(hw, (unsigned)n_members);
+    auto work = [&](int t0) {
+      for (int i = t0; i < n_members; i += nt) rcs[i] = prep_one(meshes[i], prm->p, chunk, block, parts[i], msgs[i]);
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &x : th) x.join();
+  }
+  for (int32_t i = 0; i < n_members; ++i)
+    if (rcs[i] != DGSWE_OK) {
+      msg = n_members > 1 ? "mesh " + std::to_string(i) + ": " + msgs[i] : msgs[i];
+      return fail(nullptr, (dgswe_status)rcs[i], msg);
+    }
+  // arenas sized to the meshes
+  long long cap[A_COUNT] = {};
+  int chunk_cap = 0;
+  for (const Prep &q : parts) {
+    long long need[A_COUNT];
+    arena_need(q, prm->p, need);
+    for (int a = 0; a < A_COUNT; ++a) cap[a] += need[a];
+    chunk_cap += q.nch;
+  }
+  dgswe_solver *S = nullptr;
+  dgswe_status st = alloc_solver(prm, block, cap, chunk_cap, n_members, hip_stream, &S);
+  if (st != DGSWE_OK) return st;
+  for (int32_t i = 0; i < n_members; ++i) {
+    st = place_member(S, i, parts[(size_t)i]);
+    parts[(size_t)i] = Prep();
+    if (st != DGSWE_OK) {
+      msg = S->err;
+      free_all(S);
+      delete S;
+      return fail(nullptr, st, msg);
+    }
+  }
+  st = rebuild(S);
+  if (st == DGSWE_OK && hipStreamSynchronize(S->stream) != hipSuccess) st = DGSWE_E_DEVICE;
+  if (st != DGSWE_OK) {
+    msg = S->err;
     free_all(S);
     delete S;
-    return fail(nullptr, DGSWE_E_DEVICE, "device initialisation failed");
+    return fail(nullptr, st, "device initialisation failed: " + msg);
   }
   *out = S;
   return DGSWE_OK;
@@ -383,7 +676,7 @@ dgswe_status set_state_impl(dgswe_solver *S, int32_t member, double t, const dou
   if (!std::isfinite(t)) return fail(S, DGSWE_E_INVALID, "time is not finite");
   MemberHost &h = S->mh[member];
   const Member &f = S->mem[member];
-  const size_t ne = (size_t)h.ne, NE = (size_t)S->ne, nm = (size_t)S->nm;
+  const size_t ne = (size_t)h.ne, NE = (size_t)S->m.ne, nm = (size_t)S->nm;
   const bool mixed = S->precision == DGSWE_MIXED;
   // member-order image: zeta modes FP64, momentum modes FP64 or FP32
   S->stage_raw.resize(state_bytes(ne, S->precision, S->order));
@@ -434,7 +727,7 @@ dgswe_status set_forcing_impl(dgswe_solver *S, int32_t member, const dgswe_forci
     return fail(S, DGSWE_E_INVALID, "Holland rmax, B and rho_air must be positive");
   MemberHost &h = S->mh[member];
   Member &f = S->mem[member];
-  const size_t ne = (size_t)h.ne, nn = (size_t)h.nn, NN = (size_t)S->nn;
+  const size_t ne = (size_t)h.ne, nn = (size_t)h.nn, NN = (size_t)S->m.nn, NE = (size_t)S->m.ne;
   hipError_t e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
   f.n_tide = fr->n_tide;
@@ -463,18 +756,12 @@ dgswe_status set_forcing_impl(dgswe_solver *S, int32_t member, const dgswe_forci
     if (e == hipSuccess) e = hipMemcpy(S->d_manf + f.e0, tf.data(), ne * sizeof(float), hipMemcpyHostToDevice);
   } else {
     const float nf = (float)fr->manning_n;
-    e = hipMemcpy(S->d_man + S->ne + member, &fr->manning_n, sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(S->d_manf + S->ne + member, &nf, sizeof(float), hipMemcpyHostToDevice);
+    e = hipMemcpy(S->d_man + NE + member, &fr->manning_n, sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(S->d_manf + NE + member, &nf, sizeof(float), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
-  for (int c = f.chunk0; c < f.chunk0 + f.nchunk; ++c) {
-    int *r = &S->chunk_rec[(size_t)c * kChunkRec];
-    r[11] = per_elem ? r[0] : S->ne + member;
-    r[12] = per_elem ? 1 : 0;
-  }
-  e = hipMemcpy(S->d_chunk_rec + (size_t)f.chunk0 * kChunkRec, &S->chunk_rec[(size_t)f.chunk0 * kChunkRec],
-                (size_t)f.nchunk * kChunkRec * sizeof(int), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
+  // the member's chunk records point at the Manning values that apply
+  h.man_elem = per_elem;
   h.holland = fr->holland != 0;
   if (!h.holland) {
     // static fields of this member's nodes: (tau_x, tau_y) pairs, then p_a
@@ -488,7 +775,7 @@ dgswe_status set_forcing_impl(dgswe_solver *S, int32_t member, const dgswe_forci
       e = hipMemcpy(S->s.nodal + 2 * NN + (size_t)f.n0, pa.data(), nn * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
   }
-  return sync_members(S);
+  return rebuild(S);
 }
 
 dgswe_status read_state_impl(dgswe_solver *S, int32_t member, double *w_out, dgswe_diag *d) {
@@ -502,6 +789,14 @@ dgswe_status read_state_impl(dgswe_solver *S, int32_t member, double *w_out, dgs
   if (w_out) {
     // the state at the boundary is post-processed, FP64
     const size_t nv = 3 * (size_t)S->nm;
+    if (S->rb_elems < ne) {
+      if (S->rb) (void)hipFree(S->rb);
+      S->rb = nullptr;
+      S->rb_elems = 0;
+      e = hipMalloc(&S->rb, nv * ne * sizeof(double));
+      if (e != hipSuccess) return hip_fail(S, e, "hipMalloc");
+      S->rb_elems = ne;
+    }
     if (S->order == 2)
       e = launch_post_only2(S->m, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
                             S->stream);
@@ -605,6 +900,7 @@ dgswe_status dgswe_step(dgswe_solver *S, int32_t n_steps) {
   DevState &st = S->s;
   const Params &p = S->prm;
   const int want_dt = (p.dt_fixed > 0.0) ? 0 : 1;
+  if (m.nch == 0) return DGSWE_OK;  // no member
   for (int i = 0; i < n_steps; ++i) {
     const int slot = (int)(S->steps_enq & 1);
     // rotation: w^n in cur, stage 1 -> s1, stage 2 -> nx (both unlimited)
@@ -705,7 +1001,8 @@ dgswe_status dgswe_mesh_info(const dgswe_solver *S, int64_t out[4]) {
 }
 
 dgswe_status dgswe_member_info(const dgswe_solver *S, int32_t member, int64_t out[4]) {
-  if (!S || !out || member < 0 || member >= (int32_t)S->mh.size()) return DGSWE_E_INVALID;
+  if (!S || !out || member < 0 || member >= (int32_t)S->mh.size() || !S->mh[(size_t)member].active)
+    return DGSWE_E_INVALID;
   const MemberHost &h = S->mh[member];
   out[0] = h.nn;
   out[1] = h.ne;
@@ -715,5 +1012,112 @@ dgswe_status dgswe_member_info(const dgswe_solver *S, int32_t member, int64_t ou
 }
 
 int32_t dgswe_member_count(const dgswe_solver *S) { return S ? (int32_t)S->mh.size() : 0; }
+
+dgswe_status dgswe_create_pool(int64_t max_elems, int32_t max_members, const dgswe_params *prm, void *hip_stream,
+                               dgswe_solver **out) {
+  if (!out) return fail(nullptr, DGSWE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string msg;
+  if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
+  if (max_elems < 1 || max_elems > 0x3fffffffLL || max_members < 1 || max_members > 65536)
+    return fail(nullptr, DGSWE_E_INVALID, "pool capacity out of range");
+  int chunk, block;
+  if (!chunk_config(chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+  long long cap[A_COUNT];
+  int chunk_cap = 0;
+  pool_caps(max_elems, max_members, prm->p, cap, chunk_cap);
+  dgswe_solver *S = nullptr;
+  dgswe_status st = alloc_solver(prm, block, cap, chunk_cap, max_members, hip_stream, &S);
+  if (st != DGSWE_OK) return st;
+  S->is_pool = true;
+  st = rebuild(S);
+  if (st != DGSWE_OK) {
+    msg = S->err;
+    free_all(S);
+    delete S;
+    return fail(nullptr, st, msg);
+  }
+  *out = S;
+  return DGSWE_OK;
+}
+
+dgswe_status dgswe_prepare_mesh(const dgswe_mesh *mesh, const dgswe_params *prm, dgswe_prepared **out) {
+  if (!out) return fail(nullptr, DGSWE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  std::string msg;
+  if (!mesh) return fail(nullptr, DGSWE_E_INVALID, "mesh is NULL");
+  if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
+  int chunk, block;
+  if (!chunk_config(chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+  dgswe_prepared *P = new (std::nothrow) dgswe_prepared();
+  if (!P) return fail(nullptr, DGSWE_E_NOMEM, "host allocation failed");
+  P->order = prm->p;
+  const int rc = prep_one(*mesh, prm->p, chunk, block, P->P, msg);
+  if (rc != DGSWE_OK) {
+    delete P;
+    return fail(nullptr, (dgswe_status)rc, msg);
+  }
+  *out = P;
+  return DGSWE_OK;
+}
+
+void dgswe_prepared_free(dgswe_prepared *P) { delete P; }
+
+int64_t dgswe_prepared_elems(const dgswe_prepared *P) { return P ? P->P.ne : 0; }
+
+dgswe_status dgswe_member_add_prepared(dgswe_solver *S, dgswe_prepared *P, int32_t *member) {
+  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+  if (!P || !member) return fail(S, DGSWE_E_INVALID, "prepared mesh or member is NULL");
+  if (!S->is_pool) return fail(S, DGSWE_E_INVALID, "members join only a pool (dgswe_create_pool)");
+  if (P->order != S->order) return fail(S, DGSWE_E_INVALID, "the mesh was prepared for another order p");
+  int slot = -1;
+  for (size_t i = 0; i < S->mh.size(); ++i)
+    if (!S->mh[i].active) { slot = (int)i; break; }
+  if (slot < 0) return fail(S, DGSWE_E_NOMEM, "every member slot is taken");
+  hipError_t e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+  dgswe_status st = place_member(S, slot, P->P);
+  if (st != DGSWE_OK) return st;
+  delete P;
+  st = rebuild(S);
+  if (st != DGSWE_OK) return st;
+  *member = slot;
+  return DGSWE_OK;
+}
+
+dgswe_status dgswe_member_add(dgswe_solver *S, const dgswe_mesh *mesh, int32_t *member) {
+  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+  dgswe_prepared *P = nullptr;
+  dgswe_status st = dgswe_prepare_mesh(mesh, &S->uprm, &P);
+  if (st != DGSWE_OK) return fail(S, st, g_create_error);
+  st = dgswe_member_add_prepared(S, P, member);
+  if (st != DGSWE_OK) dgswe_prepared_free(P);
+  return st;
+}
+
+dgswe_status dgswe_member_remove(dgswe_solver *S, int32_t member) {
+  dgswe_status st = check_member(S, member);
+  if (st != DGSWE_OK) return st;
+  if (!S->is_pool) return fail(S, DGSWE_E_INVALID, "members leave only a pool (dgswe_create_pool)");
+  hipError_t e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+  MemberHost &h = S->mh[(size_t)member];
+  for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(h.off[a], h.len[a]);
+  h = MemberHost{};
+  return rebuild(S);
+}
+
+dgswe_status dgswe_pool_usage(const dgswe_solver *S, int64_t out[5]) {
+  if (!S || !out) return DGSWE_E_INVALID;
+  const Arena &a = S->arena[A_ELEM];
+  out[0] = a.cap() - a.free_total();
+  out[1] = a.cap();
+  int64_t act = 0;
+  for (const MemberHost &h : S->mh) act += h.active ? 1 : 0;
+  out[2] = act;
+  out[3] = (int64_t)S->mh.size();
+  out[4] = (int64_t)S->dev_bytes;
+  return DGSWE_OK;
+}
 
 }  // extern "C"

@@ -24,7 +24,9 @@ EXPORTED = ("dgswe_default_params", "dgswe_create_mesh", "dgswe_set_state", "dgs
             "dgswe_step", "dgswe_read_state", "dgswe_destroy", "dgswe_last_error", "dgswe_profile",
             "dgswe_profile_read", "dgswe_mesh_info", "dgswe_create_batch", "dgswe_member_count",
             "dgswe_member_set_state", "dgswe_member_set_forcing", "dgswe_member_read_state",
-            "dgswe_member_info")
+            "dgswe_member_info", "dgswe_create_pool", "dgswe_prepare_mesh", "dgswe_prepared_free",
+            "dgswe_prepared_elems", "dgswe_member_add_prepared", "dgswe_member_add", "dgswe_member_remove",
+            "dgswe_pool_usage")
 
 
 class dgswe_params(C.Structure):
@@ -112,6 +114,22 @@ def load_library(path: str = LIB_PATH):
     L.dgswe_member_read_state.restype = C.c_int
     L.dgswe_member_info.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64)]
     L.dgswe_member_info.restype = C.c_int
+    L.dgswe_create_pool.argtypes = [C.c_int64, C.c_int32, C.POINTER(dgswe_params), vp, C.POINTER(vp)]
+    L.dgswe_create_pool.restype = C.c_int
+    L.dgswe_prepare_mesh.argtypes = [C.POINTER(dgswe_mesh), C.POINTER(dgswe_params), C.POINTER(vp)]
+    L.dgswe_prepare_mesh.restype = C.c_int
+    L.dgswe_prepared_free.argtypes = [vp]
+    L.dgswe_prepared_free.restype = None
+    L.dgswe_prepared_elems.argtypes = [vp]
+    L.dgswe_prepared_elems.restype = C.c_int64
+    L.dgswe_member_add_prepared.argtypes = [vp, vp, ip]
+    L.dgswe_member_add_prepared.restype = C.c_int
+    L.dgswe_member_add.argtypes = [vp, C.POINTER(dgswe_mesh), ip]
+    L.dgswe_member_add.restype = C.c_int
+    L.dgswe_member_remove.argtypes = [vp, C.c_int32]
+    L.dgswe_member_remove.restype = C.c_int
+    L.dgswe_pool_usage.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.dgswe_pool_usage.restype = C.c_int
     _lib = L
     return L
 
@@ -150,21 +168,81 @@ def dgswe_create_mesh(xy, hb, tri, bnd, bnd_type, prm: dgswe_params, hip_stream=
     return h
 
 
+def _mesh_desc(m, keep):
+    """dgswe_mesh view of an object with xy, hb, tri, bnd, bnd_type (the
+    arrays are appended to `keep`, which must outlive the call)."""
+    ip = C.POINTER(C.c_int32)
+    xy = np.ascontiguousarray(m.xy, dtype=np.float64)
+    hb = np.ascontiguousarray(m.hb, dtype=np.float64)
+    tri = np.ascontiguousarray(m.tri, dtype=np.int32)
+    bnd = np.ascontiguousarray(m.bnd, dtype=np.int32).reshape(-1, 2)
+    bt = np.ascontiguousarray(m.bnd_type, dtype=np.int32)
+    keep += [xy, hb, tri, bnd, bt]
+    return dgswe_mesh(xy.shape[0], _d(xy), _d(hb), tri.shape[0], tri.ctypes.data_as(ip), bnd.shape[0],
+                      bnd.ctypes.data_as(ip), bt.ctypes.data_as(ip))
+
+
+def dgswe_create_pool(max_elems, max_members, prm: dgswe_params, hip_stream=None):
+    L = load_library()
+    h = C.c_void_p()
+    st = L.dgswe_create_pool(int(max_elems), int(max_members), C.byref(prm),
+                             C.c_void_p(hip_stream) if hip_stream else None, C.byref(h))
+    if st != DGSWE_OK:
+        raise DgsweError(st, L.dgswe_last_error(None).decode())
+    return h
+
+
+def dgswe_prepare_mesh(mesh, prm: dgswe_params):
+    """Host-only preprocessing (thread safe; the GIL is released meanwhile)."""
+    L = load_library()
+    keep = []
+    desc = _mesh_desc(mesh, keep)
+    h = C.c_void_p()
+    st = L.dgswe_prepare_mesh(C.byref(desc), C.byref(prm), C.byref(h))
+    if st != DGSWE_OK:
+        raise DgsweError(st, L.dgswe_last_error(None).decode())
+    return h
+
+
+def dgswe_prepared_free(h):
+    load_library().dgswe_prepared_free(h)
+
+
+def dgswe_member_add_prepared(h, prep):
+    """Returns the member slot; raises DgsweError (status 3) when the pool has
+    no room, in which case the caller still owns `prep`."""
+    L = load_library()
+    slot = C.c_int32(-1)
+    _check(h, L.dgswe_member_add_prepared(h, prep, C.byref(slot)))
+    return slot.value
+
+
+def dgswe_member_add(h, mesh):
+    L = load_library()
+    keep = []
+    desc = _mesh_desc(mesh, keep)
+    slot = C.c_int32(-1)
+    _check(h, L.dgswe_member_add(h, C.byref(desc), C.byref(slot)))
+    return slot.value
+
+
+def dgswe_member_remove(h, member):
+    _check(h, load_library().dgswe_member_remove(h, int(member)))
+
+
+def dgswe_pool_usage(h):
+    out = (C.c_int64 * 5)()
+    _check(h, load_library().dgswe_pool_usage(h, out))
+    return dict(elems_used=out[0], elems_cap=out[1], members=out[2], slots=out[3], device_bytes=out[4])
+
+
 def dgswe_create_batch(meshes, prm: dgswe_params, hip_stream=None):
     """meshes: objects with xy, hb, tri, bnd, bnd_type (e.g. workloads.Mesh)."""
     L = load_library()
     keep = []
     descs = (dgswe_mesh * len(meshes))()
-    ip = C.POINTER(C.c_int32)
     for i, m in enumerate(meshes):
-        xy = np.ascontiguousarray(m.xy, dtype=np.float64)
-        hb = np.ascontiguousarray(m.hb, dtype=np.float64)
-        tri = np.ascontiguousarray(m.tri, dtype=np.int32)
-        bnd = np.ascontiguousarray(m.bnd, dtype=np.int32).reshape(-1, 2)
-        bt = np.ascontiguousarray(m.bnd_type, dtype=np.int32)
-        keep += [xy, hb, tri, bnd, bt]
-        descs[i] = dgswe_mesh(xy.shape[0], _d(xy), _d(hb), tri.shape[0], tri.ctypes.data_as(ip), bnd.shape[0],
-                              bnd.ctypes.data_as(ip), bt.ctypes.data_as(ip))
+        descs[i] = _mesh_desc(m, keep)
     h = C.c_void_p()
     st = L.dgswe_create_batch(len(meshes), descs, C.byref(prm), C.c_void_p(hip_stream) if hip_stream else None,
                               C.byref(h))
@@ -372,6 +450,78 @@ class Batch:
 
     def info(self, i=None):
         return dgswe_mesh_info(self.h, i)
+
+    def close(self):
+        if self.h:
+            dgswe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """A serving pool (dgswe_create_pool): members join and leave between
+    steps; a member's state has shape (3, nm, its n_elems)."""
+
+    def __init__(self, max_elems, max_members, params: dict | None = None, hip_stream=None):
+        self.h = None
+        self.params = dict(params or {})
+        self.prm = params_from_dict(self.params)
+        self.nm = modes_per_variable(params)
+        self.h = dgswe_create_pool(max_elems, max_members, self.prm, hip_stream)
+        self.ne = {}
+
+    def prepare(self, mesh):
+        """host-only preprocessing; returns a handle for add()"""
+        return dgswe_prepare_mesh(mesh, self.prm)
+
+    def add(self, mesh=None, prepared=None, forcing=None, w=None, t=0.0, postprocess=False):
+        """Admit a mesh (or a prepared handle, consumed on success); returns the
+        member slot.  Raises DgsweError with status 3 when it does not fit."""
+        if prepared is None:
+            prepared = self.prepare(mesh)
+            try:
+                slot = dgswe_member_add_prepared(self.h, prepared)
+            except DgsweError:
+                dgswe_prepared_free(prepared)
+                raise
+        else:
+            slot = dgswe_member_add_prepared(self.h, prepared)
+        info = dgswe_mesh_info(self.h, slot)
+        self.ne[slot] = info["n_elems"]
+        if forcing:
+            dgswe_set_forcing(self.h, forcing, info["n_elems"], info["n_nodes"], member=slot)
+        if w is not None:
+            self.set_state(slot, w, t, postprocess)
+        return slot
+
+    def set_state(self, slot, w, t=0.0, postprocess=False):
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(3, self.nm, self.ne[slot])
+        dgswe_set_state(self.h, t, w, postprocess, member=slot)
+
+    def remove(self, slot):
+        dgswe_member_remove(self.h, slot)
+        self.ne.pop(slot, None)
+
+    def step(self, n=1):
+        dgswe_step(self.h, n)
+
+    def state(self, slot):
+        w = np.empty((3, self.nm, self.ne[slot]), dtype=np.float64)
+        d = dgswe_read_state(self.h, w, True, member=slot)
+        return w, d
+
+    def diagnostics(self, slot):
+        d = dgswe_read_state(self.h, None, True, member=slot)
+        return dict(t=d.t, dt_last=d.dt_last, mass=d.mass, volume=d.volume, steps=d.steps,
+                    n_wet=d.n_wet, n_dry=d.n_dry)
+
+    def usage(self):
+        return dgswe_pool_usage(self.h)
 
     def close(self):
         if self.h:

@@ -121,3 +121,33 @@ def test_batch_validation_before_device_work():
     assert L.dgswe_member_count(None) == 0
     out = (C.c_int64 * 4)()
     assert L.dgswe_member_info(None, 0, out) == 1
+
+
+def test_prepare_mesh_and_pool_validation_on_host():
+    """dgswe_prepare_mesh is host-only work: it runs (and validates) without a
+    device; pool capacities are checked before any device work."""
+    m = W.rect_mesh(6, 4, 600.0, 400.0)
+    L = D.load_library()
+    prep = D.dgswe_prepare_mesh(m, D.dgswe_default_params())
+    assert L.dgswe_prepared_elems(prep) == m.n_elems
+    D.dgswe_prepared_free(prep)
+    prep2 = D.dgswe_prepare_mesh(m, D.params_from_dict(dict(p=2)))
+    assert L.dgswe_prepared_elems(prep2) == m.n_elems
+    D.dgswe_prepared_free(prep2)
+    bad = W.Mesh(m.xy, m.hb, m.tri[:, [0, 2, 1]].copy(), m.bnd, m.bnd_type)
+    with pytest.raises(D.DgsweError) as ei:
+        D.dgswe_prepare_mesh(bad, D.dgswe_default_params())
+    assert ei.value.status == 2
+    with pytest.raises(D.DgsweError) as ei:
+        D.dgswe_prepare_mesh(m, D.params_from_dict(dict(p=3)))
+    assert ei.value.status == 1
+    for cap, slots in ((0, 4), (1000, 0), (1 << 31, 4)):
+        with pytest.raises(D.DgsweError) as ei:
+            D.dgswe_create_pool(cap, slots, D.dgswe_default_params())
+        assert ei.value.status == 1
+    # NULL handles
+    out = (C.c_int64 * 5)()
+    assert L.dgswe_pool_usage(None, out) == 1
+    assert L.dgswe_member_remove(None, 0) == 1
+    assert L.dgswe_prepared_elems(None) == 0
+    L.dgswe_prepared_free(None)
