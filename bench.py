@@ -15,8 +15,12 @@ against 8 TB/s), under "variants" the same workload in mixed precision
 batched storm-surge ensemble (64 coastal meshes of 50k-500k triangles,
 19.5M in total, each with its own hurricane track and Manning n, mixed
 precision, one launch per stage for all members), the same 4M workload at
-p = 2 (six modes per variable) in FP64 and mixed precision, and the FP64
-CPU oracle timed on a bounded sample of the same workload on the host cores.
+p = 2 (six modes per variable) in FP64 and mixed precision, a serving run
+(Poisson arrivals of solve requests of 10k-1M triangles and 100-5,000
+steps at ~80 % of the pool's throughput, continuous batching in a
+device-resident pool in mixed precision, p50/p99 latency against the same
+requests served one at a time in FP64), and the FP64 CPU oracle timed on a
+bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -293,6 +297,36 @@ def measure_batched(steps, warmup, stream, profile):
     return elapsed, ne, len(ens), kernels
 
 
+def measure_serving(n_requests, pool_rate_hint, stream):
+    """Serving: the pool (mixed, continuous batching) and the one-at-a-time
+    FP64 baseline on the same Poisson arrivals; the arrival rate offers 80 %
+    of pool_rate_hint (elem-stage/s)."""
+    from paper_2508_21208_amd import workloads as W
+    from paper_2508_21208_amd.serving import serve_one_at_a_time, serve_pool, summarize
+    t0 = time.perf_counter()
+    meshes = W.serving_meshes()
+    reqs = W.cfg_serving(n_requests, meshes=meshes)
+    work = float(np.mean([r.mesh.n_elems * r.horizon * 2 for r in reqs]))
+    lam = 0.8 * pool_rate_hint / work
+    log(f"serving: {len(reqs)} requests on {len(meshes)} meshes ({min(m.n_elems for m in meshes)}-"
+        f"{max(m.n_elems for m in meshes)} triangles) in {time.perf_counter() - t0:.1f} s; "
+        f"{lam:.2f} requests/s")
+    out, el = serve_pool(reqs, W.default_params(precision=1, dt_max=0.3), lam, max_elems=16_000_000,
+                         max_members=256, round_cap=100, hip_stream=stream.cuda_stream)
+    pool = summarize(out, el)
+    log("serving pool: " + json.dumps(pool))
+    out2, el2 = serve_one_at_a_time(reqs, W.default_params(precision=0, dt_max=0.3), lam, deadline_s=3 * el,
+                                    hip_stream=stream.cuda_stream)
+    alone = summarize(out2, el2) if out2 else None
+    if alone:
+        alone["completed_of"] = len(reqs)
+    log("serving one at a time: " + json.dumps(alone))
+    return {"requests": len(reqs), "arrival_rate_per_s": lam, "offered_load": 0.8,
+            "mean_request_elem_stages": work, "pool_mixed": pool, "one_at_a_time_fp64": alone,
+            "p50_speedup": alone["p50_s"] / pool["p50_s"] if alone else None,
+            "p99_speedup": alone["p99_s"] / pool["p99_s"] if alone else None}
+
+
 def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
     if not kernels:
         return None
@@ -320,6 +354,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision variant")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble variant")
     ap.add_argument("--no-p2", action="store_true", help="skip the p = 2 variants")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline run (fp64 is the metric's)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -380,6 +416,10 @@ def main():
                                "kernels": k3}
         if k3:
             log("batched kernels: " + json.dumps(k3))
+
+    if not args.no_serving:
+        hint = variants.get("mixed", {}).get("value") or 1.2e10
+        variants["serving"] = measure_serving(args.serving_requests, hint, stream)
 
     if args.copy_probe:
         n = 2 * 1024 ** 3 // 8

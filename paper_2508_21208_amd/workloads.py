@@ -389,3 +389,63 @@ def cfg_ensemble(n_members=64, n_meshes=8, min_elems=50_000, max_elems=500_000, 
         out.append(Workload(f"ensemble_{i}_{m.n_elems}", m, coastal_initial_state(m), default_params(dt_max=0.3), f,
                             steps, True))
     return out
+
+
+@dataclass
+class Request:
+    """One solve request of the serving workload: a mesh, its forcing and
+    initial state, a horizon in steps and an arrival time in units of the
+    mean inter-arrival gap (scale by 1 / rate)."""
+    rid: int
+    mesh: Mesh
+    forcing: dict
+    w0: np.ndarray
+    horizon: int
+    arrival: float
+
+
+def serving_meshes(n_meshes=10, min_elems=10_000, max_elems=1_000_000, seed=BASE_SEED + 5000) -> list:
+    """The distinct meshes of the serving workload, log-spaced in size from
+    min_elems to max_elems (coarser coastlines for the small ones)."""
+    sizes = np.geomspace(min_elems, max_elems, n_meshes)
+    out = []
+    for k, n in enumerate(sizes):
+        n = int(round(n))
+        if n < 30_000:
+            m = coastal_mesh(n, seed + 1 + k, hmin=1000.0, hmax=15000.0)
+        elif n < 200_000:
+            m = coastal_mesh(n, seed + 1 + k, hmin=200.0)
+        else:
+            m = coastal_mesh(n, seed + 1 + k, hmin=50.0)
+        out.append(m)
+    return out
+
+
+def cfg_serving(n_requests=100, meshes=None, min_steps=100, max_steps=5000, seed=BASE_SEED + 5000) -> list:
+    """Serving workload: requests with mesh sizes log-uniform over the
+    serving meshes (10k-1M triangles), horizons uniform in [min_steps,
+    max_steps], a random forcing (M2 tide of random amplitude, or a Holland
+    storm track as in the ensemble), Poisson arrivals (exponential gaps of
+    mean 1, to be scaled to the wanted load).  The step is capped at 0.3 s as
+    in the ensemble (explicit friction of shallow cells on coarse meshes)."""
+    if meshes is None:
+        meshes = serving_meshes(seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    t = 0.0
+    out = []
+    states = {}
+    for i in range(n_requests):
+        t += float(rng.exponential(1.0))
+        m = meshes[int(rng.integers(0, len(meshes)))]
+        if rng.uniform() < 0.5:
+            f = default_forcing(manning_n=float(rng.uniform(0.015, 0.035)), **m2_tide(float(rng.uniform(0.5, 1.5))))
+        else:
+            f = default_forcing(manning_n=float(rng.uniform(0.015, 0.035)), **m2_tide(1.0),
+                                **holland_track(m, speed=float(rng.uniform(3.0, 8.0)),
+                                                heading=float(rng.uniform(-np.pi / 6.0, np.pi / 6.0)),
+                                                offshore=float(rng.uniform(100e3, 160e3)),
+                                                y0=float(rng.uniform(200e3, 400e3))))
+        if id(m) not in states:
+            states[id(m)] = coastal_initial_state(m)
+        out.append(Request(i, m, f, states[id(m)], int(rng.integers(min_steps, max_steps + 1)), t))
+    return out
