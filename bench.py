@@ -39,9 +39,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "elem-stage updates/s @4M tri p=1, FP64 vs mixed/batched; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_hbm_traffic_hurricane_4M.json")
-KERNEL_SOURCES = ("paper_2508_21208_amd/csrc/dgswe_kernels.hip", "paper_2508_21208_amd/csrc/dgswe_internal.h",
-                  "paper_2508_21208_amd/csrc/mesh_prep.cpp", "paper_2508_21208_amd/csrc/dgswe_api.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hurricane_4M.json")
+KERNEL_SOURCES = ("paper_2508_21208_amd/csrc/dgswe_kernels.hip", "paper_2508_21208_amd/csrc/dgswe_p2.hip",
+                  "paper_2508_21208_amd/csrc/dgswe_device.h",
+                  "paper_2508_21208_amd/csrc/dgswe_internal.h", "paper_2508_21208_amd/csrc/mesh_prep.cpp",
+                  "paper_2508_21208_amd/csrc/dgswe_api.hip")
 
 
 def log(msg):
@@ -97,9 +99,9 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(precision: str):
-    """HBM bytes per k_stage launch measured with rocprofv3 counters for the
-    current sources, or None (no record, or the kernel changed since)."""
+def stored_traffic(kernel: str, precision: str):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 counters for
+    the current sources, or None (no record, or the kernels changed since)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -107,28 +109,42 @@ def stored_traffic(precision: str):
         return None
     if rec.get("source_sha256") != source_hash():
         return None
-    k = rec.get("k_stage", {}).get(precision)
+    k = rec.get("kernels", {}).get(kernel, {}).get(precision)
     return None if k is None else k["bytes_per_launch"]
 
 
-def stage_kernel_precision(name: str):
-    """'double' / 'float' for a k_stage<NT, WPE, T, STAGE> kernel name, else None."""
-    if "k_stage<" not in name:
-        return None
-    args = name.split("k_stage<", 1)[1].split(">", 1)[0].split(",")
-    return args[2].strip() if len(args) >= 3 else None
+PROFILED = ("k_stage", "k_pp2", "k_rhs2")
+
+
+def kernel_key(name: str):
+    """(kernel, 'fp64' | 'mixed') for a k_stage<NT, WPE, T, STAGE>,
+    k_pp2<T, STAGE> or k_rhs2<T, STAGE, WPE> kernel name, else None."""
+    for k in PROFILED:
+        tag = k + "<"
+        if tag in name:
+            args = [a.strip() for a in name.split(tag, 1)[1].split(">", 1)[0].split(",")]
+            t = args[2] if k == "k_stage" else args[0]
+            return k, ("mixed" if t == "float" else "fp64")
+    return None
+
+
+CMD_TRACE = ("rocprofv3 --kernel-trace --stats -d $OUT/prof -o bench --output-format csv -- "
+             "python3 $REPO/bench.py --steps 50 --warmup 5 --no-cpu-baseline --no-profile --no-batched --no-serving")
+CMD_PMC = ("rocprofv3 --pmc {c} -d $OUT/pmc/{c} -o run --output-format csv -- python3 $REPO/bench.py --steps 3 "
+           "--warmup 1 --no-cpu-baseline --no-profile --copy-probe --no-batched --no-serving")
 
 
 def summarize_pmc(pmc_dir: str, stats_csv: str | None, out_md: str | None):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
-    dispatch) of `bench.py --copy-probe` into HBM bytes per k_stage launch.
-    Each counter is scaled by what it reads for the 2 GiB device copy in the
-    same run (bytes moved / counter reading)."""
+    dispatch) of `bench.py --copy-probe` into HBM bytes per launch of each
+    stage kernel and precision.  Each counter is scaled by what it reads for
+    the 2 GiB device copy in the same run (bytes moved / counter reading).
+    out_md: the p = 1 summary; the p = 2 one goes beside it."""
     def load(tag):
         with open(os.path.join(pmc_dir, tag, "run_counter_collection.csv")) as fh:
             return list(csv.DictReader(fh))
     copy_bytes = 2 * 1024 ** 3
-    res = {"source_sha256": source_hash(), "k_stage": {}, "calibration": {}}
+    res = {"source_sha256": source_hash(), "kernels": {}, "calibration": {}}
     vals = {}
     for tag in ("FETCH_SIZE", "WRITE_SIZE"):
         rows = load(tag)
@@ -136,69 +152,78 @@ def summarize_pmc(pmc_dir: str, stats_csv: str | None, out_md: str | None):
         big = max(copies)
         scale = copy_bytes / (big * 1024.0)
         res["calibration"][tag] = {"copy_KiB": big, "bytes_per_KiB": round(scale * 1024.0, 1), "factor": round(scale, 3)}
-        for prec, key in (("fp64", "double"), ("mixed", "float")):
-            v = [float(r["Counter_Value"]) for r in rows if stage_kernel_precision(r["Kernel_Name"]) == key]
-            if v:
-                vals.setdefault(prec, {})[tag] = (sum(v) / len(v), len(v), scale)
-    for prec, d in vals.items():
+        for r in rows:
+            kk = kernel_key(r["Kernel_Name"])
+            if kk:
+                vals.setdefault(kk, {}).setdefault(tag, []).append(float(r["Counter_Value"]))
+    for (k, prec), d in vals.items():
         if len(d) < 2:
             continue
-        fk, fn, fs = d["FETCH_SIZE"]
-        wk, wn, ws = d["WRITE_SIZE"]
-        b = fk * 1024.0 * fs + wk * 1024.0 * ws
-        res["k_stage"][prec] = {"fetch_KiB": round(fk, 1), "write_KiB": round(wk, 1), "dispatches": [fn, wn],
-                                "bytes_per_launch": round(b)}
+        fk = sum(d["FETCH_SIZE"]) / len(d["FETCH_SIZE"])
+        wk = sum(d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
+        b = fk * 1024.0 * res["calibration"]["FETCH_SIZE"]["factor"] + wk * 1024.0 * res["calibration"]["WRITE_SIZE"]["factor"]
+        res["kernels"].setdefault(k, {})[prec] = {"fetch_KiB": round(fk, 1), "write_KiB": round(wk, 1),
+                                                   "dispatches": [len(d["FETCH_SIZE"]), len(d["WRITE_SIZE"])],
+                                                   "bytes_per_launch": round(b)}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res, indent=1))
-    if out_md:
-        lines = ["# k_stage on the 4M-triangle hurricane workload: kernel times and HBM traffic", "",
-                 "Commands, on one MI355X, with REPO = the repository root and OUT = an output folder:", "",
-                 "```",
-                 "cd /tmp && export TMPDIR=/tmp",
-                 "rocprofv3 --kernel-trace --stats -d $OUT/prof -o bench --output-format csv -- "
-                 "python3 $REPO/bench.py --steps 50 --warmup 5 --no-cpu-baseline --no-profile",
-                 "rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc/FETCH_SIZE -o run --output-format csv -- "
-                 "python3 $REPO/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-profile --copy-probe",
-                 "rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc/WRITE_SIZE -o run --output-format csv -- "
-                 "python3 $REPO/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-profile --copy-probe",
-                 "cd $REPO && python3 bench.py --summarize-pmc $OUT/pmc --kernel-stats "
-                 "$OUT/prof/bench_kernel_stats.csv --summary-md profiles/k_stage_hurricane_4M.md",
-                 "```", "", "The bench runs the FP64 headline and then the mixed-precision variant in the same "
-                 "process, so both precisions appear below.", "",
-                 f"Kernel sources sha256 (bench.py reports this traffic only for these sources): "
-                 f"`{res['source_sha256']}`", ""]
-        if stats_csv:
-            with open(stats_csv) as fh:
-                rows = list(csv.DictReader(fh))
-            lines += ["## Kernel trace (`--kernel-trace --stats`, 50 timed + 5 warm-up steps per precision)", "",
-                      "| kernel | calls | avg us | min us | max us | share % |", "|---|---|---|---|---|---|"]
-            for r in rows[:10]:
+    if not out_md:
+        return
+    rows = []
+    if stats_csv:
+        with open(stats_csv) as fh:
+            rows = list(csv.DictReader(fh))
+    c = res["calibration"]
+    head = ["Commands, on one MI355X, with REPO = the repository root and OUT = an output folder:", "", "```",
+            "cd /tmp && export TMPDIR=/tmp", CMD_TRACE, CMD_PMC.format(c="FETCH_SIZE"), CMD_PMC.format(c="WRITE_SIZE"),
+            "cd $REPO && python3 bench.py --summarize-pmc $OUT/pmc --kernel-stats "
+            "$OUT/prof/bench_kernel_stats.csv --summary-md profiles/k_stage_hurricane_4M.md", "```", "",
+            "One bench process runs the p = 1 FP64 headline, the p = 1 mixed variant, then p = 2 in FP64 and "
+            "mixed, on the same 4M-triangle mesh.", "",
+            f"Kernel sources sha256 (bench.py reports this traffic only for these sources): `{res['source_sha256']}`",
+            ""]
+    calib = ["", "Calibration: a 2 GiB device copy in the same runs reads "
+             f"{c['FETCH_SIZE']['copy_KiB']:.0f} KiB FETCH_SIZE and {c['WRITE_SIZE']['copy_KiB']:.0f} KiB "
+             f"WRITE_SIZE, so fetched bytes = FETCH_SIZE x {c['FETCH_SIZE']['bytes_per_KiB']} B and written "
+             f"bytes = WRITE_SIZE x {c['WRITE_SIZE']['bytes_per_KiB']} B.", ""]
+
+    def section(title, kernels):
+        out = [f"# {title}", ""] + head
+        sel = [r for r in rows if (kernel_key(r["Name"]) or ("",))[0] in kernels]
+        if sel:
+            out += ["## Kernel trace (`--kernel-trace --stats`, 50 timed + 5 warm-up steps per variant)", "",
+                    "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+            for r in sel:
                 nm = r["Name"].split("(")[0].replace("dgswe::", "")
-                lines.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
-                             f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
-                             f"{float(r['Percentage']):.1f} |")
-            lines.append("")
-            for key, prec in (("double", "fp64"), ("float", "mixed")):
-                sel = [r for r in rows if stage_kernel_precision(r["Name"]) == key]
-                if sel:
-                    n = sum(int(r["Calls"]) for r in sel)
-                    tot = sum(float(r["TotalDurationNs"]) for r in sel)
-                    lines.append(f"k_stage {prec}, both RK stages: {n} launches, average {tot / n / 1e3:.1f} us "
-                                 f"(bench.py reports the HIP-event average over the same two kernels).")
-            lines.append("")
-        lines += ["## HBM traffic per k_stage launch (mean over both RK stages)", "",
-                  "| precision | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch (calibrated) |",
-                  "|---|---|---|---|"]
-        for prec, d in res["k_stage"].items():
-            lines.append(f"| {prec} | {d['fetch_KiB']:.0f} | {d['write_KiB']:.0f} | {d['bytes_per_launch'] / 1e9:.3f} GB |")
-        c = res["calibration"]
-        lines += ["", "Calibration: a 2 GiB device copy in the same runs reads "
-                  f"{c['FETCH_SIZE']['copy_KiB']:.0f} KiB FETCH_SIZE and {c['WRITE_SIZE']['copy_KiB']:.0f} KiB "
-                  f"WRITE_SIZE, so fetched bytes = FETCH_SIZE x {c['FETCH_SIZE']['bytes_per_KiB']} B and written "
-                  f"bytes = WRITE_SIZE x {c['WRITE_SIZE']['bytes_per_KiB']} B.", ""]
-        with open(out_md, "w") as fh:
-            fh.write("\n".join(lines))
+                out.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                           f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+            out.append("")
+            for k in kernels:
+                for prec in ("fp64", "mixed"):
+                    ss = [r for r in sel if kernel_key(r["Name"]) == (k, prec)]
+                    if ss:
+                        n = sum(int(r["Calls"]) for r in ss)
+                        tot = sum(float(r["TotalDurationNs"]) for r in ss)
+                        out.append(f"{k} {prec}, both RK stages: {n} launches, average {tot / n / 1e3:.1f} us "
+                                   f"(bench.py reports the HIP-event average over the same kernels).")
+            out.append("")
+        out += ["## HBM traffic per launch (mean over both RK stages)", "",
+                "| kernel | precision | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch (calibrated) |",
+                "|---|---|---|---|---|"]
+        for k in kernels:
+            for prec, d in res["kernels"].get(k, {}).items():
+                out.append(f"| {k} | {prec} | {d['fetch_KiB']:.0f} | {d['write_KiB']:.0f} | "
+                           f"{d['bytes_per_launch'] / 1e9:.3f} GB |")
+        return out + calib
+
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(section("k_stage (p = 1) on the 4M-triangle hurricane workload: kernel times and HBM "
+                                   "traffic", ("k_stage",))))
+    p2_md = os.path.join(os.path.dirname(out_md), "k_rhs2_k_pp2_hurricane_4M_p2.md")
+    with open(p2_md, "w") as fh:
+        fh.write("\n".join(section("k_pp2 and k_rhs2 (p = 2) on the 4M-triangle hurricane workload: kernel times "
+                                   "and HBM traffic", ("k_pp2", "k_rhs2"))))
 
 
 def cpu_baseline(wl, target_s=12.0):
@@ -337,7 +362,7 @@ def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
     for k in kernels:
         kb = algorithmic_bytes(k, ne, ned, nn, precision)
         kernels[k]["alg_GBs"] = round(kb / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
-    traffic = stored_traffic(precision) if (dom == "k_stage" and with_traffic) else None
+    traffic = stored_traffic(dom, precision) if with_traffic else None
     return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": int(b), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
@@ -404,7 +429,7 @@ def main():
             el4, _, k4, d4 = measure(wl, prec, args.steps, args.warmup, stream, profile, order=2)
             variants["p2_" + prec] = {"value": ne * 2 * args.steps / el4, "unit": "elem-stage/s", "p": 2,
                                       "precision": prec, "ms_per_step": 1e3 * el4 / args.steps,
-                                      "roofline": roofline(k4, ne, ned, nn, prec, with_traffic=False),
+                                      "roofline": roofline(k4, ne, ned, nn, prec),
                                       "kernels": k4, "t_end": d4["t"]}
             if k4:
                 log(f"p2 {prec} kernels: " + json.dumps(k4))
