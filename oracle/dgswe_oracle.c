@@ -62,6 +62,7 @@ typedef void (*or_source_fn)(double t, int32_t npts, const double *xy, double *o
 typedef struct {
   double g, rho0, h0, cfl, dt_fixed, dt_max;
   int32_t limiter, wetdry;
+  int32_t rk;       /* 22, 33, 32, 42, 52: SSPRK(s, q) */
 } or_params;
 
 typedef struct {
@@ -415,6 +416,7 @@ or_mesh *or_create(int32_t nn, const double *xy, const double *hb, int32_t ne, c
   M->extra = NULL;
   if (!M->w || !M->w1 || !M->wt || !M->dw || !M->slot || !M->nodal) { or_destroy(M); *status = OR_E_NOMEM; return NULL; }
   M->nm = 3; M->nq = 3;
+  M->prm.rk = 22;
   M->prm.g = 9.81; M->prm.rho0 = 1000.0; M->prm.h0 = 0.01; M->prm.cfl = 0.2;
   M->prm.dt_fixed = 0.0; M->prm.dt_max = 0.0; M->prm.limiter = 1; M->prm.wetdry = 1;
   M->frc.pn = 101300.0;
@@ -864,6 +866,36 @@ static int32_t pick_dt(const or_mesh *M, const double *w, double *dt) {
  * paper's optimized scheme whose coefficients are not given):
  *   w1      = PP(w^n + dt L(w^n, t^n))
  *   w^{n+1} = PP(1/2 w^n + 1/2 (w1 + dt L(w1, t^n + dt))) */
+/* The time steppers in Shu-Osher form (Eq. RKSSP; the paper names
+ * optimized SSP schemes without coefficients, reading Z7):
+ *   SSPRK(2,2): w1 = w + dt L(w), w+ = 1/2 w + 1/2 (w1 + dt L(w1));
+ *   SSPRK(3,3): w1 = w + dt L(w), w2 = 3/4 w + 1/4 (w1 + dt L(w1)),
+ *               w+ = 1/3 w + 2/3 (w2 + dt L(w2)), stage times t, t+dt, t+dt/2;
+ *   SSPRK(s,2): w_k = w_{k-1} + dt/(s-1) L(w_{k-1}) for k < s,
+ *               w+ = 1/s w + (s-1)/s (w_{s-1} + dt/(s-1) L(w_{s-1})),
+ *               stage k at t + k dt/(s-1).
+ * Each stage is post-processed. */
+int32_t or_set_scheme(or_mesh *M, int32_t rk) {
+  if (rk != 22 && rk != 33 && rk != 32 && rk != 42 && rk != 52) return OR_E_INVALID;
+  M->prm.rk = rk;
+  return OR_OK;
+}
+
+/* stage k of scheme rk: out = a w + b (in + h dt L(in)) at time t + c dt */
+static int scheme_stage(int32_t rk, int k, double *a, double *b, double *h, double *c) {
+  if (rk == 33) {
+    static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0}, Cc[3] = {0.0, 1.0, 0.5};
+    *a = A[k]; *b = B[k]; *h = 1.0; *c = Cc[k];
+    return 3;
+  }
+  int s = rk / 10;  /* 22 -> 2 */
+  *h = 1.0 / (s - 1);
+  *c = k * (*h);
+  if (k == s - 1) { *a = 1.0 / s; *b = (double)(s - 1) / s; *c = 1.0; }
+  else { *a = 0.0; *b = 1.0; }
+  return s;
+}
+
 int32_t or_step(or_mesh *M, int32_t nsteps) {
   const int32_t ne = M->ne;
   const size_t n9 = 3 * (size_t)M->nm * ne;
@@ -871,14 +903,23 @@ int32_t or_step(or_mesh *M, int32_t nsteps) {
     double dt;
     int32_t st = pick_dt(M, M->w, &dt);
     if (st != OR_OK) return st;
-    or_rhs(M, M->w, M->t, M->dw);
+    double a, b, h, c;
+    const int ns = scheme_stage(M->prm.rk, 0, &a, &b, &h, &c);
+    for (int k = 0; k < ns; ++k) {
+      scheme_stage(M->prm.rk, k, &a, &b, &h, &c);
+      const double *in = k == 0 ? M->w : M->w1;
+      const double hdt = h * dt;
+      or_rhs(M, in, M->t + c * dt, M->dw);
+      if (a == 0.0) {
 #pragma omp parallel for schedule(static)
-    for (size_t i = 0; i < n9; ++i) M->wt[i] = M->w[i] + dt * M->dw[i];
-    or_postprocess(M, M->wt, M->w1);
-    or_rhs(M, M->w1, M->t + dt, M->dw);
+        for (size_t i = 0; i < n9; ++i) M->wt[i] = in[i] + hdt * M->dw[i];
+      } else {
 #pragma omp parallel for schedule(static)
-    for (size_t i = 0; i < n9; ++i) M->wt[i] = 0.5 * M->w[i] + 0.5 * (M->w1[i] + dt * M->dw[i]);
-    or_postprocess(M, M->wt, M->w);
+        for (size_t i = 0; i < n9; ++i) M->wt[i] = a * M->w[i] + b * (in[i] + hdt * M->dw[i]);
+      }
+      /* the last stage's result becomes w; earlier ones go to w1 */
+      or_postprocess(M, M->wt, k == ns - 1 ? M->w : M->w1);
+    }
     M->t += dt;
     M->dt_last = dt;
     M->steps += 1;

@@ -70,6 +70,8 @@ def load_oracle():
     L.or_llf.argtypes = [C.c_double, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int32,
                          C.c_int32, _dp]
     L.or_wall.argtypes = [C.c_double, _dp, C.c_double, C.c_double, C.c_double, C.c_int32, _dp]
+    L.or_set_scheme.argtypes = [C.c_void_p, C.c_int32]
+    L.or_set_scheme.restype = C.c_int32
     L.or_set_order.argtypes = [C.c_void_p, C.c_int32]
     L.or_set_order.restype = C.c_int32
     L.or_basis2.argtypes = [C.c_double, C.c_double, _dp, _dp]
@@ -145,6 +147,9 @@ class Oracle:
                                  int(p.get("limiter", 1)), int(p.get("wetdry", 1)))
         if r:
             raise OracleError(f"or_set_params: {r}")
+        r = self.L.or_set_scheme(self.h, int(p.get("rk", 22)))
+        if r:
+            raise OracleError(f"or_set_scheme: {r}")
 
     def set_forcing(self, f: dict):
         me = f.get("manning_n_elem")
