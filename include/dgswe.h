@@ -77,7 +77,22 @@ typedef struct {
   double dt_max;     /* > 0: upper bound on the CFL time step [s] */
   int32_t limiter;   /* 1: slope limiter after each stage */
   int32_t wetdry;    /* 1: wetting/drying after each stage */
+  int32_t rk;        /* time stepper: 22 = SSPRK(2,2), 33 = SSPRK(3,3),
+                        32, 42, 52 = SSPRK(s,2) with s = 3, 4, 5 stages */
 } dgswe_params;
+
+/* Time steppers (Sec. 2.2: the paper names "optimized" SSP Runge-Kutta
+ * schemes without their coefficients).  Every stage is followed by the
+ * slope limiter and the wet/dry step; stage k of a step evaluates the
+ * forcing and the tide at t^n + c_k dt.
+ *   22: SSPRK(2,2), c = (0, 1) (the default).
+ *   33: SSPRK(3,3): w1 = w + dt L(w); w2 = 3/4 w + 1/4 (w1 + dt L(w1));
+ *       w^{n+1} = 1/3 w + 2/3 (w2 + dt L(w2)); c = (0, 1, 1/2).
+ *   s2 (s = 3, 4, 5): SSPRK(s,2): s - 1 Euler steps of dt/(s - 1), then
+ *       w^{n+1} = 1/s w + (s - 1)/s (w_{s-1} + dt/(s - 1) L(w_{s-1}));
+ *       c_k = k/(s - 1).  Its SSP coefficient is s - 1: the CFL number may
+ *       be s - 1 times that of SSPRK(2,2) for the same stability.
+ * dt is formed from cfl as for every scheme; choose cfl accordingly. */
 
 /* Precision.  DGSWE_FP64 computes and stores everything in FP64.
  * DGSWE_MIXED (the paper computes in FP32 throughout, Sec. 5) keeps in
@@ -101,7 +116,7 @@ typedef struct {
  * The CFL number should be smaller than at p = 1 (about 0.1). */
 
 /* Fill `p` with the defaults: p=1, FP64, g=9.81, rho0=1000, h0=0.01,
- * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1. */
+ * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1, rk=22. */
 void dgswe_default_params(dgswe_params *p);
 
 /* Build a solver for one mesh and allocate its device-resident state.

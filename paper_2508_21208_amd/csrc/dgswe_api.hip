@@ -26,6 +26,34 @@
 
 using namespace dgswe;
 
+namespace dgswe {
+// Shu-Osher forms: SSPRK(2,2) and SSPRK(3,3) (Shu and Osher 1988), and the
+// optimal second-order SSPRK(s,2) (s - 1 forward-Euler steps of dt/(s-1),
+// then the average with w^n weighted 1/s), whose SSP coefficient s - 1
+// allows a CFL number s - 1 times that of a single Euler step.
+int rk_stages(int rk, StageCoef out[5]) {
+  if (rk == 22) {
+    out[0] = {0.0, 1.0, 1.0, 0.0, 0};
+    out[1] = {0.5, 0.5, 1.0, 1.0, 1};
+    return 2;
+  }
+  if (rk == 33) {
+    out[0] = {0.0, 1.0, 1.0, 0.0, 0};
+    out[1] = {0.75, 0.25, 1.0, 1.0, 0};
+    out[2] = {1.0 / 3.0, 2.0 / 3.0, 1.0, 0.5, 1};
+    return 3;
+  }
+  if (rk == 32 || rk == 42 || rk == 52) {
+    const int s = rk / 10;
+    const double h = 1.0 / (s - 1);
+    for (int i = 0; i < s - 1; ++i) out[i] = {0.0, 1.0, h, i * h, 0};
+    out[s - 1] = {1.0 / s, (double)(s - 1) / s, h, 1.0, 1};
+    return s;
+  }
+  return 0;
+}
+}  // namespace dgswe
+
 namespace {
 thread_local std::string g_create_error = "no error";
 
@@ -202,6 +230,8 @@ bool validate_params(const dgswe_params *p, std::string &msg) {
   // (shared by every member of a batch)
   if (!p) { msg = "params is NULL"; return false; }
   if (p->p != 1 && p->p != 2) { msg = "p must be 1 or 2"; return false; }
+  StageCoef sc[5];
+  if (rk_stages(p->rk, sc) == 0) { msg = "rk must be 22, 33, 32, 42 or 52"; return false; }
   if (p->precision != DGSWE_FP64 && p->precision != DGSWE_MIXED) {
     msg = "precision must be DGSWE_FP64 or DGSWE_MIXED";
     return false;
@@ -849,6 +879,7 @@ extern "C" {
 
 void dgswe_default_params(dgswe_params *p) {
   if (!p) return;
+  p->rk = 22;
   p->p = 1;
   p->precision = DGSWE_FP64;
   p->g = 9.81;
@@ -901,42 +932,43 @@ dgswe_status dgswe_step(dgswe_solver *S, int32_t n_steps) {
   const Params &p = S->prm;
   const int want_dt = (p.dt_fixed > 0.0) ? 0 : 1;
   if (m.nch == 0) return DGSWE_OK;  // no member
+  StageCoef sc[5];
+  const int ns = rk_stages(S->uprm.rk, sc);
   for (int i = 0; i < n_steps; ++i) {
     const int slot = (int)(S->steps_enq & 1);
-    // rotation: w^n in cur, stage 1 -> s1, stage 2 -> nx (both unlimited)
-    const int cur = S->cur, s1 = (cur + 1) % 3, nx = (cur + 2) % 3;
+    // buffers: stage k reads buf[(cur + k) % 3] and writes buf[(cur + k + 1)
+    // % 3] (unlimited); wpp holds the post-processed w^n (RK base), so the
+    // buffer of w^n is free from the second stage on
+    const int cur = S->cur;
     hipError_t e = hipSuccess;
-    for (int stage = 0; stage < 2 && e == hipSuccess; ++stage) {
+    for (int stage = 0; stage < ns && e == hipSuccess; ++stage) {
+      void *in = st.buf[(cur + stage) % 3], *out = st.buf[(cur + stage + 1) % 3];
+      const int wd = sc[stage].last ? want_dt : 0;
       if (S->nfblk > 0) {
         Timed t(S, K_FORCING);
-        e = launch_forcing(m, st, p, S->nfblk, slot, stage, S->stream);
+        e = launch_forcing(m, st, p, S->nfblk, slot, sc[stage].c, S->stream);
       }
       if (e != hipSuccess) break;
       if (S->order == 2) {
-        // records of the stage input: w^n's go to wpp (the RK base of the
-        // second stage), the first stage result's to the buffer of w^n,
-        // which is no longer read
-        void *rec = stage == 0 ? st.wpp : st.buf[cur];
+        // records of the stage input: w^n's go to wpp (the RK base), a later
+        // stage's to the one buffer it neither reads nor writes
+        void *rec = stage == 0 ? st.wpp : st.buf[(cur + stage + 2) % 3];
         {
           Timed t(S, K_PP2);
-          e = launch_pp2(m, st, p, stage == 0 ? st.buf[cur] : st.buf[s1], rec, slot, stage, S->precision, S->stream);
+          e = launch_pp2(m, st, p, in, rec, slot, stage == 0 ? 0 : 1, S->precision, S->stream);
         }
         if (e != hipSuccess) break;
         Timed t(S, K_RHS2);
-        e = launch_rhs2(m, st, p, rec, stage == 0 ? nullptr : st.wpp, stage == 0 ? st.buf[s1] : st.buf[nx], slot,
-                        stage, stage == 0 ? 0 : want_dt, S->precision, S->stream);
+        e = launch_rhs2(m, st, p, rec, stage == 0 ? nullptr : st.wpp, out, slot, stage == 0, sc[stage], wd,
+                        S->precision, S->stream);
         continue;
       }
       Timed t(S, K_STAGE);
-      if (stage == 0)
-        e = launch_stage(m, st, p, st.buf[cur], nullptr, st.buf[s1], st.wpp, slot, 0, 0, S->block, S->precision,
-                         S->stream);
-      else
-        e = launch_stage(m, st, p, st.buf[s1], st.wpp, st.buf[nx], nullptr, slot, 1, want_dt, S->block,
-                         S->precision, S->stream);
+      e = launch_stage(m, st, p, in, stage == 0 ? nullptr : st.wpp, out, stage == 0 ? st.wpp : nullptr, slot,
+                       stage == 0, sc[stage], wd, S->block, S->precision, S->stream);
     }
     if (e != hipSuccess) return hip_fail(S, e, "kernel launch");
-    S->cur = nx;
+    S->cur = (cur + ns) % 3;
     for (MemberHost &h : S->mh) h.cur_is_pp = false;
     S->steps_enq += 1;
   }

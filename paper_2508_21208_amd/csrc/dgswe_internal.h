@@ -91,6 +91,20 @@ struct DevMesh {
   const double *hmean;
 };
 
+// One stage of an SSP Runge-Kutta scheme in Shu-Osher form: the stage
+// result is a * w^n + b * (w_in + h dt L(w_in)) (post-processed w^n; a = 0:
+// w_in + h dt L(w_in)), with the forcing and tide at time t^n + c dt.  last:
+// the step's final stage (advances the member's time and step count and
+// forms the next step's CFL minimum).
+struct StageCoef {
+  double a, b, h, c;
+  int last;
+};
+
+// The stages of scheme `rk` (22, 33, 32, 42, 52: SSPRK(s, q)); returns the
+// stage count, 0 for an unknown scheme.
+int rk_stages(int rk, StageCoef out[5]);
+
 // Parameters shared by all members of a batch.
 struct Params {
   double g, rho0, h0, cfl, dt_fixed, dt_max;
@@ -169,17 +183,17 @@ int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *
 // Kernel launchers (dgswe_kernels.hip).  Each returns hipGetLastError().
 // Holland forcing at the stage time for the nodes of every member with a
 // moving vortex (nfblk = the total number of forcing blocks).
-hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int nfblk, int slot, int stage,
+hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int nfblk, int slot, double c,
                           hipStream_t st);
 // One RK stage of every member: post-process `win` (where the member's
 // control block asks for it), edge fluxes, area integrals, gather, RK
-// combination; writes the unlimited result to `wout`.  The first stage
-// (stage 0) also writes the post-processed input to `wpp`; the second stage
-// reads it back as the RK base `wbase`.  `precision` is DGSWE_FP64 or
-// DGSWE_MIXED (state buffer layout and kernels).
+// combination `sc`; writes the unlimited result to `wout`.  The first stage
+// (first != 0) also writes the post-processed input to `wpp`; later stages
+// with sc.a != 0 read it back as the RK base `wbase`.  `precision` is
+// DGSWE_FP64 or DGSWE_MIXED (state buffer layout and kernels).
 hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const void *win,
-                        const void *wbase, void *wout, void *wpp, int slot, int stage, int want_dt, int block,
-                        int precision, hipStream_t st);
+                        const void *wbase, void *wout, void *wpp, int slot, int first, const StageCoef &sc,
+                        int want_dt, int block, int precision, hipStream_t st);
 // thread-block sizes the stage kernel is built for
 constexpr int kStageBlocks[] = {256};
 // Elements [e0, e0 + count) of a state as FP64 [9][count] (post-processed if
@@ -202,7 +216,8 @@ hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, con
 hipError_t launch_pp2(const DevMesh &m, const DevState &s, const Params &p, const void *win, void *rec, int slot,
                       int stage, int precision, hipStream_t st);
 hipError_t launch_rhs2(const DevMesh &m, const DevState &s, const Params &p, const void *rec, const void *rbase,
-                       void *wout, int slot, int stage, int want_dt, int precision, hipStream_t st);
+                       void *wout, int slot, int first, const StageCoef &sc, int want_dt, int precision,
+                       hipStream_t st);
 // p = 2 read-back: elements [e0, e0 + count) as FP64 [18][count]
 hipError_t launch_post_only2(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
                              double *wout, int precision, hipStream_t st);

@@ -578,10 +578,11 @@ HD void load_elem_forcing(const DevMesh &m, const DevState &s, const int node[3]
 
 // phase A for chunk element i; returns the CFL candidate of the output when
 // want_dt, and sets bad on a non-finite output.  base: combine with the
-// post-processed RK base held in P (second stage).
+// post-processed RK base held in P, out = a base + b (w + hdt L(w)), else
+// out = w + hdt L(w).
 template <class QT>
 HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, const ElemPre<QT> &P, bool base,
-                     St<QT> wout, size_t ne, double dt, int want_dt, int i, bool &bad) {
+                     double ca, double cb, St<QT> wout, size_t ne, double dt, int want_dt, int i, bool &bad) {
   const size_t e = (size_t)(k.c0 + i);
   double z[3];
   QT q[6];
@@ -623,7 +624,7 @@ HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, cons
   QT oq[6];
   for (int j = 0; j < 3; ++j) {
     const double dw = rz[j] * imu[j];
-    oz[j] = base ? 0.5 * P.wbz[j] + 0.5 * (z[j] + dt * dw) : z[j] + dt * dw;
+    oz[j] = base ? ca * P.wbz[j] + cb * (z[j] + dt * dw) : z[j] + dt * dw;
     wout.z[j * ne + e] = oz[j];
     fin = fin && __builtin_isfinite(oz[j]);
   }
@@ -631,7 +632,7 @@ HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, cons
   for (int j = 0; j < 6; ++j) {
     QT dw = rq[j] * (QT)imu[j % 3];
     if (!wet) dw = (QT)0;
-    oq[j] = base ? (QT)0.5 * P.wbq[j] + (QT)0.5 * (q[j] + dtq * dw) : q[j] + dtq * dw;
+    oq[j] = base ? (QT)ca * P.wbq[j] + (QT)cb * (q[j] + dtq * dw) : q[j] + dtq * dw;
     wout.q[j * ne + e] = oq[j];
     fin = fin && __builtin_isfinite(oq[j]);
   }
@@ -645,7 +646,7 @@ HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, cons
 
 // Forcing blocks are numbered member by member (members without a moving
 // vortex have none); block b finds its member by bisection of fblk_off.
-__global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Params p, int slot, int stage) {
+__global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Params p, int slot, double c) {
   const int b = blockIdx.x;
   int lo = 0, hi = m.nmem;  // fblk_off[lo] <= b < fblk_off[hi]
   while (hi - lo > 1) {
@@ -661,12 +662,13 @@ __global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Param
   if (!step_dt(ctl, p, slot, dt)) return;
   const int n = f.n0 + i;
   double out[3];
-  holland(f, m.node_x[n], m.node_y[n], ctl->t[slot] + (stage ? dt : 0.0), out);
+  holland(f, m.node_x[n], m.node_y[n], ctl->t[slot] + c * dt, out);
   ((double2 *)s.nodal)[n] = make_double2(out[0], out[1]);
   s.nodal[2 * (size_t)m.nn + n] = out[2];
 }
 
-// One RK stage (STAGE 0 or 1) over one chunk per workgroup of NT lanes
+// One RK stage (STAGE 0: the first, else a later one; the combination in
+// sc) over one chunk per workgroup of NT lanes
 // (chunk size C <= NT, chunk + ring 1 <= 2 NT, chunk-local edges <= 2 NT).
 // The chunks of all members of a batch form one grid; each workgroup reads
 // its member's forcing and control block.  The first stage also writes the
@@ -674,7 +676,8 @@ __global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Param
 // reads.
 template <int NT, int WPE, class QT, int STAGE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_stage(
-    DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase, St<QT> wout, St<QT> wpp, int slot, int want_dt) {
+    DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase, St<QT> wout, St<QT> wpp, StageCoef sc, int slot,
+    int want_dt) {
   extern __shared__ double lds_raw[];
   __shared__ double red[NT / 64];
   const int tid = threadIdx.x;
@@ -715,7 +718,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   load_edge_rec(m, k, j1, r1);
   GeoReg<QT> geo;
   load_geo(m, k, cei, geo, pre.inr2);
-  load_elem_pre<QT>(m, k, cei, STAGE ? &wbase : nullptr, pre);
+  const bool use_base = STAGE != 0 && sc.a != 0.0;
+  load_elem_pre<QT>(m, k, cei, use_base ? &wbase : nullptr, pre);
   pre.manning = manning_of(m, k, cei, (QT)0);
   // Round 3: gathers through the indices (kept after round 2 in the
   // instruction stream, so the index loads return while round 2 is issued).
@@ -768,20 +772,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   if (a0) phase_post<QT>(p, k, L, pp_in, i0, h0, nb0, wpp_out, ne);
   if (a1) phase_post<QT>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne);
   __syncthreads();
-  const double ts = t0 + (STAGE ? dt : 0.0);
+  const double ts = t0 + sc.c * dt;
   const double zb = tide ? tide_level(F, ts) : 0.0;
   if (tid < k.ne_loc) phase_edge<QT>(p, L, zb, tid, r0);
   if (tid + NT < k.ne_loc) phase_edge<QT>(p, L, zb, tid + NT, r1);
   __syncthreads();
   double cand = INFINITY;
   bool bad = false;
-  if (ae && active) cand = phase_area<QT>(p, k, L, pre, STAGE != 0, wout, ne, dt, want_dt, tid, bad);
+  if (ae && active)
+    cand = phase_area<QT>(p, k, L, pre, use_base, sc.a, sc.b, wout, ne, sc.h * dt, want_dt, tid, bad);
   if (bad) atomicCAS(&ctl->status, 0, (int)DGSWE_E_NONFINITE);
   if (want_dt) {
     const double bm = block_min<NT>(cand, red);
     if (tid == 0 && bm < INFINITY) atomicMin(&ctl->dtmin[slot ^ 1], double_to_bits(bm));
   }
-  if (STAGE == 1 && active && k.first && tid == 0) {
+  if (sc.last && active && k.first && tid == 0) {
     ctl->t[slot ^ 1] = t0 + dt;
     ctl->dt_last = dt;
     ctl->steps = ctl->steps + 1;
@@ -906,15 +911,16 @@ bool stage_block_ok(int block) {
 }
 
 
-hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int nfblk, int slot, int stage,
+hipError_t launch_forcing(const DevMesh &m, const DevState &s, const Params &p, int nfblk, int slot, double c,
                           hipStream_t st) {
-  if (nfblk > 0) hipLaunchKernelGGL(k_forcing, dim3(nfblk), dim3(kBlock), 0, st, m, s, p, slot, stage);
+  if (nfblk > 0) hipLaunchKernelGGL(k_forcing, dim3(nfblk), dim3(kBlock), 0, st, m, s, p, slot, c);
   return hipGetLastError();
 }
 
 template <class QT>
 static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const void *win, const void *wbase,
-                     void *wout, void *wpp, int slot, int stage, int want_dt, int block, hipStream_t st) {
+                     void *wout, void *wpp, int slot, int first, const StageCoef &sc, int want_dt, int block,
+                     hipStream_t st) {
   const size_t ne = (size_t)m.ne;
   const size_t lds = lds_bytes<QT>(m);
   const CSt<QT> a = csplit<QT>(win, ne);
@@ -922,20 +928,21 @@ static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const
   const St<QT> o = split<QT>(wout, ne);
   const St<QT> q = wpp ? split<QT>(wpp, ne) : St<QT>{nullptr, nullptr};
 #define DGSWE_STAGE(NT, W, S)                                                                             \
-  hipLaunchKernelGGL((k_stage<NT, W, QT, S>), dim3(m.nch), dim3(NT), lds, st, m, s, p, a, b, o, q, slot, want_dt)
+  hipLaunchKernelGGL((k_stage<NT, W, QT, S>), dim3(m.nch), dim3(NT), lds, st, m, s, p, a, b, o, q, sc, slot, \
+                     want_dt)
   (void)block;  // 256 lanes (the local ids and edge codes are packed for it)
-  if (stage) DGSWE_STAGE(256, 2, 1);
+  if (!first) DGSWE_STAGE(256, 2, 1);
   else DGSWE_STAGE(256, 2, 0);
 #undef DGSWE_STAGE
 }
 
 hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, const void *win, const void *wbase,
-                        void *wout, void *wpp, int slot, int stage, int want_dt, int block, int precision,
-                        hipStream_t st) {
+                        void *wout, void *wpp, int slot, int first, const StageCoef &sc, int want_dt, int block,
+                        int precision, hipStream_t st) {
   if (precision == DGSWE_MIXED)
-    stage_qt<float>(m, s, p, win, wbase, wout, wpp, slot, stage, want_dt, block, st);
+    stage_qt<float>(m, s, p, win, wbase, wout, wpp, slot, first, sc, want_dt, block, st);
   else
-    stage_qt<double>(m, s, p, win, wbase, wout, wpp, slot, stage, want_dt, block, st);
+    stage_qt<double>(m, s, p, win, wbase, wout, wpp, slot, first, sc, want_dt, block, st);
   return hipGetLastError();
 }
 

@@ -315,10 +315,10 @@ __global__ __launch_bounds__(kBlock) void k_pp2(DevMesh m, DevState s, Params p,
 // 1/2 base + 1/2 (u + dt L(u)); zeta modes in out, momentum modes in oqv,
 // the CFL candidate of the result in cand.  Returns false on a non-finite
 // result.
-template <class QT, int STAGE>
+template <class QT>
 HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const ChunkInfo &k, const Member &F,
-                     const Rec2<QT> *__restrict__ u, const Rec2<QT> *__restrict__ base, int i, double t0, double dt,
-                     double out[6], QT oqv[12], double &cand) {
+                     const Rec2<QT> *__restrict__ u, const Rec2<QT> *__restrict__ base, const StageCoef &sc, int i,
+                     double t0, double dt, double out[6], QT oqv[12], double &cand) {
   using R = QT;
   const size_t ne = (size_t)m.ne;
   const int e = k.c0 + i;
@@ -434,7 +434,7 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   }
 
   // edges: each evaluated in its own orientation with both sides' traces
-  const double ts = t0 + (STAGE ? dt : 0.0);
+  const double ts = t0 + sc.c * dt;
   const bool tide = F.n_tide > 0 || F.tide_offset != 0.0;
   const double zb = tide ? tide_level(F, ts) : 0.0;
 #pragma unroll 1
@@ -516,22 +516,24 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   load_rec<QT>(u, e, z, q);
   double bz[6];
   R bq[12];
-  if (STAGE) load_rec<QT>(base, e, bz, bq);
+  const bool use_base = base != nullptr;
+  if (use_base) load_rec<QT>(base, e, bz, bq);
   else {
     for (int j = 0; j < 6; ++j) bz[j] = 0.0;
     for (int j = 0; j < 12; ++j) bq[j] = (R)0;
   }
+  const double hdt = sc.h * dt;
   bool fin = true;
   for (int j = 0; j < 6; ++j) {
     const double dw = rz[j] * kMu2Inv[j];
-    out[j] = STAGE ? 0.5 * bz[j] + 0.5 * (z[j] + dt * dw) : z[j] + dt * dw;
+    out[j] = use_base ? sc.a * bz[j] + sc.b * (z[j] + hdt * dw) : z[j] + hdt * dw;
     fin = fin && __builtin_isfinite(out[j]);
   }
-  const R dtq = (R)dt;
+  const R dtq = (R)hdt;
   for (int j = 0; j < 12; ++j) {
     R dw = rq[j] * (R)kMu2Inv[j % 6];
     if (!wet) dw = (R)0;
-    oqv[j] = STAGE ? (R)0.5 * bq[j] + (R)0.5 * (q[j] + dtq * dw) : q[j] + dtq * dw;
+    oqv[j] = use_base ? (R)sc.a * bq[j] + (R)sc.b * (q[j] + dtq * dw) : q[j] + dtq * dw;
     fin = fin && __builtin_isfinite(oqv[j]);
   }
   cand = cfl_candidate(out[0], (double)oqv[0], (double)oqv[6], hm, ai.y, p);
@@ -539,11 +541,11 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
 }
 
 // WPE: minimum waves per SIMD the register allocation is held to
-template <class QT, int STAGE, int WPE>
+template <class QT, int WPE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_rhs2(
     DevMesh m, DevState s, Params p, const Rec2<QT> *__restrict__ u,
-                                                 const Rec2<QT> *__restrict__ base, St<QT> wout, int slot,
-                                                 int want_dt) {
+                                                 const Rec2<QT> *__restrict__ base, St<QT> wout, StageCoef sc,
+                                                 int slot, int want_dt) {
   __shared__ double red[kBlock / 64];
   const int c = chunk_of_block(blockIdx.x, m.nch);
   if (c < 0) return;
@@ -562,7 +564,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const bool act = active && tid < k.cc;
   double out[6], cand = INFINITY;
   QT oqv[12];
-  const bool fin = rhs2_element<QT, STAGE>(m, s, p, k, F, u, base, act ? tid : k.cc - 1, t0, dt, out, oqv, cand);
+  const bool fin = rhs2_element<QT>(m, s, p, k, F, u, base, sc, act ? tid : k.cc - 1, t0, dt, out, oqv, cand);
   const int e = k.c0 + tid;
   if (act) {
     for (int j = 0; j < 6; ++j) wout.z[j * ne + e] = out[j];
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     const double bm = block_min<kBlock>(act ? cand : (double)INFINITY, red);
     if (tid == 0 && bm < INFINITY) atomicMin(&ctl->dtmin[slot ^ 1], double_to_bits(bm));
   }
-  if (STAGE == 1 && active && k.first && tid == 0) {
+  if (sc.last && active && k.first && tid == 0) {
     ctl->t[slot ^ 1] = t0 + dt;
     ctl->dt_last = dt;
     ctl->steps = ctl->steps + 1;
@@ -602,8 +604,8 @@ static inline unsigned nblk2(long long n) { return (unsigned)((n + kBlock - 1) /
 
 template <class QT>
 static void stage2_qt(const DevMesh &m, const DevState &s, const Params &p, const void *win, void *rec,
-                      const void *rbase, void *wout, int slot, int stage, int want_dt, hipStream_t st, bool pp_only,
-                      bool rhs_only) {
+                      const void *rbase, void *wout, int slot, int stage, const StageCoef &sc, int want_dt,
+                      hipStream_t st, bool pp_only, bool rhs_only) {
   const size_t ne = (size_t)m.ne;
   const CSt<QT> a = {(const double *)win, (const QT *)((const double *)win + 6 * ne)};
   const St<QT> o = {(double *)wout, (QT *)((double *)wout + 6 * ne)};
@@ -619,37 +621,37 @@ static void stage2_qt(const DevMesh &m, const DevState &s, const Params &p, cons
       const int w = ev ? std::atoi(ev) : 0;
       return (w >= 1 && w <= 4) ? w : (sizeof(QT) == 8 ? kRhs2WpeFp64 : kRhs2WpeMixed);
     }();
-#define DGSWE_RHS2(S, W) \
-  hipLaunchKernelGGL((k_rhs2<QT, S, W>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, slot, want_dt)
-#define DGSWE_RHS2_W(S)                \
-  switch (wpe) {                       \
-    case 1: DGSWE_RHS2(S, 1); break;   \
-    case 2: DGSWE_RHS2(S, 2); break;   \
-    case 3: DGSWE_RHS2(S, 3); break;   \
-    default: DGSWE_RHS2(S, 4); break;  \
-  }
-    if (stage) { DGSWE_RHS2_W(1) }
-    else { DGSWE_RHS2_W(0) }
-#undef DGSWE_RHS2_W
+#define DGSWE_RHS2(W) \
+  hipLaunchKernelGGL((k_rhs2<QT, W>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, sc, slot, want_dt)
+    switch (wpe) {
+      case 1: DGSWE_RHS2(1); break;
+      case 2: DGSWE_RHS2(2); break;
+      case 3: DGSWE_RHS2(3); break;
+      default: DGSWE_RHS2(4); break;
+    }
 #undef DGSWE_RHS2
   }
 }
 
 hipError_t launch_pp2(const DevMesh &m, const DevState &s, const Params &p, const void *win, void *rec, int slot,
                       int stage, int precision, hipStream_t st) {
+  const StageCoef none{0.0, 1.0, 1.0, 0.0, 0};
   if (precision == DGSWE_MIXED)
-    stage2_qt<float>(m, s, p, win, rec, nullptr, nullptr, slot, stage, 0, st, true, false);
+    stage2_qt<float>(m, s, p, win, rec, nullptr, nullptr, slot, stage, none, 0, st, true, false);
   else
-    stage2_qt<double>(m, s, p, win, rec, nullptr, nullptr, slot, stage, 0, st, true, false);
+    stage2_qt<double>(m, s, p, win, rec, nullptr, nullptr, slot, stage, none, 0, st, true, false);
   return hipGetLastError();
 }
 
 hipError_t launch_rhs2(const DevMesh &m, const DevState &s, const Params &p, const void *rec, const void *rbase,
-                       void *wout, int slot, int stage, int want_dt, int precision, hipStream_t st) {
+                       void *wout, int slot, int first, const StageCoef &sc, int want_dt, int precision,
+                       hipStream_t st) {
+  // the RK base is read only by stages that combine with it
+  const void *b = sc.a != 0.0 ? rbase : nullptr;
   if (precision == DGSWE_MIXED)
-    stage2_qt<float>(m, s, p, nullptr, (void *)rec, rbase, wout, slot, stage, want_dt, st, false, true);
+    stage2_qt<float>(m, s, p, nullptr, (void *)rec, b, wout, slot, first ? 0 : 1, sc, want_dt, st, false, true);
   else
-    stage2_qt<double>(m, s, p, nullptr, (void *)rec, rbase, wout, slot, stage, want_dt, st, false, true);
+    stage2_qt<double>(m, s, p, nullptr, (void *)rec, b, wout, slot, first ? 0 : 1, sc, want_dt, st, false, true);
   return hipGetLastError();
 }
 
