@@ -247,7 +247,7 @@ def cpu_baseline(wl, target_s=12.0):
                       f"{secs:.1f} s, OpenMP threads={threads}"}
 
 
-def measure(wl, precision, steps, warmup, stream, profile, order=1):
+def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None):
     """Create the solver on `stream`, warm up, time `steps` steps with the
     stream synchronised on both sides; returns (elapsed s, solver info,
     per-kernel HIP-event times, diagnostics).  order 2: p = 2 with CFL 0.1,
@@ -260,6 +260,7 @@ def measure(wl, precision, steps, warmup, stream, profile, order=1):
         prm.update(p=2, cfl=0.1)
         w0 = np.zeros((3, 6, wl.w0.shape[2]))
         w0[:, :3] = wl.w0
+    prm.update(extra or {})
     s = Solver(wl.mesh, prm, wl.forcing, hip_stream=stream.cuda_stream)
     info = s.info()
     s.set_state(w0, 0.0, wl.postprocess_initial)
@@ -380,6 +381,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble variant")
     ap.add_argument("--no-p2", action="store_true", help="skip the p = 2 variants")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-rk", action="store_true", help="skip the time-stepper variants")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline run (fp64 is the metric's)")
@@ -433,6 +435,23 @@ def main():
                                       "kernels": k4, "t_end": d4["t"]}
             if k4:
                 log(f"p2 {prec} kernels: " + json.dumps(k4))
+    if not args.no_rk:
+        # time steppers at their SSP limits: model seconds per wall second
+        # is what a larger stable step buys
+        for rk, cfl in ((33, 0.2), (52, 0.8)):
+            from paper_2508_21208_amd.dgswe import DgsweError
+            try:
+                el5, _, k5, d5 = measure(wl, "fp64", args.steps, args.warmup, stream, profile,
+                                         extra=dict(rk=rk, cfl=cfl))
+                ns = 3 if rk == 33 else 5
+                variants[f"ssprk{rk}"] = {
+                    "value": ne * ns * args.steps / el5, "unit": "elem-stage/s", "cfl": cfl, "stages": ns,
+                    "ms_per_step": 1e3 * el5 / args.steps, "dt_last": d5["dt_last"],
+                    "model_s_per_wall_s": d5["dt_last"] / (el5 / args.steps),
+                    "model_s_per_wall_s_ssprk22": d["dt_last"] / (elapsed / args.steps),
+                    "roofline": roofline(k5, ne, ned, nn, "fp64")}
+            except DgsweError as ex:
+                variants[f"ssprk{rk}"] = {"error": str(ex), "cfl": cfl}
     if not args.no_batched:
         el3, ne3, nm3, k3 = measure_batched(args.steps, args.warmup, stream, profile)
         variants["batched"] = {"value": ne3 * 2 * args.steps / el3, "unit": "elem-stage/s",
