@@ -63,6 +63,7 @@ typedef struct {
   double g, rho0, h0, cfl, dt_fixed, dt_max;
   int32_t limiter, wetdry;
   int32_t rk;       /* 22, 33, 32, 42, 52: SSPRK(s, q) */
+  int32_t flux;     /* 0: local Lax-Friedrichs, 1: Roe on edges wet on both sides */
 } or_params;
 
 typedef struct {
@@ -213,6 +214,58 @@ void or_llf(double g, const double wl[3], const double wr[3], double hb, double 
     double fl = Fl[m][0] * nx + Fl[m][1] * ny;
     double fr = Fr[m][0] * nx + Fr[m][1] * ny;
     out[m] = 0.5 * (fl + fr) - 0.5 * lam * (wr[m] - wl[m]);
+  }
+}
+
+/* Roe's flux (the paper names it beside LLF, Sec. 2.2) for two wet sides,
+ * normal n from L to R, in the normal / tangential frame t = (-ny, nx):
+ * Roe averages u = (sqrt(H_L) u_L + sqrt(H_R) u_R) / (sqrt(H_L) + sqrt(H_R))
+ * (both components) and c = sqrt(g (H_L + H_R) / 2); waves u_n - c, u_n,
+ * u_n + c with eigenvectors (1, u_n - c, u_t), (0, 0, 1), (1, u_n + c, u_t)
+ * on (H, q_n, q_t) and strengths a1 = ((u_n + c) dH - dq_n) / (2c),
+ * a2 = dq_t - u_t dH, a3 = (dq_n - (u_n - c) dH) / (2c), dH = zeta_R -
+ * zeta_L (the bathymetry is shared);
+ * F = (F_L + F_R).n / 2 - sum_k |lam_k| a_k r_k / 2.
+ * READING: Harten-Hyman entropy fix on the two acoustic waves, |lam| ->
+ * (lam^2 + d^2) / (2 d) when |lam| < d = max(0, lam - lam(L), lam(R) - lam);
+ * a side with zero or negative depth at the point falls back to LLF. */
+void or_roe(double g, const double wl[3], const double wr[3], double hb, double nx, double ny, double out[3]) {
+  double Hl = wl[0] + hb, Hr = wr[0] + hb;
+  if (!(Hl > 0.0 && Hr > 0.0)) {
+    or_llf(g, wl, wr, hb, nx, ny, 1, 1, out);
+    return;
+  }
+  double Fl[3][2], Fr[3][2];
+  phys_flux(g, wl[0], wl[1], wl[2], hb, 1, Fl);
+  phys_flux(g, wr[0], wr[1], wr[2], hb, 1, Fr);
+  double unl = (wl[1] * nx + wl[2] * ny) / Hl, unr = (wr[1] * nx + wr[2] * ny) / Hr;
+  double utl = (-wl[1] * ny + wl[2] * nx) / Hl, utr = (-wr[1] * ny + wr[2] * nx) / Hr;
+  double sl = sqrt(Hl), sr = sqrt(Hr);
+  double un = (sl * unl + sr * unr) / (sl + sr);
+  double ut = (sl * utl + sr * utr) / (sl + sr);
+  double c = sqrt(g * 0.5 * (Hl + Hr));
+  double dH = wr[0] - wl[0];
+  double dqn = (wr[1] - wl[1]) * nx + (wr[2] - wl[2]) * ny;
+  double dqt = -(wr[1] - wl[1]) * ny + (wr[2] - wl[2]) * nx;
+  double a1 = ((un + c) * dH - dqn) / (2.0 * c);
+  double a2 = dqt - ut * dH;
+  double a3 = (dqn - (un - c) * dH) / (2.0 * c);
+  double l1 = un - c, l2 = un, l3 = un + c;
+  double cl = sqrt(g * Hl), cr = sqrt(g * Hr);
+  double d1 = fmax(0.0, fmax(l1 - (unl - cl), (unr - cr) - l1));
+  double d3 = fmax(0.0, fmax(l3 - (unl + cl), (unr + cr) - l3));
+  double m1 = fabs(l1), m2 = fabs(l2), m3 = fabs(l3);
+  if (m1 < d1) m1 = (l1 * l1 + d1 * d1) / (2.0 * d1);
+  if (m3 < d3) m3 = (l3 * l3 + d3 * d3) / (2.0 * d3);
+  /* dissipation on (H, q_n, q_t), then back to (q_x, q_y) */
+  double DH = m1 * a1 + m3 * a3;
+  double Dn = m1 * a1 * (un - c) + m3 * a3 * (un + c);
+  double Dt = m1 * a1 * ut + m2 * a2 + m3 * a3 * ut;
+  double D[3] = {DH, Dn * nx - Dt * ny, Dn * ny + Dt * nx};
+  for (int m = 0; m < 3; ++m) {
+    double fl = Fl[m][0] * nx + Fl[m][1] * ny;
+    double fr = Fr[m][0] * nx + Fr[m][1] * ny;
+    out[m] = 0.5 * (fl + fr) - 0.5 * D[m];
   }
 }
 
@@ -417,6 +470,7 @@ or_mesh *or_create(int32_t nn, const double *xy, const double *hb, int32_t ne, c
   if (!M->w || !M->w1 || !M->wt || !M->dw || !M->slot || !M->nodal) { or_destroy(M); *status = OR_E_NOMEM; return NULL; }
   M->nm = 3; M->nq = 3;
   M->prm.rk = 22;
+  M->prm.flux = 0;
   M->prm.g = 9.81; M->prm.rho0 = 1000.0; M->prm.h0 = 0.01; M->prm.cfl = 0.2;
   M->prm.dt_fixed = 0.0; M->prm.dt_max = 0.0; M->prm.limiter = 1; M->prm.wetdry = 1;
   M->frc.pn = 101300.0;
@@ -587,7 +641,10 @@ static void edge_integrals(or_mesh *M, const double *w, double t) {
         for (int m = 0; m < 3; ++m) { Fp[gq][m] = 0.0; Fm[gq][m] = 0.0; }
     } else {
       double F[3][3];
-      for (int gq = 0; gq < 3; ++gq) or_llf(g, wp[gq], wm[gq], hbq[gq], nx, ny, wetp, wetm, F[gq]);
+      for (int gq = 0; gq < 3; ++gq) {
+        if (M->prm.flux == 1 && wetp && wetm) or_roe(g, wp[gq], wm[gq], hbq[gq], nx, ny, F[gq]);
+        else or_llf(g, wp[gq], wm[gq], hbq[gq], nx, ny, wetp, wetm, F[gq]);
+      }
       int flood = 1;
       if (!(wetp && wetm)) {
         double mflux = 0.0;
@@ -875,6 +932,14 @@ static int32_t pick_dt(const or_mesh *M, const double *w, double *dt) {
  *               w+ = 1/s w + (s-1)/s (w_{s-1} + dt/(s-1) L(w_{s-1})),
  *               stage k at t + k dt/(s-1).
  * Each stage is post-processed. */
+/* interior numerical flux: 0 LLF (default), 1 Roe where both sides are wet
+ * (an edge with a dry side keeps the LLF wet/dry rules) */
+int32_t or_set_flux(or_mesh *M, int32_t flux) {
+  if (flux != 0 && flux != 1) return OR_E_INVALID;
+  M->prm.flux = flux;
+  return OR_OK;
+}
+
 int32_t or_set_scheme(or_mesh *M, int32_t rk) {
   if (rk != 22 && rk != 33 && rk != 32 && rk != 42 && rk != 52) return OR_E_INVALID;
   M->prm.rk = rk;
@@ -1117,7 +1182,10 @@ static void edge_integrals2(or_mesh *M, const double *w, double t) {
         for (int m = 0; m < 3; ++m) { Fp[gq][m] = 0.0; Fm[gq][m] = 0.0; }
     } else {
       double F[4][3];
-      for (int gq = 0; gq < 4; ++gq) or_llf(g, wp[gq], wm[gq], hbq[gq], nx, ny, wetp, wetm, F[gq]);
+      for (int gq = 0; gq < 4; ++gq) {
+        if (M->prm.flux == 1 && wetp && wetm) or_roe(g, wp[gq], wm[gq], hbq[gq], nx, ny, F[gq]);
+        else or_llf(g, wp[gq], wm[gq], hbq[gq], nx, ny, wetp, wetm, F[gq]);
+      }
       int flood = 1;
       if (!(wetp && wetm)) {
         double mflux = 0.0;

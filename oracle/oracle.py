@@ -70,6 +70,9 @@ def load_oracle():
     L.or_llf.argtypes = [C.c_double, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int32,
                          C.c_int32, _dp]
     L.or_wall.argtypes = [C.c_double, _dp, C.c_double, C.c_double, C.c_double, C.c_int32, _dp]
+    L.or_set_flux.argtypes = [C.c_void_p, C.c_int32]
+    L.or_set_flux.restype = C.c_int32
+    L.or_roe.argtypes = [C.c_double, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
     L.or_set_scheme.argtypes = [C.c_void_p, C.c_int32]
     L.or_set_scheme.restype = C.c_int32
     L.or_set_order.argtypes = [C.c_void_p, C.c_int32]
@@ -150,6 +153,9 @@ class Oracle:
         r = self.L.or_set_scheme(self.h, int(p.get("rk", 22)))
         if r:
             raise OracleError(f"or_set_scheme: {r}")
+        r = self.L.or_set_flux(self.h, int(p.get("flux", 0)))
+        if r:
+            raise OracleError(f"or_set_flux: {r}")
 
     def set_forcing(self, f: dict):
         me = f.get("manning_n_elem")
@@ -265,6 +271,14 @@ def llf(g, wl, wr, hb, n, wetl=1, wetr=1):
     wl = np.ascontiguousarray(wl, dtype=np.float64); wr = np.ascontiguousarray(wr, dtype=np.float64)
     out = np.zeros(3)
     L.or_llf(g, _d(wl), _d(wr), hb, n[0], n[1], int(wetl), int(wetr), _d(out))
+    return out
+
+
+def roe(g, wl, wr, hb, n):
+    L = load_oracle()
+    wl = np.ascontiguousarray(wl, dtype=np.float64); wr = np.ascontiguousarray(wr, dtype=np.float64)
+    out = np.zeros(3)
+    L.or_roe(g, _d(wl), _d(wr), hb, n[0], n[1], _d(out))
     return out
 
 
