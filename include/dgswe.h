@@ -79,7 +79,15 @@ typedef struct {
   int32_t wetdry;    /* 1: wetting/drying after each stage */
   int32_t rk;        /* time stepper: 22 = SSPRK(2,2), 33 = SSPRK(3,3),
                         32, 42, 52 = SSPRK(s,2) with s = 3, 4, 5 stages */
+  int32_t flux;      /* numerical flux: 0 = local Lax-Friedrichs, 1 = Roe */
 } dgswe_params;
+
+/* Numerical flux (Sec. 2.2 names local Lax-Friedrichs and Roe).  flux = 1
+ * uses Roe's flux (Roe averages of the velocity with square-root depth
+ * weights, c = sqrt(g (H_L + H_R)/2), Harten-Hyman entropy fixes on the
+ * acoustic waves) on interior and ocean edges whose two sides are wet; an
+ * edge with a dry side keeps the local Lax-Friedrichs wet/dry rules, and a
+ * point without positive depth on a side falls back to LLF. */
 
 /* Time steppers (Sec. 2.2: the paper names "optimized" SSP Runge-Kutta
  * schemes without their coefficients).  Every stage is followed by the
@@ -116,7 +124,7 @@ typedef struct {
  * The CFL number should be smaller than at p = 1 (about 0.1). */
 
 /* Fill `p` with the defaults: p=1, FP64, g=9.81, rho0=1000, h0=0.01,
- * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1, rk=22. */
+ * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1, rk=22, flux=0. */
 void dgswe_default_params(dgswe_params *p);
 
 /* Build a solver for one mesh and allocate its device-resident state.

@@ -232,6 +232,7 @@ bool validate_params(const dgswe_params *p, std::string &msg) {
   if (p->p != 1 && p->p != 2) { msg = "p must be 1 or 2"; return false; }
   StageCoef sc[5];
   if (rk_stages(p->rk, sc) == 0) { msg = "rk must be 22, 33, 32, 42 or 52"; return false; }
+  if (p->flux != 0 && p->flux != 1) { msg = "flux must be 0 (LLF) or 1 (Roe)"; return false; }
   if (p->precision != DGSWE_FP64 && p->precision != DGSWE_MIXED) {
     msg = "precision must be DGSWE_FP64 or DGSWE_MIXED";
     return false;
@@ -364,6 +365,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   pp.g = prm->g; pp.rho0 = prm->rho0; pp.h0 = prm->h0; pp.cfl = prm->cfl;
   pp.dt_fixed = prm->dt_fixed; pp.dt_max = prm->dt_max;
   pp.limiter = prm->limiter ? 1 : 0; pp.wetdry = prm->wetdry ? 1 : 0;
+  pp.flux = prm->flux;
   for (int a = 0; a < A_COUNT; ++a) S->arena[a].init(cap[a]);
   S->chunk_cap = chunk_cap;
   S->mh.resize((size_t)slots);
@@ -880,6 +882,7 @@ extern "C" {
 void dgswe_default_params(dgswe_params *p) {
   if (!p) return;
   p->rk = 22;
+  p->flux = 0;
   p->p = 1;
   p->precision = DGSWE_FP64;
   p->g = 9.81;

@@ -146,6 +146,49 @@ HD void llf(double g, double zl, R qlx, R qly, double zr, R qrx, R qry, double h
   for (int m = 0; m < 3; ++m) out[m] = (R)0.5 * (fl[m] + fr[m]) - (R)0.5 * lam * jump[m];
 }
 
+// Roe flux from side L (normal n from L to R) for two wet sides: Roe
+// averages of the normal and tangential velocity (square-root depth
+// weights) and c = sqrt(g (H_L + H_R)/2); waves u_n - c, u_n, u_n + c on
+// (H, q_n, q_t) with Harten-Hyman entropy fixes on the two acoustic waves.
+// Depths and the zeta jump are formed in FP64; a side without positive
+// depth at the point falls back to LLF.
+template <class R>
+HD void roe(double g, double zl, R qlx, R qly, double zr, R qrx, R qry, double hb, R nx, R ny, R out[3]) {
+  const double Hld = zl + hb, Hrd = zr + hb;
+  if (!(Hld > 0.0 && Hrd > 0.0)) {
+    llf<R>(g, zl, qlx, qly, zr, qrx, qry, hb, nx, ny, true, true, out);
+    return;
+  }
+  R unl, unr, fl[3], fr[3];
+  flux_n<R>(g, zl, qlx, qly, hb, true, nx, ny, unl, fl);
+  flux_n<R>(g, zr, qrx, qry, hb, true, nx, ny, unr, fr);
+  const R Hl = (R)Hld, Hr = (R)Hrd;
+  const R utl = (qly * nx - qlx * ny) * rcp_nr(Hl), utr = (qry * nx - qrx * ny) * rcp_nr(Hr);
+  const R sl = sqrt_nr(Hl), sr = sqrt_nr(Hr);
+  const R isum = rcp_nr(sl + sr);
+  const R un = (sl * unl + sr * unr) * isum, ut = (sl * utl + sr * utr) * isum;
+  const R c = sqrt_nr((R)(0.5 * g * (Hld + Hrd)));
+  const R dH = (R)(zr - zl);
+  const R dqx = qrx - qlx, dqy = qry - qly;
+  const R dqn = dqx * nx + dqy * ny, dqt = dqy * nx - dqx * ny;
+  const R i2c = rcp_nr((R)2 * c);
+  const R a1 = ((un + c) * dH - dqn) * i2c, a2 = dqt - ut * dH, a3 = (dqn - (un - c) * dH) * i2c;
+  const R l1 = un - c, l3 = un + c;
+  const R cl = sqrt_nr((R)(g * Hld)), cr = sqrt_nr((R)(g * Hrd));
+  const R d1 = fmax((R)0, fmax(l1 - (unl - cl), (unr - cr) - l1));
+  const R d3 = fmax((R)0, fmax(l3 - (unl + cl), (unr + cr) - l3));
+  R m1 = fabs(l1), m3 = fabs(l3);
+  const R m2 = fabs(un);
+  if (m1 < d1) m1 = (l1 * l1 + d1 * d1) * rcp_nr((R)2 * d1);
+  if (m3 < d3) m3 = (l3 * l3 + d3 * d3) * rcp_nr((R)2 * d3);
+  const R DH = m1 * a1 + m3 * a3;
+  const R Dn = m1 * a1 * l1 + m3 * a3 * l3;
+  const R Dt = (m1 * a1 + m3 * a3) * ut + m2 * a2;
+  out[0] = (R)0.5 * (fl[0] + fr[0]) - (R)0.5 * DH;
+  out[1] = (R)0.5 * (fl[1] + fr[1]) - (R)0.5 * (Dn * nx - Dt * ny);
+  out[2] = (R)0.5 * (fl[2] + fr[2]) - (R)0.5 * (Dn * ny + Dt * nx);
+}
+
 // land wall: LLF against the mirror state, closed form, zero mass flux
 template <class R>
 HD void wall(double g, double ze, R qx, R qy, double hb, R nx, R ny, bool wet, R out[3]) {

@@ -109,6 +109,7 @@ int rk_stages(int rk, StageCoef out[5]);
 struct Params {
   double g, rho0, h0, cfl, dt_fixed, dt_max;
   int limiter, wetdry;
+  int flux;  // 0: LLF, 1: Roe on edges wet on both sides
 };
 
 // Buffers of one solver touched by the step.  The state lives in three

@@ -107,7 +107,7 @@ struct EdgeGeo {
 // flux moments m0 = sum_g w_g F_g and m1 = sum_g w_g s_g F_g (before the
 // factor len/2) and the mass-flux integral.  kind 0: LLF between the two
 // sides; 1: land wall seen from e+ (wet flag wetp); 2: wall seen from e-
-// (normal -n).  States: zeta modes (FP64) and momentum modes (R) of e+ and
+// (normal -n); 3: Roe between the two (wet) sides.  States: zeta modes (FP64) and momentum modes (R) of e+ and
 // e-; ghost: the e- trace is (zb, momentum of e+).
 template <class R>
 HD void edge_pass(int kind, const double zp[3], const R qp[6], const double zm[3], const R qm[6], bool ghost,
@@ -133,6 +133,7 @@ HD void edge_pass(int kind, const double zp[3], const R qp[6], const double zm[3
     }
     R F[3];
     if (kind == 0) llf<R>(p.g, zpg, qxp, qyp, zmg, qxm, qym, G.hq[g], G.nx, G.ny, wetp, wetm, F);
+    else if (kind == 3) roe<R>(p.g, zpg, qxp, qyp, zmg, qxm, qym, G.hq[g], G.nx, G.ny, F);
     else if (kind == 1) wall<R>(p.g, zpg, qxp, qyp, G.hq[g], G.nx, G.ny, wetp, F);
     else wall<R>(p.g, zmg, qxm, qym, G.hq[g], -G.nx, -G.ny, true, F);
     const R sg = (R)(g - 1);
@@ -179,7 +180,7 @@ HD int edge_flux(const double zp[3], const R qp[6], const double zm[3], const R 
     for (int v = 0; v < 6; ++v) mom[v] = (R)0;
     return 3;
   } else {
-    edge_pass<R>(0, zp, qp, zm, qm, ghost, zb, wetp, wetm, G, p, m0, m1, mflux);
+    edge_pass<R>((p.flux == 1 && wetp && wetm) ? 3 : 0, zp, qp, zm, qm, ghost, zb, wetp, wetm, G, p, m0, m1, mflux);
     mode = ghost ? 1 : 0;
     if (!(wetp && wetm)) {
       const bool flood = wetp ? (mflux > (R)0) : (mflux < (R)0);

@@ -494,6 +494,7 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
       const double hq = edge_hb(hA, hB, g);
       if (kind == EK_WALL_P) wall<R>(p.g, pz[g], px[g], py[g], hq, nx, ny, wetp, Fg);
       else if (kind == EK_WALL_M) wall<R>(p.g, mz[g], mx[g], my[g], hq, -nx, -ny, wetm, Fg);
+      else if (p.flux == 1 && wetp && wetm) roe<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], hq, nx, ny, Fg);
       else llf<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], hq, nx, ny, wetp, wetm, Fg);
       // own basis at the point (e- runs the edge backwards)
       double xi, eta, fb[6];

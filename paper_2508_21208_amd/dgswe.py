@@ -32,7 +32,7 @@ EXPORTED = ("dgswe_default_params", "dgswe_create_mesh", "dgswe_set_state", "dgs
 class dgswe_params(C.Structure):
     _fields_ = [("p", C.c_int32), ("precision", C.c_int32), ("g", C.c_double), ("rho0", C.c_double),
                 ("h0", C.c_double), ("cfl", C.c_double), ("dt_fixed", C.c_double), ("dt_max", C.c_double),
-                ("limiter", C.c_int32), ("wetdry", C.c_int32), ("rk", C.c_int32)]
+                ("limiter", C.c_int32), ("wetdry", C.c_int32), ("rk", C.c_int32), ("flux", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
