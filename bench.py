@@ -381,7 +381,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble variant")
     ap.add_argument("--no-p2", action="store_true", help="skip the p = 2 variants")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
-    ap.add_argument("--no-rk", action="store_true", help="skip the time-stepper variants")
+    ap.add_argument("--no-rk", action="store_true", help="skip the time-stepper and Roe-flux variants")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline run (fp64 is the metric's)")
@@ -438,20 +438,21 @@ def main():
     if not args.no_rk:
         # time steppers at their SSP limits: model seconds per wall second
         # is what a larger stable step buys
-        for rk, cfl in ((33, 0.2), (52, 0.8)):
-            from paper_2508_21208_amd.dgswe import DgsweError
+        from paper_2508_21208_amd.dgswe import DgsweError
+        for name, extra, ns in (("ssprk33", dict(rk=33, cfl=0.2), 3), ("ssprk52", dict(rk=52, cfl=0.8), 5),
+                                ("roe", dict(flux=1), 2)):
             try:
-                el5, _, k5, d5 = measure(wl, "fp64", args.steps, args.warmup, stream, profile,
-                                         extra=dict(rk=rk, cfl=cfl))
-                ns = 3 if rk == 33 else 5
-                variants[f"ssprk{rk}"] = {
-                    "value": ne * ns * args.steps / el5, "unit": "elem-stage/s", "cfl": cfl, "stages": ns,
+                el5, _, k5, d5 = measure(wl, "fp64", args.steps, args.warmup, stream, profile, extra=extra)
+                variants[name] = {
+                    "value": ne * ns * args.steps / el5, "unit": "elem-stage/s", **extra, "stages": ns,
                     "ms_per_step": 1e3 * el5 / args.steps, "dt_last": d5["dt_last"],
                     "model_s_per_wall_s": d5["dt_last"] / (el5 / args.steps),
-                    "model_s_per_wall_s_ssprk22": d["dt_last"] / (elapsed / args.steps),
+                    "model_s_per_wall_s_default": d["dt_last"] / (elapsed / args.steps),
                     "roofline": roofline(k5, ne, ned, nn, "fp64")}
+                if k5:
+                    log(f"{name} kernels: " + json.dumps(k5))
             except DgsweError as ex:
-                variants[f"ssprk{rk}"] = {"error": str(ex), "cfl": cfl}
+                variants[name] = {"error": str(ex), **extra}
     if not args.no_batched:
         el3, ne3, nm3, k3 = measure_batched(args.steps, args.warmup, stream, profile)
         variants["batched"] = {"value": ne3 * 2 * args.steps / el3, "unit": "elem-stage/s",
