@@ -92,6 +92,42 @@ HD float cbrt_nr(float x) {
 #endif
 }
 
+// Cache policy of the stage kernel's global accesses.  ld_once: records a
+// launch reads exactly once (packed chunk records, element geometry); st_out:
+// stage results no kernel of this launch reads back.  With the non-temporal
+// forms they do not displace the state arrays that neighbouring chunks
+// re-read from L2.
+#ifndef DGSWE_NT_LOAD
+#define DGSWE_NT_LOAD 1
+#endif
+#ifndef DGSWE_NT_STORE
+#define DGSWE_NT_STORE 0
+#endif
+#if defined(__HIP_DEVICE_COMPILE__) && DGSWE_NT_LOAD
+typedef double dgswe_d2v __attribute__((ext_vector_type(2)));
+typedef int dgswe_i4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double2 ld_once(const double2 *p) {
+  const dgswe_d2v v = __builtin_nontemporal_load((const dgswe_d2v *)p);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ int4 ld_once(const int4 *p) {
+  const dgswe_i4v v = __builtin_nontemporal_load((const dgswe_i4v *)p);
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+template <class T>
+__device__ __forceinline__ T ld_once(const T *p) { return __builtin_nontemporal_load(p); }
+#else
+template <class T>
+HD T ld_once(const T *p) { return *p; }
+#endif
+#if defined(__HIP_DEVICE_COMPILE__) && DGSWE_NT_STORE
+template <class T>
+__device__ __forceinline__ void st_out(T *p, T v) { __builtin_nontemporal_store(v, p); }
+#else
+template <class T>
+HD void st_out(T *p, T v) { *p = v; }
+#endif
+
 // dt of the current step: fixed, or cfl x the CFL minimum of w^n (capped),
 // from the bit pattern of that minimum.  Returns false when no wet element
 // defines it and there is no cap.

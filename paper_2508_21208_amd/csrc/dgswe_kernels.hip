@@ -380,7 +380,7 @@ struct EdgeRec {
 
 HD void load_edge_rec(const DevMesh &m, const ChunkInfo &k, int j, EdgeRec<double> &R) {
   const size_t r = (size_t)(k.leo + j);
-  const double2 a = m.le_a[r], b = m.le_b[r];
+  const double2 a = ld_once(m.le_a + r), b = ld_once(m.le_b + r);
   R.nx = a.x; R.ny = a.y; R.hl = b.x;
   R.ids = ids_of(b.y);
 }
@@ -393,15 +393,15 @@ HD void load_edge_rec(const DevMesh &m, const ChunkInfo &k, int j, EdgeRec<float
 
 // vertex bathymetry of local element i in [0, nl) of chunk + ring 1
 HD void load_local_hb(const DevMesh &m, const ChunkInfo &k, int i, double h[3]) {
-  const double2 a = m.lhb01[k.lo + i];
+  const double2 a = ld_once(m.lhb01 + k.lo + i);
   h[0] = a.x;
   h[1] = a.y;
-  h[2] = m.lhb2[k.lo + i];
+  h[2] = ld_once(m.lhb2 + k.lo + i);
 }
 
 // local neighbour indices of local element i (chunk + ring 1)
 HD void load_local_nb(const DevMesh &m, const ChunkInfo &k, int i, uint16_t nb[3]) {
-  const unsigned long long v = m.lnb[k.lo + i];
+  const unsigned long long v = ld_once(m.lnb + k.lo + i);
   for (int q = 0; q < 3; ++q) nb[q] = (uint16_t)(v >> (16 * q));
 }
 
@@ -412,7 +412,7 @@ HD void load_local_nb(const DevMesh &m, const ChunkInfo &k, int i, uint16_t nb[3
 // gathers through the indices; LDS is written after all of them.
 
 // global element id of local element i in [0, nl) of chunk + ring 1
-HD int local_to_global(const DevMesh &m, const ChunkInfo &k, int i) { return m.lgid[k.lo + i]; }
+HD int local_to_global(const DevMesh &m, const ChunkInfo &k, int i) { return ld_once(m.lgid + k.lo + i); }
 
 // full state of element g
 template <class QT>
@@ -454,7 +454,7 @@ struct GeoReg {
 // gradients, area and 2 x inradius of chunk element i
 HD void load_geo(const DevMesh &m, const ChunkInfo &k, int i, GeoReg<double> &G, double &inr2) {
   const int e = k.c0 + i;
-  const double2 a = m.eg1[e], b = m.eg2[e], c = m.eai[e];
+  const double2 a = ld_once(m.eg1 + e), b = ld_once(m.eg2 + e), c = ld_once(m.eai + e);
   G.g[0] = a.x; G.g[1] = a.y; G.g[2] = b.x; G.g[3] = b.y;
   G.area = c.x;
   inr2 = c.y;
@@ -470,7 +470,7 @@ HD void load_geo(const DevMesh &m, const ChunkInfo &k, int i, GeoReg<float> &G, 
 
 // node ids and local edge codes of chunk element i
 HD void load_elem_node(const DevMesh &m, const ChunkInfo &k, int i, int node[3], int ledge[3]) {
-  const int4 v = m.enode[k.c0 + i];
+  const int4 v = ld_once(m.enode + k.c0 + i);
   node[0] = v.x; node[1] = v.y; node[2] = v.z;
   for (int q = 0; q < 3; ++q) ledge[q] = (v.w >> (10 * q)) & 0x3FF;
 }
@@ -512,8 +512,8 @@ HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp
   L.WET[i] = (p.wetdry ? (u[0] + hmean > p.h0) : true) ? 1 : 0;
   if (wpp && i < k.cc) {
     const size_t e = (size_t)(k.c0 + i);
-    for (int j = 0; j < 3; ++j) wpp->z[j * ne + e] = u[j];
-    for (int j = 0; j < 6; ++j) wpp->q[j * ne + e] = (QT)u[3 + j];
+    for (int j = 0; j < 3; ++j) st_out(wpp->z + j * ne + e, u[j]);
+    for (int j = 0; j < 6; ++j) st_out(wpp->q + j * ne + e, (QT)u[3 + j]);
   }
 }
 
@@ -626,7 +626,7 @@ HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, cons
   for (int j = 0; j < 3; ++j) {
     const double dw = rz[j] * imu[j];
     oz[j] = base ? ca * P.wbz[j] + cb * (z[j] + dt * dw) : z[j] + dt * dw;
-    wout.z[j * ne + e] = oz[j];
+    st_out(wout.z + j * ne + e, oz[j]);
     fin = fin && __builtin_isfinite(oz[j]);
   }
   const QT dtq = (QT)dt;
@@ -634,7 +634,7 @@ HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, cons
     QT dw = rq[j] * (QT)imu[j % 3];
     if (!wet) dw = (QT)0;
     oq[j] = base ? (QT)ca * P.wbq[j] + (QT)cb * (q[j] + dtq * dw) : q[j] + dtq * dw;
-    wout.q[j * ne + e] = oq[j];
+    st_out(wout.q + j * ne + e, oq[j]);
     fin = fin && __builtin_isfinite(oq[j]);
   }
   bad = !fin;
