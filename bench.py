@@ -353,6 +353,32 @@ def measure_serving(n_requests, pool_rate_hint, stream):
             "p99_speedup": alone["p99_s"] / pool["p99_s"] if alone else None}
 
 
+def measure_graphs(stream, steps=600):
+    """Launch cost on a small mesh: the 1,600-element Gaussian hump (FP64),
+    steps launched one by one against replays of captured 60-step graphs."""
+    import torch
+    from paper_2508_21208_amd.dgswe import Solver
+    from paper_2508_21208_amd import workloads as W
+    wl = W.cfg_gaussian_1600()
+    out = {"workload": "Gaussian hump, 1,600 triangles, FP64", "steps": steps}
+    for name, g in (("plain", 0), ("graphs", 60)):
+        s = Solver(wl.mesh, wl.params, wl.forcing, hip_stream=stream.cuda_stream)
+        s.set_state(wl.w0)
+        s.use_graphs(g)
+        s.step(120)
+        s.diagnostics()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.diagnostics()
+        el = time.perf_counter() - t0
+        s.close()
+        out[name] = {"steps_per_s": steps / el, "us_per_step": 1e6 * el / steps}
+    out["speedup"] = out["graphs"]["steps_per_s"] / out["plain"]["steps_per_s"]
+    log("graphs: " + json.dumps(out))
+    return out
+
+
 def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
     if not kernels:
         return None
@@ -381,6 +407,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ensemble variant")
     ap.add_argument("--no-p2", action="store_true", help="skip the p = 2 variants")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-graphs", action="store_true", help="skip the step-graph launch-cost run")
     ap.add_argument("--no-rk", action="store_true", help="skip the time-stepper and Roe-flux variants")
     ap.add_argument("--serving-requests", type=int, default=60)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
@@ -462,6 +489,8 @@ def main():
         if k3:
             log("batched kernels: " + json.dumps(k3))
 
+    if not args.no_graphs:
+        variants["graphs_small_mesh"] = measure_graphs(stream)
     if not args.no_serving:
         hint = variants.get("mixed", {}).get("value") or 1.2e10
         variants["serving"] = measure_serving(args.serving_requests, hint, stream)

@@ -282,6 +282,17 @@ dgswe_status dgswe_member_set_forcing(dgswe_solver *s, int32_t member, const dgs
  * by its next read. */
 dgswe_status dgswe_step(dgswe_solver *s, int32_t n_steps);
 
+/* Step graphs: steps_per_graph > 0 (rounded up to a multiple of 6) makes
+ * dgswe_step enqueue its steps in whole graphs of that many steps, each
+ * captured once (per buffer rotation and step parity) into a HIP graph and
+ * replayed, and the remainder launch by launch; 0 turns graphs off.  The
+ * results are bitwise those of the launches themselves.  Graphs are dropped
+ * and recaptured when the launch tables change (members join or leave,
+ * forcing changes); profiling (dgswe_profile) uses the plain launches.  For
+ * small meshes, where a stage takes a few microseconds, this removes the
+ * per-launch host cost. */
+dgswe_status dgswe_use_graphs(dgswe_solver *s, int32_t steps_per_graph);
+
 typedef struct {
   double t;        /* model time [s] */
   double dt_last;  /* dt of the last step [s] */

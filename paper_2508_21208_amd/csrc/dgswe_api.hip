@@ -169,6 +169,11 @@ struct dgswe_solver {
   std::string err = "no error";
   std::vector<double> stage_buf;
   std::vector<unsigned char> stage_raw;
+  // step graphs: G steps captured once per (buffer rotation, step parity)
+  // and replayed; dropped whenever the launch tables change
+  int graph_steps = 0;
+  bool capturing = false;
+  hipGraphExec_t graph[6] = {};
   // kernel timing
   bool prof = false;
   struct Rec { int k; hipEvent_t a, b; };
@@ -212,7 +217,15 @@ hipError_t upload(dgswe_solver *S, const T **dst, const std::vector<T> &v) {
   return e;
 }
 
+void drop_graphs(dgswe_solver *S) {
+  for (hipGraphExec_t &g : S->graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
 void free_all(dgswe_solver *S) {
+  drop_graphs(S);
   for (void *p : S->allocs) (void)hipFree(p);
   S->allocs.clear();
   if (S->rb) (void)hipFree(S->rb);
@@ -248,7 +261,7 @@ struct Timed {
   int k;
   hipEvent_t a = nullptr, b = nullptr;
   Timed(dgswe_solver *S_, int k_) : S(S_), k(k_) {
-    if (!S->prof) return;
+    if (!S->prof || S->capturing) return;
     a = take();
     b = take();
     if (a && b) (void)hipEventRecord(a, S->stream);
@@ -260,7 +273,7 @@ struct Timed {
     return ev;
   }
   ~Timed() {
-    if (!S->prof) return;
+    if (!S->prof || S->capturing) return;
     if (a && b) {
       (void)hipEventRecord(b, S->stream);
       S->recs.push_back({k, a, b});
@@ -576,6 +589,7 @@ dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
 dgswe_status rebuild(dgswe_solver *S) {
   hipError_t e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+  drop_graphs(S);
   DevMesh &m = S->m;
   const int E = m.ne;
   S->chunk_rec.clear();
@@ -875,6 +889,92 @@ dgswe_status single(dgswe_solver *S) {
   return DGSWE_OK;
 }
 
+// Enqueue n steps launch by launch (also the body of a captured graph).
+dgswe_status enqueue_steps(dgswe_solver *S, int32_t n_steps) {
+  const DevMesh &m = S->m;
+  DevState &st = S->s;
+  const Params &p = S->prm;
+  const int want_dt = (p.dt_fixed > 0.0) ? 0 : 1;
+  StageCoef sc[5];
+  const int ns = rk_stages(S->uprm.rk, sc);
+  for (int i = 0; i < n_steps; ++i) {
+    const int slot = (int)(S->steps_enq & 1);
+    // buffers: stage k reads buf[(cur + k) % 3] and writes buf[(cur + k + 1)
+    // % 3] (unlimited); wpp holds the post-processed w^n (RK base), so the
+    // buffer of w^n is free from the second stage on
+    const int cur = S->cur;
+    hipError_t e = hipSuccess;
+    for (int stage = 0; stage < ns && e == hipSuccess; ++stage) {
+      void *in = st.buf[(cur + stage) % 3], *out = st.buf[(cur + stage + 1) % 3];
+      const int wd = sc[stage].last ? want_dt : 0;
+      if (S->nfblk > 0) {
+        Timed t(S, K_FORCING);
+        e = launch_forcing(m, st, p, S->nfblk, slot, sc[stage].c, S->stream);
+      }
+      if (e != hipSuccess) break;
+      if (S->order == 2) {
+        // records of the stage input: w^n's go to wpp (the RK base), a later
+        // stage's to the one buffer it neither reads nor writes
+        void *rec = stage == 0 ? st.wpp : st.buf[(cur + stage + 2) % 3];
+        {
+          Timed t(S, K_PP2);
+          e = launch_pp2(m, st, p, in, rec, slot, stage == 0 ? 0 : 1, S->precision, S->stream);
+        }
+        if (e != hipSuccess) break;
+        Timed t(S, K_RHS2);
+        e = launch_rhs2(m, st, p, rec, stage == 0 ? nullptr : st.wpp, out, slot, stage == 0, sc[stage], wd,
+                        S->precision, S->stream);
+        continue;
+      }
+      Timed t(S, K_STAGE);
+      e = launch_stage(m, st, p, in, stage == 0 ? nullptr : st.wpp, out, stage == 0 ? st.wpp : nullptr, slot,
+                       stage == 0, sc[stage], wd, S->block, S->precision, S->stream);
+    }
+    if (e != hipSuccess) return hip_fail(S, e, "kernel launch");
+    S->cur = (cur + ns) % 3;
+    for (MemberHost &h : S->mh) h.cur_is_pp = false;
+    S->steps_enq += 1;
+  }
+  return DGSWE_OK;
+}
+
+// One graph launch of graph_steps steps from the current (rotation,
+// parity), captured on first use.  graph_steps is a multiple of 6, so the
+// buffer rotation and the step parity are back where they started.
+dgswe_status graph_steps(dgswe_solver *S) {
+  const int key = S->cur * 2 + (int)(S->steps_enq & 1);
+  if (!S->graph[key]) {
+    const int cur = S->cur;
+    const long long se = S->steps_enq;
+    hipError_t e = hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(S, e, "hipStreamBeginCapture");
+    S->capturing = true;
+    dgswe_status st = enqueue_steps(S, S->graph_steps);
+    S->capturing = false;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(S->stream, &g);
+    // the capture only recorded: put the bookkeeping back
+    S->cur = cur;
+    S->steps_enq = se;
+    if (st != DGSWE_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(S, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&S->graph[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      S->graph[key] = nullptr;
+      return hip_fail(S, e, "hipGraphInstantiate");
+    }
+  }
+  hipError_t e = hipGraphLaunch(S->graph[key], S->stream);
+  if (e != hipSuccess) return hip_fail(S, e, "hipGraphLaunch");
+  for (MemberHost &h : S->mh) h.cur_is_pp = false;
+  S->steps_enq += S->graph_steps;
+  return DGSWE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -930,51 +1030,25 @@ dgswe_status dgswe_member_set_forcing(dgswe_solver *S, int32_t member, const dgs
 dgswe_status dgswe_step(dgswe_solver *S, int32_t n_steps) {
   if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
   if (n_steps < 0) return fail(S, DGSWE_E_INVALID, "n_steps < 0");
-  const DevMesh &m = S->m;
-  DevState &st = S->s;
-  const Params &p = S->prm;
-  const int want_dt = (p.dt_fixed > 0.0) ? 0 : 1;
-  if (m.nch == 0) return DGSWE_OK;  // no member
-  StageCoef sc[5];
-  const int ns = rk_stages(S->uprm.rk, sc);
-  for (int i = 0; i < n_steps; ++i) {
-    const int slot = (int)(S->steps_enq & 1);
-    // buffers: stage k reads buf[(cur + k) % 3] and writes buf[(cur + k + 1)
-    // % 3] (unlimited); wpp holds the post-processed w^n (RK base), so the
-    // buffer of w^n is free from the second stage on
-    const int cur = S->cur;
-    hipError_t e = hipSuccess;
-    for (int stage = 0; stage < ns && e == hipSuccess; ++stage) {
-      void *in = st.buf[(cur + stage) % 3], *out = st.buf[(cur + stage + 1) % 3];
-      const int wd = sc[stage].last ? want_dt : 0;
-      if (S->nfblk > 0) {
-        Timed t(S, K_FORCING);
-        e = launch_forcing(m, st, p, S->nfblk, slot, sc[stage].c, S->stream);
-      }
-      if (e != hipSuccess) break;
-      if (S->order == 2) {
-        // records of the stage input: w^n's go to wpp (the RK base), a later
-        // stage's to the one buffer it neither reads nor writes
-        void *rec = stage == 0 ? st.wpp : st.buf[(cur + stage + 2) % 3];
-        {
-          Timed t(S, K_PP2);
-          e = launch_pp2(m, st, p, in, rec, slot, stage == 0 ? 0 : 1, S->precision, S->stream);
-        }
-        if (e != hipSuccess) break;
-        Timed t(S, K_RHS2);
-        e = launch_rhs2(m, st, p, rec, stage == 0 ? nullptr : st.wpp, out, slot, stage == 0, sc[stage], wd,
-                        S->precision, S->stream);
-        continue;
-      }
-      Timed t(S, K_STAGE);
-      e = launch_stage(m, st, p, in, stage == 0 ? nullptr : st.wpp, out, stage == 0 ? st.wpp : nullptr, slot,
-                       stage == 0, sc[stage], wd, S->block, S->precision, S->stream);
+  if (S->m.nch == 0) return DGSWE_OK;  // no member
+  int32_t left = n_steps;
+  if (S->graph_steps > 0 && !S->prof) {
+    while (left >= S->graph_steps) {
+      dgswe_status st = graph_steps(S);
+      if (st != DGSWE_OK) return st;
+      left -= S->graph_steps;
     }
-    if (e != hipSuccess) return hip_fail(S, e, "kernel launch");
-    S->cur = (cur + ns) % 3;
-    for (MemberHost &h : S->mh) h.cur_is_pp = false;
-    S->steps_enq += 1;
   }
+  return enqueue_steps(S, left);
+}
+
+dgswe_status dgswe_use_graphs(dgswe_solver *S, int32_t steps_per_graph) {
+  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+  if (steps_per_graph < 0) return fail(S, DGSWE_E_INVALID, "steps_per_graph < 0");
+  hipError_t e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+  drop_graphs(S);
+  S->graph_steps = steps_per_graph == 0 ? 0 : (steps_per_graph + 5) / 6 * 6;
   return DGSWE_OK;
 }
 

@@ -26,7 +26,7 @@ EXPORTED = ("dgswe_default_params", "dgswe_create_mesh", "dgswe_set_state", "dgs
             "dgswe_member_set_state", "dgswe_member_set_forcing", "dgswe_member_read_state",
             "dgswe_member_info", "dgswe_create_pool", "dgswe_prepare_mesh", "dgswe_prepared_free",
             "dgswe_prepared_elems", "dgswe_member_add_prepared", "dgswe_member_add", "dgswe_member_remove",
-            "dgswe_pool_usage")
+            "dgswe_pool_usage", "dgswe_use_graphs")
 
 
 class dgswe_params(C.Structure):
@@ -130,6 +130,8 @@ def load_library(path: str = LIB_PATH):
     L.dgswe_member_remove.restype = C.c_int
     L.dgswe_pool_usage.argtypes = [vp, C.POINTER(C.c_int64)]
     L.dgswe_pool_usage.restype = C.c_int
+    L.dgswe_use_graphs.argtypes = [vp, C.c_int32]
+    L.dgswe_use_graphs.restype = C.c_int
     _lib = L
     return L
 
@@ -305,6 +307,10 @@ def dgswe_step(h, n_steps):
     _check(h, load_library().dgswe_step(h, int(n_steps)))
 
 
+def dgswe_use_graphs(h, steps_per_graph):
+    _check(h, load_library().dgswe_use_graphs(h, int(steps_per_graph)))
+
+
 def dgswe_read_state(h, w_out=None, diag=True, member=None):
     d = dgswe_diag()
     L = load_library()
@@ -385,6 +391,9 @@ class Solver:
     def step(self, n=1):
         dgswe_step(self.h, n)
 
+    def use_graphs(self, steps_per_graph):
+        dgswe_use_graphs(self.h, steps_per_graph)
+
     def state(self):
         w = np.empty((3, self.nm, self.ne), dtype=np.float64)
         self.diag = dgswe_read_state(self.h, w)
@@ -437,6 +446,9 @@ class Batch:
 
     def step(self, n=1):
         dgswe_step(self.h, n)
+
+    def use_graphs(self, steps_per_graph):
+        dgswe_use_graphs(self.h, steps_per_graph)
 
     def state(self, i):
         w = np.empty((3, self.nm, int(self.meshes[i].tri.shape[0])), dtype=np.float64)
@@ -509,6 +521,9 @@ class Pool:
 
     def step(self, n=1):
         dgswe_step(self.h, n)
+
+    def use_graphs(self, steps_per_graph):
+        dgswe_use_graphs(self.h, steps_per_graph)
 
     def state(self, slot):
         w = np.empty((3, self.nm, self.ne[slot]), dtype=np.float64)
