@@ -379,6 +379,23 @@ def measure_graphs(stream, steps=600):
     return out
 
 
+def measure_autotune(stream):
+    """The launch autotuner on two coastal meshes (10k and 130k triangles,
+    FP64, tide): microseconds per step for each chunk size."""
+    from paper_2508_21208_amd import workloads as W
+    from paper_2508_21208_amd.autotune import tune
+    out = {}
+    for n, seed in ((10_000, W.BASE_SEED + 5001), (130_000, W.BASE_SEED + 5006)):
+        m = W.coastal_mesh(n, seed, hmin=1000.0 if n < 30_000 else 200.0, hmax=15000.0 if n < 30_000 else 5000.0)
+        best, table = tune(m, W.default_params(dt_max=0.3), W.default_forcing(manning_n=0.025, **W.m2_tide(1.0)),
+                           W.coastal_initial_state(m), steps=40, hip_stream=stream.cuda_stream, use_cache=False)
+        default = [r[2] for r in table if r[0] == 256][0]
+        out[str(m.n_elems)] = {"us_per_step": {str(r[0]): round(r[2], 1) for r in table}, "best_chunk": best["chunk"],
+                               "speedup_vs_256": default / min(r[2] for r in table)}
+    log("autotune: " + json.dumps(out))
+    return out
+
+
 def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
     if not kernels:
         return None
@@ -491,6 +508,7 @@ def main():
 
     if not args.no_graphs:
         variants["graphs_small_mesh"] = measure_graphs(stream)
+        variants["autotune"] = measure_autotune(stream)
     if not args.no_serving:
         hint = variants.get("mixed", {}).get("value") or 1.2e10
         variants["serving"] = measure_serving(args.serving_requests, hint, stream)

@@ -80,6 +80,10 @@ typedef struct {
   int32_t rk;        /* time stepper: 22 = SSPRK(2,2), 33 = SSPRK(3,3),
                         32, 42, 52 = SSPRK(s,2) with s = 3, 4, 5 stages */
   int32_t flux;      /* numerical flux: 0 = local Lax-Friedrichs, 1 = Roe */
+  int32_t chunk;     /* launch tuning: elements per workgroup chunk, 64..256
+                        (0: 256); results do not depend on it */
+  int32_t waves;     /* launch tuning: waves per SIMD the p = 2 stage kernel's
+                        registers are budgeted for, 1..4 (0: 2) */
 } dgswe_params;
 
 /* Numerical flux (Sec. 2.2 names local Lax-Friedrichs and Roe).  flux = 1
@@ -124,7 +128,8 @@ typedef struct {
  * The CFL number should be smaller than at p = 1 (about 0.1). */
 
 /* Fill `p` with the defaults: p=1, FP64, g=9.81, rho0=1000, h0=0.01,
- * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1, rk=22, flux=0. */
+ * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1, rk=22, flux=0, chunk=0,
+ * waves=0. */
 void dgswe_default_params(dgswe_params *p);
 
 /* Build a solver for one mesh and allocate its device-resident state.

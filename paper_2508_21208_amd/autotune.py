@@ -1,0 +1,48 @@
+"""Launch-configuration autotuner: times candidate chunk sizes (elements
+per workgroup chunk of the stage kernels) and, at p = 2, the register
+budget of the stage kernel (waves per SIMD) on the mesh at hand, with its
+own forcing and state, and returns the fastest.  The configurations change
+only how the work is split over workgroups, never the results (bitwise).
+
+Small meshes favour small chunks (more workgroups for a short grid, less
+time per chunk), large ones the default 256 (less halo recomputation).
+Results are cached per (order, precision, mesh-size decade).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+from .dgswe import Solver
+
+_cache: dict = {}
+
+
+def candidates(params: dict):
+    chunks = (64, 128, 192, 256)
+    waves = (1, 2, 3) if int(params.get("p", 1)) == 2 else (0,)
+    return [(c, w) for c in chunks for w in waves]
+
+
+def tune(mesh, params: dict, forcing: dict, w0, postprocess=True, steps=20, hip_stream=None, use_cache=True):
+    """Returns (best params dict, table of (chunk, waves, us per step))."""
+    key = (int(params.get("p", 1)), int(params.get("precision", 0)), int(math.log10(max(1, mesh.n_elems))))
+    if use_cache and key in _cache:
+        best = _cache[key]
+        return dict(params, chunk=best[0], waves=best[1]), None
+    import torch
+    table = []
+    for c, w in candidates(params):
+        s = Solver(mesh, dict(params, chunk=c, waves=w), forcing, hip_stream=hip_stream)
+        s.set_state(w0, 0.0, postprocess)
+        s.step(3)
+        s.diagnostics()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.diagnostics()
+        table.append((c, w, 1e6 * (time.perf_counter() - t0) / steps))
+        s.close()
+    best = min(table, key=lambda r: r[2])
+    _cache[key] = best[:2]
+    return dict(params, chunk=best[0], waves=best[1]), table

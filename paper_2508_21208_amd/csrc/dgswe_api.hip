@@ -123,7 +123,7 @@ struct MemberHost {
   long long off[A_COUNT] = {}, len[A_COUNT] = {};
   // chunks relative to the member's ranges: c0, cc, n1, h2o, n2, leo, ne_loc, lo
   std::vector<int> chunks;
-  int nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
+  int nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0, C = 0;
 };
 constexpr int kChunkHost = 8;
 }  // namespace
@@ -246,6 +246,8 @@ bool validate_params(const dgswe_params *p, std::string &msg) {
   StageCoef sc[5];
   if (rk_stages(p->rk, sc) == 0) { msg = "rk must be 22, 33, 32, 42 or 52"; return false; }
   if (p->flux != 0 && p->flux != 1) { msg = "flux must be 0 (LLF) or 1 (Roe)"; return false; }
+  if (p->chunk != 0 && (p->chunk < 64 || p->chunk > 256)) { msg = "chunk must be 0 or in [64, 256]"; return false; }
+  if (p->waves < 0 || p->waves > 4) { msg = "waves must be in [0, 4]"; return false; }
   if (p->precision != DGSWE_FP64 && p->precision != DGSWE_MIXED) {
     msg = "precision must be DGSWE_FP64 or DGSWE_MIXED";
     return false;
@@ -345,8 +347,8 @@ void arena_need(const Prep &q, int order, long long need[A_COUNT]) {
   need[A_EDGE] = order == 2 ? q.ned : 0;
 }
 
-bool chunk_config(int &chunk, int &block) {
-  chunk = 256;
+bool chunk_config(const dgswe_params *prm, int &chunk, int &block) {
+  chunk = prm && prm->chunk > 0 ? prm->chunk : 256;
   block = 256;
   if (const char *ev = std::getenv("DGSWE_CHUNK")) chunk = std::atoi(ev);
   if (const char *ev = std::getenv("DGSWE_BLOCK")) block = std::atoi(ev);
@@ -379,6 +381,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   pp.dt_fixed = prm->dt_fixed; pp.dt_max = prm->dt_max;
   pp.limiter = prm->limiter ? 1 : 0; pp.wetdry = prm->wetdry ? 1 : 0;
   pp.flux = prm->flux;
+  pp.waves = prm->waves;
   for (int a = 0; a < A_COUNT; ++a) S->arena[a].init(cap[a]);
   S->chunk_cap = chunk_cap;
   S->mh.resize((size_t)slots);
@@ -472,7 +475,7 @@ dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
     DevMesh t = S->m;
     t.nl_max = std::max(t.nl_max, q.nl_max); t.nm_max = std::max(t.nm_max, q.nm_max);
     t.ed_max = std::max(t.ed_max, q.ed_max); t.n2_max = std::max(t.n2_max, q.n2_max);
-    t.C = q.C;
+    t.C = std::max(t.C, q.C);
     if (stage_lds_bytes(t, S->precision) > 80 * 1024) {
       for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(off[a], need[a]);
       return fail(S, DGSWE_E_MESH, "element chunks have halos too large for the LDS");
@@ -560,7 +563,8 @@ dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
     r[7] = q.lo_off[c];
   }
   h.nl_max = q.nl_max; h.nm_max = q.nm_max; h.ed_max = q.ed_max; h.n2_max = q.n2_max;
-  S->m.C = q.C;
+  h.C = q.C;
+  S->m.C = std::max(S->m.C, q.C);
   Member f{};
   f.e0 = e0; f.ne = q.ne; f.n0 = n0; f.nn = q.nn;
   f.pn = 101300.0;
@@ -596,6 +600,7 @@ dgswe_status rebuild(dgswe_solver *S) {
   int nch = 0;
   S->nn = S->ne = S->ned = S->nbnd = 0;
   m.nl_max = m.nm_max = m.ed_max = m.n2_max = 1;
+  m.C = 1;
   for (size_t i = 0; i < S->mh.size(); ++i) {
     MemberHost &h = S->mh[i];
     Member &f = S->mem[i];
@@ -625,6 +630,7 @@ dgswe_status rebuild(dgswe_solver *S) {
     S->nn += h.nn; S->ne += h.ne; S->ned += h.ned; S->nbnd += h.nbnd;
     m.nl_max = std::max(m.nl_max, h.nl_max); m.nm_max = std::max(m.nm_max, h.nm_max);
     m.ed_max = std::max(m.ed_max, h.ed_max); m.n2_max = std::max(m.n2_max, h.n2_max);
+    m.C = std::max(m.C, h.C);
   }
   if (nch > S->chunk_cap) return fail(S, DGSWE_E_NOMEM, "chunk table full");
   m.nch = nch;
@@ -656,7 +662,7 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
   std::string msg;
   if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
   int chunk, block;
-  if (!chunk_config(chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+  if (!chunk_config(prm, chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
   long long ne_total = 0;
   for (int32_t i = 0; i < n_members; ++i) ne_total += meshes[i].n_elems > 0 ? meshes[i].n_elems : 0;
   if (ne_total > 0x7fffffffLL) return fail(nullptr, DGSWE_E_INVALID, "more than 2^31 - 1 elements in the batch");
@@ -983,6 +989,8 @@ void dgswe_default_params(dgswe_params *p) {
   if (!p) return;
   p->rk = 22;
   p->flux = 0;
+  p->chunk = 0;
+  p->waves = 0;
   p->p = 1;
   p->precision = DGSWE_FP64;
   p->g = 9.81;
@@ -1131,7 +1139,7 @@ dgswe_status dgswe_create_pool(int64_t max_elems, int32_t max_members, const dgs
   if (max_elems < 1 || max_elems > 0x3fffffffLL || max_members < 1 || max_members > 65536)
     return fail(nullptr, DGSWE_E_INVALID, "pool capacity out of range");
   int chunk, block;
-  if (!chunk_config(chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+  if (!chunk_config(prm, chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
   long long cap[A_COUNT];
   int chunk_cap = 0;
   pool_caps(max_elems, max_members, prm->p, cap, chunk_cap);
@@ -1157,7 +1165,7 @@ dgswe_status dgswe_prepare_mesh(const dgswe_mesh *mesh, const dgswe_params *prm,
   if (!mesh) return fail(nullptr, DGSWE_E_INVALID, "mesh is NULL");
   if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
   int chunk, block;
-  if (!chunk_config(chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+  if (!chunk_config(prm, chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
   dgswe_prepared *P = new (std::nothrow) dgswe_prepared();
   if (!P) return fail(nullptr, DGSWE_E_NOMEM, "host allocation failed");
   P->order = prm->p;

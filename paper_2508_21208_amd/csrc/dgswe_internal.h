@@ -110,6 +110,7 @@ struct Params {
   double g, rho0, h0, cfl, dt_fixed, dt_max;
   int limiter, wetdry;
   int flux;  // 0: LLF, 1: Roe on edges wet on both sides
+  int waves; // register budget of the p = 2 stage kernel (waves per SIMD), 0: default
 };
 
 // Buffers of one solver touched by the step.  The state lives in three

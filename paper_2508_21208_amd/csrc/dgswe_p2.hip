@@ -617,11 +617,12 @@ static void stage2_qt(const DevMesh &m, const DevState &s, const Params &p, cons
     else hipLaunchKernelGGL((k_pp2<QT, 0>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, a, r, slot);
   }
   if (!pp_only) {
-    static const int wpe = [] {
+    static const int wpe_env = [] {
       const char *ev = std::getenv("DGSWE_RHS2_WPE");
       const int w = ev ? std::atoi(ev) : 0;
-      return (w >= 1 && w <= 4) ? w : (sizeof(QT) == 8 ? kRhs2WpeFp64 : kRhs2WpeMixed);
+      return (w >= 1 && w <= 4) ? w : 0;
     }();
+    const int wpe = wpe_env ? wpe_env : (p.waves ? p.waves : (sizeof(QT) == 8 ? kRhs2WpeFp64 : kRhs2WpeMixed));
 #define DGSWE_RHS2(W) \
   hipLaunchKernelGGL((k_rhs2<QT, W>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, sc, slot, want_dt)
     switch (wpe) {

@@ -32,7 +32,8 @@ EXPORTED = ("dgswe_default_params", "dgswe_create_mesh", "dgswe_set_state", "dgs
 class dgswe_params(C.Structure):
     _fields_ = [("p", C.c_int32), ("precision", C.c_int32), ("g", C.c_double), ("rho0", C.c_double),
                 ("h0", C.c_double), ("cfl", C.c_double), ("dt_fixed", C.c_double), ("dt_max", C.c_double),
-                ("limiter", C.c_int32), ("wetdry", C.c_int32), ("rk", C.c_int32), ("flux", C.c_int32)]
+                ("limiter", C.c_int32), ("wetdry", C.c_int32), ("rk", C.c_int32), ("flux", C.c_int32),
+                ("chunk", C.c_int32), ("waves", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -490,6 +491,11 @@ class Pool:
     def prepare(self, mesh):
         """host-only preprocessing; returns a handle for add()"""
         return dgswe_prepare_mesh(mesh, self.prm)
+
+    def prepare_with(self, mesh, params: dict):
+        """host-only preprocessing with other launch tuning (chunk) than the
+        pool's own; order and precision must match the pool's"""
+        return dgswe_prepare_mesh(mesh, params_from_dict(params))
 
     def add(self, mesh=None, prepared=None, forcing=None, w=None, t=0.0, postprocess=False):
         """Admit a mesh (or a prepared handle, consumed on success); returns the
