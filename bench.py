@@ -337,8 +337,10 @@ def measure_serving(n_requests, pool_rate_hint, stream):
     log(f"serving: {len(reqs)} requests on {len(meshes)} meshes ({min(m.n_elems for m in meshes)}-"
         f"{max(m.n_elems for m in meshes)} triangles) in {time.perf_counter() - t0:.1f} s; "
         f"{lam:.2f} requests/s")
+    # chunk sizes from the autotuner's measurements: 128 below 50k triangles
     out, el = serve_pool(reqs, W.default_params(precision=1, dt_max=0.3), lam, max_elems=16_000_000,
-                         max_members=256, round_cap=100, hip_stream=stream.cuda_stream)
+                         max_members=256, round_cap=100, hip_stream=stream.cuda_stream,
+                         chunk_rule=lambda n: 128 if n < 50_000 else 256)
     pool = summarize(out, el)
     log("serving pool: " + json.dumps(pool))
     out2, el2 = serve_one_at_a_time(reqs, W.default_params(precision=0, dt_max=0.3), lam, deadline_s=3 * el,

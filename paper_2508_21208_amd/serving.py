@@ -53,9 +53,11 @@ def summarize(outcomes: list, elapsed: float) -> dict:
 
 def serve_pool(requests, params: dict, rate: float, max_elems: int, max_members: int = 256,
                round_cap: int = 100, prep_workers: int = 8, keep_states: bool = False, hip_stream=None,
-               log=None):
+               log=None, chunk_rule=None):
     """Run `requests` (workloads.Request, arrival in mean gaps) arriving at
-    `rate` per second through a pool; returns (outcomes, elapsed s)."""
+    `rate` per second through a pool; returns (outcomes, elapsed s).
+    chunk_rule(n_elems) -> chunk size used to prepare each mesh (e.g. from
+    the autotuner: smaller chunks for small meshes); default: the pool's."""
     pool = Pool(max_elems, max_members, params, hip_stream=hip_stream)
     reqs = sorted(requests, key=lambda r: r.arrival)
     arrive = [r.arrival / rate for r in reqs]
@@ -74,7 +76,11 @@ def serve_pool(requests, params: dict, rate: float, max_elems: int, max_members:
         while len(outcomes) < len(reqs):
             # arrivals: start their host preparation
             while nxt < len(reqs) and arrive[nxt] <= now():
-                futures[nxt] = ex.submit(pool.prepare, reqs[nxt].mesh)
+                if chunk_rule is None:
+                    futures[nxt] = ex.submit(pool.prepare, reqs[nxt].mesh)
+                else:
+                    futures[nxt] = ex.submit(pool.prepare_with, reqs[nxt].mesh,
+                                             dict(params, chunk=chunk_rule(reqs[nxt].mesh.n_elems)))
                 waiting.append(nxt)
                 nxt += 1
             # admission, in arrival order, while the pool has room
