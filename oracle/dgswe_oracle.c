@@ -78,6 +78,9 @@ typedef struct {
   /* Holland (1980) parametric vortex moving at constant velocity */
   int32_t holland;
   double x0, y0, vx, vy, dp, pn, rmax, B, rho_air, coriolis_f, wind_factor;
+  /* Coriolis parameter of the momentum equations (1/s) and a uniform
+   * rainfall rate (m/s): the remaining sources of Sec. 2.1 */
+  double coriolis, rain;
 } or_forcing;
 
 typedef struct or_mesh {
@@ -516,6 +519,15 @@ int32_t or_set_forcing(or_mesh *M, double manning_n, const double *manning_elem,
   return OR_OK;
 }
 
+/* READING (Sec. 2.1 lists Coriolis and rain among the sources): Coriolis
+ * S_Qx += f Qy, S_Qy -= f Qx in wet elements; rain S_zeta += R everywhere
+ * (a dry element fills and wets). */
+int32_t or_set_sources(or_mesh *M, double coriolis, double rain) {
+  M->frc.coriolis = coriolis;
+  M->frc.rain = rain;
+  return OR_OK;
+}
+
 void or_set_extra_source(or_mesh *M, or_source_fn fn, void *ctx) {
   M->src_fn = fn; M->src_ctx = ctx;
   free(M->extra); M->extra = NULL;
@@ -748,9 +760,10 @@ static void element_rhs(or_mesh *M, const double *w, double t, double *dw) {
         double fr = g * n * n * qm / pow(Hf, 7.0 / 3.0);
         double txq = AREA_BARY[q][0] * tx[0] + AREA_BARY[q][1] * tx[1] + AREA_BARY[q][2] * tx[2];
         double tyq = AREA_BARY[q][0] * ty[0] + AREA_BARY[q][1] * ty[1] + AREA_BARY[q][2] * ty[2];
-        S[1] = g * ze * dhx - fr * qx + txq / rho0 - H / rho0 * dpx;
-        S[2] = g * ze * dhy - fr * qy + tyq / rho0 - H / rho0 * dpy;
+        S[1] = g * ze * dhx - fr * qx + txq / rho0 - H / rho0 * dpx + M->frc.coriolis * qy;
+        S[2] = g * ze * dhy - fr * qy + tyq / rho0 - H / rho0 * dpy - M->frc.coriolis * qx;
       }
+      S[0] += M->frc.rain;
       if (M->extra)
         for (int m = 0; m < 3; ++m) S[m] += M->extra[(size_t)m * 3 * ne + 3 * (size_t)e + q];
       double wA = AREA_WFRAC[q] * A;
@@ -1278,9 +1291,10 @@ static void element_rhs2(or_mesh *M, const double *w, double t, double *dw) {
         double fr = g * n * n * qm / pow(Hf, 7.0 / 3.0);
         double txq = AREA2_BARY[q][0] * tx[0] + AREA2_BARY[q][1] * tx[1] + AREA2_BARY[q][2] * tx[2];
         double tyq = AREA2_BARY[q][0] * ty[0] + AREA2_BARY[q][1] * ty[1] + AREA2_BARY[q][2] * ty[2];
-        S[1] = g * ze * dhx - fr * qx + txq / rho0 - H / rho0 * dpx;
-        S[2] = g * ze * dhy - fr * qy + tyq / rho0 - H / rho0 * dpy;
+        S[1] = g * ze * dhx - fr * qx + txq / rho0 - H / rho0 * dpx + M->frc.coriolis * qy;
+        S[2] = g * ze * dhy - fr * qy + tyq / rho0 - H / rho0 * dpy - M->frc.coriolis * qx;
       }
+      S[0] += M->frc.rain;
       if (M->extra)
         for (int m = 0; m < 3; ++m) S[m] += M->extra[(size_t)m * 6 * ne + 6 * (size_t)e + q];
       for (int m = 0; m < 3; ++m)

@@ -70,6 +70,8 @@ def load_oracle():
     L.or_llf.argtypes = [C.c_double, _dp, _dp, C.c_double, C.c_double, C.c_double, C.c_int32,
                          C.c_int32, _dp]
     L.or_wall.argtypes = [C.c_double, _dp, C.c_double, C.c_double, C.c_double, C.c_int32, _dp]
+    L.or_set_sources.argtypes = [C.c_void_p, C.c_double, C.c_double]
+    L.or_set_sources.restype = C.c_int32
     L.or_set_flux.argtypes = [C.c_void_p, C.c_int32]
     L.or_set_flux.restype = C.c_int32
     L.or_roe.argtypes = [C.c_double, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
@@ -174,6 +176,7 @@ class Oracle:
                                   int(f.get("holland", 0)), _d(hp))
         if r:
             raise OracleError(f"or_set_forcing: {r}")
+        self.L.or_set_sources(self.h, float(f.get("coriolis", 0.0)), float(f.get("rain", 0.0)))
 
     def set_extra_source(self, fn):
         """fn(t, xy (npts,2)) -> array (3, npts): added to s at area points."""
