@@ -270,6 +270,10 @@ typedef struct {
   const double *patm;
   int32_t holland;
   double x0, y0, vx, vy, dp, pn, rmax, B, rho_air, coriolis_f, wind_factor;
+  double coriolis;   /* Coriolis parameter f of the momentum equations (1/s):
+                        S_Qx += f Qy, S_Qy -= f Qx in wet elements; 0: off */
+  double rain;       /* uniform rainfall rate R (m/s): S_zeta += R everywhere
+                        (Sec. 2.1 lists both among the sources) */
 } dgswe_forcing;
 
 dgswe_status dgswe_set_forcing(dgswe_solver *s, const dgswe_forcing *f);

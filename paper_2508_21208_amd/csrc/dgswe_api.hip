@@ -794,6 +794,8 @@ dgswe_status set_forcing_impl(dgswe_solver *S, int32_t member, const dgswe_forci
   f.x0 = fr->x0; f.y0 = fr->y0; f.vx = fr->vx; f.vy = fr->vy; f.dp = fr->dp; f.pn = fr->pn;
   f.rmax = fr->rmax; f.B = fr->B; f.rho_air = fr->rho_air; f.coriolis_f = fr->coriolis_f;
   f.wind_factor = fr->wind_factor;
+  f.coriolis = fr->coriolis;
+  f.rain = fr->rain;
   // Manning n: the member's per-element range, or its uniform slot after
   // the per-element values; its chunk records point at the one that applies
   const bool per_elem = fr->manning_n_elem != nullptr;

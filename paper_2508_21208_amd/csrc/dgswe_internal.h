@@ -42,6 +42,7 @@ struct Member {
   int holland, n_tide;
   double tide_amp[kMaxTide], tide_omega[kMaxTide], tide_phase[kMaxTide], tide_offset;
   double x0, y0, vx, vy, dp, pn, rmax, B, rho_air, coriolis_f, wind_factor;
+  double coriolis, rain;          // momentum Coriolis parameter, rainfall rate
 };
 
 // Mesh on the device (internal order).  Arrays read by the stage kernel are

@@ -221,6 +221,8 @@ struct ElemPre {
   QT wbq[6];
   double inr2;
   QT manning;
+  QT coriolis;
+  double rain;
   int ledge[3];
 };
 
@@ -273,15 +275,15 @@ HD void area_terms(const double z[3], const R q[6], bool wet, const ElemPre<R> &
       const R txq = l0 * E.tx[0] + l1 * E.tx[1] + l2 * E.tx[2];
       const R tyq = l0 * E.ty[0] + l1 * E.ty[1] + l2 * E.ty[2];
       const R gz = (R)(p.g * ze);
-      const R sx = gz * dhx - fr * qx + txq * irho - H * irho * dpx;
-      const R sy = gz * dhy - fr * qy + tyq * irho - H * irho * dpy;
+      const R sx = gz * dhx - fr * qx + txq * irho - H * irho * dpx + E.coriolis * qy;
+      const R sy = gz * dhy - fr * qy + tyq * irho - H * irho * dpy - E.coriolis * qx;
       S0[0] += sx;          S0[1] += sy;
       S1[0] += c1 * sx;     S1[1] += c1 * sy;
       S2[0] += c2 * sx;     S2[1] += c2 * sy;
     }
   }
   const R third = (R)(1.0 / 3.0);
-  rz[0] = 0.0;  // no mass source
+  rz[0] = E.rain;  // the only mass source: uniform rain (projects on mode 0 alone)
   rz[1] = (double)((g1x * sF[0][0] + g1y * sF[0][1]) * third);
   rz[2] = (double)((g2x * sF[0][0] + g2y * sF[0][1]) * third);
   for (int v = 0; v < 2; ++v) {
@@ -722,6 +724,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   const bool use_base = STAGE != 0 && sc.a != 0.0;
   load_elem_pre<QT>(m, k, cei, use_base ? &wbase : nullptr, pre);
   pre.manning = manning_of(m, k, cei, (QT)0);
+  pre.coriolis = (QT)F.coriolis;
+  pre.rain = F.rain;
   // Round 3: gathers through the indices (kept after round 2 in the
   // instruction stream, so the index loads return while round 2 is issued).
 #ifdef __HIP_DEVICE_COMPILE__

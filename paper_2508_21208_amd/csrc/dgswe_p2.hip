@@ -423,8 +423,9 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
         const R txq = (R)L[0] * tx[0] + (R)L[1] * tx[1] + (R)L[2] * tx[2];
         const R tyq = (R)L[0] * ty[0] + (R)L[1] * ty[1] + (R)L[2] * ty[2];
         const R gz = (R)(p.g * ze);
-        const R sx = (gz * dhx - fr * qx + txq * irho - H * irho * dpx) * w;
-        const R sy = (gz * dhy - fr * qy + tyq * irho - H * irho * dpy) * w;
+        const R cor = (R)F.coriolis;
+        const R sx = (gz * dhx - fr * qx + txq * irho - H * irho * dpx + cor * qy) * w;
+        const R sy = (gz * dhy - fr * qy + tyq * irho - H * irho * dpy - cor * qx) * w;
         for (int j = 0; j < 6; ++j) {
           rq[j] += (R)f[j] * sx;
           rq[6 + j] += (R)f[j] * sy;
@@ -433,6 +434,7 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
     }
   }
 
+  rz[0] += F.rain;  // uniform rain projects on mode 0 alone
   // edges: each evaluated in its own orientation with both sides' traces
   const double ts = t0 + sc.c * dt;
   const bool tide = F.n_tide > 0 || F.tide_offset != 0.0;

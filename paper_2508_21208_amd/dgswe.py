@@ -45,7 +45,8 @@ class dgswe_forcing(C.Structure):
                 ("wind_tau", _dp), ("patm", _dp), ("holland", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("vx", C.c_double), ("vy", C.c_double),
                 ("dp", C.c_double), ("pn", C.c_double), ("rmax", C.c_double), ("B", C.c_double),
-                ("rho_air", C.c_double), ("coriolis_f", C.c_double), ("wind_factor", C.c_double)]
+                ("rho_air", C.c_double), ("coriolis_f", C.c_double), ("wind_factor", C.c_double),
+                ("coriolis", C.c_double), ("rain", C.c_double)]
 
 
 class dgswe_mesh(C.Structure):
@@ -297,6 +298,8 @@ def dgswe_set_forcing(h, f: dict, n_elems: int | None = None, n_nodes: int | Non
     fs.holland = int(f.get("holland", 0))
     for k in HOLLAND_KEYS:
         setattr(fs, k, float(f.get(k, 0.0)))
+    fs.coriolis = float(f.get("coriolis", 0.0))
+    fs.rain = float(f.get("rain", 0.0))
     L = load_library()
     if member is None:
         _check(h, L.dgswe_set_forcing(h, C.byref(fs)))

@@ -298,7 +298,8 @@ def default_forcing(**kw) -> dict:
              tide_amp=[], tide_omega=[], tide_phase=[], tide_offset=0.0,
              wind_tau=None, patm=None,
              holland=0, x0=0.0, y0=0.0, vx=0.0, vy=0.0, dp=0.0, pn=101300.0,
-             rmax=40.0e3, B=1.5, rho_air=1.15, coriolis_f=7.07e-5, wind_factor=0.9)
+             rmax=40.0e3, B=1.5, rho_air=1.15, coriolis_f=7.07e-5, wind_factor=0.9,
+             coriolis=0.0, rain=0.0)
     f.update(kw)
     return f
 
