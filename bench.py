@@ -247,7 +247,7 @@ def cpu_baseline(wl, target_s=12.0):
                       f"{secs:.1f} s, OpenMP threads={threads}"}
 
 
-def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None):
+def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, forcing=None):
     """Create the solver on `stream`, warm up, time `steps` steps with the
     stream synchronised on both sides; returns (elapsed s, solver info,
     per-kernel HIP-event times, diagnostics).  order 2: p = 2 with CFL 0.1,
@@ -261,7 +261,7 @@ def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None):
         w0 = np.zeros((3, 6, wl.w0.shape[2]))
         w0[:, :3] = wl.w0
     prm.update(extra or {})
-    s = Solver(wl.mesh, prm, wl.forcing, hip_stream=stream.cuda_stream)
+    s = Solver(wl.mesh, prm, dict(wl.forcing, **(forcing or {})), hip_stream=stream.cuda_stream)
     info = s.info()
     s.set_state(w0, 0.0, wl.postprocess_initial)
     log(f"{precision}: solver ready: {info['n_elems']} elements, {info['n_edges']} edges")
@@ -485,12 +485,14 @@ def main():
         # time steppers at their SSP limits: model seconds per wall second
         # is what a larger stable step buys
         from paper_2508_21208_amd.dgswe import DgsweError
-        for name, extra, ns in (("ssprk33", dict(rk=33, cfl=0.2), 3), ("ssprk52", dict(rk=52, cfl=0.8), 5),
-                                ("roe", dict(flux=1), 2)):
+        # "sources": Coriolis (f at 30 N) and heavy rain (50 mm/h) added
+        for name, extra, ns, fx in (("ssprk33", dict(rk=33, cfl=0.2), 3, {}), ("ssprk52", dict(rk=52, cfl=0.8), 5, {}),
+                                    ("roe", dict(flux=1), 2, {}),
+                                    ("sources", {}, 2, dict(coriolis=7.29e-5, rain=50e-3 / 3600))):
             try:
-                el5, _, k5, d5 = measure(wl, "fp64", args.steps, args.warmup, stream, profile, extra=extra)
+                el5, _, k5, d5 = measure(wl, "fp64", args.steps, args.warmup, stream, profile, extra=extra, forcing=fx)
                 variants[name] = {
-                    "value": ne * ns * args.steps / el5, "unit": "elem-stage/s", **extra, "stages": ns,
+                    "value": ne * ns * args.steps / el5, "unit": "elem-stage/s", **extra, **fx, "stages": ns,
                     "ms_per_step": 1e3 * el5 / args.steps, "dt_last": d5["dt_last"],
                     "model_s_per_wall_s": d5["dt_last"] / (el5 / args.steps),
                     "model_s_per_wall_s_default": d["dt_last"] / (elapsed / args.steps),

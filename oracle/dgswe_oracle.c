@@ -61,7 +61,8 @@ typedef void (*or_source_fn)(double t, int32_t npts, const double *xy, double *o
 
 typedef struct {
   double g, rho0, h0, cfl, dt_fixed, dt_max;
-  int32_t limiter, wetdry;
+  int32_t limiter;  /* 0: off, 1: face-neighbour, 2: vertex-based (p = 1) */
+  int32_t wetdry;
   int32_t rk;       /* 22, 33, 32, 42, 52: SSPRK(s, q) */
   int32_t flux;     /* 0: local Lax-Friedrichs, 1: Roe on edges wet on both sides */
 } or_params;
@@ -487,6 +488,7 @@ or_mesh *or_create(int32_t nn, const double *xy, const double *hb, int32_t ne, c
 int32_t or_set_params(or_mesh *M, double g, double rho0, double h0, double cfl, double dt_fixed,
                       double dt_max, int32_t limiter, int32_t wetdry) {
   if (!(g > 0.0) || !(rho0 > 0.0) || !(h0 > 0.0) || (dt_fixed <= 0.0 && !(cfl > 0.0))) return OR_E_INVALID;
+  if (limiter < 0 || limiter > 2) return OR_E_INVALID;
   M->prm.g = g; M->prm.rho0 = rho0; M->prm.h0 = h0; M->prm.cfl = cfl; M->prm.dt_fixed = dt_fixed;
   M->prm.dt_max = dt_max; M->prm.limiter = limiter; M->prm.wetdry = wetdry;
   return OR_OK;
@@ -826,12 +828,50 @@ int32_t or_postprocess(or_mesh *M, const double *wt, double *out) {
   if (M->nm == 6) return postprocess2(M, wt, out);
   const int32_t ne = M->ne;
   const double h0 = M->prm.h0;
+  /* vertex-based limiter (READING of the optional limiter, after Kuzmin's
+   * vertex-based limiter): the bounds at a mesh node are the smallest and
+   * largest unlimited mean of the elements that have the node as a vertex;
+   * each element then takes the largest alpha in [0, 1] that keeps all three
+   * of its vertex values, mean + alpha (u_v - mean), inside the bounds of
+   * the node at that vertex. */
+  double *nlo = NULL, *nhi = NULL;
+  if (M->prm.limiter == 2) {
+    const int32_t nn = M->nn;
+    nlo = malloc(sizeof(double) * 3 * (size_t)nn);
+    nhi = malloc(sizeof(double) * 3 * (size_t)nn);
+    if (!nlo || !nhi) { free(nlo); free(nhi); return OR_E_NOMEM; }
+    for (size_t i = 0; i < 3 * (size_t)nn; ++i) { nlo[i] = INFINITY; nhi[i] = -INFINITY; }
+    for (int32_t e = 0; e < ne; ++e)
+      for (int i = 0; i < 3; ++i) {
+        const int32_t n = M->tri[3 * e + i];
+        for (int m = 0; m < 3; ++m) {
+          const double mean = W(wt, m, 0, e, ne);
+          if (mean < nlo[3 * n + m]) nlo[3 * n + m] = mean;
+          if (mean > nhi[3 * n + m]) nhi[3 * n + m] = mean;
+        }
+      }
+  }
 #pragma omp parallel for schedule(static)
   for (int32_t e = 0; e < ne; ++e) {
     double u[3][3];
     for (int m = 0; m < 3; ++m)
       for (int k = 0; k < 3; ++k) u[m][k] = W(wt, m, k, e, ne);
-    if (M->prm.limiter) {
+    if (M->prm.limiter == 2) {
+      for (int m = 0; m < 3; ++m) {
+        const double mean = u[m][0];
+        double vv[3];
+        to_vertices(u[m][0], u[m][1], u[m][2], vv);
+        double alpha = 1.0;
+        for (int i = 0; i < 3; ++i) {
+          const int32_t n = M->tri[3 * e + i];
+          double a = 1.0;
+          if (vv[i] > mean) a = fmin(1.0, (nhi[3 * n + m] - mean) / (vv[i] - mean));
+          else if (vv[i] < mean) a = fmin(1.0, (nlo[3 * n + m] - mean) / (vv[i] - mean));
+          if (a < alpha) alpha = a;
+        }
+        u[m][1] *= alpha; u[m][2] *= alpha;
+      }
+    } else if (M->prm.limiter) {
       for (int m = 0; m < 3; ++m) {
         double mean = u[m][0], hi = mean, lo = mean;
         for (int l = 0; l < 3; ++l) {
@@ -896,6 +936,8 @@ int32_t or_postprocess(or_mesh *M, const double *wt, double *out) {
     for (int m = 0; m < 3; ++m)
       for (int k = 0; k < 3; ++k) W(out, m, k, e, ne) = u[m][k];
   }
+  free(nlo);
+  free(nhi);
   return OR_OK;
 }
 
@@ -977,6 +1019,7 @@ static int scheme_stage(int32_t rk, int k, double *a, double *b, double *h, doub
 int32_t or_step(or_mesh *M, int32_t nsteps) {
   const int32_t ne = M->ne;
   const size_t n9 = 3 * (size_t)M->nm * ne;
+  if (M->nm == 6 && M->prm.limiter == 2) return OR_E_INVALID;
   for (int32_t s = 0; s < nsteps; ++s) {
     double dt;
     int32_t st = pick_dt(M, M->w, &dt);
@@ -1336,6 +1379,7 @@ static void to_points2(const double u[6], double v[6]) {
  * edge midpoint drops the quadratic modes of all variables and gets the
  * p = 1 vertex correction of its linear part; otherwise it is unchanged. */
 static int32_t postprocess2(or_mesh *M, const double *wt, double *out) {
+  if (M->prm.limiter == 2) return OR_E_INVALID;  /* the vertex-based limiter is p = 1 only */
   const int32_t ne = M->ne;
   const double h0 = M->prm.h0;
 #pragma omp parallel for schedule(static)

@@ -152,6 +152,8 @@ class Oracle:
                                  int(p.get("limiter", 1)), int(p.get("wetdry", 1)))
         if r:
             raise OracleError(f"or_set_params: {r}")
+        if int(p.get("limiter", 1)) == 2 and self.order == 2:
+            raise OracleError("the vertex-based limiter (limiter = 2) is defined for p = 1 only")
         r = self.L.or_set_scheme(self.h, int(p.get("rk", 22)))
         if r:
             raise OracleError(f"or_set_scheme: {r}")
