@@ -487,7 +487,7 @@ def main():
         from paper_2508_21208_amd.dgswe import DgsweError
         # "sources": Coriolis (f at 30 N) and heavy rain (50 mm/h) added
         for name, extra, ns, fx in (("ssprk33", dict(rk=33, cfl=0.2), 3, {}), ("ssprk52", dict(rk=52, cfl=0.8), 5, {}),
-                                    ("roe", dict(flux=1), 2, {}),
+                                    ("roe", dict(flux=1), 2, {}), ("vertex_limiter", dict(limiter=2), 2, {}),
                                     ("sources", {}, 2, dict(coriolis=7.29e-5, rain=50e-3 / 3600))):
             try:
                 el5, _, k5, d5 = measure(wl, "fp64", args.steps, args.warmup, stream, profile, extra=extra, forcing=fx)

@@ -75,7 +75,13 @@ typedef struct {
   double cfl;        /* CFL number, used when dt_fixed <= 0 */
   double dt_fixed;   /* > 0: fixed time step [s] */
   double dt_max;     /* > 0: upper bound on the CFL time step [s] */
-  int32_t limiter;   /* 1: slope limiter after each stage */
+  int32_t limiter;   /* slope limiter after each stage: 0 off; 1 face-neighbour
+                        (the range of the element's and its face neighbours'
+                        means bounds its vertex values); 2 vertex-based, p = 1
+                        only (the range of the means of all elements sharing a
+                        mesh node bounds the value at that vertex; keeps linear
+                        fields on any element whose vertices each lie inside
+                        the hull of the surrounding centroids) */
   int32_t wetdry;    /* 1: wetting/drying after each stage */
   int32_t rk;        /* time stepper: 22 = SSPRK(2,2), 33 = SSPRK(3,3),
                         32, 42, 52 = SSPRK(s,2) with s = 3, 4, 5 stages */

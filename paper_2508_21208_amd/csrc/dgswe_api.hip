@@ -57,8 +57,8 @@ int rk_stages(int rk, StageCoef out[5]) {
 namespace {
 thread_local std::string g_create_error = "no error";
 
-enum KernelId { K_FORCING = 0, K_STAGE, K_PP2, K_RHS2, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage", "k_pp2", "k_rhs2"};
+enum KernelId { K_FORCING = 0, K_STAGE, K_PP2, K_RHS2, K_VBOUNDS, K_COUNT };
+const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage", "k_pp2", "k_rhs2", "k_vbounds"};
 
 // First-fit allocator over [0, cap) with coalescing of freed ranges.
 class Arena {
@@ -248,6 +248,8 @@ bool validate_params(const dgswe_params *p, std::string &msg) {
   if (p->flux != 0 && p->flux != 1) { msg = "flux must be 0 (LLF) or 1 (Roe)"; return false; }
   if (p->chunk != 0 && (p->chunk < 64 || p->chunk > 256)) { msg = "chunk must be 0 or in [64, 256]"; return false; }
   if (p->waves < 0 || p->waves > 4) { msg = "waves must be in [0, 4]"; return false; }
+  if (p->limiter < 0 || p->limiter > 2) { msg = "limiter must be 0, 1 or 2"; return false; }
+  if (p->limiter == 2 && p->p != 1) { msg = "the vertex-based limiter (limiter = 2) needs p = 1"; return false; }
   if (p->precision != DGSWE_FP64 && p->precision != DGSWE_MIXED) {
     msg = "precision must be DGSWE_FP64 or DGSWE_MIXED";
     return false;
@@ -379,7 +381,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   Params &pp = S->prm;
   pp.g = prm->g; pp.rho0 = prm->rho0; pp.h0 = prm->h0; pp.cfl = prm->cfl;
   pp.dt_fixed = prm->dt_fixed; pp.dt_max = prm->dt_max;
-  pp.limiter = prm->limiter ? 1 : 0; pp.wetdry = prm->wetdry ? 1 : 0;
+  pp.limiter = prm->limiter; pp.wetdry = prm->wetdry ? 1 : 0;
   pp.flux = prm->flux;
   pp.waves = prm->waves;
   for (int a = 0; a < A_COUNT; ++a) S->arena[a].init(cap[a]);
@@ -410,6 +412,8 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   al(&m.lgid, L); al(&m.lhb01, L); al(&m.lhb2, L); al(&m.lnb, L);
   al(&m.h2, R2);
   if (S->order == 2) { al(&m.e2edge, 3 * E); al(&m.hmean, E); al(&m.ed2a, D); al(&m.ed2b, D); }
+  if (pp.limiter == 2 && 3 * E > 0x7fffffffULL) ok = false;  // incidence positions are int
+  if (pp.limiter == 2) { al(&m.nd_rng, N); al(&m.nd_el, 3 * E); }
   chk(dev_alloc(S, &S->d_chunk_rec, (size_t)std::max(1, chunk_cap) * kChunkRec));
   m.chunk_rec = S->d_chunk_rec;
   chk(dev_alloc(S, &S->d_man, E + (size_t)slots));
@@ -436,11 +440,17 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   }
   chk(dev_alloc(S, &st.nodal, 3 * N)); chk(dev_alloc(S, &st.partial, 3 * (size_t)diag_blocks((int)E)));
   chk(dev_alloc(S, &st.ctrl, (size_t)slots)); chk(dev_alloc(S, &S->d_diag, 4));
+  if (pp.limiter == 2) chk(dev_alloc(S, &st.vb, 6 * N));
   if (ok) {
     // ring-2 entries are read clamped, so every entry is a valid element id
     chk(hipMemset((void *)m.h2, 0, R2 * sizeof(int)));
     chk(hipMemset(S->d_man, 0, (E + (size_t)slots) * sizeof(double)));
     chk(hipMemset(S->d_manf, 0, (E + (size_t)slots) * sizeof(float)));
+    // node ranges of unused node slots: empty; element ids: valid
+    if (pp.limiter == 2) {
+      chk(hipMemset((void *)m.nd_rng, 0, N * sizeof(int2)));
+      chk(hipMemset((void *)m.nd_el, 0, 3 * E * sizeof(int)));
+    }
   }
   if (!ok) {
     free_all(S);
@@ -507,6 +517,25 @@ dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
     std::vector<int4> en(q.enode);
     for (int4 &v : en) { v.x += n0; v.y += n0; v.z += n0; }
     chk(put(m.enode, e0, en.data(), ne));
+  }
+  if (S->prm.limiter == 2) {
+    // node -> element incidence (the member's 3 ne entries follow its
+    // element range: positions [3 e0, 3 e0 + 3 ne))
+    std::vector<int2> rng(nn, make_int2(0, 0));
+    for (const int4 &v : q.enode) { ++rng[(size_t)v.x].y; ++rng[(size_t)v.y].y; ++rng[(size_t)v.z].y; }
+    int at = 3 * e0;
+    for (int2 &r : rng) { r.x = at; at += r.y; r.y = 0; }
+    std::vector<int> inc(3 * ne);
+    for (size_t i = 0; i < ne; ++i) {
+      const int4 v = q.enode[i];
+      for (int n : {v.x, v.y, v.z}) {
+        int2 &r = rng[(size_t)n];
+        inc[(size_t)(r.x - 3 * e0 + r.y)] = (int)i + e0;
+        ++r.y;
+      }
+    }
+    chk(put(m.nd_rng, (size_t)n0, rng.data(), nn));
+    chk(put(m.nd_el, 3 * (size_t)e0, inc.data(), 3 * ne));
   }
   if (mixed) {
     chk(put(m.egf, e0, q.egf.data(), ne));
@@ -855,7 +884,7 @@ dgswe_status read_state_impl(dgswe_solver *S, int32_t member, double *w_out, dgs
       e = launch_post_only2(S->m, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
                             S->stream);
     else
-      e = launch_post_only(S->m, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
+      e = launch_post_only(S->m, S->s, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
                            S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "post-processing kernel");
     S->stage_buf.resize(nv * ne);
@@ -933,6 +962,11 @@ dgswe_status enqueue_steps(dgswe_solver *S, int32_t n_steps) {
         e = launch_rhs2(m, st, p, rec, stage == 0 ? nullptr : st.wpp, out, slot, stage == 0, sc[stage], wd,
                         S->precision, S->stream);
         continue;
+      }
+      if (p.limiter == 2) {
+        Timed t(S, K_VBOUNDS);
+        e = launch_vbounds(m, st, in, S->precision, S->stream);
+        if (e != hipSuccess) break;
       }
       Timed t(S, K_STAGE);
       e = launch_stage(m, st, p, in, stage == 0 ? nullptr : st.wpp, out, stage == 0 ? st.wpp : nullptr, slot,

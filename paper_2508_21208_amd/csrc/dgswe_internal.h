@@ -57,6 +57,10 @@ struct DevMesh {
   const int *el_nb;                     // [3][ne] neighbour across local edge, -1 none
   // nodes
   const double *node_x, *node_y;
+  // vertex-based limiter only: the elements having node n as a vertex are
+  // nd_el[nd_rng[n].x .. nd_rng[n].x + nd_rng[n].y) (ascending ids)
+  const int2 *nd_rng;
+  const int *nd_el;
   // members of the batch
   int nmem;
   const Member *mem;
@@ -109,7 +113,8 @@ int rk_stages(int rk, StageCoef out[5]);
 // Parameters shared by all members of a batch.
 struct Params {
   double g, rho0, h0, cfl, dt_fixed, dt_max;
-  int limiter, wetdry;
+  int limiter;     // 0: off, 1: face-neighbour, 2: vertex-based (p = 1)
+  int wetdry;
   int flux;  // 0: LLF, 1: Roe on edges wet on both sides
   int waves; // register budget of the p = 2 stage kernel (waves per SIMD), 0: default
 };
@@ -125,6 +130,8 @@ struct DevState {
   void *wpp;       // post-processed w^n of the current step (RK base), same layout
   double *nodal;   // wind stress (x, y) pairs [nn], then pressure [nn], at the nodes
   double *partial; // [3][nblk] diagnostics partial sums
+  double *vb;      // vertex-based limiter: per node (lo, hi) of the element
+                   // means of zeta, Qx, Qy (3 double2 per node)
   Ctrl *ctrl;      // [nmem]
 };
 
@@ -201,7 +208,9 @@ hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, co
 constexpr int kStageBlocks[] = {256};
 // Elements [e0, e0 + count) of a state as FP64 [9][count] (post-processed if
 // pp), e.g. to read a member back.
-hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
+// The vertex bounds of the limiter (limiter = 2) from the unlimited state win.
+hipError_t launch_vbounds(const DevMesh &m, const DevState &s, const void *win, int precision, hipStream_t st);
+hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p, const void *win, int pp, int e0, int count,
                             double *wout, int precision, hipStream_t st);
 // Reset member `mb`'s control block to time t (both parities; pp_in: the
 // stored state still needs post-processing) and put the CFL candidates of

@@ -23,7 +23,9 @@
 // post-processing leaves the mean depth and, in wet elements, the mean
 // momentum unchanged.  No floating-point atomics: results are deterministic.
 // k_forcing evaluates the Holland vortex once per mesh node and stage (the
-// paper's WIND node loops).
+// paper's WIND node loops).  With the vertex-based limiter, k_vbounds
+// first forms per mesh node the range of the unlimited element means around
+// it, and phase P limits each element against the ranges at its vertices.
 //
 // Precision.  The kernels are templated on QT, the storage type of the
 // momentum modes and the arithmetic type of the flux, volume and source
@@ -41,28 +43,47 @@ namespace dgswe {
 
 // ---------------------------------------------------------------- per-item math
 // Post-processing of one element (slope limiter, then wet/dry), FP64 in
-// both paths.  u[9] is the unlimited state [var*3 + mode]; nbm[v][k] the
-// unlimited mean of variable v of neighbour k (has[k] false: no neighbour);
-// h[3] the vertex bathymetry.
-HD void postprocess(double u[9], const double nbm[3][3], const bool has[3], const double h[3],
-                    double hmean, const Params &p) {
-  if (p.limiter) {
-    for (int v = 0; v < 3; ++v) {
-      const double mean = u[3 * v];
-      double hi = mean, lo = mean;
-      for (int k = 0; k < 3; ++k)
-        if (has[k]) { hi = fmax(hi, nbm[v][k]); lo = fmin(lo, nbm[v][k]); }
-      const double a = u[3 * v + 1], b = u[3 * v + 2];
-      const double d0 = (mean - a - b) - mean, d1 = (mean + a - b) - mean, d2 = (mean + 2.0 * b) - mean;
-      // the smallest vertex ratio belongs to the largest excursion on each side
-      const double dmax = fmax(d0, fmax(d1, d2)), dmin = fmin(d0, fmin(d1, d2));
-      double alpha = 1.0;
-      if (dmax > 0.0 && hi - mean < dmax) alpha = fmin(alpha, (hi - mean) / dmax);
-      if (dmin < 0.0 && lo - mean > dmin) alpha = fmin(alpha, (lo - mean) / dmin);
-      u[3 * v + 1] = a * alpha;
-      u[3 * v + 2] = b * alpha;
-    }
+// both paths.  u[9] is the unlimited state [var*3 + mode].
+
+// Face-neighbour limiter: nbm[v][k] the unlimited mean of variable v of
+// neighbour k (has[k] false: no neighbour).
+HD void limit_face(double u[9], const double nbm[3][3], const bool has[3]) {
+  for (int v = 0; v < 3; ++v) {
+    const double mean = u[3 * v];
+    double hi = mean, lo = mean;
+    for (int k = 0; k < 3; ++k)
+      if (has[k]) { hi = fmax(hi, nbm[v][k]); lo = fmin(lo, nbm[v][k]); }
+    const double a = u[3 * v + 1], b = u[3 * v + 2];
+    const double d0 = (mean - a - b) - mean, d1 = (mean + a - b) - mean, d2 = (mean + 2.0 * b) - mean;
+    // the smallest vertex ratio belongs to the largest excursion on each side
+    const double dmax = fmax(d0, fmax(d1, d2)), dmin = fmin(d0, fmin(d1, d2));
+    double alpha = 1.0;
+    if (dmax > 0.0 && hi - mean < dmax) alpha = fmin(alpha, (hi - mean) / dmax);
+    if (dmin < 0.0 && lo - mean > dmin) alpha = fmin(alpha, (lo - mean) / dmin);
+    u[3 * v + 1] = a * alpha;
+    u[3 * v + 2] = b * alpha;
   }
+}
+
+// Vertex-based limiter: lo[v][i], hi[v][i] the range of the unlimited means
+// of variable v over the elements sharing the element's vertex i; alpha is
+// the largest value in [0, 1] that keeps every vertex value inside.
+HD void limit_vertex(double u[9], const double lo[3][3], const double hi[3][3]) {
+  for (int v = 0; v < 3; ++v) {
+    const double mean = u[3 * v], a = u[3 * v + 1], b = u[3 * v + 2];
+    const double d[3] = {(mean - a - b) - mean, (mean + a - b) - mean, (mean + 2.0 * b) - mean};
+    double alpha = 1.0;
+    for (int i = 0; i < 3; ++i) {
+      if (d[i] > 0.0) alpha = fmin(alpha, (hi[v][i] - mean) / d[i]);
+      else if (d[i] < 0.0) alpha = fmin(alpha, (lo[v][i] - mean) / d[i]);
+    }
+    u[3 * v + 1] = a * alpha;
+    u[3 * v + 2] = b * alpha;
+  }
+}
+
+// Wet/dry treatment; h[3] the vertex bathymetry.
+HD void wetdry_fix(double u[9], const double h[3], double hmean, const Params &p) {
   if (p.wetdry) {
     const double z0 = u[0] - u[1] - u[2], z1 = u[0] + u[1] - u[2], z2 = u[0] + 2.0 * u[2];
     double H[3] = {z0 + h[0], z1 + h[1], z2 + h[2]};
@@ -92,6 +113,23 @@ HD void postprocess(double u[9], const double nbm[3][3], const bool has[3], cons
       u[2] = 0.5 * (y2 - u[0]);
     }
   }
+}
+
+HD void postprocess(double u[9], const double nbm[3][3], const bool has[3], const double h[3],
+                    double hmean, const Params &p) {
+  if (p.limiter == 1) limit_face(u, nbm, has);
+  wetdry_fix(u, h, hmean, p);
+}
+
+// vertex bounds of an element with nodes nd from the node ranges vb
+HD void load_vbounds(const double *vb, int4 nd, double lo[3][3], double hi[3][3]) {
+  const int n[3] = {nd.x, nd.y, nd.z};
+  for (int i = 0; i < 3; ++i)
+    for (int v = 0; v < 3; ++v) {
+      const double2 r = ((const double2 *)vb)[3 * (size_t)n[i] + v];
+      lo[v][i] = r.x;
+      hi[v][i] = r.y;
+    }
 }
 
 // Trace coefficients, bathymetry and normal of one edge at its three
@@ -298,11 +336,20 @@ HD void area_terms(const double z[3], const R q[6], bool wet, const ElemPre<R> &
 // Element e of a state, post-processed with neighbour means read from the
 // same state if pp, as FP64 (read-back)
 template <class QT>
-HD void load_pp_global(const DevMesh &m, const Params &p, CSt<QT> w, int e, bool pp, double u[9]) {
+HD void load_pp_global(const DevMesh &m, const Params &p, const double *vb, CSt<QT> w, int e, bool pp,
+                       double u[9]) {
   const size_t ne = (size_t)m.ne;
   for (int k = 0; k < 3; ++k) u[k] = w.z[k * ne + e];
   for (int k = 0; k < 6; ++k) u[3 + k] = (double)w.q[k * ne + e];
   if (!pp) return;
+  if (p.limiter == 2) {
+    double h[3], lo[3][3], hi[3][3];
+    for (int k = 0; k < 3; ++k) h[k] = m.hbv[k * ne + e];
+    load_vbounds(vb, m.enode[e], lo, hi);
+    limit_vertex(u, lo, hi);
+    wetdry_fix(u, h, mean3(h), p);
+    return;
+  }
   double h[3], nbm[3][3];
   bool has[3];
   for (int k = 0; k < 3; ++k) h[k] = m.hbv[k * ne + e];
@@ -487,15 +534,24 @@ HD void store_geo_lds(const Lds<QT> &L, int i, const GeoReg<QT> &G) {
 // phase P for local element i of chunk + ring 1 (h: its vertex bathymetry,
 // nb: local neighbour indices); the post-processed state of a chunk element
 // also goes to wpp if given
-template <class QT>
+// (VL: the vertex-based limiter, with the node ranges vb and the global
+// id g of the element)
+template <class QT, bool VL>
 HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp_in, int i, const double h[3],
-                   const uint16_t nb[3], const St<QT> *wpp, size_t ne) {
+                   const uint16_t nb[3], const St<QT> *wpp, size_t ne, const DevMesh &m, const double *vb, int g) {
   const int nl = k.nl();
   const double hmean = mean3(h);
   double u[9];
   for (int j = 0; j < 3; ++j) u[j] = L.SZ[j * L.nls + i];
   for (int j = 0; j < 6; ++j) u[3 + j] = (double)L.SQ[j * L.nls + i];
-  if (pp_in) {
+  if (VL && pp_in) {
+    double lo[3][3], hi[3][3];
+    load_vbounds(vb, m.enode[g], lo, hi);
+    limit_vertex(u, lo, hi);
+    wetdry_fix(u, h, hmean, p);
+    for (int j = 1; j < 3; ++j) L.SZ[j * L.nls + i] = u[j];
+    for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = (QT)u[3 + j];
+  } else if (pp_in) {
     double nbm[3][3];
     bool has[3];
     for (int q = 0; q < 3; ++q) {
@@ -677,7 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_forcing(DevMesh m, DevState s, Param
 // its member's forcing and control block.  The first stage also writes the
 // post-processed w^n of its chunk to wpp, the RK base that the second stage
 // reads.
-template <int NT, int WPE, class QT, int STAGE>
+template <int NT, int WPE, class QT, int STAGE, bool VL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void k_stage(
     DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase, St<QT> wout, St<QT> wpp, StageCoef sc, int slot,
     int want_dt) {
@@ -774,8 +830,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   for (int q = 0; q < 3; ++q) pre.h[q] = h0[q];
   __syncthreads();
   const St<QT> *wpp_out = (STAGE == 0 && active) ? &wpp : nullptr;
-  if (a0) phase_post<QT>(p, k, L, pp_in, i0, h0, nb0, wpp_out, ne);
-  if (a1) phase_post<QT>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne);
+  if (a0) phase_post<QT, VL>(p, k, L, pp_in, i0, h0, nb0, wpp_out, ne, m, s.vb, g0);
+  if (a1) phase_post<QT, VL>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne, m, s.vb, g1);
   __syncthreads();
   const double ts = t0 + sc.c * dt;
   const double zb = tide ? tide_level(F, ts) : 0.0;
@@ -802,13 +858,34 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 // elements [e0, e0 + count) of a state (post-processed if pp) as FP64
 // [9][count], for read-back
 template <class QT>
-__global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, CSt<QT> win, int pp, int e0, int count,
-                                                      double *__restrict__ wout) {
+__global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, const double *vb, CSt<QT> win, int pp,
+                                                      int e0, int count, double *__restrict__ wout) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= count) return;
   double u[9];
-  load_pp_global<QT>(m, p, win, e0 + i, pp != 0, u);
+  load_pp_global<QT>(m, p, vb, win, e0 + i, pp != 0, u);
   for (int j = 0; j < 9; ++j) wout[(size_t)j * count + i] = u[j];
+}
+
+// Vertex-based limiter: per mesh node, the smallest and largest unlimited
+// mean of zeta, Qx, Qy over the elements having the node as a vertex.
+template <class QT>
+__global__ __launch_bounds__(kBlock) void k_vbounds(DevMesh m, CSt<QT> w, double *__restrict__ vb) {
+  const int n = blockIdx.x * kBlock + threadIdx.x;
+  if (n >= m.nn) return;
+  const int2 r = m.nd_rng[n];
+  const size_t ne = (size_t)m.ne;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int j = 0; j < r.y; ++j) {
+    const int e = m.nd_el[r.x + j];
+    const double v[3] = {w.z[e], (double)w.q[e], (double)w.q[3 * ne + e]};
+    for (int q = 0; q < 3; ++q) {
+      lo[q] = fmin(lo[q], v[q]);
+      hi[q] = fmax(hi[q], v[q]);
+    }
+  }
+  double2 *o = (double2 *)vb + 3 * (size_t)n;
+  for (int q = 0; q < 3; ++q) o[q] = make_double2(lo[q], hi[q]);
 }
 
 __global__ void k_ctrl_reset(Ctrl *c, double t, int pp_in) {
@@ -932,12 +1009,17 @@ static void stage_qt(const DevMesh &m, const DevState &s, const Params &p, const
   const CSt<QT> b = wbase ? csplit<QT>(wbase, ne) : CSt<QT>{nullptr, nullptr};
   const St<QT> o = split<QT>(wout, ne);
   const St<QT> q = wpp ? split<QT>(wpp, ne) : St<QT>{nullptr, nullptr};
-#define DGSWE_STAGE(NT, W, S)                                                                             \
-  hipLaunchKernelGGL((k_stage<NT, W, QT, S>), dim3(m.nch), dim3(NT), lds, st, m, s, p, a, b, o, q, sc, slot, \
+#define DGSWE_STAGE(NT, W, S, V)                                                                             \
+  hipLaunchKernelGGL((k_stage<NT, W, QT, S, V>), dim3(m.nch), dim3(NT), lds, st, m, s, p, a, b, o, q, sc, slot, \
                      want_dt)
   (void)block;  // 256 lanes (the local ids and edge codes are packed for it)
-  if (!first) DGSWE_STAGE(256, 2, 1);
-  else DGSWE_STAGE(256, 2, 0);
+  if (p.limiter == 2) {
+    if (!first) DGSWE_STAGE(256, 2, 1, true);
+    else DGSWE_STAGE(256, 2, 0, true);
+  } else {
+    if (!first) DGSWE_STAGE(256, 2, 1, false);
+    else DGSWE_STAGE(256, 2, 0, false);
+  }
 #undef DGSWE_STAGE
 }
 
@@ -951,16 +1033,29 @@ hipError_t launch_stage(const DevMesh &m, const DevState &s, const Params &p, co
   return hipGetLastError();
 }
 
-hipError_t launch_post_only(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
-                            double *wout, int precision, hipStream_t st) {
+hipError_t launch_vbounds(const DevMesh &m, const DevState &s, const void *win, int precision, hipStream_t st) {
+  const size_t ne = (size_t)m.ne;
+  if (precision == DGSWE_MIXED)
+    hipLaunchKernelGGL(k_vbounds<float>, dim3(nblk(m.nn)), dim3(kBlock), 0, st, m, csplit<float>(win, ne), s.vb);
+  else
+    hipLaunchKernelGGL(k_vbounds<double>, dim3(nblk(m.nn)), dim3(kBlock), 0, st, m, csplit<double>(win, ne), s.vb);
+  return hipGetLastError();
+}
+
+hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p, const void *win, int pp, int e0,
+                            int count, double *wout, int precision, hipStream_t st) {
   const size_t ne = (size_t)m.ne;
   if (count <= 0) return hipSuccess;
+  if (pp && p.limiter == 2) {
+    const hipError_t e = launch_vbounds(m, s, win, precision, st);
+    if (e != hipSuccess) return e;
+  }
   if (precision == DGSWE_MIXED)
-    hipLaunchKernelGGL(k_post_only<float>, dim3(nblk(count)), dim3(kBlock), 0, st, m, p, csplit<float>(win, ne), pp,
-                       e0, count, wout);
+    hipLaunchKernelGGL(k_post_only<float>, dim3(nblk(count)), dim3(kBlock), 0, st, m, p, (const double *)s.vb,
+                       csplit<float>(win, ne), pp, e0, count, wout);
   else
-    hipLaunchKernelGGL(k_post_only<double>, dim3(nblk(count)), dim3(kBlock), 0, st, m, p, csplit<double>(win, ne),
-                       pp, e0, count, wout);
+    hipLaunchKernelGGL(k_post_only<double>, dim3(nblk(count)), dim3(kBlock), 0, st, m, p, (const double *)s.vb,
+                       csplit<double>(win, ne), pp, e0, count, wout);
   return hipGetLastError();
 }
 

@@ -117,6 +117,11 @@ def test_batch_validation_before_device_work():
     with pytest.raises(D.DgsweError) as ei:
         D.dgswe_create_batch([m, m], D.params_from_dict(dict(p=3)))
     assert ei.value.status == 1
+    # limiter: 0, 1, or 2 (vertex-based, p = 1 only)
+    for bad_p in (dict(limiter=3), dict(limiter=-1), dict(limiter=2, p=2)):
+        with pytest.raises(D.DgsweError) as ei:
+            D.dgswe_create_batch([m, m], D.params_from_dict(bad_p))
+        assert ei.value.status == 1, bad_p
     L = D.load_library()
     assert L.dgswe_member_count(None) == 0
     out = (C.c_int64 * 4)()
