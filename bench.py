@@ -129,9 +129,10 @@ def kernel_key(name: str):
 
 
 CMD_TRACE = ("rocprofv3 --kernel-trace --stats -d $OUT/prof -o bench --output-format csv -- "
-             "python3 $REPO/bench.py --steps 50 --warmup 5 --no-cpu-baseline --no-profile --no-batched --no-serving")
+             "python3 $REPO/bench.py --steps 50 --warmup 5 --no-cpu-baseline --no-profile --no-batched --no-serving "
+             "--no-rk --no-graphs")
 CMD_PMC = ("rocprofv3 --pmc {c} -d $OUT/pmc/{c} -o run --output-format csv -- python3 $REPO/bench.py --steps 3 "
-           "--warmup 1 --no-cpu-baseline --no-profile --copy-probe --no-batched --no-serving")
+           "--warmup 1 --no-cpu-baseline --no-profile --copy-probe --no-batched --no-serving --no-rk --no-graphs")
 
 
 def summarize_pmc(pmc_dir: str, stats_csv: str | None, out_md: str | None):
