@@ -79,13 +79,19 @@ def algorithmic_bytes(kernel: str, ne: int, ned: int, nn: int, precision: str = 
     """Algorithmic bytes of one launch: k_stage carries the whole p = 1
     stage (B_ALG_FP64 or B_ALG_MIXED per element), k_pp2 and k_rhs2 the
     p = 2 stage (B_ALG_P2); k_forcing reads node coordinates and writes the
-    nodal wind stress and pressure (40 B per node)."""
+    nodal wind stress and pressure (40 B per node); k_vbounds forms the
+    vertex-based limiter's node ranges."""
     if kernel == "k_stage":
         return (B_ALG_MIXED if precision == "mixed" else B_ALG_FP64) * ne
     if (kernel, precision) in B_ALG_P2:
         return B_ALG_P2[(kernel, precision)] * ne
     if kernel == "k_forcing":
         return 40.0 * nn
+    if kernel == "k_vbounds":
+        # per node: incidence range 8 + six bounds out 48; per element: its
+        # three incidence entries 12 and its three means, each read once
+        # (24 FP64, 16 mixed)
+        return 56.0 * nn + (12.0 + (16.0 if precision == "mixed" else 24.0)) * ne
     raise KeyError(kernel)
 
 

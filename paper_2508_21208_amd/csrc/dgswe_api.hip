@@ -413,7 +413,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   al(&m.h2, R2);
   if (S->order == 2) { al(&m.e2edge, 3 * E); al(&m.hmean, E); al(&m.ed2a, D); al(&m.ed2b, D); }
   if (pp.limiter == 2 && 3 * E > 0x7fffffffULL) ok = false;  // incidence positions are int
-  if (pp.limiter == 2) { al(&m.nd_rng, N); al(&m.nd_el, 3 * E); }
+  if (pp.limiter == 2) { al(&m.nd_rng, N); al(&m.nd_el, 3 * E); al(&m.evb, E); }
   chk(dev_alloc(S, &S->d_chunk_rec, (size_t)std::max(1, chunk_cap) * kChunkRec));
   m.chunk_rec = S->d_chunk_rec;
   chk(dev_alloc(S, &S->d_man, E + (size_t)slots));
@@ -519,23 +519,36 @@ dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
     chk(put(m.enode, e0, en.data(), ne));
   }
   if (S->prm.limiter == 2) {
-    // node -> element incidence (the member's 3 ne entries follow its
-    // element range: positions [3 e0, 3 e0 + 3 ne))
+    // node -> element incidence for the vertex-based limiter: range slots
+    // in order of first appearance in the element list (unused nodes
+    // last), the member's 3 ne entries at positions [3 e0, 3 e0 + 3 ne)
+    std::vector<int> slot_of(nn, -1);
+    int na = 0;
+    for (const int4 &v : q.enode)
+      for (int n : {v.x, v.y, v.z})
+        if (slot_of[(size_t)n] < 0) slot_of[(size_t)n] = na++;
+    for (int &a : slot_of)
+      if (a < 0) a = na++;
     std::vector<int2> rng(nn, make_int2(0, 0));
-    for (const int4 &v : q.enode) { ++rng[(size_t)v.x].y; ++rng[(size_t)v.y].y; ++rng[(size_t)v.z].y; }
+    for (const int4 &v : q.enode)
+      for (int n : {v.x, v.y, v.z}) ++rng[(size_t)slot_of[(size_t)n]].y;
     int at = 3 * e0;
     for (int2 &r : rng) { r.x = at; at += r.y; r.y = 0; }
     std::vector<int> inc(3 * ne);
+    std::vector<int4> evb(ne);
     for (size_t i = 0; i < ne; ++i) {
       const int4 v = q.enode[i];
-      for (int n : {v.x, v.y, v.z}) {
-        int2 &r = rng[(size_t)n];
+      const int a[3] = {slot_of[(size_t)v.x], slot_of[(size_t)v.y], slot_of[(size_t)v.z]};
+      for (int j = 0; j < 3; ++j) {
+        int2 &r = rng[(size_t)a[j]];
         inc[(size_t)(r.x - 3 * e0 + r.y)] = (int)i + e0;
         ++r.y;
       }
+      evb[i] = make_int4(a[0] + n0, a[1] + n0, a[2] + n0, 0);
     }
     chk(put(m.nd_rng, (size_t)n0, rng.data(), nn));
     chk(put(m.nd_el, 3 * (size_t)e0, inc.data(), 3 * ne));
+    chk(put(m.evb, (size_t)e0, evb.data(), ne));
   }
   if (mixed) {
     chk(put(m.egf, e0, q.egf.data(), ne));

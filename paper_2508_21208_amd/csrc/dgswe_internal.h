@@ -57,10 +57,14 @@ struct DevMesh {
   const int *el_nb;                     // [3][ne] neighbour across local edge, -1 none
   // nodes
   const double *node_x, *node_y;
-  // vertex-based limiter only: the elements having node n as a vertex are
-  // nd_el[nd_rng[n].x .. nd_rng[n].x + nd_rng[n].y) (ascending ids)
+  // vertex-based limiter only.  Its node ranges are numbered in the order
+  // the nodes first appear in the (Hilbert-ordered) element list, so that
+  // both passes over them read compact stretches: range slot a covers the
+  // elements nd_el[nd_rng[a].x .. nd_rng[a].x + nd_rng[a].y) (ascending
+  // ids); evb[e] holds the slots of element e's three vertices.
   const int2 *nd_rng;
   const int *nd_el;
+  const int4 *evb;
   // members of the batch
   int nmem;
   const Member *mem;
@@ -130,8 +134,8 @@ struct DevState {
   void *wpp;       // post-processed w^n of the current step (RK base), same layout
   double *nodal;   // wind stress (x, y) pairs [nn], then pressure [nn], at the nodes
   double *partial; // [3][nblk] diagnostics partial sums
-  double *vb;      // vertex-based limiter: per node (lo, hi) of the element
-                   // means of zeta, Qx, Qy (3 double2 per node)
+  double *vb;      // vertex-based limiter: per node range slot (lo, hi) of
+                   // the element means of zeta, Qx, Qy (3 double2 per slot)
   Ctrl *ctrl;      // [nmem]
 };
 

@@ -121,7 +121,7 @@ HD void postprocess(double u[9], const double nbm[3][3], const bool has[3], cons
   wetdry_fix(u, h, hmean, p);
 }
 
-// vertex bounds of an element with nodes nd from the node ranges vb
+// vertex bounds of an element whose vertices have the range slots nd
 HD void load_vbounds(const double *vb, int4 nd, double lo[3][3], double hi[3][3]) {
   const int n[3] = {nd.x, nd.y, nd.z};
   for (int i = 0; i < 3; ++i)
@@ -345,7 +345,7 @@ HD void load_pp_global(const DevMesh &m, const Params &p, const double *vb, CSt<
   if (p.limiter == 2) {
     double h[3], lo[3][3], hi[3][3];
     for (int k = 0; k < 3; ++k) h[k] = m.hbv[k * ne + e];
-    load_vbounds(vb, m.enode[e], lo, hi);
+    load_vbounds(vb, m.evb[e], lo, hi);
     limit_vertex(u, lo, hi);
     wetdry_fix(u, h, mean3(h), p);
     return;
@@ -534,11 +534,11 @@ HD void store_geo_lds(const Lds<QT> &L, int i, const GeoReg<QT> &G) {
 // phase P for local element i of chunk + ring 1 (h: its vertex bathymetry,
 // nb: local neighbour indices); the post-processed state of a chunk element
 // also goes to wpp if given
-// (VL: the vertex-based limiter, with the node ranges vb and the global
-// id g of the element)
+// (VL: the vertex-based limiter, with the node ranges vb and the range
+// slots ev of the element's vertices)
 template <class QT, bool VL>
 HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp_in, int i, const double h[3],
-                   const uint16_t nb[3], const St<QT> *wpp, size_t ne, const DevMesh &m, const double *vb, int g) {
+                   const uint16_t nb[3], bool to_wpp, const St<QT> &wpp, size_t ne, const double *vb, int4 ev) {
   const int nl = k.nl();
   const double hmean = mean3(h);
   double u[9];
@@ -546,7 +546,7 @@ HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp
   for (int j = 0; j < 6; ++j) u[3 + j] = (double)L.SQ[j * L.nls + i];
   if (VL && pp_in) {
     double lo[3][3], hi[3][3];
-    load_vbounds(vb, m.enode[g], lo, hi);
+    load_vbounds(vb, ev, lo, hi);
     limit_vertex(u, lo, hi);
     wetdry_fix(u, h, hmean, p);
     for (int j = 1; j < 3; ++j) L.SZ[j * L.nls + i] = u[j];
@@ -568,10 +568,10 @@ HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp
     for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = (QT)u[3 + j];
   }
   L.WET[i] = (p.wetdry ? (u[0] + hmean > p.h0) : true) ? 1 : 0;
-  if (wpp && i < k.cc) {
+  if (to_wpp && i < k.cc) {
     const size_t e = (size_t)(k.c0 + i);
-    for (int j = 0; j < 3; ++j) st_out(wpp->z + j * ne + e, u[j]);
-    for (int j = 0; j < 6; ++j) st_out(wpp->q + j * ne + e, (QT)u[3 + j]);
+    for (int j = 0; j < 3; ++j) st_out(wpp.z + j * ne + e, u[j]);
+    for (int j = 0; j < 6; ++j) st_out(wpp.q + j * ne + e, (QT)u[3 + j]);
   }
 }
 
@@ -771,6 +771,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   load_local_nb(m, k, c0i, nb0);
   load_local_hb(m, k, c1i, h1);
   load_local_nb(m, k, c1i, nb1);
+  int4 ev0 = make_int4(0, 0, 0, 0), ev1 = ev0;
+  if (VL) {
+    ev0 = m.evb[g0];
+    ev1 = m.evb[g1];
+  }
   EdgeRec<QT> r0, r1;
   const int j0 = tid < k.ne_loc ? tid : k.ne_loc - 1, j1 = tid + NT < k.ne_loc ? tid + NT : k.ne_loc - 1;
   load_edge_rec(m, k, j0, r0);
@@ -829,9 +834,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   }
   for (int q = 0; q < 3; ++q) pre.h[q] = h0[q];
   __syncthreads();
-  const St<QT> *wpp_out = (STAGE == 0 && active) ? &wpp : nullptr;
-  if (a0) phase_post<QT, VL>(p, k, L, pp_in, i0, h0, nb0, wpp_out, ne, m, s.vb, g0);
-  if (a1) phase_post<QT, VL>(p, k, L, pp_in, i1, h1, nb1, wpp_out, ne, m, s.vb, g1);
+  const bool to_wpp = STAGE == 0 && active;
+  if (a0) phase_post<QT, VL>(p, k, L, pp_in, i0, h0, nb0, to_wpp, wpp, ne, s.vb, ev0);
+  if (a1) phase_post<QT, VL>(p, k, L, pp_in, i1, h1, nb1, to_wpp, wpp, ne, s.vb, ev1);
   __syncthreads();
   const double ts = t0 + sc.c * dt;
   const double zb = tide ? tide_level(F, ts) : 0.0;
@@ -867,8 +872,9 @@ __global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, const
   for (int j = 0; j < 9; ++j) wout[(size_t)j * count + i] = u[j];
 }
 
-// Vertex-based limiter: per mesh node, the smallest and largest unlimited
-// mean of zeta, Qx, Qy over the elements having the node as a vertex.
+// Vertex-based limiter: per mesh node (range slot n), the smallest and
+// largest unlimited mean of zeta, Qx, Qy over the elements having the node
+// as a vertex.
 template <class QT>
 __global__ __launch_bounds__(kBlock) void k_vbounds(DevMesh m, CSt<QT> w, double *__restrict__ vb) {
   const int n = blockIdx.x * kBlock + threadIdx.x;
