@@ -296,16 +296,12 @@ def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, 
     return elapsed, info, kernels, d
 
 
-def measure_batched(steps, warmup, stream, profile):
+def measure_batched(ens, steps, warmup, stream, profile):
     """The ensemble as one batch in mixed precision: (elapsed s, total
     elements, members, per-kernel HIP-event times)."""
     import torch
-    from paper_2508_21208_amd import workloads as W
     from paper_2508_21208_amd.dgswe import DGSWE_MIXED, Batch, dgswe_profile, dgswe_profile_read
-    t0 = time.perf_counter()
-    ens = W.cfg_ensemble()
     ne = sum(w.mesh.n_elems for w in ens)
-    log(f"batched: {len(ens)} members, {ne} elements, generated in {time.perf_counter() - t0:.1f} s")
     t0 = time.perf_counter()
     b = Batch([w.mesh for w in ens], dict(ens[0].params, precision=DGSWE_MIXED), [w.forcing for w in ens],
               hip_stream=stream.cuda_stream)
@@ -328,6 +324,38 @@ def measure_batched(steps, warmup, stream, profile):
     log(f"batched: timed {steps} steps in {elapsed:.4f} s; member times {min(ts):.1f}-{max(ts):.1f} s")
     kernels = {k: {"avg_us": 1e3 * ms / n, "launches": n, "total_ms": ms} for k, (ms, n) in prof.items() if n}
     return elapsed, ne, len(ens), kernels
+
+
+def measure_ensemble_orders(ens, steps, warmup, stream):
+    """The same ensemble with seeded orders p in {1, 2} per member, mixed
+    precision, 6-step graphs (dgswe.Ensemble: one batch per order)."""
+    import torch
+    from paper_2508_21208_amd import workloads as W
+    from paper_2508_21208_amd.dgswe import DGSWE_MIXED, Ensemble
+    orders = W.ensemble_orders(len(ens))
+    ne = {p: sum(w.mesh.n_elems for w, o in zip(ens, orders) if o == p) for p in (1, 2)}
+    t0 = time.perf_counter()
+    e = Ensemble([w.mesh for w in ens], orders, dict(ens[0].params, precision=DGSWE_MIXED),
+                 [w.forcing for w in ens], hip_stream=stream.cuda_stream, order_params={2: dict(cfl=0.1)})
+    e.use_graphs(6)
+    for i, w in enumerate(ens):
+        e.set_state(i, w.w0, 0.0, w.postprocess_initial)
+    log(f"ensemble p in {{1, 2}}: {orders.count(1)} p=1 members ({ne[1]} el), {orders.count(2)} p=2 members "
+        f"({ne[2]} el), ready in {time.perf_counter() - t0:.1f} s")
+    e.step(warmup)
+    e.diagnostics(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ts = [e.diagnostics(i)["t"] for i in range(len(ens))]
+    e.close()
+    log(f"ensemble p in {{1, 2}}: timed {steps} steps in {elapsed:.4f} s; member times {min(ts):.1f}-{max(ts):.1f} s")
+    return {"value": 2 * (ne[1] + ne[2]) * steps / elapsed, "unit": "elem-stage/s", "precision": "mixed",
+            "members_p1": orders.count(1), "members_p2": orders.count(2), "n_elems_p1": ne[1], "n_elems_p2": ne[2],
+            "ms_per_step": 1e3 * elapsed / steps, "graphs": 6,
+            "note": "element-stages of both orders counted alike; a p = 2 element-stage does about 2.6x the work"}
 
 
 def measure_serving(n_requests, pool_rate_hint, stream):
@@ -509,13 +537,20 @@ def main():
             except DgsweError as ex:
                 variants[name] = {"error": str(ex), **extra}
     if not args.no_batched:
-        el3, ne3, nm3, k3 = measure_batched(args.steps, args.warmup, stream, profile)
+        from paper_2508_21208_amd import workloads as W
+        t0 = time.perf_counter()
+        ens = W.cfg_ensemble()
+        log(f"batched: {len(ens)} members, {sum(w.mesh.n_elems for w in ens)} elements, generated in "
+            f"{time.perf_counter() - t0:.1f} s")
+        el3, ne3, nm3, k3 = measure_batched(ens, args.steps, args.warmup, stream, profile)
         variants["batched"] = {"value": ne3 * 2 * args.steps / el3, "unit": "elem-stage/s",
                                "ms_per_step": 1e3 * el3 / args.steps, "members": nm3, "n_elems": ne3,
                                "precision": "mixed", "roofline": roofline(k3, ne3, 0, 0, "mixed", with_traffic=False),
                                "kernels": k3}
         if k3:
             log("batched kernels: " + json.dumps(k3))
+        variants["batched_p12"] = measure_ensemble_orders(ens, args.steps, args.warmup, stream)
+        del ens
 
     if not args.no_graphs:
         variants["graphs_small_mesh"] = measure_graphs(stream)

@@ -479,6 +479,90 @@ class Batch:
             pass
 
 
+class Ensemble:
+    """Members of both polynomial orders advanced together.  A batch holds
+    one order (its state layout has one mode count per variable), so the
+    ensemble keeps one batch per order present, on the same stream, and
+    steps them in turn: per RK stage one stage launch for all p = 1 members
+    and one pair (post-processing, right-hand side) for all p = 2 members.
+    Member i is meshes[i] at order orders[i]; order_params[p] overrides
+    params for the batch of order p (e.g. a smaller CFL number at p = 2).
+    Each member's result equals its solo run at its order, bitwise."""
+
+    def __init__(self, meshes, orders, params: dict | None = None, forcings=None, hip_stream=None,
+                 order_params: dict | None = None):
+        self.batches = {}
+        self.where = []  # member -> (order, index in that order's batch)
+        meshes = list(meshes)
+        orders = [int(o) for o in orders]
+        if len(orders) != len(meshes) or any(o not in (1, 2) for o in orders):
+            raise DgsweError(1, "one order (1 or 2) per mesh")
+        forcings = list(forcings) if forcings else [None] * len(meshes)
+        count = {1: 0, 2: 0}
+        for o in orders:
+            self.where.append((o, count[o]))
+            count[o] += 1
+        try:
+            for p in (1, 2):
+                idx = [i for i, o in enumerate(orders) if o == p]
+                if idx:
+                    prm = dict(params or {}, **((order_params or {}).get(p, {})), p=p)
+                    self.batches[p] = Batch([meshes[i] for i in idx], prm, [forcings[i] for i in idx],
+                                            hip_stream=hip_stream)
+        except Exception:
+            self.close()
+            raise
+
+    def __len__(self):
+        return len(self.where)
+
+    def _member(self, i):
+        o, j = self.where[i]
+        return self.batches[o], j
+
+    def set_forcing(self, i, f: dict):
+        b, j = self._member(i)
+        b.set_forcing(j, f)
+
+    def set_state(self, i, w, t=0.0, postprocess=False):
+        """w: (3, 3, n_elems) for a p = 1 member, (3, 6, n_elems) for p = 2
+        (a (3, 3, n) state given to a p = 2 member fills the linear modes)."""
+        b, j = self._member(i)
+        w = np.asarray(w, dtype=np.float64)
+        if b.nm == 6 and w.shape[1] == 3:
+            w6 = np.zeros((3, 6, w.shape[2]))
+            w6[:, :3] = w
+            w = w6
+        b.set_state(j, w, t, postprocess)
+
+    def step(self, n=1):
+        for p in sorted(self.batches):
+            self.batches[p].step(n)
+
+    def use_graphs(self, steps_per_graph):
+        for b in self.batches.values():
+            b.use_graphs(steps_per_graph)
+
+    def state(self, i):
+        b, j = self._member(i)
+        return b.state(j)
+
+    def diagnostics(self, i):
+        b, j = self._member(i)
+        return b.diagnostics(j)
+
+    def close(self):
+        for b in self.batches.values():
+            b.close()
+        self.batches = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Pool:
     """A serving pool (dgswe_create_pool): members join and leave between
     steps; a member's state has shape (3, nm, its n_elems)."""

@@ -392,6 +392,13 @@ def cfg_ensemble(n_members=64, n_meshes=8, min_elems=50_000, max_elems=500_000, 
     return out
 
 
+def ensemble_orders(n_members=64, seed=BASE_SEED + 1000 + 999) -> list:
+    """The polynomial order of each ensemble member: 1 or 2 with equal
+    probability, seeded."""
+    rng = np.random.default_rng(seed)
+    return [int(x) for x in rng.integers(1, 3, size=n_members)]
+
+
 @dataclass
 class Request:
     """One solve request of the serving workload: a mesh, its forcing and

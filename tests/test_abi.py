@@ -156,3 +156,14 @@ def test_prepare_mesh_and_pool_validation_on_host():
     assert L.dgswe_member_remove(None, 0) == 1
     assert L.dgswe_prepared_elems(None) == 0
     L.dgswe_prepared_free(None)
+
+
+def test_ensemble_order_validation_before_device_work():
+    m = W.rect_mesh(3, 2, 3.0, 2.0)
+    with pytest.raises(D.DgsweError) as ei:
+        D.Ensemble([m, m], [1], {})
+    assert ei.value.status == 1
+    with pytest.raises(D.DgsweError):
+        D.Ensemble([m], [3], {})
+    orders = W.ensemble_orders()
+    assert len(orders) == 64 and set(orders) == {1, 2} and orders == W.ensemble_orders()
