@@ -8,17 +8,20 @@
  *     with bathymetry h_b positive downward and H = zeta + h_b
  *     (Sec. 2.1, Eq. SWE; Sec. 2.2, Eq. cons_form);
  *   - element weak form with a numerical flux coupling neighbours
- *     (Sec. 2.2, Eq. elem_weak_form), local Lax-Friedrichs flux;
- *   - p = 1 orthogonal Dubiner modal basis, diagonal mass matrix
- *     (Sec. 2.2, Eq. dubiner);
+ *     (Sec. 2.2, Eq. elem_weak_form): local Lax-Friedrichs, or Roe's flux
+ *     on edges wet on both sides (the two fluxes the paper names);
+ *   - orthogonal Dubiner modal basis, diagonal mass matrix, p = 1 (the
+ *     paper's) or p = 2 (Sec. 2.2, Eq. dubiner);
  *   - explicit SSP Runge-Kutta time stepping of the semi-discrete system
- *     (Sec. 2.2, Eq. RKSSP), here SSP-RK(2,2), each stage followed by a
- *     slope limiter and wetting/drying;
+ *     (Sec. 2.2, Eq. RKSSP): SSP-RK(2,2) by default, SSP-RK(3,3) and the
+ *     optimal SSP-RK(s,2), s = 3..5; each stage followed by a slope limiter
+ *     (face-neighbour or vertex-based) and wetting/drying;
  *   - boundaries: land (no normal flow) and ocean (prescribed tidal
  *     elevation) (Sec. 2.1 boundary partition; Sec. 6.1 tidal forcing);
  *   - sources: bathymetric slope, Manning bottom friction, wind stress and
- *     atmospheric pressure gradient (Sec. 2.1 source list), the latter from
- *     a moving Holland parametric hurricane or static nodal fields.
+ *     atmospheric pressure gradient, Coriolis, rain (Sec. 2.1 source list),
+ *     the wind and pressure from a moving Holland parametric hurricane or
+ *     static nodal fields.
  *
  * Conventions shared by every entry point:
  *   - Element vertices are counter-clockwise; local edge l of an element lies
