@@ -366,6 +366,22 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   const R dpx = pm1 * g1x + pm2 * g2x, dpy = pm1 * g1y + pm2 * g2y;
   const R man = manning_of(m, k, i, (QT)0);
 
+  // the edges' codes, neighbours, length/type records and the neighbours'
+  // wet flags, fetched before the area integrals so that the edge loop does
+  // not wait for them
+  int ecode[3], enb[3];
+  for (int l = 0; l < 3; ++l) {
+    ecode[l] = m.e2edge[(size_t)l * ne + e];
+    enb[l] = m.el_nb[(size_t)l * ne + e];
+  }
+  bool owv[3];
+  double2 ebv[3];
+  for (int l = 0; l < 3; ++l) {
+    const int o = enb[l] >= 0 ? enb[l] : e;
+    owv[l] = p.wetdry ? (u[o].z[0] + m.hmean[o] > p.h0) : true;
+    ebv[l] = m.ed2b[ecode[l] >> 1];
+  }
+
   // area part: rz[k] = (1/A) sum_q w_q A grad phi_k . F_zeta (FP64 sums of
   // R terms), rq[v][k] likewise for the momentum rows with the sources
   double rz[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -441,16 +457,16 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   const double zb = tide ? tide_level(F, ts) : 0.0;
 #pragma unroll 1
   for (int l = 0; l < 3; ++l) {
-    const int code = m.e2edge[(size_t)l * ne + e];
+    const int code = ecode[l];
     const int d = code >> 1;
     const bool minus = (code & 1) != 0;
-    const double2 en = m.ed2a[d], eb = m.ed2b[d];
+    const double2 en = m.ed2a[d], eb = ebv[l];
     const uint32_t info = info_bits(eb.y);
     const int lp = info & 3, lm = (info >> 2) & 3, type = (int)(info >> 4) & 3;
-    const int f = m.el_nb[(size_t)l * ne + e];
+    const int f = enb[l];
     // the other element (itself on a boundary edge, which has no e- side)
     const int o = f >= 0 ? f : e;
-    const bool owet = p.wetdry ? (u[o].z[0] + m.hmean[o] > p.h0) : true;
+    const bool owet = owv[l];
     // bathymetry at the edge ends (s = -1: vertex lp+1 of e+, which is
     // vertex lm+2 of e-; s = +1: vertex lp+2 of e+, vertex lm+1 of e-)
     const int va = minus ? (lm == 0 ? 2 : lm - 1) : (lp == 2 ? 0 : lp + 1);
