@@ -254,7 +254,7 @@ def cpu_baseline(wl, target_s=12.0):
                       f"{secs:.1f} s, OpenMP threads={threads}"}
 
 
-def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, forcing=None):
+def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, forcing=None, keep=None):
     """Create the solver on `stream`, warm up, time `steps` steps with the
     stream synchronised on both sides; returns (elapsed s, solver info,
     per-kernel HIP-event times, diagnostics).  order 2: p = 2 with CFL 0.1,
@@ -286,6 +286,8 @@ def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, 
     if profile:
         dgswe_profile(s.h, 0)
     d = s.diagnostics()
+    if keep is not None:
+        keep["state"] = s.state()  # after the timed region
     s.close()
     log(f"{precision}: timed {steps} steps in {elapsed:.4f} s; t={d['t']:.2f} s, dt={d['dt_last']:.4f}, "
         f"wet={d['n_wet']} dry={d['n_dry']}")
@@ -294,6 +296,18 @@ def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, 
         if n:
             kernels[k] = {"avg_us": 1e3 * ms / n, "launches": n, "total_ms": ms}
     return elapsed, info, kernels, d
+
+
+def mixed_error(wm, wf):
+    """The mixed-precision state against the FP64 one after the same steps
+    (the FP64 path equals the FP64 oracle to 1e-12, tested at this size):
+    largest vertex elevation difference, largest element-mean depth and
+    momentum differences, relative L2 per variable."""
+    V = np.array([[1.0, -1.0, -1.0], [1.0, 1.0, -1.0], [1.0, 0.0, 2.0]])
+    dz = np.abs(V @ (wm[0] - wf[0])).max()
+    rel = [float(np.linalg.norm(wm[v] - wf[v]) / max(np.linalg.norm(wf[v]), 1e-300)) for v in range(3)]
+    return {"zeta_vertex_max_m": float(dz), "zeta_mean_max_m": float(np.abs(wm[0, 0] - wf[0, 0]).max()),
+            "q_mean_max_m2s": float(np.abs(wm[1:, 0] - wf[1:, 0]).max()), "rel_l2": rel}
 
 
 def measure_batched(ens, steps, warmup, stream, profile):
@@ -492,7 +506,9 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     profile = not args.no_profile
-    elapsed, info, kernels, d = measure(wl, args.precision, args.steps, args.warmup, stream, profile)
+    kept = {}
+    elapsed, info, kernels, d = measure(wl, args.precision, args.steps, args.warmup, stream, profile,
+                                        keep=None if args.no_mixed else kept)
     ne, ned, nn = info["n_elems"], info["n_edges"], info["n_nodes"]
     rate = ne * 2 * args.steps / elapsed
     roof = roofline(kernels, ne, ned, nn, args.precision)
@@ -501,10 +517,17 @@ def main():
     variants = {}
     other = "mixed" if args.precision == "fp64" else "fp64"
     if not args.no_mixed:
-        el2, _, k2, d2 = measure(wl, other, args.steps, args.warmup, stream, profile)
+        kept2 = {}
+        el2, _, k2, d2 = measure(wl, other, args.steps, args.warmup, stream, profile, keep=kept2)
+        err = mixed_error(kept2["state"], kept["state"]) if other == "mixed" else \
+            mixed_error(kept["state"], kept2["state"])
+        kept.clear()
+        kept2.clear()
+        log(f"mixed vs fp64 after {args.warmup + args.steps} steps: " + json.dumps(err))
         variants[other] = {"value": ne * 2 * args.steps / el2, "unit": "elem-stage/s",
                            "ms_per_step": 1e3 * el2 / args.steps, "roofline": roofline(k2, ne, ned, nn, other),
-                           "kernels": k2, "t_end": d2["t"]}
+                           "kernels": k2, "t_end": d2["t"], "t_end_" + args.precision: d["t"],
+                           "error_vs_fp64": err}
         if k2:
             log(f"{other} kernels: " + json.dumps(k2))
     if not args.no_p2:
