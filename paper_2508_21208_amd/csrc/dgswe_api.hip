@@ -144,6 +144,11 @@ struct dgswe_solver {
   Arena arena[A_COUNT];
   int chunk_cap = 0;            // capacity of the chunk-record array
   bool is_pool = false;         // members may join and leave
+  // the nodal forcing buffer holds the forcing at the time the next step
+  // starts (the last stage of the previous step ran at t + 1.0 dt, which is
+  // that time bit for bit); cleared by anything that changes times or fields
+  bool forcing_fresh = false;
+  bool forcing_every_stage = false;  // DGSWE_FORCING_EVERY_STAGE=1: never reuse
   size_t dev_bytes = 0;         // device memory held
   std::vector<MemberHost> mh;
   std::vector<Member> mem;      // host mirror of the device member table
@@ -218,6 +223,7 @@ hipError_t upload(dgswe_solver *S, const T **dst, const std::vector<T> &v) {
 }
 
 void drop_graphs(dgswe_solver *S) {
+  S->forcing_fresh = false;
   for (hipGraphExec_t &g : S->graph) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
@@ -373,6 +379,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
     S->own_stream = true;
   }
   S->uprm = *prm;
+  if (const char *ev = std::getenv("DGSWE_FORCING_EVERY_STAGE")) S->forcing_every_stage = std::atoi(ev) != 0;
   S->precision = prm->precision;
   S->order = prm->p;
   S->nm = prm->p == 2 ? 6 : 3;
@@ -802,6 +809,7 @@ dgswe_status set_state_impl(dgswe_solver *S, int32_t member, double t, const dou
   // The stored state is post-processed by the first stage that reads it; a
   // state given without post-processing is marked as already done.
   h.cur_is_pp = postprocess == 0;
+  S->forcing_fresh = false;
   e = launch_init_state(S->m, S->s, S->prm, S->s.buf[S->cur], member, f.e0, f.ne, t, (int)(S->steps_enq & 1),
                         postprocess ? 1 : 0, S->precision, S->order, S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "init kernel");
@@ -824,6 +832,7 @@ dgswe_status set_forcing_impl(dgswe_solver *S, int32_t member, const dgswe_forci
   const size_t ne = (size_t)h.ne, nn = (size_t)h.nn, NN = (size_t)S->m.nn, NE = (size_t)S->m.ne;
   hipError_t e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+  S->forcing_fresh = false;
   f.n_tide = fr->n_tide;
   for (int i = 0; i < kMaxTide; ++i) {
     const bool on = i < fr->n_tide;
@@ -947,6 +956,10 @@ dgswe_status enqueue_steps(dgswe_solver *S, int32_t n_steps) {
   const int want_dt = (p.dt_fixed > 0.0) ? 0 : 1;
   StageCoef sc[5];
   const int ns = rk_stages(S->uprm.rk, sc);
+  // a captured graph may be replayed after the forcing changed: it always
+  // computes its first stage's forcing
+  bool fresh = S->forcing_fresh && !S->capturing;
+  const bool reuse = sc[ns - 1].c == 1.0 && !S->forcing_every_stage;
   for (int i = 0; i < n_steps; ++i) {
     const int slot = (int)(S->steps_enq & 1);
     // buffers: stage k reads buf[(cur + k) % 3] and writes buf[(cur + k + 1)
@@ -957,7 +970,7 @@ dgswe_status enqueue_steps(dgswe_solver *S, int32_t n_steps) {
     for (int stage = 0; stage < ns && e == hipSuccess; ++stage) {
       void *in = st.buf[(cur + stage) % 3], *out = st.buf[(cur + stage + 1) % 3];
       const int wd = sc[stage].last ? want_dt : 0;
-      if (S->nfblk > 0) {
+      if (S->nfblk > 0 && !(stage == 0 && fresh)) {
         Timed t(S, K_FORCING);
         e = launch_forcing(m, st, p, S->nfblk, slot, sc[stage].c, S->stream);
       }
@@ -989,7 +1002,9 @@ dgswe_status enqueue_steps(dgswe_solver *S, int32_t n_steps) {
     S->cur = (cur + ns) % 3;
     for (MemberHost &h : S->mh) h.cur_is_pp = false;
     S->steps_enq += 1;
+    fresh = reuse;
   }
+  if (!S->capturing) S->forcing_fresh = fresh;
   return DGSWE_OK;
 }
 
@@ -1026,6 +1041,11 @@ dgswe_status graph_steps(dgswe_solver *S) {
   hipError_t e = hipGraphLaunch(S->graph[key], S->stream);
   if (e != hipSuccess) return hip_fail(S, e, "hipGraphLaunch");
   for (MemberHost &h : S->mh) h.cur_is_pp = false;
+  {
+    StageCoef sc[5];
+    const int ns = rk_stages(S->uprm.rk, sc);
+    S->forcing_fresh = sc[ns - 1].c == 1.0 && !S->forcing_every_stage;
+  }
   S->steps_enq += S->graph_steps;
   return DGSWE_OK;
 }
