@@ -141,6 +141,19 @@ typedef struct {
  * waves=0. */
 void dgswe_default_params(dgswe_params *p);
 
+/* Environment variables read when a solver, batch or pool is created (for
+ * tuning and testing; none of them changes any result, bitwise):
+ *   DGSWE_CHUNK=n          chunk size (64..256), overrides params.chunk;
+ *   DGSWE_BLOCK=n          stage-kernel block size (only 256 is accepted);
+ *   DGSWE_RHS2_WPE=n       p = 2: waves per SIMD the right-hand-side kernel's
+ *                          registers are held to (1..4), overrides
+ *                          params.waves (read once per process, at the
+ *                          first p = 2 step);
+ *   DGSWE_FORCING_EVERY_STAGE=1
+ *                          evaluate the hurricane forcing at every stage
+ *                          instead of reusing the last stage's for the next
+ *                          step's first stage (the same time). */
+
 /* Build a solver for one mesh and allocate its device-resident state.
  * (Sec. 2.2: the triangulation Omega = union of elements; Sec. 2.1: the
  * boundary partition into ocean and land sections.)
