@@ -62,6 +62,11 @@ int prepare_mesh(int nn, const double *xy, const double *hb, int ne, const int *
       return DGSWE_E_MESH;
     }
   }
+  for (int i = 0; i < nn; ++i)
+    if (!std::isfinite(xy[2 * i]) || !std::isfinite(xy[2 * i + 1]) || !std::isfinite(hb[i])) {
+      err = "node " + std::to_string(i) + " has a non-finite coordinate or bathymetry";
+      return DGSWE_E_MESH;
+    }
   for (int64_t i = 0; i < 3LL * ne; ++i)
     if (tri[i] < 0 || tri[i] >= nn) {
       err = "triangle node index out of range";

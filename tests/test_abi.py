@@ -88,6 +88,22 @@ def test_mesh_validation_before_device_work():
     with pytest.raises(D.DgsweError) as ei:
         _create(W.Mesh(m.xy, m.hb, bad, m.bnd, m.bnd_type))
     assert ei.value.status == 2
+    # empty and degenerate input
+    empty = W.Mesh(m.xy, m.hb, np.zeros((0, 3), np.int32), np.zeros((0, 2), np.int32), np.zeros(0, np.int32))
+    with pytest.raises(D.DgsweError) as ei:
+        _create(empty)
+    assert ei.value.status == 1
+    line = W.Mesh(np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0]]), np.ones(3), np.array([[0, 1, 2]], np.int32),
+                  np.array([[0, 1], [1, 2], [2, 0]], np.int32), np.ones(3, np.int32))
+    with pytest.raises(D.DgsweError) as ei:
+        _create(line)  # zero area
+    assert ei.value.status == 2
+    for field in ("xy", "hb"):
+        xy, hb = m.xy.copy(), m.hb.copy()
+        (xy if field == "xy" else hb).flat[4] = np.nan
+        with pytest.raises(D.DgsweError) as ei:
+            _create(W.Mesh(xy, hb, m.tri, m.bnd, m.bnd_type))
+        assert ei.value.status == 2 and "non-finite" in str(ei.value), field
     # an edge shared by three triangles
     t3 = np.concatenate([m.tri, m.tri[:1]], axis=0)
     with pytest.raises(D.DgsweError) as ei:
