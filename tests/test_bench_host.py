@@ -1,0 +1,48 @@
+"""Host-side behaviour of bench.py that needs no GPU: the one-GPU contract
+(--gpus above 1 exits with a message), the algorithmic byte counts the
+roofline uses, and the mixed-precision error report."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_algorithmic_bytes():
+    ne, ned, nn = 4_000_000, 6_000_000, 2_000_000
+    assert bench.algorithmic_bytes("k_stage", ne, ned, nn, "fp64") == 315.0 * ne
+    assert bench.algorithmic_bytes("k_stage", ne, ned, nn, "mixed") == 217.0 * ne
+    assert bench.algorithmic_bytes("k_rhs2", ne, ned, nn, "fp64") == 548.0 * ne
+    assert bench.algorithmic_bytes("k_forcing", ne, ned, nn) == 40.0 * nn
+    assert bench.algorithmic_bytes("k_vbounds", ne, ned, nn, "fp64") == 56.0 * nn + 36.0 * ne
+
+
+def test_roofline_fraction_from_kernel_times():
+    kernels = {"k_stage": {"avg_us": 400.0, "launches": 10, "total_ms": 4.0},
+               "k_forcing": {"avg_us": 30.0, "launches": 5, "total_ms": 0.15}}
+    r = bench.roofline(kernels, 1_000_000, 1_500_000, 500_000, "fp64", with_traffic=False)
+    assert r["kernel"] == "k_stage" and r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["achieved"] - 315e6 / 400e-6 / 1e9) < 0.1
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
+
+
+def test_mixed_error_report():
+    rng = np.random.default_rng(1)
+    wf = rng.normal(size=(3, 3, 50))
+    wm = wf.copy()
+    wm[0, 2, 7] += 1e-6  # mode 2 of zeta: vertex values change by -1e-6, -1e-6, +2e-6
+    e = bench.mixed_error(wm, wf)
+    assert abs(e["zeta_vertex_max_m"] - 2e-6) < 1e-15 and e["zeta_mean_max_m"] == 0.0 and e["q_mean_max_m2s"] == 0.0
