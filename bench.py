@@ -298,6 +298,31 @@ def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, 
     return elapsed, info, kernels, d
 
 
+def measure_host_roundtrip(wl, steps, stream):
+    """The same FP64 solve with the state handed over through host memory
+    (the boundary's dgswe_set_state / dgswe_read_state, i.e. PCIe and the
+    host-side reordering into the caller's element order): elapsed seconds
+    of upload, steps and read-back."""
+    import torch
+    from paper_2508_21208_amd.dgswe import Solver
+    s = Solver(wl.mesh, dict(wl.params), wl.forcing, hip_stream=stream.cuda_stream)
+    s.set_state(wl.w0, 0.0, wl.postprocess_initial)  # warm-up of every path
+    s.step(2)
+    s.state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_state(wl.w0, 0.0, wl.postprocess_initial)
+    t1 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    w = s.state()
+    t3 = time.perf_counter()
+    s.close()
+    del w
+    return {"upload_s": t1 - t0, "steps_s": t2 - t1, "readback_s": t3 - t2, "total_s": t3 - t0}
+
+
 def mixed_error(wm, wf):
     """The mixed-precision state against the FP64 one after the same steps
     (the FP64 path equals the FP64 oracle to 1e-12, tested at this size):
@@ -530,6 +555,12 @@ def main():
                            "error_vs_fp64": err}
         if k2:
             log(f"{other} kernels: " + json.dumps(k2))
+    rt = measure_host_roundtrip(wl, args.steps, stream)
+    variants["host_roundtrip"] = {
+        "value": ne * 2 * args.steps / rt["total_s"], "unit": "elem-stage/s", "precision": "fp64",
+        "note": "state uploaded from and read back to host memory through the C ABI, inside the timed region",
+        **{k: round(v, 4) for k, v in rt.items()}}
+    log("host round trip: " + json.dumps(variants["host_roundtrip"]))
     if not args.no_p2:
         for prec in ("fp64", "mixed"):
             el4, _, k4, d4 = measure(wl, prec, args.steps, args.warmup, stream, profile, order=2)
