@@ -172,8 +172,9 @@ struct dgswe_solver {
   int order = 1;                // polynomial degree p
   int nm = 3;                   // modes per variable
   std::string err = "no error";
-  std::vector<double> stage_buf;
-  std::vector<unsigned char> stage_raw;
+  // pinned host staging for state uploads and read-backs (grown on demand)
+  void *stage_in = nullptr, *stage_out = nullptr;
+  size_t stage_in_bytes = 0, stage_out_bytes = 0;
   // step graphs: G steps captured once per (buffer rotation, step parity)
   // and replayed; dropped whenever the launch tables change
   int graph_steps = 0;
@@ -232,6 +233,10 @@ void drop_graphs(dgswe_solver *S) {
 
 void free_all(dgswe_solver *S) {
   drop_graphs(S);
+  if (S->stage_in) (void)hipHostFree(S->stage_in);
+  if (S->stage_out) (void)hipHostFree(S->stage_out);
+  S->stage_in = S->stage_out = nullptr;
+  S->stage_in_bytes = S->stage_out_bytes = 0;
   for (void *p : S->allocs) (void)hipFree(p);
   S->allocs.clear();
   if (S->rb) (void)hipFree(S->rb);
@@ -243,6 +248,46 @@ void free_all(dgswe_solver *S) {
   S->pool.clear();
   if (S->own_stream && S->stream) (void)hipStreamDestroy(S->stream);
   S->stream = nullptr;
+}
+
+// A pinned host buffer of at least `bytes` (kept and grown across calls).
+hipError_t pinned(void *&buf, size_t &have, size_t bytes) {
+  if (have >= bytes) return hipSuccess;
+  if (buf) (void)hipHostFree(buf);
+  buf = nullptr;
+  have = 0;
+  const hipError_t e = hipHostMalloc(&buf, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) have = bytes;
+  return e;
+}
+
+// f(j) for every plane j < nplanes of a state of ne elements; large states
+// spread the planes over host threads (the permutation between the caller's
+// and the internal element order is a gather over the whole plane).
+template <class F>
+void for_planes(size_t nplanes, size_t ne, F &&f) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nt = ne < 65536 ? 1 : std::min({nplanes, hw, (size_t)16});
+  if (nt > 1) {
+    std::vector<std::thread> th;
+    try {
+      for (size_t t = 0; t < nt; ++t)
+        th.emplace_back([&f, t, nt, nplanes] {
+          for (size_t j = t; j < nplanes; j += nt) f(j);
+        });
+    } catch (...) {
+      // no threads to be had: the planes not started run here (each plane
+      // is written by one thread only)
+      const size_t started = th.size();
+      for (std::thread &x : th) x.join();
+      for (size_t t = started; t < nt; ++t)
+        for (size_t j = t; j < nplanes; j += nt) f(j);
+      return;
+    }
+    for (std::thread &x : th) x.join();
+    return;
+  }
+  for (size_t j = 0; j < nplanes; ++j) f(j);
 }
 
 bool validate_params(const dgswe_params *p, std::string &msg) {
@@ -780,19 +825,23 @@ dgswe_status set_state_impl(dgswe_solver *S, int32_t member, double t, const dou
   const size_t ne = (size_t)h.ne, NE = (size_t)S->m.ne, nm = (size_t)S->nm;
   const bool mixed = S->precision == DGSWE_MIXED;
   // member-order image: zeta modes FP64, momentum modes FP64 or FP32
-  S->stage_raw.resize(state_bytes(ne, S->precision, S->order));
-  double *z = (double *)S->stage_raw.data();
-  for (size_t j = 0; j < nm; ++j)
-    for (size_t i = 0; i < ne; ++i) z[j * ne + i] = w[j * ne + (size_t)h.perm[i]];
-  if (mixed) {
-    float *q = (float *)(z + nm * ne);
-    for (size_t j = 0; j < 2 * nm; ++j)
-      for (size_t i = 0; i < ne; ++i) q[j * ne + i] = (float)w[(nm + j) * ne + (size_t)h.perm[i]];
-  } else {
-    double *q = z + nm * ne;
-    for (size_t j = 0; j < 2 * nm; ++j)
-      for (size_t i = 0; i < ne; ++i) q[j * ne + i] = w[(nm + j) * ne + (size_t)h.perm[i]];
+  {
+    const hipError_t e0 = pinned(S->stage_in, S->stage_in_bytes, state_bytes(ne, S->precision, S->order));
+    if (e0 != hipSuccess) return hip_fail(S, e0, "hipHostMalloc");
   }
+  double *z = (double *)S->stage_in;
+  const int *perm = h.perm.data();
+  for_planes(3 * nm, ne, [&](size_t j) {
+    if (j < nm) {
+      for (size_t i = 0; i < ne; ++i) z[j * ne + i] = w[j * ne + (size_t)perm[i]];
+    } else if (mixed) {
+      float *q = (float *)(z + nm * ne) + (j - nm) * ne;
+      for (size_t i = 0; i < ne; ++i) q[i] = (float)w[j * ne + (size_t)perm[i]];
+    } else {
+      double *q = z + nm * ne + (j - nm) * ne;
+      for (size_t i = 0; i < ne; ++i) q[i] = w[j * ne + (size_t)perm[i]];
+    }
+  });
   // into the member's range of every mode array of the current buffer
   unsigned char *base = (unsigned char *)S->s.buf[S->cur];
   const size_t qs = mixed ? sizeof(float) : sizeof(double);
@@ -909,12 +958,16 @@ dgswe_status read_state_impl(dgswe_solver *S, int32_t member, double *w_out, dgs
       e = launch_post_only(S->m, S->s, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
                            S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "post-processing kernel");
-    S->stage_buf.resize(nv * ne);
-    e = hipMemcpyAsync(S->stage_buf.data(), S->rb, nv * ne * sizeof(double), hipMemcpyDeviceToHost, S->stream);
+    e = pinned(S->stage_out, S->stage_out_bytes, nv * ne * sizeof(double));
+    if (e != hipSuccess) return hip_fail(S, e, "hipHostMalloc");
+    const double *sb = (const double *)S->stage_out;
+    e = hipMemcpyAsync(S->stage_out, S->rb, nv * ne * sizeof(double), hipMemcpyDeviceToHost, S->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "hipMemcpy");
-    for (size_t j = 0; j < nv; ++j)
-      for (size_t i = 0; i < ne; ++i) w_out[j * ne + (size_t)h.perm[i]] = S->stage_buf[j * ne + i];
+    const int *perm = h.perm.data();
+    for_planes(nv, ne, [&](size_t j) {
+      for (size_t i = 0; i < ne; ++i) w_out[j * ne + (size_t)perm[i]] = sb[j * ne + i];
+    });
   }
   Ctrl c{};
   if (d) {
