@@ -588,3 +588,43 @@ def test_stoker_dam_break_converges():
         del zn
     assert errs[1] < errs[0] and errs[2] < errs[1], errs
     assert errs[2] < 0.05, errs
+
+
+def test_ocean_boundary_closed_form():
+    """Ocean (tidal) boundary, Sec. 2.1 boundary partition and Sec. 6.1
+    tide; reading Z12: ghost state (zeta_b(t), Q+) then LLF.  Still water
+    (zeta = 0, Q = 0) on a flat bed next to the open boundary: the only
+    fluxes are the boundary's, so the domain gains mass at
+    (1/2) lambda zeta_b L and x-momentum at (1/2) p_h(zeta_b) L, with
+    lambda = sqrt(g max(h, h + zeta_b)) (the larger of the two sides' wave
+    speeds), p_h = (g/2) zeta_b (zeta_b + 2 h) and L the open boundary's
+    length; zeta_b(t) = A cos(omega t + phase)."""
+    h, A, L, g = 10.0, 0.3, 4000.0, 9.81
+    m = W.rect_mesh(6, 4, 6000.0, L, hb=h, types=(W.BC_LAND, W.BC_LAND, W.BC_LAND, W.BC_OCEAN))
+    omega = 1.405189e-4
+    ph0 = 0.7
+    f = W.default_forcing(tide_amp=[A], tide_omega=[omega], tide_phase=[ph0])
+    o = O.Oracle(m, W.default_params(limiter=0), f)
+    area = o.geometry()["area"]
+    w = np.zeros((3, 3, o.ne))
+    for t, zb in (((2 * math.pi - ph0) / omega, A), ((math.pi - ph0) / omega, -A)):
+        dw = o.rhs(w, t)
+        lam = math.sqrt(g * (h + max(zb, 0.0)))  # the deeper side's wave speed
+        assert math.isclose(float(np.sum(area * dw[0, 0])), 0.5 * lam * zb * L, rel_tol=1e-12)
+        ph = 0.5 * g * zb * (zb + 2 * h)
+        assert math.isclose(float(np.sum(area * dw[1, 0])), 0.5 * ph * L, rel_tol=1e-12)
+        assert abs(float(np.sum(area * dw[2, 0]))) < 1e-9
+        # only the elements on the open boundary (x = 0) change
+        cen = m.xy[m.tri].mean(axis=1)
+        assert np.all(dw[0, 0][cen[:, 0] > 1000.0] == 0.0)
+    # at a zero crossing of the tide nothing moves
+    t0 = (0.5 * math.pi - ph0) / omega
+    dw = o.rhs(w, t0)
+    assert np.abs(dw).max() < 1e-12
+    # uniform inflow (Qx > 0) at the zero crossing: the ghost state equals
+    # the interior one, so the open boundary passes the physical mass flux
+    # and the domain gains Qx L (the other sides are walls)
+    qx = 0.8
+    w[1, 0] = qx
+    dw = o.rhs(w, t0)
+    assert math.isclose(float(np.sum(area * dw[0, 0])), qx * L, rel_tol=1e-12)
