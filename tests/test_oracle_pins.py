@@ -213,6 +213,14 @@ def test_manning_friction_closed_form():
     assert np.allclose(dw[2, 0, inner], -k * qy, rtol=1e-12)
     assert np.abs(dw[0, :, inner]).max() < 1e-15
     assert np.abs(dw[1:, 1:, inner]).max() < 1e-14
+    # a per-element Manning field: each element with its own n (the caller's
+    # element order)
+    n_e = np.random.default_rng(3).uniform(0.015, 0.035, o.ne)
+    o2 = O.Oracle(m, W.default_params(limiter=0), W.default_forcing(manning_n=0.0, manning_n_elem=n_e))
+    dw2 = o2.rhs(w)
+    k2 = G * n_e[inner] ** 2 * qm / H ** (7.0 / 3.0)
+    assert np.allclose(dw2[1, 0, inner], -k2 * qx, rtol=1e-12)
+    assert np.allclose(dw2[2, 0, inner], -k2 * qy, rtol=1e-12)
 
 
 def test_wind_and_pressure_sources_closed_form():
