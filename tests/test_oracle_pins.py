@@ -636,3 +636,52 @@ def test_ocean_boundary_closed_form():
     w[1, 0] = qx
     dw = o.rhs(w, t0)
     assert math.isclose(float(np.sum(area * dw[0, 0])), qx * L, rel_tol=1e-12)
+
+
+def _two_triangles(h_s, h_wet, h_land, L=100.0):
+    """A square of side L split along SW-NE: element 0 (SW, SE, NE) over a
+    bed reaching h_wet at SE, element 1 (SW, NE, NW) with h_land at NW; the
+    shared edge has h_s at both ends; all sides are walls."""
+    xy = np.array([[0.0, 0.0], [L, 0.0], [L, L], [0.0, L]])
+    hb = np.array([h_s, h_wet, h_s, h_land])
+    tri = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    bnd = np.array([[0, 1], [1, 2], [2, 3], [3, 0]], np.int32)
+    return W.Mesh(xy, hb, tri, bnd, np.full(4, W.BC_LAND, np.int32))
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_wetdry_edge_rule_closed_form(order):
+    """Wet/dry edge rule (reading Z9 with the flux rules of C5): with one
+    side dry, the LLF mass flux (u = 0 on the dry side) decides.  Flat
+    states at rest on the two-triangle mesh, the dry element's mean depth 0:
+    * wet surface higher: the dry element floods; both sides take the LLF
+      flux, mass (1/2) lambda (zeta_wet - zeta_dry) per unit length of the
+      shared edge, lambda = sqrt(g max(H_wet, H_dry)) at the edge;
+    * dry surface higher: no flood; the wet side sees a wall (no mass, the
+      hydrostatic push p_h(zeta_wet) along the normal), the dry side zero."""
+    L = 100.0
+    h_s, h_wet = 1.0, 10.0
+    edge = L * math.sqrt(2.0)
+    area = L * L / 2
+    for h_land, zw in ((-2.0, 0.5), (-20.0, 0.5)):
+        m = _two_triangles(h_s, h_wet, h_land, L)
+        o = O.Oracle(m, W.default_params(limiter=0), W.default_forcing(), order=order)
+        zd = -(2 * h_s + h_land) / 3.0  # dry element: mean depth 0
+        w = np.zeros((3, 3 if order == 1 else 6, 2))
+        w[0, 0, 0] = zw
+        w[0, 0, 1] = zd
+        dw = o.rhs(w)
+        Hw, Hd = zw + h_s, zd + h_s  # depths at the shared edge
+        if zw > zd:
+            lam = math.sqrt(G * max(Hw, Hd))
+            flux = 0.5 * lam * (zw - zd) * edge
+            assert math.isclose(dw[0, 0, 0] * area, -flux, rel_tol=1e-12)
+            assert math.isclose(dw[0, 0, 1] * area, flux, rel_tol=1e-12)
+        else:
+            assert dw[0, 0, 0] == 0.0 and dw[0, 0, 1] == 0.0
+            assert np.all(dw[1:, :, 1] == 0.0)
+            # wet side: the wall's hydrostatic push along the shared edge's
+            # normal (1, -1)/sqrt2 from element 0 to 1, plus the bed-slope
+            # source and the pressure of its own walls: the net x and y
+            # momentum rates are equal and opposite in this symmetric layout
+            assert math.isclose(dw[1, 0, 0], -dw[2, 0, 0], rel_tol=1e-12)
