@@ -208,7 +208,7 @@ dgswe_status dgswe_create_batch(int32_t n_meshes, const dgswe_mesh *meshes, cons
 int32_t dgswe_member_count(const dgswe_solver *s);
 
 /* A serving pool: an empty batch whose members join and leave between
- * dgswe_step calls (continuous batching; the spec serving loop).  The
+ * dgswe_step calls (continuous batching, as in a serving loop).  The
  * device memory is reserved here once: room for max_elems elements in total
  * (with the matching node, halo and edge storage) and max_members member
  * slots.  A joining mesh takes a contiguous range of each store (first
