@@ -38,7 +38,8 @@
  *     caller keeps ownership and may free it when the call returns.  Output
  *     buffers are allocated by the caller.  All device memory is owned by the
  *     solver and released by dgswe_destroy.
- *   - Every call returns a dgswe_status; nothing throws across the boundary.
+ *   - Every call returns a dgswe_status; nothing throws across the boundary
+ *     (a failed host allocation returns DGSWE_E_NOMEM).
  *     On DGSWE_E_INVALID / DGSWE_E_MESH / DGSWE_E_NOMEM the handle (if any)
  *     is left unchanged.  dgswe_last_error gives a message for the last
  *     failed call on a handle.

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <new>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1103,6 +1104,28 @@ dgswe_status graph_steps(dgswe_solver *S) {
   return DGSWE_OK;
 }
 
+// Entry points return a status and never let an exception cross the C ABI:
+// a failed host allocation (std::bad_alloc) becomes DGSWE_E_NOMEM, anything
+// else DGSWE_E_DEVICE, with the message in dgswe_last_error.
+template <class F>
+dgswe_status guard(dgswe_solver *S, F &&f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    try {
+      return fail(S, DGSWE_E_NOMEM, "host allocation failed");
+    } catch (...) {
+      return DGSWE_E_NOMEM;
+    }
+  } catch (...) {
+    try {
+      return fail(S, DGSWE_E_DEVICE, "unexpected host error");
+    } catch (...) {
+      return DGSWE_E_DEVICE;
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1129,72 +1152,95 @@ dgswe_status dgswe_create_mesh(int32_t n_nodes, const double *node_xy, const dou
                                int32_t n_elems, const int32_t *tri, int32_t n_bnd,
                                const int32_t *bnd_nodes, const int32_t *bnd_type,
                                const dgswe_params *prm, void *hip_stream, dgswe_solver **out) {
-  dgswe_mesh d{n_nodes, node_xy, node_hb, n_elems, tri, n_bnd, bnd_nodes, bnd_type};
-  return create_impl(1, &d, prm, hip_stream, out);
+  return guard(nullptr, [&]() -> dgswe_status {
+    dgswe_mesh d{n_nodes, node_xy, node_hb, n_elems, tri, n_bnd, bnd_nodes, bnd_type};
+    return create_impl(1, &d, prm, hip_stream, out);
+  });
 }
 
 dgswe_status dgswe_create_batch(int32_t n_meshes, const dgswe_mesh *meshes, const dgswe_params *prm,
                                 void *hip_stream, dgswe_solver **out) {
-  return create_impl(n_meshes, meshes, prm, hip_stream, out);
+  return guard(nullptr, [&]() -> dgswe_status {
+    return create_impl(n_meshes, meshes, prm, hip_stream, out);
+  });
 }
 
 dgswe_status dgswe_set_state(dgswe_solver *S, double t, const double *w, int32_t postprocess) {
-  dgswe_status st = single(S);
-  return st != DGSWE_OK ? st : set_state_impl(S, 0, t, w, postprocess);
+  return guard(S, [&]() -> dgswe_status {
+    dgswe_status st = single(S);
+    return st != DGSWE_OK ? st : set_state_impl(S, 0, t, w, postprocess);
+  });
 }
 
 dgswe_status dgswe_member_set_state(dgswe_solver *S, int32_t member, double t, const double *w,
                                     int32_t postprocess) {
-  return set_state_impl(S, member, t, w, postprocess);
+  return guard(S, [&]() -> dgswe_status {
+    return set_state_impl(S, member, t, w, postprocess);
+  });
 }
 
 dgswe_status dgswe_set_forcing(dgswe_solver *S, const dgswe_forcing *f) {
-  dgswe_status st = single(S);
-  return st != DGSWE_OK ? st : set_forcing_impl(S, 0, f);
+  return guard(S, [&]() -> dgswe_status {
+    dgswe_status st = single(S);
+    return st != DGSWE_OK ? st : set_forcing_impl(S, 0, f);
+  });
 }
 
 dgswe_status dgswe_member_set_forcing(dgswe_solver *S, int32_t member, const dgswe_forcing *f) {
-  return set_forcing_impl(S, member, f);
+  return guard(S, [&]() -> dgswe_status {
+    return set_forcing_impl(S, member, f);
+  });
 }
 
 dgswe_status dgswe_step(dgswe_solver *S, int32_t n_steps) {
-  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
-  if (n_steps < 0) return fail(S, DGSWE_E_INVALID, "n_steps < 0");
-  if (S->m.nch == 0) return DGSWE_OK;  // no member
-  int32_t left = n_steps;
-  if (S->graph_steps > 0 && !S->prof) {
-    while (left >= S->graph_steps) {
-      dgswe_status st = graph_steps(S);
-      if (st != DGSWE_OK) return st;
-      left -= S->graph_steps;
+  return guard(S, [&]() -> dgswe_status {
+    if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+    if (n_steps < 0) return fail(S, DGSWE_E_INVALID, "n_steps < 0");
+    if (S->m.nch == 0) return DGSWE_OK;  // no member
+    int32_t left = n_steps;
+    if (S->graph_steps > 0 && !S->prof) {
+      while (left >= S->graph_steps) {
+        dgswe_status st = graph_steps(S);
+        if (st != DGSWE_OK) return st;
+        left -= S->graph_steps;
+      }
     }
-  }
-  return enqueue_steps(S, left);
+    return enqueue_steps(S, left);
+  });
 }
 
 dgswe_status dgswe_use_graphs(dgswe_solver *S, int32_t steps_per_graph) {
-  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
-  if (steps_per_graph < 0) return fail(S, DGSWE_E_INVALID, "steps_per_graph < 0");
-  hipError_t e = hipStreamSynchronize(S->stream);
-  if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
-  drop_graphs(S);
-  S->graph_steps = steps_per_graph == 0 ? 0 : (steps_per_graph + 5) / 6 * 6;
-  return DGSWE_OK;
+  return guard(S, [&]() -> dgswe_status {
+    if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+    if (steps_per_graph < 0) return fail(S, DGSWE_E_INVALID, "steps_per_graph < 0");
+    hipError_t e = hipStreamSynchronize(S->stream);
+    if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+    drop_graphs(S);
+    S->graph_steps = steps_per_graph == 0 ? 0 : (steps_per_graph + 5) / 6 * 6;
+    return DGSWE_OK;
+  });
 }
 
 dgswe_status dgswe_read_state(dgswe_solver *S, double *w_out, dgswe_diag *d) {
-  dgswe_status st = single(S);
-  return st != DGSWE_OK ? st : read_state_impl(S, 0, w_out, d);
+  return guard(S, [&]() -> dgswe_status {
+    dgswe_status st = single(S);
+    return st != DGSWE_OK ? st : read_state_impl(S, 0, w_out, d);
+  });
 }
 
 dgswe_status dgswe_member_read_state(dgswe_solver *S, int32_t member, double *w_out, dgswe_diag *d) {
-  return read_state_impl(S, member, w_out, d);
+  return guard(S, [&]() -> dgswe_status {
+    return read_state_impl(S, member, w_out, d);
+  });
 }
 
 void dgswe_destroy(dgswe_solver *S) {
   if (!S) return;
-  if (S->stream) (void)hipStreamSynchronize(S->stream);
-  free_all(S);
+  try {
+    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    free_all(S);
+  } catch (...) {
+  }
   delete S;
 }
 
@@ -1203,31 +1249,35 @@ const char *dgswe_last_error(const dgswe_solver *S) {
 }
 
 dgswe_status dgswe_profile(dgswe_solver *S, int32_t enable) {
-  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
-  dgswe_status st = drain_profile(S);
-  if (st != DGSWE_OK) return st;
-  for (int k = 0; k < K_COUNT; ++k) { S->prof_ms[k] = 0.0; S->prof_n[k] = 0; }
-  S->prof = enable != 0;
-  return DGSWE_OK;
+  return guard(S, [&]() -> dgswe_status {
+    if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+    dgswe_status st = drain_profile(S);
+    if (st != DGSWE_OK) return st;
+    for (int k = 0; k < K_COUNT; ++k) { S->prof_ms[k] = 0.0; S->prof_n[k] = 0; }
+    S->prof = enable != 0;
+    return DGSWE_OK;
+  });
 }
 
 dgswe_status dgswe_profile_read(dgswe_solver *S, int32_t max_kernels, char *names, double *total_ms,
                                 int64_t *launches, int32_t *n_out) {
-  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
-  if (max_kernels < 0 || (max_kernels > 0 && (!names || !total_ms || !launches)) || !n_out)
-    return fail(S, DGSWE_E_INVALID, "bad output buffers");
-  dgswe_status st = drain_profile(S);
-  if (st != DGSWE_OK) return st;
-  int n = 0;
-  for (int k = 0; k < K_COUNT && n < max_kernels; ++k) {
-    std::strncpy(names + 32 * n, kKernelNames[k], 31);
-    names[32 * n + 31] = 0;
-    total_ms[n] = S->prof_ms[k];
-    launches[n] = S->prof_n[k];
-    ++n;
-  }
-  *n_out = n;
-  return DGSWE_OK;
+  return guard(S, [&]() -> dgswe_status {
+    if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+    if (max_kernels < 0 || (max_kernels > 0 && (!names || !total_ms || !launches)) || !n_out)
+      return fail(S, DGSWE_E_INVALID, "bad output buffers");
+    dgswe_status st = drain_profile(S);
+    if (st != DGSWE_OK) return st;
+    int n = 0;
+    for (int k = 0; k < K_COUNT && n < max_kernels; ++k) {
+      std::strncpy(names + 32 * n, kKernelNames[k], 31);
+      names[32 * n + 31] = 0;
+      total_ms[n] = S->prof_ms[k];
+      launches[n] = S->prof_n[k];
+      ++n;
+    }
+    *n_out = n;
+    return DGSWE_OK;
+  });
 }
 
 dgswe_status dgswe_mesh_info(const dgswe_solver *S, int64_t out[4]) {
@@ -1254,50 +1304,54 @@ int32_t dgswe_member_count(const dgswe_solver *S) { return S ? (int32_t)S->mh.si
 
 dgswe_status dgswe_create_pool(int64_t max_elems, int32_t max_members, const dgswe_params *prm, void *hip_stream,
                                dgswe_solver **out) {
-  if (!out) return fail(nullptr, DGSWE_E_INVALID, "out is NULL");
-  *out = nullptr;
-  std::string msg;
-  if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
-  if (max_elems < 1 || max_elems > 0x3fffffffLL || max_members < 1 || max_members > 65536)
-    return fail(nullptr, DGSWE_E_INVALID, "pool capacity out of range");
-  int chunk, block;
-  if (!chunk_config(prm, chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
-  long long cap[A_COUNT];
-  int chunk_cap = 0;
-  pool_caps(max_elems, max_members, prm->p, cap, chunk_cap);
-  dgswe_solver *S = nullptr;
-  dgswe_status st = alloc_solver(prm, block, cap, chunk_cap, max_members, hip_stream, &S);
-  if (st != DGSWE_OK) return st;
-  S->is_pool = true;
-  st = rebuild(S);
-  if (st != DGSWE_OK) {
-    msg = S->err;
-    free_all(S);
-    delete S;
-    return fail(nullptr, st, msg);
-  }
-  *out = S;
-  return DGSWE_OK;
+  return guard(nullptr, [&]() -> dgswe_status {
+    if (!out) return fail(nullptr, DGSWE_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::string msg;
+    if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
+    if (max_elems < 1 || max_elems > 0x3fffffffLL || max_members < 1 || max_members > 65536)
+      return fail(nullptr, DGSWE_E_INVALID, "pool capacity out of range");
+    int chunk, block;
+    if (!chunk_config(prm, chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+    long long cap[A_COUNT];
+    int chunk_cap = 0;
+    pool_caps(max_elems, max_members, prm->p, cap, chunk_cap);
+    dgswe_solver *S = nullptr;
+    dgswe_status st = alloc_solver(prm, block, cap, chunk_cap, max_members, hip_stream, &S);
+    if (st != DGSWE_OK) return st;
+    S->is_pool = true;
+    st = rebuild(S);
+    if (st != DGSWE_OK) {
+      msg = S->err;
+      free_all(S);
+      delete S;
+      return fail(nullptr, st, msg);
+    }
+    *out = S;
+    return DGSWE_OK;
+  });
 }
 
 dgswe_status dgswe_prepare_mesh(const dgswe_mesh *mesh, const dgswe_params *prm, dgswe_prepared **out) {
-  if (!out) return fail(nullptr, DGSWE_E_INVALID, "out is NULL");
-  *out = nullptr;
-  std::string msg;
-  if (!mesh) return fail(nullptr, DGSWE_E_INVALID, "mesh is NULL");
-  if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
-  int chunk, block;
-  if (!chunk_config(prm, chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
-  dgswe_prepared *P = new (std::nothrow) dgswe_prepared();
-  if (!P) return fail(nullptr, DGSWE_E_NOMEM, "host allocation failed");
-  P->order = prm->p;
-  const int rc = prep_one(*mesh, prm->p, chunk, block, P->P, msg);
-  if (rc != DGSWE_OK) {
-    delete P;
-    return fail(nullptr, (dgswe_status)rc, msg);
-  }
-  *out = P;
-  return DGSWE_OK;
+  return guard(nullptr, [&]() -> dgswe_status {
+    if (!out) return fail(nullptr, DGSWE_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::string msg;
+    if (!mesh) return fail(nullptr, DGSWE_E_INVALID, "mesh is NULL");
+    if (!validate_params(prm, msg)) return fail(nullptr, DGSWE_E_INVALID, msg);
+    int chunk, block;
+    if (!chunk_config(prm, chunk, block)) return fail(nullptr, DGSWE_E_INVALID, "unsupported chunk/block configuration");
+    dgswe_prepared *P = new (std::nothrow) dgswe_prepared();
+    if (!P) return fail(nullptr, DGSWE_E_NOMEM, "host allocation failed");
+    P->order = prm->p;
+    const int rc = prep_one(*mesh, prm->p, chunk, block, P->P, msg);
+    if (rc != DGSWE_OK) {
+      delete P;
+      return fail(nullptr, (dgswe_status)rc, msg);
+    }
+    *out = P;
+    return DGSWE_OK;
+  });
 }
 
 void dgswe_prepared_free(dgswe_prepared *P) { delete P; }
@@ -1305,45 +1359,51 @@ void dgswe_prepared_free(dgswe_prepared *P) { delete P; }
 int64_t dgswe_prepared_elems(const dgswe_prepared *P) { return P ? P->P.ne : 0; }
 
 dgswe_status dgswe_member_add_prepared(dgswe_solver *S, dgswe_prepared *P, int32_t *member) {
-  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
-  if (!P || !member) return fail(S, DGSWE_E_INVALID, "prepared mesh or member is NULL");
-  if (!S->is_pool) return fail(S, DGSWE_E_INVALID, "members join only a pool (dgswe_create_pool)");
-  if (P->order != S->order) return fail(S, DGSWE_E_INVALID, "the mesh was prepared for another order p");
-  int slot = -1;
-  for (size_t i = 0; i < S->mh.size(); ++i)
-    if (!S->mh[i].active) { slot = (int)i; break; }
-  if (slot < 0) return fail(S, DGSWE_E_NOMEM, "every member slot is taken");
-  hipError_t e = hipStreamSynchronize(S->stream);
-  if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
-  dgswe_status st = place_member(S, slot, P->P);
-  if (st != DGSWE_OK) return st;
-  delete P;
-  st = rebuild(S);
-  if (st != DGSWE_OK) return st;
-  *member = slot;
-  return DGSWE_OK;
+  return guard(S, [&]() -> dgswe_status {
+    if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+    if (!P || !member) return fail(S, DGSWE_E_INVALID, "prepared mesh or member is NULL");
+    if (!S->is_pool) return fail(S, DGSWE_E_INVALID, "members join only a pool (dgswe_create_pool)");
+    if (P->order != S->order) return fail(S, DGSWE_E_INVALID, "the mesh was prepared for another order p");
+    int slot = -1;
+    for (size_t i = 0; i < S->mh.size(); ++i)
+      if (!S->mh[i].active) { slot = (int)i; break; }
+    if (slot < 0) return fail(S, DGSWE_E_NOMEM, "every member slot is taken");
+    hipError_t e = hipStreamSynchronize(S->stream);
+    if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+    dgswe_status st = place_member(S, slot, P->P);
+    if (st != DGSWE_OK) return st;
+    delete P;
+    st = rebuild(S);
+    if (st != DGSWE_OK) return st;
+    *member = slot;
+    return DGSWE_OK;
+  });
 }
 
 dgswe_status dgswe_member_add(dgswe_solver *S, const dgswe_mesh *mesh, int32_t *member) {
-  if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
-  dgswe_prepared *P = nullptr;
-  dgswe_status st = dgswe_prepare_mesh(mesh, &S->uprm, &P);
-  if (st != DGSWE_OK) return fail(S, st, g_create_error);
-  st = dgswe_member_add_prepared(S, P, member);
-  if (st != DGSWE_OK) dgswe_prepared_free(P);
-  return st;
+  return guard(S, [&]() -> dgswe_status {
+    if (!S) return fail(nullptr, DGSWE_E_INVALID, "solver is NULL");
+    dgswe_prepared *P = nullptr;
+    dgswe_status st = dgswe_prepare_mesh(mesh, &S->uprm, &P);
+    if (st != DGSWE_OK) return fail(S, st, g_create_error);
+    st = dgswe_member_add_prepared(S, P, member);
+    if (st != DGSWE_OK) dgswe_prepared_free(P);
+    return st;
+  });
 }
 
 dgswe_status dgswe_member_remove(dgswe_solver *S, int32_t member) {
-  dgswe_status st = check_member(S, member);
-  if (st != DGSWE_OK) return st;
-  if (!S->is_pool) return fail(S, DGSWE_E_INVALID, "members leave only a pool (dgswe_create_pool)");
-  hipError_t e = hipStreamSynchronize(S->stream);
-  if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
-  MemberHost &h = S->mh[(size_t)member];
-  for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(h.off[a], h.len[a]);
-  h = MemberHost{};
-  return rebuild(S);
+  return guard(S, [&]() -> dgswe_status {
+    dgswe_status st = check_member(S, member);
+    if (st != DGSWE_OK) return st;
+    if (!S->is_pool) return fail(S, DGSWE_E_INVALID, "members leave only a pool (dgswe_create_pool)");
+    hipError_t e = hipStreamSynchronize(S->stream);
+    if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
+    MemberHost &h = S->mh[(size_t)member];
+    for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(h.off[a], h.len[a]);
+    h = MemberHost{};
+    return rebuild(S);
+  });
 }
 
 dgswe_status dgswe_pool_usage(const dgswe_solver *S, int64_t out[5]) {
