@@ -57,10 +57,26 @@ def log(msg):
 # Manning n 8 + nodal forcing 12 (0.5 nodes per element) + wet/dry status 2.
 B_ALG_FP64 = 315.0
 # Mixed precision: momentum modes in FP32 (state in 24 + 24, RK base 12 + 12,
-# state out 24 + 24), gradients of the basis 16 + area 8, edge normal and
-# length in FP32 18, Manning n 4; bathymetry, neighbour data, nodal forcing
-# and wet/dry status as in FP64.
-B_ALG_MIXED = 217.0
+# state out 24 + 24), inverse Jacobian and area in FP32 20, edge normal and
+# length in FP32 18, Manning n 4, nodal forcing in FP32 6; bathymetry,
+# neighbour data and wet/dry status as in FP64.  This is the count the
+# roofline fraction uses.
+B_ALG_MIXED = 207.0
+# The mixed path as built keeps the element area (8 B instead of 4) and the
+# nodal forcing (12 B instead of 6) in FP64: 217 B per element-stage,
+# reported beside the 207-B figure.
+B_ALG_MIXED_AS_BUILT = 217.0
+# Context only (not a target, other hardware and precision): the paper's
+# AREA + EDGE + GATHER kernels on one H100 (GH200, 4 TB/s HBM3) in FP32 on
+# its 6,675,517-triangle mesh: per-launch FLOP counts over the achieved
+# FLOP rates give 2.15 + 6.12 + 1.00 = 9.27 ms per stage, i.e. about
+# 7.2e8 element-stage updates/s for those three kernels alone (no wet/dry,
+# limiter, wind or RK update).
+PAPER_CONTEXT = {"value": 7.2e8, "unit": "elem-stage/s", "precision": "fp32",
+                 "hardware": "NVIDIA H100 96 GB HBM3, 4 TB/s (GH200 node), one GPU",
+                 "workload": "Hurricane Harvey on the 6,675,517-triangle TX2008 mesh, p=1",
+                 "covers": "AREA + EDGE + GATHER kernels only, derived from the paper's per-kernel FLOP counts and "
+                           "measured FLOP rates (Sec. 6.2); context, not a target"}
 
 
 # p = 2, per element and launch (averaged over the two stages), every array
@@ -233,32 +249,67 @@ def summarize_pmc(pmc_dir: str, stats_csv: str | None, out_md: str | None):
                                    "and HBM traffic", ("k_pp2", "k_rhs2"))))
 
 
-def cpu_baseline(wl, target_s=12.0):
-    """The FP64 oracle on the same mesh and forcing, on the host cores."""
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo, as lscpu shows it)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of this process (the oracle's runtime)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except (OSError, AttributeError):
+        return False
+
+
+def cpu_baseline(wl, steps=50, single_s=8.0):
+    """The FP64 oracle as it stands on the same mesh and forcing: `steps`
+    steps on all the host threads OpenMP is given, then a bounded sample on
+    one thread."""
     from oracle.oracle import Oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     o = Oracle(wl.mesh, wl.params, wl.forcing)
     o.set_state(wl.w0, 0.0, wl.postprocess_initial)
-    t0 = time.perf_counter()
     o.step(1)
-    t1 = time.perf_counter() - t0
-    more = max(0, min(50, int(target_s / max(t1, 1e-3)) - 1))
     t0 = time.perf_counter()
-    if more:
-        o.step(more)
-    t2 = time.perf_counter() - t0
-    steps, secs = (more, t2) if more else (1, t1)
+    o.step(steps)
+    secs = time.perf_counter() - t0
     rate = wl.mesh.n_elems * 2 * steps / secs
-    return {"value": rate, "unit": "elem-stage/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} steps of the same {wl.mesh.n_elems}-element workload after 1 untimed step, "
-                      f"{secs:.1f} s, OpenMP threads={threads}"}
+    out = {"value": rate, "unit": "elem-stage/s", "cores": threads, "kind": "oracle", "cpu": cpu_model(),
+           "logical_cpus": os.cpu_count(),
+           "sample": f"{steps} steps of the same {wl.mesh.n_elems}-element workload after 1 untimed step, "
+                     f"{secs:.1f} s, OpenMP threads={threads}"}
+    if _omp_threads(1):
+        t0 = time.perf_counter()
+        o.step(1)
+        t1 = time.perf_counter() - t0
+        n1 = max(0, int(single_s / max(t1, 1e-3)) - 1)
+        t0 = time.perf_counter()
+        if n1:
+            o.step(n1)
+        t2 = time.perf_counter() - t0
+        n_1, s_1 = (n1, t2) if n1 else (1, t1)
+        _omp_threads(threads)
+        out["single_thread"] = {"value": wl.mesh.n_elems * 2 * n_1 / s_1, "unit": "elem-stage/s",
+                                "sample": f"{n_1} steps after 1 untimed step on one thread, {s_1:.1f} s"}
+    return out
 
 
-def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, forcing=None, keep=None):
-    """Create the solver on `stream`, warm up, time `steps` steps with the
-    stream synchronised on both sides; returns (elapsed s, solver info,
-    per-kernel HIP-event times, diagnostics).  order 2: p = 2 with CFL 0.1,
-    starting from the p = 1 initial state with zero quadratic modes."""
+def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, forcing=None, keep=None, repeats=1):
+    """Create the solver on `stream`, warm up, then `repeats` times time
+    `steps` steps with the stream synchronised on both sides; returns (median
+    elapsed s, solver info, per-kernel HIP-event times over all repeats,
+    diagnostics, every elapsed s).  order 2: p = 2 with CFL 0.1, starting
+    from the p = 1 initial state with zero quadratic modes."""
     import torch
     from paper_2508_21208_amd.dgswe import DGSWE_FP64, DGSWE_MIXED, Solver, dgswe_profile, dgswe_profile_read
     prm = dict(wl.params, precision=DGSWE_MIXED if precision == "mixed" else DGSWE_FP64)
@@ -277,25 +328,30 @@ def measure(wl, precision, steps, warmup, stream, profile, order=1, extra=None, 
     torch.cuda.synchronize()
     if profile:
         dgswe_profile(s.h, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    runs = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t0)
+    elapsed = float(np.median(runs))
     prof = dgswe_profile_read(s.h) if profile else {}
     if profile:
         dgswe_profile(s.h, 0)
     d = s.diagnostics()
     if keep is not None:
         keep["state"] = s.state()  # after the timed region
+        keep["steps"] = warmup + repeats * steps
     s.close()
-    log(f"{precision}: timed {steps} steps in {elapsed:.4f} s; t={d['t']:.2f} s, dt={d['dt_last']:.4f}, "
+    log(f"{precision}: timed {repeats} x {steps} steps, median {elapsed:.4f} s "
+        f"({', '.join(f'{r:.4f}' for r in runs)}); t={d['t']:.2f} s, dt={d['dt_last']:.4f}, "
         f"wet={d['n_wet']} dry={d['n_dry']}")
     kernels = {}
     for k, (ms, n) in prof.items():
         if n:
             kernels[k] = {"avg_us": 1e3 * ms / n, "launches": n, "total_ms": ms}
-    return elapsed, info, kernels, d
+    return elapsed, info, kernels, d, runs
 
 
 def measure_host_roundtrip(wl, steps, stream):
@@ -333,6 +389,54 @@ def mixed_error(wm, wf):
     rel = [float(np.linalg.norm(wm[v] - wf[v]) / max(np.linalg.norm(wf[v]), 1e-300)) for v in range(3)]
     return {"zeta_vertex_max_m": float(dz), "zeta_mean_max_m": float(np.abs(wm[0, 0] - wf[0, 0]).max()),
             "q_mean_max_m2s": float(np.abs(wm[1:, 0] - wf[1:, 0]).max()), "rel_l2": rel}
+
+
+MIXED_ERROR_FILE = os.path.join(ROOT, "profiles", "mixed_error_vs_oracle.json")
+
+
+def mixed_error_vs_oracle(stream):
+    """Largest elevation error at element vertices and velocity error at
+    element means of the mixed path against the FP64 oracle at the
+    configured horizons.  The 1,600-element Gaussian hump (200 steps) is
+    measured here; the two full-size coastal workloads (600k triangles at
+    2,000 steps, 4M at 1,000) take the oracle minutes, so their figures come
+    from the full-horizon parity tests' report (profiles/, with the kernel
+    sources' hash they were measured on)."""
+    import torch
+    from oracle.oracle import Oracle
+    from paper_2508_21208_amd import workloads as W
+    from paper_2508_21208_amd.dgswe import DGSWE_MIXED, Solver
+    wl = W.cfg_gaussian_1600()
+    s = Solver(wl.mesh, dict(wl.params, precision=DGSWE_MIXED), wl.forcing, hip_stream=stream.cuda_stream)
+    s.set_state(wl.w0, 0.0, wl.postprocess_initial)
+    s.step(wl.steps)
+    wg = s.state()
+    dg = s.diagnostics()
+    s.close()
+    torch.cuda.synchronize()
+    o = Oracle(wl.mesh, wl.params, wl.forcing)
+    o.set_state(wl.w0, 0.0, wl.postprocess_initial)
+    o.step(wl.steps)
+    wo = o.state()
+    V = np.array([[1.0, -1.0, -1.0], [1.0, 1.0, -1.0], [1.0, 0.0, 2.0]])
+    H = wo[0, 0] + wl.mesh.hb[wl.mesh.tri].mean(axis=1)
+    Hg = wg[0, 0] + wl.mesh.hb[wl.mesh.tri].mean(axis=1)
+    ok = H >= 0.5
+    ev = max(float(np.abs(wg[v, 0][ok] / Hg[ok] - wo[v, 0][ok] / H[ok]).max()) for v in (1, 2))
+    out = {"gaussian_1600/mixed": {"steps": wl.steps, "zeta_vertex_max_m": float(np.abs(V @ (wg[0] - wo[0])).max()),
+                                   "velocity_mean_max_ms": ev, "t_end": dg["t"], "t_oracle": o.t,
+                                   "source": "measured by this run"}}
+    try:
+        with open(MIXED_ERROR_FILE) as fh:
+            rec = json.load(fh)
+        same = rec.get("source_sha256") == source_hash()
+        for k, v in rec.get("results", {}).items():
+            if k.endswith("/mixed"):
+                out[k] = dict(v, source="tests/test_full_horizon_gpu.py report in profiles/",
+                              sources_match_this_build=same)
+    except (OSError, ValueError):
+        pass
+    return out
 
 
 def measure_batched(ens, steps, warmup, stream, profile):
@@ -483,9 +587,14 @@ def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
         kb = algorithmic_bytes(k, ne, ned, nn, precision)
         kernels[k]["alg_GBs"] = round(kb / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
     traffic = stored_traffic(dom, precision) if with_traffic else None
-    return {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "bytes_per_launch": int(b), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
+    out = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "bytes_per_launch": int(b), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
+    if dom == "k_stage" and precision == "mixed":
+        b2 = B_ALG_MIXED_AS_BUILT * ne
+        out["as_built"] = {"bytes_per_element_stage": B_ALG_MIXED_AS_BUILT, "bytes_per_launch": int(b2),
+                           "frac": round(b2 / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def main():
@@ -493,6 +602,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of --steps steps each for the headline and mixed lines (the median is reported)")
     ap.add_argument("--elems", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -532,8 +643,8 @@ def main():
     stream = torch.cuda.current_stream(dev)
     profile = not args.no_profile
     kept = {}
-    elapsed, info, kernels, d = measure(wl, args.precision, args.steps, args.warmup, stream, profile,
-                                        keep=None if args.no_mixed else kept)
+    elapsed, info, kernels, d, runs = measure(wl, args.precision, args.steps, args.warmup, stream, profile,
+                                              keep=None if args.no_mixed else kept, repeats=args.repeats)
     ne, ned, nn = info["n_elems"], info["n_edges"], info["n_nodes"]
     rate = ne * 2 * args.steps / elapsed
     roof = roofline(kernels, ne, ned, nn, args.precision)
@@ -543,16 +654,20 @@ def main():
     other = "mixed" if args.precision == "fp64" else "fp64"
     if not args.no_mixed:
         kept2 = {}
-        el2, _, k2, d2 = measure(wl, other, args.steps, args.warmup, stream, profile, keep=kept2)
+        el2, _, k2, d2, runs2 = measure(wl, other, args.steps, args.warmup, stream, profile, keep=kept2,
+                                        repeats=args.repeats)
         err = mixed_error(kept2["state"], kept["state"]) if other == "mixed" else \
             mixed_error(kept["state"], kept2["state"])
         kept.clear()
         kept2.clear()
-        log(f"mixed vs fp64 after {args.warmup + args.steps} steps: " + json.dumps(err))
+        n_cmp = kept2.get("steps")
+        log(f"mixed vs fp64 GPU after {n_cmp} steps: " + json.dumps(err))
         variants[other] = {"value": ne * 2 * args.steps / el2, "unit": "elem-stage/s",
-                           "ms_per_step": 1e3 * el2 / args.steps, "roofline": roofline(k2, ne, ned, nn, other),
+                           "ms_per_step": 1e3 * el2 / args.steps, "runs_ms_per_step": [1e3 * r / args.steps for r in runs2],
+                           "roofline": roofline(k2, ne, ned, nn, other),
                            "kernels": k2, "t_end": d2["t"], "t_end_" + args.precision: d["t"],
-                           "error_vs_fp64": err}
+                           "error_vs_fp64_gpu": dict(err, steps=n_cmp),
+                           "error_vs_oracle": mixed_error_vs_oracle(stream)}
         if k2:
             log(f"{other} kernels: " + json.dumps(k2))
     rt = measure_host_roundtrip(wl, args.steps, stream)
@@ -563,7 +678,7 @@ def main():
     log("host round trip: " + json.dumps(variants["host_roundtrip"]))
     if not args.no_p2:
         for prec in ("fp64", "mixed"):
-            el4, _, k4, d4 = measure(wl, prec, args.steps, args.warmup, stream, profile, order=2)
+            el4, _, k4, d4, _ = measure(wl, prec, args.steps, args.warmup, stream, profile, order=2)
             variants["p2_" + prec] = {"value": ne * 2 * args.steps / el4, "unit": "elem-stage/s", "p": 2,
                                       "precision": prec, "ms_per_step": 1e3 * el4 / args.steps,
                                       "roofline": roofline(k4, ne, ned, nn, prec),
@@ -579,7 +694,8 @@ def main():
                                     ("roe", dict(flux=1), 2, {}), ("vertex_limiter", dict(limiter=2), 2, {}),
                                     ("sources", {}, 2, dict(coriolis=7.29e-5, rain=50e-3 / 3600))):
             try:
-                el5, _, k5, d5 = measure(wl, "fp64", args.steps, args.warmup, stream, profile, extra=extra, forcing=fx)
+                el5, _, k5, d5, _ = measure(wl, "fp64", args.steps, args.warmup, stream, profile, extra=extra,
+                                            forcing=fx)
                 variants[name] = {
                     "value": ne * ns * args.steps / el5, "unit": "elem-stage/s", **extra, **fx, "stages": ns,
                     "ms_per_step": 1e3 * el5 / args.steps, "dt_last": d5["dt_last"],
@@ -638,6 +754,9 @@ def main():
                                f"at 5 m/s, M2 tide, Manning 0.025, wet/dry, SSP-RK2",
                    "n_elems": ne, "n_edges": ned, "n_nodes": nn, "p": 1, "precision": args.precision},
         "roofline": roof, "kernels": kernels, "variants": variants, "cpu_baseline": cpu,
+        "timing": {"repeats": args.repeats, "statistic": "median",
+                   "runs_ms_per_step": [1e3 * r / args.steps for r in runs]},
+        "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(out), flush=True)
 

@@ -235,9 +235,10 @@ int64_t dgswe_prepared_elems(const dgswe_prepared *p);
 /* Admit a prepared mesh into a free slot of a pool (state zero at t = 0, no
  * forcing; then dgswe_member_set_forcing / dgswe_member_set_state).  On
  * success the pool owns `p` (do not free it) and *member receives the slot.
- * Admission is by memory: no free slot or no contiguous room in some store
- * -> DGSWE_E_NOMEM and the pool is unchanged (the caller keeps `p`); `p`
- * prepared for another order p, or `s` not a pool -> DGSWE_E_INVALID.
+ * On any error the pool is unchanged and the caller keeps `p` (free it or
+ * try again later).  Admission is by memory: no free slot or no contiguous
+ * room in some store -> DGSWE_E_NOMEM; `p` prepared for another order p,
+ * or `s` not a pool -> DGSWE_E_INVALID.
  * Waits for the stream (the step tables are rewritten). */
 dgswe_status dgswe_member_add_prepared(dgswe_solver *s, dgswe_prepared *p, int32_t *member);
 
@@ -304,9 +305,10 @@ dgswe_status dgswe_set_forcing(dgswe_solver *s, const dgswe_forcing *f);
 /* dgswe_set_forcing for one member of a batch (arrays sized for its mesh). */
 dgswe_status dgswe_member_set_forcing(dgswe_solver *s, int32_t member, const dgswe_forcing *f);
 
-/* Enqueue n_steps SSP-RK(2,2) steps of every member on the solver's stream
- * and return without waiting (Sec. 2.2, Eq. RKSSP; Sec. 5.2, Algorithms
- * 1-3).  Each step computes its dt on the device, per member: dt_fixed if
+/* Enqueue n_steps time steps of every member, with the SSP Runge-Kutta
+ * scheme params.rk selects (SSPRK(2,2) by default; the list is above), on
+ * the solver's stream and return without waiting (Sec. 2.2, Eq. RKSSP;
+ * Sec. 5.2, Algorithms 1-3).  Each step computes its dt on the device, per member: dt_fixed if
  * > 0, otherwise cfl * min over the member's wet elements of
  * 2 r_e / (|Q_mean|/H_mean + sqrt(g H_mean)) (r_e the inradius), capped by
  * dt_max if > 0.  Errors detected by the kernels (DGSWE_E_NONFINITE,

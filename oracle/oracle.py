@@ -14,20 +14,36 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "dgswe_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_SANITIZE = os.path.join(HERE, "liboracle_asan.so")
+# DGSWE_ORACLE_LIB names another build of the oracle (the sanitizer build)
+LIB_OVERRIDE = os.environ.get("DGSWE_ORACLE_LIB")
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 SOURCE_FN = C.CFUNCTYPE(None, C.c_double, C.c_int32, _dp, _dp, C.c_void_p)
 
 
-def build_oracle(verbose=False) -> str:
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-           "-Wall", "-Wno-unused-function", SRC, "-o", LIB + ".tmp", "-lm"]
+def build_oracle(verbose=False, sanitize=False) -> str:
+    """gcc -O2 -ffp-contract=off -fopenmp.  sanitize=True: liboracle_asan.so,
+    built by clang under AddressSanitizer + UndefinedBehaviorSanitizer (the
+    runtime of the sanitized HIP library's host code) without OpenMP (the
+    oracle's results do not depend on its thread count)."""
+    if sanitize:
+        clang = "/opt/rocm/llvm/bin/clang"
+        out = LIB_SANITIZE
+        cmd = [clang, "-O1", "-g", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-Wall",
+               "-Wno-unused-function", "-Wno-unknown-pragmas", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-shared-libasan", SRC, "-o", out + ".tmp",
+               "-lm"]
+    else:
+        out = LIB
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+               "-Wall", "-Wno-unused-function", SRC, "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 _lib = None
@@ -37,9 +53,12 @@ def load_oracle():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        build_oracle()
-    L = C.CDLL(LIB)
+    if LIB_OVERRIDE:
+        L = C.CDLL(LIB_OVERRIDE)
+    else:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build_oracle()
+        L = C.CDLL(LIB)
     L.or_create.restype = C.c_void_p
     L.or_create.argtypes = [C.c_int32, _dp, _dp, C.c_int32, _ip, C.c_int32, _ip, _ip, _ip]
     L.or_destroy.argtypes = [C.c_void_p]

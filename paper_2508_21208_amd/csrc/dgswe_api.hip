@@ -377,15 +377,32 @@ dgswe_status check_member(dgswe_solver *S, int32_t member) {
   return DGSWE_OK;
 }
 
-// Host preprocessing of one mesh for the solver's order and chunking.
-int prep_one(const dgswe_mesh &d, int order, int chunk, int block, Prep &P, std::string &msg) {
+// Whether the chunks of P fit the p = 1 stage kernel: at most 2 x block
+// local elements (chunk + ring 1) and local edges per chunk (each lane
+// holds two), and the chunk's LDS within kStageLdsMax.
+bool chunks_fit(const Prep &P, int precision, int block) {
+  if (P.nl_max > 2 * block || P.ed_max > 2 * block) return false;
+  DevMesh t{};
+  t.nl_max = P.nl_max; t.nm_max = P.nm_max; t.ed_max = P.ed_max; t.n2_max = P.n2_max; t.C = P.C;
+  return stage_lds_bytes(t, precision) <= kStageLdsMax;
+}
+
+// Host preprocessing of one mesh for the solver's order and chunking.  At
+// p = 1, a mesh whose chunks of `chunk` elements have halos too large for
+// the stage kernel is chunked again with 32 fewer elements per chunk, and
+// so on: at 64 every mesh fits (at most 256 local elements, 192 local
+// edges, about 50 KB of LDS), so no valid mesh is refused.  The p = 2
+// kernels use only the chunk ranges, not the halos.
+int prep_one(const dgswe_mesh &d, int order, int precision, int chunk, int block, Prep &P, std::string &msg) {
   int rc = prepare_mesh(d.n_nodes, d.node_xy, d.node_hb, d.n_elems, d.tri, d.n_bnd, d.bnd_nodes, d.bnd_type, P, msg);
   if (rc != DGSWE_OK) return rc;
-  build_chunks(P, chunk);
-  // (the p = 2 kernels use only the chunk ranges, not the halos)
-  if (order == 1 && (P.nl_max > 2 * block || P.ed_max > 2 * block)) {
-    msg = "element chunks have halos too large for the stage kernel";
-    return DGSWE_E_MESH;
+  for (int c = chunk;; c = std::max(64, c - 32)) {
+    build_chunks(P, c);
+    if (order == 2 || chunks_fit(P, precision, block)) break;
+    if (c == 64) {
+      msg = "element chunks have halos too large for the stage kernel";
+      return DGSWE_E_MESH;
+    }
   }
   if (order == 2) p2_records(P);
   return DGSWE_OK;
@@ -524,7 +541,14 @@ hipError_t put(const T *dst, size_t off, const T *src, size_t n) {
 // Place a prepared mesh into free ranges of every arena as member `slot`
 // (state zero at t = 0, no forcing).  DGSWE_E_NOMEM when some arena has no
 // room; the solver is then unchanged.
-dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
+// Give a member's store ranges back and empty its slot (no table rebuild).
+void release_slot(dgswe_solver *S, int slot) {
+  MemberHost &h = S->mh[(size_t)slot];
+  for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(h.off[a], h.len[a]);
+  h = MemberHost{};
+}
+
+dgswe_status place_member(dgswe_solver *S, int slot, const Prep &q) {
   long long need[A_COUNT], off[A_COUNT];
   arena_need(q, S->order, need);
   for (int a = 0; a < A_COUNT; ++a) {
@@ -539,7 +563,7 @@ dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
     t.nl_max = std::max(t.nl_max, q.nl_max); t.nm_max = std::max(t.nm_max, q.nm_max);
     t.ed_max = std::max(t.ed_max, q.ed_max); t.n2_max = std::max(t.n2_max, q.n2_max);
     t.C = std::max(t.C, q.C);
-    if (stage_lds_bytes(t, S->precision) > 80 * 1024) {
+    if (stage_lds_bytes(t, S->precision) > kStageLdsMax) {
       for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(off[a], need[a]);
       return fail(S, DGSWE_E_MESH, "element chunks have halos too large for the LDS");
     }
@@ -645,7 +669,7 @@ dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
   MemberHost &h = S->mh[(size_t)slot];
   h = MemberHost{};
   h.active = true;
-  h.perm = std::move(q.perm);
+  h.perm = q.perm;  // copied: a prepared mesh stays whole until its admission has succeeded
   h.ne = q.ne; h.nn = q.nn; h.ned = q.ned; h.nbnd = q.nbnd;
   for (int a = 0; a < A_COUNT; ++a) { h.off[a] = off[a]; h.len[a] = need[a]; }
   h.chunks.resize((size_t)q.nch * kChunkHost);
@@ -678,7 +702,10 @@ dgswe_status place_member(dgswe_solver *S, int slot, Prep &q) {
   if (e == hipSuccess)
     e = launch_init_state(S->m, S->s, S->prm, S->s.buf[S->cur], slot, e0, q.ne, 0.0, (int)(S->steps_enq & 1), 0,
                           S->precision, S->order, S->stream);
-  if (e != hipSuccess) return hip_fail(S, e, "member initialisation");
+  if (e != hipSuccess) {
+    release_slot(S, slot);
+    return hip_fail(S, e, "member initialisation");
+  }
   return DGSWE_OK;
 }
 
@@ -770,7 +797,7 @@ dgswe_status create_impl(int32_t n_members, const dgswe_mesh *meshes, const dgsw
     const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     const int nt = (int)std::min<unsigned>(hw, (unsigned)n_members);
     auto work = [&](int t0) {
-      for (int i = t0; i < n_members; i += nt) rcs[i] = prep_one(meshes[i], prm->p, chunk, block, parts[i], msgs[i]);
+      for (int i = t0; i < n_members; i += nt) rcs[i] = prep_one(meshes[i], prm->p, prm->precision, chunk, block, parts[i], msgs[i]);
     };
     std::vector<std::thread> th;
     for (int t = 1; t < nt; ++t) th.emplace_back(work, t);
@@ -1344,7 +1371,7 @@ dgswe_status dgswe_prepare_mesh(const dgswe_mesh *mesh, const dgswe_params *prm,
     dgswe_prepared *P = new (std::nothrow) dgswe_prepared();
     if (!P) return fail(nullptr, DGSWE_E_NOMEM, "host allocation failed");
     P->order = prm->p;
-    const int rc = prep_one(*mesh, prm->p, chunk, block, P->P, msg);
+    const int rc = prep_one(*mesh, prm->p, prm->precision, chunk, block, P->P, msg);
     if (rc != DGSWE_OK) {
       delete P;
       return fail(nullptr, (dgswe_status)rc, msg);
@@ -1372,9 +1399,15 @@ dgswe_status dgswe_member_add_prepared(dgswe_solver *S, dgswe_prepared *P, int32
     if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
     dgswe_status st = place_member(S, slot, P->P);
     if (st != DGSWE_OK) return st;
-    delete P;
     st = rebuild(S);
-    if (st != DGSWE_OK) return st;
+    if (st != DGSWE_OK) {
+      // not admitted after all: the slot is emptied and the caller keeps P
+      const std::string msg = S->err;
+      release_slot(S, slot);
+      (void)rebuild(S);
+      return fail(S, st, msg);
+    }
+    delete P;  // owned by the pool from here on
     *member = slot;
     return DGSWE_OK;
   });
@@ -1399,9 +1432,7 @@ dgswe_status dgswe_member_remove(dgswe_solver *S, int32_t member) {
     if (!S->is_pool) return fail(S, DGSWE_E_INVALID, "members leave only a pool (dgswe_create_pool)");
     hipError_t e = hipStreamSynchronize(S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "hipStreamSynchronize");
-    MemberHost &h = S->mh[(size_t)member];
-    for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(h.off[a], h.len[a]);
-    h = MemberHost{};
+    release_slot(S, member);
     return rebuild(S);
   });
 }

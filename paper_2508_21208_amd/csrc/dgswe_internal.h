@@ -171,13 +171,6 @@ struct Prep {
 // member of each chunk.
 void chunk_records(const Prep &P, const std::vector<int> &chunk_member, std::vector<int> &rec);
 
-// Concatenate the preprocessed meshes of a batch (each after build_chunks
-// with the same C) into one: element, node, chunk, local-element and
-// local-edge ranges follow each other in member order and every stored id
-// is shifted into the batch's index space.  Per-mesh element permutations
-// stay with the parts.
-void merge_meshes(const std::vector<Prep> &parts, Prep &out);
-
 // Split the (Hilbert-ordered) elements into chunks of C and build, per chunk:
 // the ring-1 halo (neighbours outside the chunk), the ring-2 halo
 // (neighbours of ring 1 outside chunk and ring 1), the chunk-local edge list
@@ -238,6 +231,8 @@ hipError_t launch_rhs2(const DevMesh &m, const DevState &s, const Params &p, con
 hipError_t launch_post_only2(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
                              double *wout, int precision, hipStream_t st);
 size_t stage_lds_bytes(const DevMesh &m, int precision);
+// LDS one stage-kernel workgroup may use (two workgroups share a CU's 160 KB)
+constexpr size_t kStageLdsMax = 80 * 1024;
 // bytes of one state buffer: (3 zeta modes FP64 + 6 momentum modes) per
 // element at p = 1, (6 + 12) at p = 2
 size_t state_bytes(size_t ne, int precision, int order);

@@ -373,97 +373,6 @@ void build_chunks(Prep &P, int C) {
 
 namespace dgswe {
 
-void merge_meshes(const std::vector<Prep> &parts, Prep &out) {
-  out = Prep();
-  size_t ne = 0, nn = 0, nch = 0;
-  for (const Prep &q : parts) {
-    ne += (size_t)q.ne;
-    nn += (size_t)q.nn;
-    nch += (size_t)q.nch;
-    out.ned += q.ned;
-    out.nbnd += q.nbnd;
-    out.nl_max = std::max(out.nl_max, q.nl_max);
-    out.nm_max = std::max(out.nm_max, q.nm_max);
-    out.ed_max = std::max(out.ed_max, q.ed_max);
-    out.n2_max = std::max(out.n2_max, q.n2_max);
-  }
-  out.ne = (int)ne;
-  out.nn = (int)nn;
-  out.nch = (int)nch;
-  out.C = parts.empty() ? 0 : parts[0].C;
-  out.area.reserve(ne); out.inr2.reserve(ne);
-  out.hbv.assign(3 * ne, 0.0);
-  out.el_nb.assign(3 * ne, -1);
-  out.node_x.reserve(nn); out.node_y.reserve(nn);
-  out.eg1.reserve(ne); out.eg2.reserve(ne); out.egf.reserve(ne); out.eai.reserve(ne); out.enode.reserve(ne);
-  out.el_edge.assign(3 * ne, -1);
-  out.ed_info.reserve((size_t)out.ned);
-  out.ed_nx.reserve((size_t)out.ned); out.ed_ny.reserve((size_t)out.ned); out.ed_hlen.reserve((size_t)out.ned);
-  out.ch_off.reserve(nch + 1); out.h1_off.reserve(nch + 1); out.h2_off.reserve(nch + 1); out.le_off.reserve(nch + 1); out.lo_off.reserve(nch + 1);
-  int e0 = 0, n0 = 0, h1o = 0, h2o = 0, leo = 0, loo = 0, d0 = 0;
-  for (const Prep &q : parts) {
-    const size_t qne = (size_t)q.ne;
-    // edges (p = 2 records): ids shifted by the edges of earlier parts
-    for (int k = 0; k < 3; ++k)
-      for (size_t e = 0; e < qne; ++e) {
-        const int code = q.el_edge[(size_t)k * qne + e];
-        out.el_edge[(size_t)k * ne + e0 + e] = (((code >> 1) + d0) << 1) | (code & 1);
-      }
-    out.ed_info.insert(out.ed_info.end(), q.ed_info.begin(), q.ed_info.end());
-    out.ed_nx.insert(out.ed_nx.end(), q.ed_nx.begin(), q.ed_nx.end());
-    out.ed_ny.insert(out.ed_ny.end(), q.ed_ny.begin(), q.ed_ny.end());
-    out.ed_hlen.insert(out.ed_hlen.end(), q.ed_hlen.begin(), q.ed_hlen.end());
-    d0 += q.ned;
-    out.area.insert(out.area.end(), q.area.begin(), q.area.end());
-    out.inr2.insert(out.inr2.end(), q.inr2.begin(), q.inr2.end());
-    for (int k = 0; k < 3; ++k)
-      for (size_t e = 0; e < qne; ++e) {
-        out.hbv[(size_t)k * ne + e0 + e] = q.hbv[(size_t)k * qne + e];
-        const int f = q.el_nb[(size_t)k * qne + e];
-        out.el_nb[(size_t)k * ne + e0 + e] = f < 0 ? -1 : f + e0;
-      }
-    out.node_x.insert(out.node_x.end(), q.node_x.begin(), q.node_x.end());
-    out.node_y.insert(out.node_y.end(), q.node_y.begin(), q.node_y.end());
-    out.eg1.insert(out.eg1.end(), q.eg1.begin(), q.eg1.end());
-    out.eg2.insert(out.eg2.end(), q.eg2.begin(), q.eg2.end());
-    out.egf.insert(out.egf.end(), q.egf.begin(), q.egf.end());
-    out.eai.insert(out.eai.end(), q.eai.begin(), q.eai.end());
-    for (const int4 &v : q.enode) out.enode.push_back(make_int4(v.x + n0, v.y + n0, v.z + n0, v.w));
-    for (int c = 0; c < q.nch; ++c) {
-      out.ch_off.push_back(q.ch_off[c] + e0);
-      out.h1_off.push_back(q.h1_off[c] + h1o);
-      out.h2_off.push_back(q.h2_off[c] + h2o);
-      out.le_off.push_back(q.le_off[c] + leo);
-      out.lo_off.push_back(q.lo_off[c] + loo);
-    }
-    // the part's ring-2 list without its sentinel
-    for (int i = 0; i < q.h2_off[q.nch]; ++i) out.h2.push_back(q.h2[i] + e0);
-    for (int g : q.lgid) out.lgid.push_back(g + e0);
-    out.lhb01.insert(out.lhb01.end(), q.lhb01.begin(), q.lhb01.end());
-    out.lhb2.insert(out.lhb2.end(), q.lhb2.begin(), q.lhb2.end());
-    out.lnb.insert(out.lnb.end(), q.lnb.begin(), q.lnb.end());
-    out.le_a.insert(out.le_a.end(), q.le_a.begin(), q.le_a.end());
-    out.le_b.insert(out.le_b.end(), q.le_b.begin(), q.le_b.end());
-    out.le_f.insert(out.le_f.end(), q.le_f.begin(), q.le_f.end());
-    e0 += q.ne;
-    n0 += q.nn;
-    h1o += q.h1_off[q.nch];
-    h2o += q.h2_off[q.nch];
-    leo += q.le_off[q.nch];
-    loo += q.lo_off[q.nch];
-  }
-  out.ch_off.push_back(e0);
-  out.h1_off.push_back(h1o);
-  out.h2_off.push_back(h2o);
-  out.le_off.push_back(leo);
-  out.lo_off.push_back(loo);
-  out.h2.push_back(0);  // sentinel (see build_chunks)
-}
-
-}  // namespace dgswe
-
-namespace dgswe {
-
 void p2_records(Prep &P) {
   const size_t ne = (size_t)P.ne, ned = (size_t)P.ned;
   P.ed2a.resize(ned);

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdgswe.so")
+# DGSWE_LIB names another build of the same library (e.g. the host-code
+# sanitizer build, libdgswe_asan.so)
+LIB_PATH = os.environ.get("DGSWE_LIB") or os.path.join(HERE, "libdgswe.so")
 
 DGSWE_OK = 0
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_MESH", 3: "E_NOMEM", 4: "E_DEVICE",
@@ -585,23 +587,38 @@ class Pool:
         return dgswe_prepare_mesh(mesh, params_from_dict(params))
 
     def add(self, mesh=None, prepared=None, forcing=None, w=None, t=0.0, postprocess=False):
-        """Admit a mesh (or a prepared handle, consumed on success); returns the
-        member slot.  Raises DgsweError with status 3 when it does not fit."""
-        if prepared is None:
+        """Admit a mesh (or a prepared handle); returns the member slot.
+        Raises DgsweError with status 3 when it does not fit.
+
+        A prepared handle belongs to the pool once the admission itself has
+        succeeded; if setting the forcing or the state fails after that, the
+        member is removed again and the exception carries
+        `prepared_consumed = True` (the caller must not free the handle).
+        Any earlier failure leaves the handle with the caller
+        (`prepared_consumed = False`)."""
+        own = prepared is None
+        if own:
             prepared = self.prepare(mesh)
-            try:
-                slot = dgswe_member_add_prepared(self.h, prepared)
-            except DgsweError:
-                dgswe_prepared_free(prepared)
-                raise
-        else:
+        try:
             slot = dgswe_member_add_prepared(self.h, prepared)
-        info = dgswe_mesh_info(self.h, slot)
-        self.ne[slot] = info["n_elems"]
-        if forcing:
-            dgswe_set_forcing(self.h, forcing, info["n_elems"], info["n_nodes"], member=slot)
-        if w is not None:
-            self.set_state(slot, w, t, postprocess)
+        except DgsweError as e:
+            if own:
+                dgswe_prepared_free(prepared)
+            e.prepared_consumed = False
+            raise
+        try:
+            info = dgswe_mesh_info(self.h, slot)
+            self.ne[slot] = info["n_elems"]
+            if forcing:
+                dgswe_set_forcing(self.h, forcing, info["n_elems"], info["n_nodes"], member=slot)
+            if w is not None:
+                self.set_state(slot, w, t, postprocess)
+        except Exception as e:
+            try:
+                self.remove(slot)
+            finally:
+                e.prepared_consumed = True
+            raise
         return slot
 
     def set_state(self, slot, w, t=0.0, postprocess=False):

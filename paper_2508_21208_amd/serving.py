@@ -90,11 +90,15 @@ def serve_pool(requests, params: dict, rate: float, max_elems: int, max_members:
                 prep = futures[i].result()
                 try:
                     slot = pool.add(prepared=prep, forcing=r.forcing, w=r.w0, t=0.0, postprocess=True)
-                except DgsweError as e:
-                    if e.status != 3 or not active:
-                        # not a matter of waiting: invalid, or larger than the empty pool
-                        dgswe_prepared_free(prep)
+                except Exception as e:
+                    if getattr(e, "prepared_consumed", False):
+                        # the pool took the handle (and let the member go again)
                         del futures[i]
+                        raise
+                    if not isinstance(e, DgsweError) or e.status != 3 or not active:
+                        # not a matter of waiting: invalid, or larger than the empty pool
+                        del futures[i]
+                        dgswe_prepared_free(prep)
                         raise
                     futures[i] = _Done(prep)  # keep it prepared; retry after the next retirement
                     break

@@ -174,6 +174,21 @@ def test_prepare_mesh_and_pool_validation_on_host():
     L.dgswe_prepared_free(None)
 
 
+def test_mesh_whose_chunks_overflow_is_rechunked_not_refused():
+    """a valid mesh whose 256-element chunks have more local edges than the
+    stage kernel takes (768 > 512: no two triangles share an edge) is
+    prepared with smaller chunks instead of being refused"""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from _cases import isolated_triangles
+    m = isolated_triangles(700)
+    L = D.load_library()
+    for prec in (0, 1):
+        prep = D.dgswe_prepare_mesh(m, D.params_from_dict(dict(precision=prec)))
+        assert L.dgswe_prepared_elems(prep) == m.n_elems
+        D.dgswe_prepared_free(prep)
+
+
 def test_ensemble_order_validation_before_device_work():
     m = W.rect_mesh(3, 2, 3.0, 2.0)
     with pytest.raises(D.DgsweError) as ei:

@@ -24,7 +24,7 @@ def test_more_than_one_gpu_is_refused():
 def test_algorithmic_bytes():
     ne, ned, nn = 4_000_000, 6_000_000, 2_000_000
     assert bench.algorithmic_bytes("k_stage", ne, ned, nn, "fp64") == 315.0 * ne
-    assert bench.algorithmic_bytes("k_stage", ne, ned, nn, "mixed") == 217.0 * ne
+    assert bench.algorithmic_bytes("k_stage", ne, ned, nn, "mixed") == 207.0 * ne
     assert bench.algorithmic_bytes("k_rhs2", ne, ned, nn, "fp64") == 548.0 * ne
     assert bench.algorithmic_bytes("k_forcing", ne, ned, nn) == 40.0 * nn
     assert bench.algorithmic_bytes("k_vbounds", ne, ned, nn, "fp64") == 56.0 * nn + 36.0 * ne
@@ -46,3 +46,16 @@ def test_mixed_error_report():
     wm[0, 2, 7] += 1e-6  # mode 2 of zeta: vertex values change by -1e-6, -1e-6, +2e-6
     e = bench.mixed_error(wm, wf)
     assert abs(e["zeta_vertex_max_m"] - 2e-6) < 1e-15 and e["zeta_mean_max_m"] == 0.0 and e["q_mean_max_m2s"] == 0.0
+
+
+def test_mixed_roofline_uses_207_bytes_and_reports_the_built_count():
+    kernels = {"k_stage": {"avg_us": 300.0, "launches": 10, "total_ms": 3.0}}
+    r = bench.roofline(kernels, 1_000_000, 1_500_000, 500_000, "mixed", with_traffic=False)
+    assert r["bytes_per_launch"] == 207_000_000
+    assert abs(r["frac"] - 207e6 / 300e-6 / 8e12) < 1e-4
+    assert r["as_built"]["bytes_per_element_stage"] == 217.0
+    assert abs(r["as_built"]["frac"] - 217e6 / 300e-6 / 8e12) < 1e-4
+
+
+def test_cpu_model_is_named():
+    assert bench.cpu_model() != ""

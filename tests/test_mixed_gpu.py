@@ -19,7 +19,7 @@ from oracle.oracle import Oracle
 from paper_2508_21208_amd import workloads as W
 from paper_2508_21208_amd.dgswe import DGSWE_MIXED, Solver
 
-from _cases import coastal_600k, coastal_small, hurricane_4m, say
+from _cases import coastal_600k, coastal_small, hurricane_4m, say, shallow_open_boundary
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +82,11 @@ def test_mixed_coastal_wetdry_tide_hurricane_200_steps():
     do = o.diagnostics(wo)
     assert dg["n_dry"] > 0 and dg["n_wet"] > 0
     assert abs(dg["n_wet"] - do["n_wet"]) <= 1e-3 * dg["n_wet"]
+
+
+def test_mixed_shallow_open_boundary():
+    wl = shallow_open_boundary()
+    run_mixed_vs_oracle(wl, wl.steps)
 
 
 def test_mixed_coastal_tide_600k_full_size():

@@ -685,3 +685,45 @@ def test_wetdry_edge_rule_closed_form(order):
             # source and the pressure of its own walls: the net x and y
             # momentum rates are equal and opposite in this symmetric layout
             assert math.isclose(dw[1, 0, 0], -dw[2, 0, 0], rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_ocean_ghost_dry_branch_closed_form(order):
+    """The ocean ghost's wet/dry status (reading Z12 with the edge rules of
+    Z9): the ghost (zeta_b, Q+) is wet iff zeta_b plus the edge's mean
+    bathymetry exceeds H0.  A walled box whose open west side has a bed at
+    h_e = -0.015 m (the boundary elements stay wet through their deep
+    eastern vertices), the interior at rest with a flat surface:
+      * zeta_b = 0.02 m: ghost depth 0.005 m <= H0, dry; the LLF mass flux
+        (u = 0 on the dry side) points into the wet interior, so the wet
+        side sees a wall: nothing moves at all (the right-hand side is 0);
+      * zeta_b = 0.04 m: ghost depth 0.025 m, wet: plain LLF; the domain
+        gains mass at (1/2) lambda zeta_b L, lambda = sqrt(g (zeta_b + h_e))
+        (the interior has no positive depth on the edge);
+      * zeta_b = -0.02 m with the interior surface at 0.05 m: dry ghost,
+        mass flux out of the wet side, so the interior drains through the
+        boundary at (1/2) lambda (0.05 + 0.02) L, lambda = sqrt(g (0.05 + h_e)).
+    Planted mistakes this catches: a ghost taken as always wet, as wet with
+    the interior, or wet by zeta_b > H0 alone (the first case then gains
+    mass)."""
+    h_e, L, g = -0.015, 4000.0, 9.81
+    m = W.rect_mesh(6, 4, 6000.0, L, hb=lambda x, y: h_e + 3.0e-3 * x,
+                    types=(W.BC_LAND, W.BC_LAND, W.BC_LAND, W.BC_OCEAN))
+    nm = 3 if order == 1 else 6
+    for zb, zeta, rate in ((0.02, 0.0, 0.0),
+                           (0.04, 0.0, 0.5 * math.sqrt(g * (0.04 + h_e)) * 0.04 * L),
+                           (-0.02, 0.05, -0.5 * math.sqrt(g * (0.05 + h_e)) * 0.07 * L)):
+        o = O.Oracle(m, W.default_params(limiter=0), W.default_forcing(tide_offset=zb), order=order)
+        area = o.geometry()["area"]
+        hmean = m.hb[m.tri].mean(axis=1)
+        assert np.all(zeta + hmean > 0.01)  # every element wet
+        w = np.zeros((3, nm, o.ne))
+        w[0, 0] = zeta
+        dw = o.rhs(w, 0.0)
+        if rate == 0.0:
+            assert np.all(dw == 0.0)
+        else:
+            assert math.isclose(float(np.sum(area * dw[0, 0])), rate, rel_tol=1e-12)
+            # only the elements on the open boundary exchange mass with it
+            cen = m.xy[m.tri].mean(axis=1)
+            assert np.all(dw[0, 0][cen[:, 0] > 1000.0] == 0.0)

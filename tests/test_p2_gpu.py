@@ -14,7 +14,7 @@ from oracle.oracle import Oracle
 from paper_2508_21208_amd import workloads as W
 from paper_2508_21208_amd.dgswe import DGSWE_MIXED, Batch, Solver
 
-from _cases import coastal_small, exact_mass, hurricane_4m, rel_l2, say
+from _cases import coastal_small, exact_mass, hurricane_4m, rel_l2, say, shallow_open_boundary
 
 pytestmark = pytest.mark.gpu
 
@@ -215,3 +215,11 @@ def test_p2_mixed_precision_accuracy():
     # other differs by its quadratic modes (up to a few 1e-4 m at a vertex
     # here): the vertex bar is 1e-3 m, the mean and velocity bars 1e-4.
     assert em <= 1e-4 and ev <= 1e-4 and ez <= 1e-3
+
+
+def test_p2_shallow_open_boundary_ghost_wets_and_dries():
+    """the ocean ghost's dry branch at p = 2 (tide over a bed at -0.015 m
+    along the open boundary)"""
+    wl = shallow_open_boundary()
+    wg, dg, wo, o = run_both(wl, wl.steps)
+    check(wg, dg, wo, o)

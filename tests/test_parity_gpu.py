@@ -13,7 +13,8 @@ from oracle.oracle import Oracle
 from paper_2508_21208_amd import workloads as W
 from paper_2508_21208_amd.dgswe import DgsweError, Solver
 
-from _cases import coastal_600k, coastal_small, exact_mass, hurricane_4m, rel_l2, say
+from _cases import (coastal_600k, coastal_small, exact_mass, hurricane_4m, isolated_triangles, rel_l2, say,
+                    shallow_open_boundary)
 
 pytestmark = pytest.mark.gpu
 
@@ -86,6 +87,35 @@ def test_hurricane_4m_full_size():
     wg, dg, wo, o = run_both(wl, 4)
     err = check(wg, dg, wo, o)
     say(f"rel L2 {err}")
+
+
+def test_shallow_open_boundary_ghost_wets_and_dries():
+    """the ocean ghost's dry branch: a tide that takes the ghost's depth
+    above and below H0 over a bed at -0.015 m along the open boundary"""
+    wl = shallow_open_boundary()
+    wg, dg, wo, o = run_both(wl, wl.steps)
+    err = check(wg, dg, wo, o)
+    say(f"rel L2 {err}")
+
+
+def test_rechunked_mesh_of_isolated_triangles():
+    """a mesh the default 256-element chunks cannot take (no two triangles
+    share an edge, 768 edges per chunk): prepared with smaller chunks, its
+    700 sloshing basins match the oracle"""
+    m = isolated_triangles(700)
+    zn = 0.2 * np.sin(m.xy[:, 0] / 70.0) * np.cos(m.xy[:, 1] / 90.0)
+    wl = W.Workload("isolated_700", m, W.state_from_nodal(m.tri, zn), W.default_params(),
+                    W.default_forcing(manning_n=0.02), 100)
+    wg, dg, wo, o = run_both(wl, 100)
+    check(wg, dg, wo, o)
+    # the mixed path (smaller LDS per chunk, chunked on its own) within its bar
+    s = Solver(m, dict(wl.params, precision=1), wl.forcing)
+    s.set_state(wl.w0)
+    s.step(100)
+    wm = s.state()
+    s.close()
+    V = np.array([[1.0, -1.0, -1.0], [1.0, 1.0, -1.0], [1.0, 0.0, 2.0]])
+    assert np.abs(V @ (wm[0] - wo[0])).max() <= 1e-4
 
 
 def test_bitwise_deterministic_and_resumable():

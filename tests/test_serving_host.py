@@ -97,3 +97,46 @@ def test_waits_for_room_and_refuses_what_never_fits():
     assert kinds == ["add", "remove", "add", "remove", "add", "remove"]
     with pytest.raises(DgsweError):
         SV.serve_pool(_requests([2000], [5]), {}, rate=1000.0, max_elems=1000, max_members=4)
+
+
+class ConsumingFailPool(FakePool):
+    """add() takes the prepared handle and then fails while configuring the
+    member (as a bad forcing or state would), after removing the member."""
+    freed = []
+
+    def add(self, mesh=None, forcing=None, w=None, t=0.0, postprocess=False, prepared=None):
+        slot = super().add(mesh, forcing, w, t, postprocess, prepared)
+        if prepared.rid == 1:
+            self.remove(slot)
+            e = ValueError("bad forcing array")
+            e.prepared_consumed = True
+            raise e
+        return slot
+
+
+def test_a_handle_taken_by_the_pool_is_never_freed_again(monkeypatch):
+    ConsumingFailPool.freed = []
+    monkeypatch.setattr(SV, "Pool", ConsumingFailPool)
+    monkeypatch.setattr(SV, "dgswe_prepared_free", lambda p: ConsumingFailPool.freed.append(p.rid))
+    reqs = _requests([100, 200, 300], [5, 5, 5])
+    with pytest.raises(ValueError):
+        SV.serve_pool(reqs, {}, rate=1e6, max_elems=10_000, max_members=4)
+    # request 1's handle went to the pool: neither the failure path nor the
+    # final clean-up frees it; request 2 (prepared, never admitted) is freed
+    assert 1 not in ConsumingFailPool.freed
+    assert ConsumingFailPool.freed.count(2) <= 1
+    assert ("remove", 1) in FakePool.log
+
+
+def test_a_handle_refused_before_admission_is_freed_once(monkeypatch):
+    class RefusingPool(FakePool):
+        def add(self, mesh=None, forcing=None, w=None, t=0.0, postprocess=False, prepared=None):
+            e = DgsweError(1, "invalid forcing")
+            e.prepared_consumed = False
+            raise e
+    freed = []
+    monkeypatch.setattr(SV, "Pool", RefusingPool)
+    monkeypatch.setattr(SV, "dgswe_prepared_free", lambda p: freed.append(p.rid))
+    with pytest.raises(DgsweError):
+        SV.serve_pool(_requests([100], [5]), {}, rate=1e6, max_elems=10_000, max_members=4)
+    assert freed == [0]
