@@ -1367,21 +1367,53 @@ static void to_points2(const double u[6], double v[6]) {
   }
 }
 
-/* Post-processing for p = 2 (P2 READINGS), both leave the means unchanged.
- * Limiter, per variable (troubled-cell, hierarchical): with [lo, hi] the
- * range of the element and face-neighbour means and alpha the p = 1
- * Barth-Jespersen factor of the linear part (modes 0-2), the element is
- * troubled when alpha < 1 or the full field leaves [lo, hi] at a vertex or
- * an edge midpoint; a troubled element drops its quadratic modes and scales
- * its linear modes by alpha, i.e. it is limited as a p = 1 element.
- * Wet/dry: a dry element (mean depth <= H0) is flat at its mean depth with
- * zero momentum; an element whose depth falls below H0 at a vertex or an
- * edge midpoint drops the quadratic modes of all variables and gets the
- * p = 1 vertex correction of its linear part; otherwise it is unchanged. */
+/* Post-processing for p = 2 (P2 READINGS).  Both operations keep every
+ * element mean and are continuous in their inputs, so that a rounding-level
+ * change of the input (FP32 momentum, another summation order) changes the
+ * output at rounding level only.
+ *
+ * Limiter, per variable u (Barth-Jespersen over the six Lagrange nodes of a
+ * quadratic): [lo, hi] is the range of the element's and its face
+ * neighbours' means, d_i the deviation of the field from its mean u0 at the
+ * three vertices and the three edge midpoints, and
+ *   theta = min(1, min_i r_i),  r_i = (hi - u0)/d_i (d_i > 0),
+ *                               r_i = (lo - u0)/d_i (d_i < 0);
+ * modes 1-5 are multiplied by theta.  A linear field takes its extremes at
+ * the vertices, so with zero quadratic modes this is the p = 1 limiter.
+ *
+ * Wet/dry with threshold H0: the depth H = zeta + h_b is a quadratic whose
+ * modes are H_k = zeta_k + b_k, b_k the modes of the linear bed (b_k = 0 for
+ * k >= 3), with mean Hm = zeta_0 + b_0.
+ *   Hm <= H0 -> dry: flat depth Hm, all momentum set to 0 (as p = 1);
+ *   else, with Hmin the smallest depth over every point at which the stage
+ *   evaluates the element's state (the vertices, the two interior
+ *   Gauss-Lobatto points of each edge and the six area points), if
+ *   Hmin < H0 the depth's deviation from its mean is scaled by
+ *   theta = (Hm - H0)/(Hm - Hmin), which lifts the lowest point to H0:
+ *   H_k <- theta H_k for k >= 1, zeta_k = H_k - b_k; momentum unchanged. */
+static void depth_points2(double pts[15][2]) {
+  static const double V[3][2] = {{-1.0, -1.0}, {1.0, -1.0}, {-1.0, 1.0}};
+  int n = 0;
+  for (int i = 0; i < 3; ++i) { pts[n][0] = V[i][0]; pts[n][1] = V[i][1]; ++n; }
+  for (int l = 0; l < 3; ++l) {
+    const int a = (l + 1) % 3, b = (l + 2) % 3;
+    for (int g = 1; g <= 2; ++g) {
+      const double s = EDGE2_S[g];
+      pts[n][0] = V[a][0] * 0.5 * (1.0 - s) + V[b][0] * 0.5 * (1.0 + s);
+      pts[n][1] = V[a][1] * 0.5 * (1.0 - s) + V[b][1] * 0.5 * (1.0 + s);
+      ++n;
+    }
+  }
+  for (int q = 0; q < 6; ++q) { ref_point(AREA2_BARY[q], &pts[n][0], &pts[n][1]); ++n; }
+}
+
 static int32_t postprocess2(or_mesh *M, const double *wt, double *out) {
   if (M->prm.limiter == 2) return OR_E_INVALID;  /* the vertex-based limiter is p = 1 only */
   const int32_t ne = M->ne;
   const double h0 = M->prm.h0;
+  double dpts[15][2];
+  tables2();
+  depth_points2(dpts);
 #pragma omp parallel for schedule(static)
   for (int32_t e = 0; e < ne; ++e) {
     double u[3][6];
@@ -1397,64 +1429,42 @@ static int32_t postprocess2(or_mesh *M, const double *wt, double *out) {
           if (nbm > hi) hi = nbm;
           if (nbm < lo) lo = nbm;
         }
-        double vv[3];
-        to_vertices(u[m][0], u[m][1], u[m][2], vv);
-        double alpha = 1.0;
-        for (int i = 0; i < 3; ++i) {
-          double a = 1.0;
-          if (vv[i] > mean) a = fmin(1.0, (hi - mean) / (vv[i] - mean));
-          else if (vv[i] < mean) a = fmin(1.0, (lo - mean) / (vv[i] - mean));
-          if (a < alpha) alpha = a;
-        }
         double pv[6];
         to_points2(u[m], pv);
-        int troubled = alpha < 1.0;
-        for (int i = 0; i < 6; ++i)
-          if (pv[i] > hi || pv[i] < lo) troubled = 1;
-        if (troubled) {
-          u[m][1] *= alpha; u[m][2] *= alpha;
-          u[m][3] = 0.0; u[m][4] = 0.0; u[m][5] = 0.0;
+        double theta = 1.0;
+        for (int i = 0; i < 6; ++i) {
+          double d = pv[i] - mean, r = 1.0;
+          if (d > 0.0) r = (hi - mean) / d;
+          else if (d < 0.0) r = (lo - mean) / d;
+          if (r < theta) theta = r;
         }
+        for (int k = 1; k < 6; ++k) u[m][k] *= theta;
       }
     }
     if (M->prm.wetdry) {
       const int32_t *vt = M->tri + 3 * e;
       double hbv[3] = {M->hb[vt[0]], M->hb[vt[1]], M->hb[vt[2]]};
-      double hbp[6] = {hbv[0], hbv[1], hbv[2], 0.5 * (hbv[1] + hbv[2]), 0.5 * (hbv[2] + hbv[0]),
-                       0.5 * (hbv[0] + hbv[1])};
-      double Hm = u[0][0] + hb_mean(M, e);
-      double zp[6];
-      to_points2(u[0], zp);
-      int reduce = Hm <= h0;
-      for (int i = 0; i < 6 && !reduce; ++i)
-        if (zp[i] + hbp[i] < h0) reduce = 1;
-      if (reduce) {
-        for (int m = 0; m < 3; ++m) { u[m][3] = 0.0; u[m][4] = 0.0; u[m][5] = 0.0; }
-        double zv[3], Hv[3];
-        to_vertices(u[0][0], u[0][1], u[0][2], zv);
-        for (int i = 0; i < 3; ++i) Hv[i] = zv[i] + hbv[i];
-        int changed = 0;
-        if (Hm <= h0) {
-          for (int i = 0; i < 3; ++i) Hv[i] = Hm;
-          for (int k = 0; k < 6; ++k) { u[1][k] = 0.0; u[2][k] = 0.0; }
-          changed = 1;
-        } else if (fmin(Hv[0], fmin(Hv[1], Hv[2])) < h0) {
-          double D = 0.0, S = 0.0;
-          for (int i = 0; i < 3; ++i) {
-            if (Hv[i] < h0) D += h0 - Hv[i];
-            else S += Hv[i] - h0;
-          }
-          if (S > D) {
-            for (int i = 0; i < 3; ++i) Hv[i] = (Hv[i] < h0) ? h0 : Hv[i] - D * (Hv[i] - h0) / S;
-          } else {
-            for (int i = 0; i < 3; ++i) Hv[i] = Hm;
-          }
-          changed = 1;
+      const double b0 = hb_mean(M, e);
+      const double b[6] = {b0, 0.5 * (hbv[1] - hbv[0]), 0.5 * (hbv[2] - b0), 0.0, 0.0, 0.0};
+      double Hk[6];
+      for (int k = 0; k < 6; ++k) Hk[k] = u[0][k] + b[k];
+      const double Hm = u[0][0] + b0;
+      if (Hm <= h0) {
+        /* flat depth: zeta = Hm - h_b, i.e. zeta_k = -b_k for k >= 1 */
+        u[0][1] = -b[1]; u[0][2] = -b[2];
+        u[0][3] = 0.0; u[0][4] = 0.0; u[0][5] = 0.0;
+        for (int k = 0; k < 6; ++k) { u[1][k] = 0.0; u[2][k] = 0.0; }
+      } else {
+        double Hmin = INFINITY;
+        for (int i = 0; i < 15; ++i) {
+          double phi[6], s = 0.0;
+          or_basis2(dpts[i][0], dpts[i][1], phi, NULL);
+          for (int k = 0; k < 6; ++k) s += Hk[k] * phi[k];
+          if (s < Hmin) Hmin = s;
         }
-        if (changed) {
-          for (int i = 0; i < 3; ++i) zv[i] = Hv[i] - hbv[i];
-          u[0][1] = 0.5 * (zv[1] - zv[0]);
-          u[0][2] = 0.5 * (zv[2] - u[0][0]);
+        if (Hmin < h0) {
+          const double theta = (Hm - h0) / (Hm - Hmin);
+          for (int k = 1; k < 6; ++k) u[0][k] = theta * Hk[k] - b[k];
         }
       }
     }

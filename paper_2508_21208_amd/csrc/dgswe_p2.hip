@@ -143,18 +143,39 @@ HD void store_rec(Rec2<QT> *__restrict__ r, int e, const double u[18]) {
 }
 
 // ---------------------------------------------------------------- post-processing
+// Reference coordinates of the points at which a stage evaluates an
+// element's state: i = 0..2 the vertices, 3..8 the two interior
+// Gauss-Lobatto points of each edge (edge (i-3)/2, s = -+1/sqrt5), 9..14
+// the six area points.  With constant i (unrolled loops) it folds away.
+HD void depth_point2(int i, double &xi, double &eta) {
+  if (i < 3) {
+    xi = i == 1 ? 1.0 : -1.0;
+    eta = i == 2 ? 1.0 : -1.0;
+  } else if (i < 9) {
+    edge_point2((i - 3) >> 1, ((i - 3) & 1) ? kGL4S : -kGL4S, xi, eta);
+  } else {
+    double L[3], w;
+    area_point2(i - 9, L, w);
+    xi = -L[0] + L[1] - L[2];
+    eta = -L[0] - L[1] + L[2];
+  }
+}
+
 // Post-processing of one element, FP64: u[18] = zeta, Qx, Qy modes
 // [var * 6 + mode] of the raw state; nbm[v][k] the raw mean of variable v of
-// neighbour k.
-//   Limiter, per variable: alpha is the p = 1 Barth-Jespersen factor of the
-//   linear part against the range of the element and neighbour means; the
-//   element is troubled when alpha < 1 or the full field leaves the range at
-//   a vertex or an edge midpoint, and then keeps only its linear part scaled
-//   by alpha.
-//   Wet/dry: mean depth <= H0 -> flat at the mean depth, momentum 0; a depth
-//   below H0 at a vertex or an edge midpoint -> the quadratic modes of all
-//   variables are dropped and the p = 1 vertex correction is applied to the
-//   linear part; otherwise unchanged.
+// neighbour k.  Both steps keep the means and are continuous in their
+// inputs, so rounding-level input changes (FP32 momentum) move the output
+// at rounding level only.
+//   Limiter, per variable: with [lo, hi] the range of the element's and its
+//   neighbours' means and d the deviations of the field from its mean at
+//   the vertices and the edge midpoints, modes 1-5 are scaled by the
+//   largest theta <= 1 that keeps mean + theta d inside [lo, hi] (a linear
+//   field gives the p = 1 Barth-Jespersen factor).
+//   Wet/dry: mean depth <= H0 -> flat at the mean depth, momentum 0; else
+//   if the depth falls below H0 at a vertex, an interior edge quadrature
+//   point or an area point, the depth's deviation from its mean (modes 1-5
+//   of zeta plus the bed's linear modes) is scaled by (Hm - H0)/(Hm - Hmin),
+//   which lifts the lowest of those points to H0; momentum unchanged.
 HD void postprocess2(double u[18], const double nbm[3][3], const bool has[3], const double h[3], double hmean,
                      const Params &p) {
   if (p.limiter) {
@@ -164,60 +185,44 @@ HD void postprocess2(double u[18], const double nbm[3][3], const bool has[3], co
       double hi = mean, lo = mean;
       for (int k = 0; k < 3; ++k)
         if (has[k]) { hi = fmax(hi, nbm[v][k]); lo = fmin(lo, nbm[v][k]); }
-      const double a = w[1], b = w[2];
-      const double d0 = (mean - a - b) - mean, d1 = (mean + a - b) - mean, d2 = (mean + 2.0 * b) - mean;
-      const double dmax = fmax(d0, fmax(d1, d2)), dmin = fmin(d0, fmin(d1, d2));
-      double alpha = 1.0;
-      if (dmax > 0.0 && hi - mean < dmax) alpha = fmin(alpha, (hi - mean) / dmax);
-      if (dmin < 0.0 && lo - mean > dmin) alpha = fmin(alpha, (lo - mean) / dmin);
-      bool troubled = alpha < 1.0;
+      double dmax = 0.0, dmin = 0.0;
       for (int i = 0; i < 6; ++i) {
-        double s = 0.0;
-        for (int k = 0; k < 6; ++k) s += w[k] * kPt6[i][k];
-        troubled = troubled || s > hi || s < lo;
+        double d = 0.0;
+        for (int k = 1; k < 6; ++k) d += w[k] * kPt6[i][k];
+        dmax = fmax(dmax, d);
+        dmin = fmin(dmin, d);
       }
-      if (troubled) {
-        w[1] = a * alpha;
-        w[2] = b * alpha;
-        w[3] = 0.0; w[4] = 0.0; w[5] = 0.0;
-      }
+      double theta = 1.0;
+      if (dmax > 0.0 && hi - mean < dmax) theta = fmin(theta, (hi - mean) / dmax);
+      if (dmin < 0.0 && lo - mean > dmin) theta = fmin(theta, (lo - mean) / dmin);
+      if (theta < 1.0)
+        for (int k = 1; k < 6; ++k) w[k] *= theta;
     }
   }
   if (p.wetdry) {
     const double Hm = u[0] + hmean;
-    const double hp[6] = {h[0], h[1], h[2], 0.5 * (h[1] + h[2]), 0.5 * (h[2] + h[0]), 0.5 * (h[0] + h[1])};
-    bool reduce = Hm <= p.h0;
-    for (int i = 0; i < 6; ++i) {
-      double s = 0.0;
-      for (int k = 0; k < 6; ++k) s += u[k] * kPt6[i][k];
-      reduce = reduce || s + hp[i] < p.h0;
-    }
-    if (reduce) {
-      for (int v = 0; v < 3; ++v) { u[6 * v + 3] = 0.0; u[6 * v + 4] = 0.0; u[6 * v + 5] = 0.0; }
-      const double z0 = u[0] - u[1] - u[2], z1 = u[0] + u[1] - u[2], z2 = u[0] + 2.0 * u[2];
-      double H[3] = {z0 + h[0], z1 + h[1], z2 + h[2]};
-      bool changed = false;
-      if (Hm <= p.h0) {
-        H[0] = H[1] = H[2] = Hm;
-        for (int j = 6; j < 18; ++j) u[j] = 0.0;
-        changed = true;
-      } else if (fmin(H[0], fmin(H[1], H[2])) < p.h0) {
-        double D = 0.0, S = 0.0;
-        for (int i = 0; i < 3; ++i) {
-          if (H[i] < p.h0) D += p.h0 - H[i];
-          else S += H[i] - p.h0;
-        }
-        if (S > D) {
-          for (int i = 0; i < 3; ++i) H[i] = (H[i] < p.h0) ? p.h0 : H[i] - D * (H[i] - p.h0) / S;
-        } else {
-          H[0] = H[1] = H[2] = Hm;
-        }
-        changed = true;
+    const double b1 = 0.5 * (h[1] - h[0]), b2 = 0.5 * (h[2] - hmean);
+    if (Hm <= p.h0) {
+      u[1] = -b1; u[2] = -b2;
+      u[3] = 0.0; u[4] = 0.0; u[5] = 0.0;
+      for (int j = 6; j < 18; ++j) u[j] = 0.0;
+    } else {
+      const double H[6] = {0.0, u[1] + b1, u[2] + b2, u[3], u[4], u[5]};
+      double dmin = 0.0;
+#pragma unroll
+      for (int i = 0; i < 15; ++i) {
+        double xi, eta, f[6];
+        depth_point2(i, xi, eta);
+        basis2(xi, eta, f);
+        double d = 0.0;
+        for (int k = 1; k < 6; ++k) d += H[k] * f[k];
+        dmin = fmin(dmin, d);
       }
-      if (changed) {
-        const double y0 = H[0] - h[0], y1 = H[1] - h[1], y2 = H[2] - h[2];
-        u[1] = 0.5 * (y1 - y0);
-        u[2] = 0.5 * (y2 - u[0]);
+      if (Hm + dmin < p.h0) {
+        const double theta = (Hm - p.h0) / (-dmin);
+        u[1] = theta * H[1] - b1;
+        u[2] = theta * H[2] - b2;
+        for (int k = 3; k < 6; ++k) u[k] = theta * H[k];
       }
     }
   }

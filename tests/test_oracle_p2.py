@@ -194,27 +194,43 @@ def _nb_range(o, means):
     return lo, hi
 
 
-def test_postprocess2_of_linear_states_is_the_p1_postprocess():
-    """With zero quadratic modes the p = 2 limiter and wet/dry readings reduce
-    to the paper's p = 1 operations (edge midpoints are vertex averages)."""
+def test_limiter2_of_linear_states_is_the_p1_limiter():
+    """With zero quadratic modes the p = 2 limiter is the p = 1 limiter: a
+    linear field takes its extremes at the vertices, the edge midpoints are
+    vertex averages."""
     m = W.rect_mesh(12, 4, 1200.0, 400.0, hb=lambda x, y: 1.0 - x / 300.0)
     rng = np.random.default_rng(23)
     hbv = m.hb[m.tri]
     w1 = np.zeros((3, 3, m.n_elems))
     w1[0] = W.modes_from_vertices(np.maximum(0.0, 0.011 - hbv) + rng.uniform(-0.02, 0.02, hbv.shape)).T
     w1[1:] = rng.normal(scale=0.05, size=(2, 3, m.n_elems))
-    for lim, wd in ((1, 0), (0, 1), (1, 1)):
-        p = W.default_params(limiter=lim, wetdry=wd)
-        o1 = O.Oracle(m, p, W.default_forcing())
-        o2 = O.Oracle(m, p, W.default_forcing(), order=2)
-        w2 = np.zeros((3, 6, m.n_elems)); w2[:, :3] = w1
-        out1 = o1.postprocess(w1)
-        out2 = o2.postprocess(w2)
-        assert np.array_equal(out2[:, 3:], np.zeros_like(out2[:, 3:]))
-        assert np.allclose(out2[:, :3], out1, rtol=0, atol=1e-14), (lim, wd)
+    p = W.default_params(limiter=1, wetdry=0)
+    o1 = O.Oracle(m, p, W.default_forcing())
+    o2 = O.Oracle(m, p, W.default_forcing(), order=2)
+    w2 = np.zeros((3, 6, m.n_elems)); w2[:, :3] = w1
+    out1 = o1.postprocess(w1)
+    out2 = o2.postprocess(w2)
+    assert np.array_equal(out2[:, 3:], np.zeros_like(out2[:, 3:]))
+    assert np.allclose(out2[:, :3], out1, rtol=0, atol=1e-14)
+    assert not np.array_equal(out1, w1)  # the limiter did act
+
+
+def _theta6(w, lo, hi):
+    """the largest factor in [0, 1] that keeps mean + t (u - mean) inside
+    [lo, hi] at the vertices and edge midpoints, from the general Dubiner
+    formula: (nvar?, ne)"""
+    pv = _points6(w[None])[0] if w.ndim == 2 else None
+    d = pv - w[0][:, None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(d > 0, (hi - w[0])[:, None] / d, np.where(d < 0, (lo - w[0])[:, None] / d, 1.0))
+    return np.minimum(1.0, r.min(axis=1))
 
 
 def test_limiter2_invariants():
+    """Means kept bit for bit; modes 1-5 of a variable scaled by one common
+    factor in [0, 1]; the result inside the neighbour-mean range at the six
+    Lagrange nodes, touching it where the factor is below 1 (the largest
+    such factor); elements already inside left alone bit for bit."""
     m = W.rect_mesh(10, 6, 1000.0, 600.0, hb=20.0)
     o = O.Oracle(m, W.default_params(wetdry=0), W.default_forcing(), order=2)
     rng = np.random.default_rng(24)
@@ -223,21 +239,21 @@ def test_limiter2_invariants():
     out = o.postprocess(w)
     assert np.array_equal(out[:, 0], w[:, 0])  # means untouched
     pv = _points6(out)
+    pin = _points6(w)
+    n_limited = 0
     for var in range(3):
         lo, hi = _nb_range(o, w[var, 0])
-        changed = np.any(out[var] != w[var], axis=0)
-        # a limited element is linear and its linear part only shrinks
-        assert np.all(out[var, 3:, changed] == 0.0)
-        r = out[var, 1:3] / np.where(w[var, 1:3] == 0, 1, w[var, 1:3])
-        assert np.all(r >= -1e-15) and np.all(r <= 1 + 1e-15)
-        # a limited element lies within the neighbour-mean range
-        assert np.all(pv[var][changed] <= hi[changed, None] + 1e-12)
-        assert np.all(pv[var][changed] >= lo[changed, None] - 1e-12)
-        # an element left alone already lay within it at the 6 points
-        keep = ~changed
-        assert np.all(pv[var][keep] <= hi[keep, None] + 1e-12)
-        assert np.all(pv[var][keep] >= lo[keep, None] - 1e-12)
-        assert changed.any()
+        theta = _theta6(w[var], lo, hi)
+        scale = np.abs(w[var, 1:]).max(axis=0)
+        assert np.all(np.abs(out[var, 1:] - theta[None] * w[var, 1:]) <= 1e-14 * scale[None])
+        assert np.all(pv[var] <= hi[:, None] + 1e-12) and np.all(pv[var] >= lo[:, None] - 1e-12)
+        lim = theta < 1.0
+        n_limited += int(lim.sum())
+        touch = np.minimum(np.abs(pv[var] - hi[:, None]), np.abs(pv[var] - lo[:, None])).min(axis=1)
+        assert np.all(touch[lim] <= 1e-12)
+        inside = np.all((pin[var] <= hi[:, None]) & (pin[var] >= lo[:, None]), axis=1)
+        assert np.array_equal(out[var][:, inside], w[var][:, inside])
+    assert n_limited > 20
     # a smooth field with tiny slopes and curvature around scattered means:
     # most elements are untouched, bit for bit
     small = w.copy(); small[:, 1:] *= 1e-5
@@ -247,15 +263,15 @@ def test_limiter2_invariants():
 
 
 def test_limiter2_limits_on_edge_midpoints():
-    """P2 reading: an element whose linear part passes the p = 1 test but
-    whose full field leaves the neighbour-mean range at an edge midpoint is
-    limited (quadratic modes dropped, linear part kept since alpha = 1)."""
+    """An element whose vertices stay inside the neighbour-mean range but
+    whose field leaves it at an edge midpoint is limited by the factor that
+    puts that midpoint on the bound: (bound - mean) / (deviation there)."""
     m = W.rect_mesh(10, 6, 1000.0, 600.0, hb=20.0)
     o = O.Oracle(m, W.default_params(wetdry=0), W.default_forcing(), order=2)
     rng = np.random.default_rng(26)
     ne = o.ne
     # per element a bump s * lambda_1 lambda_2 (zero at the vertices, 1/4 s
-    # at the midpoint of edge v1-v2), projected onto the six modes
+    # at the midpoint of local edge 0), projected onto the six modes
     xi, eta, wt = _ref_triangle_rule(8)
     B = np.array([[_dubiner_general(i, j, a, b) for i, j in MODES] for a, b in zip(xi, eta)])
     f = (1 + xi) / 2 * (1 + eta) / 2
@@ -263,22 +279,26 @@ def test_limiter2_limits_on_edge_midpoints():
     w = np.zeros((3, 6, ne))
     w[0, 0] = rng.uniform(0.0, 1.0, ne)
     lo, hi = _nb_range(o, w[0, 0])
-    # the bump moves the midpoint by s/6 and the linear part's vertices by
-    # -2 s/15 and s/15: sized so the midpoint leaves the range on the side
-    # with less room, scaled down on a third of the elements
     up, dn = hi - w[0, 0], w[0, 0] - lo
     s = np.where(up >= dn, -dn / 0.12, up / 0.12) * np.where(rng.uniform(size=ne) < 1 / 3, 0.3, 1.0)
     w[0, 1:] = c[1:, None] * s[None, :]
     lin_ok = np.all((_vertices6(w[0, :3]) <= hi[:, None]) & (_vertices6(w[0, :3]) >= lo[:, None]), axis=1)
     pv = _points6(w[:1])[0]
+    dev = pv - w[0, 0][:, None]
     full_ok = np.all((pv <= hi[:, None]) & (pv >= lo[:, None]), axis=1)
     out = o.postprocess(w)
     mid_only = lin_ok & ~full_ok
     assert mid_only.sum() >= 3
-    assert np.all(out[0, 3:, mid_only] == 0.0)
-    assert np.array_equal(out[0, :3, mid_only], w[0, :3, mid_only])
+    # the factor: the bump's peak, the midpoint of local edge 0 (between
+    # the vertices at (1, -1) and (-1, 1); node 3), reaches its bound
+    j = 3
+    bound = np.where(dev[:, j] > 0, hi, lo)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        theta = (bound - w[0, 0]) / dev[:, j]
+    for e in np.flatnonzero(mid_only):
+        assert np.allclose(out[0, 1:, e], theta[e] * w[0, 1:, e], rtol=1e-13, atol=0), e
+        assert abs(pv[e, j] - w[0, 0, e]) > 0
     assert np.array_equal(out[0][:, lin_ok & full_ok], w[0][:, lin_ok & full_ok])
-    assert np.all(out[0, 3:, ~lin_ok] == 0.0)
 
 
 def _vertices6(u):
@@ -286,7 +306,71 @@ def _vertices6(u):
     return np.stack([u[0] - u[1] - u[2], u[0] + u[1] - u[2], u[0] + 2 * u[2]], axis=-1)
 
 
+def test_limiter2_is_continuous():
+    """A change of the input at rounding level (the momentum rounded to
+    FP32, as the mixed path stores it) changes the limited field at the six
+    nodes by no more than a small multiple of the input change, also on
+    elements sitting right at the edge of being limited.  (An
+    all-or-nothing switch, e.g. dropping the quadratic modes whenever a node
+    leaves the range, moves such elements by the size of their quadratic
+    part.)"""
+    m = W.rect_mesh(10, 6, 1000.0, 600.0, hb=20.0)
+    o = O.Oracle(m, W.default_params(wetdry=0), W.default_forcing(), order=2)
+    rng = np.random.default_rng(27)
+    w = rng.normal(size=(3, 6, o.ne)) * np.array([1, 0.3, 0.3, 0.1, 0.1, 0.1])[None, :, None]
+    # put every element on the edge of being limited: scale its modes 1-5
+    # so that its extreme node lies on the neighbour-mean bound
+    for var in range(3):
+        lo, hi = _nb_range(o, w[var, 0])
+        w[var, 1:] *= _theta6(w[var], lo, hi)[None]
+    n_edge = 0
+    for k in range(6):
+        eps = 1e-7 * rng.standard_normal(w.shape) * np.abs(w)
+        w2 = w + eps
+        out1, out2 = o.postprocess(w), o.postprocess(w2)
+        d_in = np.abs(_points6(w2) - _points6(w)).max(axis=2)
+        d_out = np.abs(_points6(out2) - _points6(out1)).max(axis=2)
+        scale = np.abs(w[:, 1:]).max(axis=1) + np.abs(w[:, 0])
+        assert np.all(d_out <= 20.0 * d_in + 1e-14 * scale), float((d_out - 20 * d_in).max())
+        n_edge += int(np.sum(np.abs(out1[:, 1:] - w[:, 1:]).max(axis=1) > 0))
+    assert n_edge > 100
+
+
+def _depth_points():
+    """reference coordinates of the points at which a p = 2 stage evaluates
+    an element's state: the three vertices, the two interior 4-point
+    Gauss-Lobatto nodes of each edge (s = -+1/sqrt5, edge l from vertex l+1
+    to vertex l+2) and the six points of the degree-4 symmetric area rule
+    (Dunavant's published orbits (a, b, b))"""
+    V = np.array([[-1.0, -1.0], [1.0, -1.0], [-1.0, 1.0]])
+    pts = [V[0], V[1], V[2]]
+    r5 = 1.0 / math.sqrt(5.0)
+    for l in range(3):
+        a, b = V[(l + 1) % 3], V[(l + 2) % 3]
+        for s in (-r5, r5):
+            pts.append(a * 0.5 * (1 - s) + b * 0.5 * (1 + s))
+    for A, Bb in ((0.108103018168070, 0.445948490915965), (0.816847572980459, 0.091576213509771)):
+        for r in range(3):
+            lam = np.full(3, Bb); lam[r] = A
+            pts.append(lam @ V)
+    return np.array(pts)
+
+
+def _depth_at_points(w, hbv):
+    """depth zeta + h_b at the 15 points, general Dubiner formula: (ne, 15)"""
+    P = _depth_points()
+    z = _eval2_modes(w[:1], P[:, 0], P[:, 1])[0]
+    lam = _ref_points(P[:, 0], P[:, 1])
+    return z + hbv @ lam.T
+
+
 def test_wetdry2_invariants():
+    """Means kept bit for bit; dry elements flat with zero momentum; in a
+    wet element the depth at every point where the stage evaluates the
+    state is >= H0; an element already deep enough there is left alone bit
+    for bit; otherwise the depth's deviation from its mean is scaled by
+    (Hm - H0)/(Hm - Hmin) (so its lowest point lands on H0), the momentum
+    left unchanged."""
     m = W.rect_mesh(12, 4, 1200.0, 400.0, hb=lambda x, y: 1.0 - x / 300.0)
     o = O.Oracle(m, W.default_params(limiter=0), W.default_forcing(), order=2)
     rng = np.random.default_rng(25)
@@ -302,21 +386,51 @@ def test_wetdry2_invariants():
     dry = Hbar <= H0
     wet = ~dry
     assert dry.any() and wet.any()
-    hb6 = np.concatenate([hbv, 0.5 * (hbv[:, [1, 2, 0]] + hbv[:, [2, 0, 1]])], axis=1)
-    H6 = _points6(out[:1])[0] + hb6
+    Hout = _depth_at_points(out, hbv)
+    Hin = _depth_at_points(w, hbv)
     assert np.all(out[1:, :, dry] == 0.0)
-    assert np.allclose(H6[dry], Hbar[dry][:, None], atol=1e-12)
-    assert np.all(H6[wet] >= H0 - 1e-12)
-    # untouched where the input was already deep enough at the 6 points
-    H6in = _points6(w[:1])[0] + hb6
-    ok = wet & np.all(H6in >= H0, axis=1)
+    assert np.allclose(Hout[dry], Hbar[dry][:, None], atol=1e-12)
+    assert np.all(Hout[wet] >= H0 - 1e-12)
+    ok = wet & np.all(Hin >= H0, axis=1)
     assert ok.any()
     assert np.array_equal(out[:, :, ok], w[:, :, ok])
-    # reduced elements lose their quadratic modes only
-    red = wet & ~ok
-    assert red.any()
-    assert np.all(out[:, 3:, red] == 0.0)
-    assert np.array_equal(out[1:, :3, red], w[1:, :3, red])
+    sc = wet & ~ok
+    assert sc.sum() > 5
+    assert np.array_equal(out[1:, :, sc], w[1:, :, sc])
+    theta = (Hbar - H0) / (Hbar - Hin.min(axis=1))
+    # depth modes: the bed's linear modes added to zeta's
+    b = np.zeros((6, o.ne))
+    b[0] = hbv.mean(axis=1); b[1] = 0.5 * (hbv[:, 1] - hbv[:, 0]); b[2] = 0.5 * (hbv[:, 2] - b[0])
+    Hm_in, Hm_out = w[0] + b, out[0] + b
+    assert np.allclose(Hm_out[1:, sc], theta[sc] * Hm_in[1:, sc], rtol=0, atol=1e-14)
+    assert np.allclose(Hout[sc].min(axis=1), H0, rtol=0, atol=1e-13)
+
+
+def test_wetdry2_is_continuous():
+    """Rounding-level changes of a wet element's elevation near the
+    threshold move the post-processed depth by a small multiple of the
+    change (the scaling factor tends to 1 as the lowest point rises to
+    H0)."""
+    m = W.rect_mesh(12, 4, 1200.0, 400.0, hb=lambda x, y: 1.0 - x / 300.0)
+    o = O.Oracle(m, W.default_params(limiter=0), W.default_forcing(), order=2)
+    rng = np.random.default_rng(28)
+    hbv = m.hb[m.tri]
+    w = np.zeros((3, 6, o.ne))
+    w[0, :3] = W.modes_from_vertices(np.maximum(0.0, 0.02 - hbv) + rng.uniform(-0.02, 0.02, hbv.shape)).T
+    w[0, 3:] = rng.normal(scale=0.003, size=(3, o.ne))
+    w[1:] = rng.normal(scale=0.05, size=(2, 6, o.ne))
+    w = o.postprocess(w)  # lowest points of the scaled elements sit on H0
+    Hbar = w[0, 0] + hbv.mean(axis=1)
+    wet = Hbar > 0.0101
+    on_edge = wet & (np.abs(_depth_at_points(w, hbv).min(axis=1) - 0.01) < 1e-13)
+    assert on_edge.sum() > 5
+    for sign in (1.0, -1.0):
+        w2 = w.copy()
+        w2[0, 1:] *= 1.0 + sign * 1e-9
+        d_in = np.abs(_depth_at_points(w2, hbv) - _depth_at_points(w, hbv)).max(axis=1)
+        out1, out2 = o.postprocess(w), o.postprocess(w2)
+        d_out = np.abs(_depth_at_points(out2, hbv) - _depth_at_points(out1, hbv)).max(axis=1)
+        assert np.all(d_out[wet] <= 20.0 * d_in[wet] + 1e-15), float((d_out[wet] - 20 * d_in[wet]).max())
 
 
 # ---------------------------------------------------------------- integral invariants
