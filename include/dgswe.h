@@ -345,6 +345,26 @@ dgswe_status dgswe_read_state(dgswe_solver *s, double *w_out, dgswe_diag *d);
  * error status). */
 dgswe_status dgswe_member_read_state(dgswe_solver *s, int32_t member, double *w_out, dgswe_diag *d);
 
+/* For callers that cannot allocate memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The read-back of
+ * dgswe_member_read_state without allocating, copying to the host or
+ * waiting: it enqueues on the solver's stream
+ *   - the member's post-processed state into w_dev (if not NULL): device
+ *     memory owned by the caller, FP64 [3][nmodes][n_elems] in the caller's
+ *     element order, exactly what dgswe_member_read_state writes;
+ *   - its diagnostics into diag_dev (if not NULL): device memory of 8
+ *     doubles, t, dt_last, mass, volume, steps, n_wet, n_dry and the
+ *     member's device status word (0, or the DGSWE_E_* a kernel reported);
+ * and returns.  The values are in place once the stream has run that far.
+ * Scratch: the diagnostics' partial sums live in one static device array
+ * per GPU (1.5 MiB, held until the process ends) sized for members of at
+ * most DGSWE_NOALLOC_MAX_ELEMS elements; a larger member gives
+ * DGSWE_E_INVALID and enqueues nothing.  Every call on a GPU uses that
+ * GPU's array: calls on one GPU that overlap (different streams with no
+ * ordering between them) race and may mix their diagnostics. */
+#define DGSWE_NOALLOC_MAX_ELEMS 16777216
+dgswe_status dgswe_member_read_state_device(dgswe_solver *s, int32_t member, double *w_dev, double *diag_dev);
+
 /* Release the solver and its device memory (NULL is ignored). */
 void dgswe_destroy(dgswe_solver *s);
 

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -57,6 +58,44 @@ int rk_stages(int rk, StageCoef out[5]) {
 
 namespace {
 thread_local std::string g_create_error = "no error";
+
+// Scratch of dgswe_member_read_state_device, the read-back for callers that
+// cannot allocate: the diagnostics' per-block partial sums of a member of
+// up to DGSWE_NOALLOC_MAX_ELEMS elements (3 per block of 256 elements)
+// followed by their three totals, 1.5 MiB.  Each GPU holds its own copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy: it uses the device address hipGetSymbolAddress gives
+// for the device, looked up once per device with that device current.
+constexpr int kNoAllocBlocks = DGSWE_NOALLOC_MAX_ELEMS / 256;
+constexpr size_t kNoAllocDoubles = 3 * (size_t)kNoAllocBlocks + 4;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on `device`
+hipError_t scratch_on(int device, double **out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *addr = nullptr;
+    e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!addr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = (double *)addr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 enum KernelId { K_FORCING = 0, K_STAGE, K_PP2, K_RHS2, K_VBOUNDS, K_COUNT };
 const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage", "k_pp2", "k_rhs2", "k_vbounds"};
@@ -474,7 +513,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
     chk(dev_alloc(S, &q, n));
     *ptr = q;
   };
-  al(&m.area, E); al(&m.inr2, E); al(&m.hbv, 3 * E); al(&m.el_nb, 3 * E);
+  al(&m.area, E); al(&m.inr2, E); al(&m.hbv, 3 * E); al(&m.el_nb, 3 * E); al(&m.perm, E);
   al(&m.node_x, N); al(&m.node_y, N);
   al(&m.eai, E); al(&m.enode, E);
   if (mixed) { al(&m.egf, E); al(&m.le_f, LE); }
@@ -576,6 +615,7 @@ dgswe_status place_member(dgswe_solver *S, int slot, const Prep &q) {
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
   chk(put(m.area, e0, q.area.data(), ne));
   chk(put(m.inr2, e0, q.inr2.data(), ne));
+  chk(put(m.perm, e0, q.perm.data(), ne));
   {
     std::vector<int> nb(ne);
     for (size_t k = 0; k < 3; ++k) {
@@ -980,11 +1020,11 @@ dgswe_status read_state_impl(dgswe_solver *S, int32_t member, double *w_out, dgs
       S->rb_elems = ne;
     }
     if (S->order == 2)
-      e = launch_post_only2(S->m, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
-                            S->stream);
+      e = launch_post_only2(S->m, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, nullptr,
+                            S->precision, S->stream);
     else
-      e = launch_post_only(S->m, S->s, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, S->precision,
-                           S->stream);
+      e = launch_post_only(S->m, S->s, S->prm, S->s.buf[S->cur], h.cur_is_pp ? 0 : 1, f.e0, f.ne, S->rb, nullptr,
+                           S->precision, S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "post-processing kernel");
     e = pinned(S->stage_out, S->stage_out_bytes, nv * ne * sizeof(double));
     if (e != hipSuccess) return hip_fail(S, e, "hipHostMalloc");
@@ -999,7 +1039,7 @@ dgswe_status read_state_impl(dgswe_solver *S, int32_t member, double *w_out, dgs
   }
   Ctrl c{};
   if (d) {
-    e = launch_diag(S->m, S->s, S->prm, S->s.buf[S->cur], f.e0, f.ne, S->d_diag, S->stream);
+    e = launch_diag(S->m, S->prm, S->s.buf[S->cur], f.e0, f.ne, S->s.partial, S->d_diag, S->stream);
     if (e != hipSuccess) return hip_fail(S, e, "diagnostics kernel");
     double out4[4];
     e = hipMemcpyAsync(out4, S->d_diag, sizeof out4, hipMemcpyDeviceToHost, S->stream);
@@ -1258,6 +1298,40 @@ dgswe_status dgswe_read_state(dgswe_solver *S, double *w_out, dgswe_diag *d) {
 dgswe_status dgswe_member_read_state(dgswe_solver *S, int32_t member, double *w_out, dgswe_diag *d) {
   return guard(S, [&]() -> dgswe_status {
     return read_state_impl(S, member, w_out, d);
+  });
+}
+
+dgswe_status dgswe_member_read_state_device(dgswe_solver *S, int32_t member, double *w_dev, double *diag_dev) {
+  return guard(S, [&]() -> dgswe_status {
+    const dgswe_status st = check_member(S, member);
+    if (st != DGSWE_OK) return st;
+    const MemberHost &h = S->mh[member];
+    const Member &f = S->mem[member];
+    if (h.ne > DGSWE_NOALLOC_MAX_ELEMS)
+      return fail(S, DGSWE_E_INVALID, "member has " + std::to_string(h.ne) +
+                                          " elements; the allocation-free read-back takes at most " +
+                                          std::to_string(DGSWE_NOALLOC_MAX_ELEMS));
+    double *scr = nullptr;
+    hipError_t e = scratch_on(S->device, &scr);
+    if (e != hipSuccess) return hip_fail(S, e, "hipGetSymbolAddress (read-back scratch)");
+    const int pp = h.cur_is_pp ? 0 : 1;
+    if (w_dev) {
+      if (S->order == 2)
+        e = launch_post_only2(S->m, S->prm, S->s.buf[S->cur], pp, f.e0, f.ne, w_dev, S->m.perm, S->precision,
+                              S->stream);
+      else
+        e = launch_post_only(S->m, S->s, S->prm, S->s.buf[S->cur], pp, f.e0, f.ne, w_dev, S->m.perm, S->precision,
+                             S->stream);
+      if (e != hipSuccess) return hip_fail(S, e, "post-processing kernel");
+    }
+    if (diag_dev) {
+      double *sums = scr + 3 * (size_t)kNoAllocBlocks;
+      e = launch_diag(S->m, S->prm, S->s.buf[S->cur], f.e0, f.ne, scr, sums, S->stream);
+      if (e == hipSuccess)
+        e = launch_diag_pack(S->s.ctrl + member, (int)(S->steps_enq & 1), f.ne, sums, diag_dev, S->stream);
+      if (e != hipSuccess) return hip_fail(S, e, "diagnostics kernel");
+    }
+    return DGSWE_OK;
   });
 }
 

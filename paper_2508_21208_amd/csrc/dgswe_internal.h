@@ -55,6 +55,7 @@ struct DevMesh {
   const double *inr2;                   // 2 x inradius
   const double *hbv;                    // [3][ne] bathymetry at the element's vertices
   const int *el_nb;                     // [3][ne] neighbour across local edge, -1 none
+  const int *perm;                      // [ne] the caller's index of each element within its member
   // nodes
   const double *node_x, *node_y;
   // vertex-based limiter only.  Its node ranges are numbered in the order
@@ -207,17 +208,25 @@ constexpr int kStageBlocks[] = {256};
 // pp), e.g. to read a member back.
 // The vertex bounds of the limiter (limiter = 2) from the unlimited state win.
 hipError_t launch_vbounds(const DevMesh &m, const DevState &s, const void *win, int precision, hipStream_t st);
+// perm != nullptr: element e0 + i goes to column perm[e0 + i] (the caller's
+// order) instead of i.
 hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p, const void *win, int pp, int e0, int count,
-                            double *wout, int precision, hipStream_t st);
+                            double *wout, const int *perm, int precision, hipStream_t st);
 // Reset member `mb`'s control block to time t (both parities; pp_in: the
 // stored state still needs post-processing) and put the CFL candidates of
 // its elements [e0, e0 + count) in `w` into dtmin[slot].
 hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &p, const void *w, int mb, int e0,
                              int count, double t, int slot, int pp_in, int precision, int order, hipStream_t st);
 // mass, volume and wet count of elements [e0, e0 + count) of a state (its
-// zeta block is read)
-hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w, int e0, int count,
+// zeta block is read) into out4[0..2]; partial: 3 diag_blocks(count)
+// doubles of per-block partial sums
+hipError_t launch_diag(const DevMesh &m, const Params &p, const void *w, int e0, int count, double *partial,
                        double *out4, hipStream_t st);
+// the diagnostics of one member as 8 doubles (t, dt_last, mass, volume,
+// steps, n_wet, n_dry, status) from its control block (time of parity
+// slot) and the sums launch_diag left in sums3
+hipError_t launch_diag_pack(const Ctrl *ctl, int slot, int count, const double *sums3, double *out8,
+                            hipStream_t st);
 // p = 2: post-processing of a stage input (raw state, structure of arrays)
 // into element records (the first stage also checks the time step and resets
 // the next CFL minimum), then the RK stage from those records (and, in the
@@ -227,9 +236,10 @@ hipError_t launch_pp2(const DevMesh &m, const DevState &s, const Params &p, cons
 hipError_t launch_rhs2(const DevMesh &m, const DevState &s, const Params &p, const void *rec, const void *rbase,
                        void *wout, int slot, int first, const StageCoef &sc, int want_dt, int precision,
                        hipStream_t st);
-// p = 2 read-back: elements [e0, e0 + count) as FP64 [18][count]
+// p = 2 read-back: elements [e0, e0 + count) as FP64 [18][count] (perm as
+// for launch_post_only)
 hipError_t launch_post_only2(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
-                             double *wout, int precision, hipStream_t st);
+                             double *wout, const int *perm, int precision, hipStream_t st);
 size_t stage_lds_bytes(const DevMesh &m, int precision);
 // LDS one stage-kernel workgroup may use (two workgroups share a CU's 160 KB)
 constexpr size_t kStageLdsMax = 80 * 1024;

@@ -864,12 +864,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 // [9][count], for read-back
 template <class QT>
 __global__ __launch_bounds__(kBlock) void k_post_only(DevMesh m, Params p, const double *vb, CSt<QT> win, int pp,
-                                                      int e0, int count, double *__restrict__ wout) {
+                                                      int e0, int count, double *__restrict__ wout,
+                                                      const int *__restrict__ perm) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= count) return;
   double u[9];
   load_pp_global<QT>(m, p, vb, win, e0 + i, pp != 0, u);
-  for (int j = 0; j < 9; ++j) wout[(size_t)j * count + i] = u[j];
+  const int c = perm ? perm[e0 + i] : i;
+  for (int j = 0; j < 9; ++j) wout[(size_t)j * count + c] = u[j];
 }
 
 // Vertex-based limiter: per mesh node (range slot n), the smallest and
@@ -928,8 +930,8 @@ __global__ __launch_bounds__(kBlock) void k_init(DevMesh m, Ctrl *ctl, Params p,
 // block adds the partials in a fixed order: deterministic.  Mean depth and
 // zeta mean are unchanged by the post-processing, so the unlimited state
 // gives the same values; z is the zeta block of a state buffer.
-__global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, DevState s, Params p, const double *__restrict__ z,
-                                                  int e0, int count) {
+__global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, Params p, const double *__restrict__ z, int e0,
+                                                  int count, double *__restrict__ partial) {
   __shared__ double sm[3][kBlock];
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const int e = e0 + i;
@@ -952,17 +954,17 @@ __global__ __launch_bounds__(kBlock) void k_diag1(DevMesh m, DevState s, Params 
   }
   if (threadIdx.x == 0) {
     const int nb = gridDim.x;
-    s.partial[blockIdx.x] = sm[0][0];
-    s.partial[nb + blockIdx.x] = sm[1][0];
-    s.partial[2 * nb + blockIdx.x] = sm[2][0];
+    partial[blockIdx.x] = sm[0][0];
+    partial[nb + blockIdx.x] = sm[1][0];
+    partial[2 * nb + blockIdx.x] = sm[2][0];
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_diag2(DevState s, int nb, double *out) {
+__global__ __launch_bounds__(kBlock) void k_diag2(const double *__restrict__ partial, int nb, double *out) {
   __shared__ double sm[3][kBlock];
   double acc[3] = {0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < nb; i += kBlock)
-    for (int q = 0; q < 3; ++q) acc[q] += s.partial[(size_t)q * nb + i];
+    for (int q = 0; q < 3; ++q) acc[q] += partial[(size_t)q * nb + i];
   for (int q = 0; q < 3; ++q) sm[q][threadIdx.x] = acc[q];
   __syncthreads();
   for (int st = kBlock / 2; st > 0; st >>= 1) {
@@ -974,8 +976,22 @@ __global__ __launch_bounds__(kBlock) void k_diag2(DevState s, int nb, double *ou
     out[0] = sm[0][0];
     out[1] = sm[1][0];
     out[2] = sm[2][0];
-    out[3] = 0.0;
   }
+}
+
+// One member's diagnostics as 8 doubles: t, dt_last, mass, volume, steps,
+// n_wet, n_dry, status.
+__global__ void k_diag_pack(const Ctrl *__restrict__ ctl, int slot, int count, const double *__restrict__ sums,
+                            double *__restrict__ out) {
+  if (threadIdx.x != 0) return;
+  out[0] = ctl->t[slot];
+  out[1] = ctl->dt_last;
+  out[2] = sums[0];
+  out[3] = sums[1];
+  out[4] = (double)ctl->steps;
+  out[5] = sums[2];
+  out[6] = (double)count - sums[2];
+  out[7] = (double)ctl->status;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1049,7 +1065,7 @@ hipError_t launch_vbounds(const DevMesh &m, const DevState &s, const void *win, 
 }
 
 hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p, const void *win, int pp, int e0,
-                            int count, double *wout, int precision, hipStream_t st) {
+                            int count, double *wout, const int *perm, int precision, hipStream_t st) {
   const size_t ne = (size_t)m.ne;
   if (count <= 0) return hipSuccess;
   if (pp && p.limiter == 2) {
@@ -1058,10 +1074,10 @@ hipError_t launch_post_only(const DevMesh &m, const DevState &s, const Params &p
   }
   if (precision == DGSWE_MIXED)
     hipLaunchKernelGGL(k_post_only<float>, dim3(nblk(count)), dim3(kBlock), 0, st, m, p, (const double *)s.vb,
-                       csplit<float>(win, ne), pp, e0, count, wout);
+                       csplit<float>(win, ne), pp, e0, count, wout, perm);
   else
     hipLaunchKernelGGL(k_post_only<double>, dim3(nblk(count)), dim3(kBlock), 0, st, m, p, (const double *)s.vb,
-                       csplit<double>(win, ne), pp, e0, count, wout);
+                       csplit<double>(win, ne), pp, e0, count, wout, perm);
   return hipGetLastError();
 }
 
@@ -1081,11 +1097,17 @@ hipError_t launch_init_state(const DevMesh &m, const DevState &s, const Params &
   return hipGetLastError();
 }
 
-hipError_t launch_diag(const DevMesh &m, const DevState &s, const Params &p, const void *w, int e0, int count,
+hipError_t launch_diag(const DevMesh &m, const Params &p, const void *w, int e0, int count, double *partial,
                        double *out4, hipStream_t st) {
   const int nb = (int)nblk(count > 0 ? count : 1);
-  hipLaunchKernelGGL(k_diag1, dim3(nb), dim3(kBlock), 0, st, m, s, p, (const double *)w, e0, count);
-  hipLaunchKernelGGL(k_diag2, dim3(1), dim3(kBlock), 0, st, s, nb, out4);
+  hipLaunchKernelGGL(k_diag1, dim3(nb), dim3(kBlock), 0, st, m, p, (const double *)w, e0, count, partial);
+  hipLaunchKernelGGL(k_diag2, dim3(1), dim3(kBlock), 0, st, (const double *)partial, nb, out4);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_pack(const Ctrl *ctl, int slot, int count, const double *sums3, double *out8,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_pack, dim3(1), dim3(64), 0, st, ctl, slot, count, sums3, out8);
   return hipGetLastError();
 }
 

@@ -611,12 +611,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 // [18][count], for read-back
 template <class QT>
 __global__ __launch_bounds__(kBlock) void k_post_only2(DevMesh m, Params p, CSt<QT> win, int pp, int e0, int count,
-                                                       double *__restrict__ wout) {
+                                                       double *__restrict__ wout, const int *__restrict__ perm) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= count) return;
   double u[18];
   load_pp2<QT>(m, p, win, e0 + i, pp != 0, u);
-  for (int j = 0; j < 18; ++j) wout[(size_t)j * count + i] = u[j];
+  const int c = perm ? perm[e0 + i] : i;
+  for (int j = 0; j < 18; ++j) wout[(size_t)j * count + c] = u[j];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -681,16 +682,16 @@ hipError_t launch_rhs2(const DevMesh &m, const DevState &s, const Params &p, con
 }
 
 hipError_t launch_post_only2(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,
-                             double *wout, int precision, hipStream_t st) {
+                             double *wout, const int *perm, int precision, hipStream_t st) {
   const size_t ne = (size_t)m.ne;
   if (count <= 0) return hipSuccess;
   if (precision == DGSWE_MIXED)
     hipLaunchKernelGGL(k_post_only2<float>, dim3(nblk2(count)), dim3(kBlock), 0, st, m, p,
                        CSt<float>{(const double *)win, (const float *)((const double *)win + 6 * ne)}, pp, e0, count,
-                       wout);
+                       wout, perm);
   else
     hipLaunchKernelGGL(k_post_only2<double>, dim3(nblk2(count)), dim3(kBlock), 0, st, m, p,
-                       CSt<double>{(const double *)win, (const double *)win + 6 * ne}, pp, e0, count, wout);
+                       CSt<double>{(const double *)win, (const double *)win + 6 * ne}, pp, e0, count, wout, perm);
   return hipGetLastError();
 }
 

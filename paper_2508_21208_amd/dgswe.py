@@ -28,7 +28,7 @@ EXPORTED = ("dgswe_default_params", "dgswe_create_mesh", "dgswe_set_state", "dgs
             "dgswe_member_set_state", "dgswe_member_set_forcing", "dgswe_member_read_state",
             "dgswe_member_info", "dgswe_create_pool", "dgswe_prepare_mesh", "dgswe_prepared_free",
             "dgswe_prepared_elems", "dgswe_member_add_prepared", "dgswe_member_add", "dgswe_member_remove",
-            "dgswe_pool_usage", "dgswe_use_graphs")
+            "dgswe_pool_usage", "dgswe_use_graphs", "dgswe_member_read_state_device")
 
 
 class dgswe_params(C.Structure):
@@ -136,6 +136,8 @@ def load_library(path: str = LIB_PATH):
     L.dgswe_pool_usage.restype = C.c_int
     L.dgswe_use_graphs.argtypes = [vp, C.c_int32]
     L.dgswe_use_graphs.restype = C.c_int
+    L.dgswe_member_read_state_device.argtypes = [vp, C.c_int32, vp, vp]
+    L.dgswe_member_read_state_device.restype = C.c_int
     _lib = L
     return L
 
@@ -325,6 +327,14 @@ def dgswe_read_state(h, w_out=None, diag=True, member=None):
     st = L.dgswe_read_state(h, wp, dd) if member is None else L.dgswe_member_read_state(h, int(member), wp, dd)
     _check(h, st)
     return d
+
+
+def dgswe_member_read_state_device(h, member, w_dev_ptr, diag_dev_ptr):
+    """Enqueue the member's post-processed state and its 8 diagnostics into
+    caller-owned device memory (integer addresses, 0 for none) on the
+    solver's stream; allocates nothing and does not wait."""
+    _check(h, load_library().dgswe_member_read_state_device(h, int(member), C.c_void_p(int(w_dev_ptr) or None),
+                                                                C.c_void_p(int(diag_dev_ptr) or None)))
 
 
 def dgswe_destroy(h):
