@@ -107,7 +107,12 @@ def test_rechunked_mesh_of_isolated_triangles():
     wl = W.Workload("isolated_700", m, W.state_from_nodal(m.tri, zn), W.default_params(),
                     W.default_forcing(manning_n=0.02), 100)
     wg, dg, wo, o = run_both(wl, 100)
-    check(wg, dg, wo, o)
+    # each closed basin's momentum decays tenfold every 10 steps (the wall
+    # flux damps it) to ~1e-10 of its size after the first steps, the
+    # residue of wall pressure terms of O(10) that cancel: its error is
+    # measured against that early momentum scale (L2 norm ~0.1), not
+    # against the residue
+    check(wg, dg, wo, o, qscale=1e-2)
     # the mixed path (smaller LDS per chunk, chunked on its own) within its bar
     s = Solver(m, dict(wl.params, precision=1), wl.forcing)
     s.set_state(wl.w0)
