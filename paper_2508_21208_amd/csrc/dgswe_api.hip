@@ -149,8 +149,8 @@ class Arena {
 };
 
 // arenas: elements, nodes, local elements (chunk + ring 1 of each chunk),
-// chunk-local edges, ring-2 entries (+1 sentinel per member), edges (p = 2)
-enum ArenaId { A_ELEM = 0, A_NODE, A_LOC, A_LEDGE, A_RING2, A_EDGE, A_COUNT };
+// chunk-local edges, ring-2 entries (+1 sentinel per member)
+enum ArenaId { A_ELEM = 0, A_NODE, A_LOC, A_LEDGE, A_RING2, A_COUNT };
 
 // Host view of one member (slot).
 struct MemberHost {
@@ -426,18 +426,18 @@ bool chunks_fit(const Prep &P, int precision, int block) {
   return stage_lds_bytes(t, precision) <= kStageLdsMax;
 }
 
-// Host preprocessing of one mesh for the solver's order and chunking.  At
-// p = 1, a mesh whose chunks of `chunk` elements have halos too large for
-// the stage kernel is chunked again with 32 fewer elements per chunk, and
-// so on: at 64 every mesh fits (at most 256 local elements, 192 local
-// edges, about 50 KB of LDS), so no valid mesh is refused.  The p = 2
-// kernels use only the chunk ranges, not the halos.
+// Host preprocessing of one mesh for the solver's order and chunking.  A
+// mesh whose chunks of `chunk` elements have halos too large for the stage
+// kernel is chunked again with 32 fewer elements per chunk, and so on: at
+// 64 every mesh fits (at most 256 local elements, 192 local edges, about
+// 50 KB of LDS at p = 1), so no valid mesh is refused.  The p = 2 kernels
+// take a chunk's local edges (two per lane) but not its halo elements.
 int prep_one(const dgswe_mesh &d, int order, int precision, int chunk, int block, Prep &P, std::string &msg) {
   int rc = prepare_mesh(d.n_nodes, d.node_xy, d.node_hb, d.n_elems, d.tri, d.n_bnd, d.bnd_nodes, d.bnd_type, P, msg);
   if (rc != DGSWE_OK) return rc;
   for (int c = chunk;; c = std::max(64, c - 32)) {
     build_chunks(P, c);
-    if (order == 2 || chunks_fit(P, precision, block)) break;
+    if (order == 2 ? P.ed_max <= 2 * block : chunks_fit(P, precision, block)) break;
     if (c == 64) {
       msg = "element chunks have halos too large for the stage kernel";
       return DGSWE_E_MESH;
@@ -454,7 +454,6 @@ void arena_need(const Prep &q, int order, long long need[A_COUNT]) {
   need[A_LOC] = q.lo_off[q.nch];
   need[A_LEDGE] = q.le_off[q.nch];
   need[A_RING2] = (long long)q.h2_off[q.nch] + 1;
-  need[A_EDGE] = order == 2 ? q.ned : 0;
 }
 
 bool chunk_config(const dgswe_params *prm, int &chunk, int &block) {
@@ -503,7 +502,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   auto chk = [&](hipError_t x) { if (x != hipSuccess) ok = false; };
   const size_t E = (size_t)std::max(1LL, cap[A_ELEM]), N = (size_t)std::max(1LL, cap[A_NODE]);
   const size_t L = (size_t)std::max(1LL, cap[A_LOC]), LE = (size_t)std::max(1LL, cap[A_LEDGE]);
-  const size_t R2 = (size_t)std::max(1LL, cap[A_RING2]), D = (size_t)std::max(1LL, cap[A_EDGE]);
+  const size_t R2 = (size_t)std::max(1LL, cap[A_RING2]);
   DevMesh &m = S->m;
   m = DevMesh{};
   m.ne = (int)E; m.nn = (int)N; m.ned = 0;
@@ -520,7 +519,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   else { al(&m.eg1, E); al(&m.eg2, E); al(&m.le_a, LE); al(&m.le_b, LE); }
   al(&m.lgid, L); al(&m.lhb01, L); al(&m.lhb2, L); al(&m.lnb, L);
   al(&m.h2, R2);
-  if (S->order == 2) { al(&m.e2edge, 3 * E); al(&m.hmean, E); al(&m.ed2a, D); al(&m.ed2b, D); }
+  if (S->order == 2) al(&m.hmean, E);
   if (pp.limiter == 2 && 3 * E > 0x7fffffffULL) ok = false;  // incidence positions are int
   if (pp.limiter == 2) { al(&m.nd_rng, N); al(&m.nd_el, 3 * E); al(&m.evb, E); }
   chk(dev_alloc(S, &S->d_chunk_rec, (size_t)std::max(1, chunk_cap) * kChunkRec));
@@ -688,20 +687,7 @@ dgswe_status place_member(dgswe_solver *S, int slot, const Prep &q) {
     for (int i = 0; i < q.h2_off[q.nch]; ++i) r2[(size_t)i] = q.h2[(size_t)i] + e0;
     chk(put(m.h2, (size_t)off[A_RING2], r2.data(), r2.size()));
   }
-  if (S->order == 2) {
-    const int d0 = (int)off[A_EDGE];
-    std::vector<int> code(ne);
-    for (size_t k = 0; k < 3; ++k) {
-      for (size_t i = 0; i < ne; ++i) {
-        const int c = q.el_edge[k * ne + i];
-        code[i] = (((c >> 1) + d0) << 1) | (c & 1);
-      }
-      chk(put(m.e2edge, k * E + e0, code.data(), ne));
-    }
-    chk(put(m.hmean, e0, q.hmean.data(), ne));
-    chk(put(m.ed2a, (size_t)d0, q.ed2a.data(), (size_t)q.ned));
-    chk(put(m.ed2b, (size_t)d0, q.ed2b.data(), (size_t)q.ned));
-  }
+  if (S->order == 2) chk(put(m.hmean, e0, q.hmean.data(), ne));
   if (e != hipSuccess) {
     for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(off[a], need[a]);
     return hip_fail(S, e, "upload");
@@ -812,7 +798,6 @@ void pool_caps(long long max_elems, int slots, int order, long long cap[A_COUNT]
   cap[A_LOC] = 2 * E + 512 * M;
   cap[A_LEDGE] = 2 * E + 512 * M;
   cap[A_RING2] = E + 256 * M;
-  cap[A_EDGE] = order == 2 ? 2 * E + 3 * M : 0;
   chunk_cap = (int)(E / 64 + 2 * M + 1);
 }
 

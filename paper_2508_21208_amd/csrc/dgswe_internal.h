@@ -92,12 +92,7 @@ struct DevMesh {
   // (the bathymetry at the edge ends is the e+ element's, read from LDS)
   const double2 *le_a, *le_b;  // FP64: (nx, ny), (len/2, ids as bits)
   const float4 *le_f;          // mixed: (nx, ny, len/2, ids as bits)
-  // p = 2 kernels (element-centric): edge of local edge l of element e as
-  // (edge << 1 | 1 if e is the edge's e- side) [3][ne]; per edge (nx, ny)
-  // from e+ to e- and (len/2, lp | lm << 2 | type << 4 as bits); mean
-  // bathymetry per element
-  const int *e2edge;
-  const double2 *ed2a, *ed2b;
+  // p = 2: mean bathymetry per element (the wet/dry test of a neighbour)
   const double *hmean;
 };
 
@@ -155,7 +150,6 @@ struct Prep {
   std::vector<int> ch_off, h1_off, h1, h2_off, h2, le_off, le_gid, lo_off;
   std::vector<double> le_nx, le_ny, le_hl;                // per local edge
   // element-centric edge records of the p = 2 kernels (see DevMesh)
-  std::vector<double2> ed2a, ed2b;
   std::vector<double> hmean;
   std::vector<uint32_t> le_ids;                            // packed ids (see DevMesh)
   std::vector<uint16_t> el_ledge;                          // [3][ne] local edge code per local edge
@@ -181,7 +175,7 @@ void chunk_records(const Prep &P, const std::vector<int> &chunk_member, std::vec
 // local edge codes).
 void build_chunks(Prep &P, int C);
 
-// The p = 2 records (ed2a, ed2b, hmean) of a (merged) mesh from its edges.
+// The p = 2 per-element mean bathymetry (hmean).
 void p2_records(Prep &P);
 
 // Returns 0 on success, else a DGSWE status code with a message in `err`.

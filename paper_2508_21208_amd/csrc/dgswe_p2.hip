@@ -5,19 +5,24 @@
 // edges).
 //
 // Two kernels per RK stage, one workgroup per chunk of 256 consecutive
-// (Hilbert-ordered) elements, one lane per element, no LDS:
+// (Hilbert-ordered) elements:
 //   k_pp2   slope limiter + wet/dry of the stage input (raw state, structure
 //           of arrays) into a post-processed copy, one 16-byte-aligned record
 //           per element (144 B in FP64), so a neighbour's state is a few
 //           contiguous 16-byte loads;
-//   k_rhs2  volume and source integrals at the six area points, the three
-//           edges of the element at four Gauss-Lobatto points each, inverse
-//           mass diagonal and the Shu-Osher RK combination, written raw.
-// An interior edge is evaluated by both of its elements, each in the edge's
-// own orientation (its e+ side first) with the same arithmetic, so both get
-// bitwise the same flux and each takes its side: no edge buffer, no atomics,
-// mass conserved to rounding.  The post-processed stage-1 input (the RK base
-// of stage 2) is kept as the first stage's record buffer.
+//   k_rhs2  first every edge touching the chunk, once, one lane per edge:
+//           both sides' traces at the four Gauss-Lobatto points from the
+//           records, the wet/dry edge rules and the numerical flux, into
+//           LDS (Algorithm 2's edge pass); then one lane per element: the
+//           volume and source integrals at the six area points, its three
+//           edges' fluxes from LDS in a fixed order (Algorithms 1 and 3),
+//           inverse mass diagonal and the Shu-Osher RK combination, written
+//           raw.
+// An edge on a chunk border is evaluated by both chunks it touches, with the
+// same instructions on the same records, so both get bitwise the same flux:
+// no edge buffer in HBM, no atomics, mass conserved to rounding.  The
+// post-processed stage-1 input (the RK base of stage 2) is kept as the first
+// stage's record buffer.
 //
 // Precision as in the p = 1 path: QT is the storage type of the momentum
 // modes and the arithmetic type of flux, volume and source terms; zeta,
@@ -89,11 +94,16 @@ HD void edge_point2(int l, double s, double &xi, double &eta) {
   eta = ay * 0.5 * (1.0 - s) + by * 0.5 * (1.0 + s);
 }
 
-// packed edge info (lp | lm << 2 | type << 4) stored in the low bits of a double
+// packed ids stored in the low bits of a double / in a float
 HD uint32_t info_bits(double v) {
   union { double d; unsigned long long u; } x;
   x.d = v;
   return (uint32_t)x.u;
+}
+HD uint32_t info_bits(float v) {
+  union { float f; uint32_t u; } x;
+  x.f = v;
+  return x.u;
 }
 
 // ---------------------------------------------------------------- records
@@ -286,6 +296,114 @@ HD double edge_hb(double hA, double hB, int g) {
 // of e+, no-flood wall of e- (normal -n), nothing.
 enum EdgeKind { EK_LLF = 0, EK_LLF_P, EK_WALL_P, EK_WALL_M, EK_NONE };
 
+// ---------------------------------------------------------------- edges in LDS
+// The right-hand side works per chunk: every chunk-local edge (the edges
+// touching the chunk's elements, chunk-border edges included) is evaluated
+// once, by one lane, into LDS; then each chunk element integrates its three
+// edges from there.  A border edge is evaluated by both chunks it touches,
+// with the same instructions on the same records, so both sides get bitwise
+// the same flux.  Per edge: the flux at the four Gauss-Lobatto points that
+// its receiving side(s) integrate, in the edge's orientation (zeta part
+// FP64 holding the QT value, momentum in QT), half its length, its kind.
+template <class QT>
+struct Lds2 {
+  double *fz;           // [4][eds]
+  double *hl;           // [eds]
+  QT *fq;               // [8][eds]: x flux at g = 0..3, then y
+  unsigned char *kind;  // [eds]
+  int eds;
+};
+
+template <class QT>
+HD size_t lds2_bytes(int ed_max) {
+  return (size_t)ed_max * (5 * sizeof(double) + 8 * sizeof(QT) + 1);
+}
+
+template <class QT>
+HD Lds2<QT> lds2_view(int ed_max, void *base) {
+  Lds2<QT> L;
+  L.eds = ed_max;
+  L.fz = (double *)base;
+  L.hl = L.fz + 4 * (size_t)ed_max;
+  L.fq = (QT *)(L.hl + (size_t)ed_max);
+  L.kind = (unsigned char *)(L.fq + 8 * (size_t)ed_max);
+  return L;
+}
+
+// Chunk-local edge j: both sides' traces from the records, the wet/dry
+// rules (as for p = 1), the flux at the four points into LDS.
+template <class QT>
+HD void edge_phase2(const DevMesh &m, const Params &p, const ChunkInfo &k, const Rec2<QT> *__restrict__ u,
+                    double zb, int j, const Lds2<QT> &L) {
+  using R = QT;
+  const size_t r = (size_t)(k.leo + j);
+  R nx, ny;
+  double hl;
+  uint32_t ids;
+  if constexpr (sizeof(QT) == 8) {
+    const double2 a = m.le_a[r], b = m.le_b[r];
+    nx = a.x; ny = a.y; hl = b.x;
+    ids = info_bits(b.y);
+  } else {
+    const float4 a = m.le_f[r];
+    nx = a.x; ny = a.y; hl = (double)a.z;
+    ids = info_bits(a.w);
+  }
+  const int info = (int)(ids >> 24);
+  const int lp = info & 3, lm = (info >> 2) & 3, type = info >> 4;
+  const int ip = (int)(ids & 0xFFFu), im = (int)((ids >> 12) & 0xFFFu);
+  const bool ghost = type != 0;
+  const int gp = m.lgid[k.lo + ip];
+  const int gm = ghost ? gp : m.lgid[k.lo + im];
+  // bathymetry at the edge ends: vertices lp+1 (s = -1) and lp+2 (s = +1) of e+
+  const double2 h01 = m.lhb01[k.lo + ip];
+  const double h2 = m.lhb2[k.lo + ip];
+  const int va = lp == 2 ? 0 : lp + 1, vb = lp == 0 ? 2 : lp - 1;
+  const double hA = va == 0 ? h01.x : (va == 1 ? h01.y : h2);
+  const double hB = vb == 0 ? h01.x : (vb == 1 ? h01.y : h2);
+  const bool wetp = p.wetdry ? (u[gp].z[0] + m.hmean[gp] > p.h0) : true;
+  const bool wetm = ghost ? (p.wetdry ? (zb + 0.5 * (hA + hB) > p.h0) : true)
+                          : (p.wetdry ? (u[gm].z[0] + m.hmean[gm] > p.h0) : true);
+  // e+ and e- traces; a ghost e- side is (zeta_b, momentum of e+)
+  double pz[4], mz[4];
+  R px[4], py[4], mx[4], my[4];
+  traces_of<QT>(u, gp, lp, false, pz, px, py);
+  if (ghost) {
+    for (int g = 0; g < 4; ++g) { mz[g] = zb; mx[g] = px[g]; my[g] = py[g]; }
+  } else {
+    traces_of<QT>(u, gm, lm, true, mz, mx, my);
+  }
+  int kind;
+  if (type == DGSWE_BC_LAND) kind = EK_WALL_P;
+  else if (!wetp && !wetm) kind = EK_NONE;
+  else if (wetp && wetm) kind = ghost ? EK_LLF_P : EK_LLF;
+  else {
+    // one side dry: the sign of the LLF mass flux decides
+    R mf = (R)0;
+    for (int g = 0; g < 4; ++g) {
+      R Fg[3];
+      llf<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], edge_hb(hA, hB, g), nx, ny, wetp, wetm, Fg);
+      mf += (R)gl4_w(g) * Fg[0];
+    }
+    const bool flood = wetp ? (mf > (R)0) : (mf < (R)0);
+    kind = flood ? (ghost ? EK_LLF_P : EK_LLF) : (wetp ? EK_WALL_P : (ghost ? EK_NONE : EK_WALL_M));
+  }
+  for (int g = 0; g < 4; ++g) {
+    R Fg[3] = {(R)0, (R)0, (R)0};
+    const double hq = edge_hb(hA, hB, g);
+    if (kind == EK_WALL_P) wall<R>(p.g, pz[g], px[g], py[g], hq, nx, ny, wetp, Fg);
+    else if (kind == EK_WALL_M) wall<R>(p.g, mz[g], mx[g], my[g], hq, -nx, -ny, wetm, Fg);
+    else if (kind == EK_NONE) {
+    } else if (p.flux == 1 && wetp && wetm) roe<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], hq, nx, ny, Fg);
+    else llf<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], hq, nx, ny, wetp, wetm, Fg);
+    L.fz[g * L.eds + j] = (double)Fg[0];
+    L.fq[g * L.eds + j] = Fg[1];
+    L.fq[(4 + g) * L.eds + j] = Fg[2];
+  }
+  L.hl[j] = hl;
+  L.kind[j] = (unsigned char)kind;
+}
+
 // ---------------------------------------------------------------- kernels
 // Post-processing of one stage input into records.  The first stage also
 // does the step's bookkeeping: ALLDRY when no time step is defined, and the
@@ -323,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_pp2(DevMesh m, DevState s, Params p,
 template <class QT>
 HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const ChunkInfo &k, const Member &F,
                      const Rec2<QT> *__restrict__ u, const Rec2<QT> *__restrict__ base, const StageCoef &sc, int i,
-                     double t0, double dt, double out[6], QT oqv[12], double &cand) {
+                     const Lds2<QT> &L, double out[6], QT oqv[12], double &cand, double dt) {
   using R = QT;
   const size_t ne = (size_t)m.ne;
   const int e = k.c0 + i;
@@ -371,21 +489,11 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   const R dpx = pm1 * g1x + pm2 * g2x, dpy = pm1 * g1y + pm2 * g2y;
   const R man = manning_of(m, k, i, (QT)0);
 
-  // the edges' codes, neighbours, length/type records and the neighbours'
-  // wet flags, fetched before the area integrals so that the edge loop does
-  // not wait for them
-  int ecode[3], enb[3];
-  for (int l = 0; l < 3; ++l) {
-    ecode[l] = m.e2edge[(size_t)l * ne + e];
-    enb[l] = m.el_nb[(size_t)l * ne + e];
-  }
-  bool owv[3];
-  double2 ebv[3];
-  for (int l = 0; l < 3; ++l) {
-    const int o = enb[l] >= 0 ? enb[l] : e;
-    owv[l] = p.wetdry ? (u[o].z[0] + m.hmean[o] > p.h0) : true;
-    ebv[l] = m.ed2b[ecode[l] >> 1];
-  }
+  // chunk-local edge codes of the three local edges (edge << 1 | 1 on the
+  // e- side)
+  const int4 nw = m.enode[e];
+  int ecode[3];
+  for (int l = 0; l < 3; ++l) ecode[l] = (nw.w >> (10 * l)) & 0x3FF;
 
   // area part: rz[k] = (1/A) sum_q w_q A grad phi_k . F_zeta (FP64 sums of
   // R terms), rq[v][k] likewise for the momentum rows with the sources
@@ -456,80 +564,30 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   }
 
   rz[0] += F.rain;  // uniform rain projects on mode 0 alone
-  // edges: each evaluated in its own orientation with both sides' traces
-  const double ts = t0 + sc.c * dt;
-  const bool tide = F.n_tide > 0 || F.tide_offset != 0.0;
-  const double zb = tide ? tide_level(F, ts) : 0.0;
+  // edges, from LDS: the side takes the flux its kind gives it, e- with the
+  // opposite sign for a flux both sides share, integrated with its own basis
+  // (e- runs the edge backwards)
 #pragma unroll 1
   for (int l = 0; l < 3; ++l) {
-    const int code = ecode[l];
-    const int d = code >> 1;
-    const bool minus = (code & 1) != 0;
-    const double2 en = m.ed2a[d], eb = ebv[l];
-    const uint32_t info = info_bits(eb.y);
-    const int lp = info & 3, lm = (info >> 2) & 3, type = (int)(info >> 4) & 3;
-    const int f = enb[l];
-    // the other element (itself on a boundary edge, which has no e- side)
-    const int o = f >= 0 ? f : e;
-    const bool owet = owv[l];
-    // bathymetry at the edge ends (s = -1: vertex lp+1 of e+, which is
-    // vertex lm+2 of e-; s = +1: vertex lp+2 of e+, vertex lm+1 of e-)
-    const int va = minus ? (lm == 0 ? 2 : lm - 1) : (lp == 2 ? 0 : lp + 1);
-    const int vb = minus ? (lm == 2 ? 0 : lm + 1) : (lp == 0 ? 2 : lp - 1);
-    const double hA = h[va], hB = h[vb];
-    const R nx = (R)en.x, ny = (R)en.y;
-    const bool ghost = type != 0;
-    const bool wetp = minus ? owet : wet;
-    const bool wetm = ghost ? (p.wetdry ? (zb + 0.5 * (hA + hB) > p.h0) : true) : (minus ? wet : owet);
-    // e+ and e- traces, both elements of the edge running the same
-    // instructions on the same records (the records are selected, not the
-    // code); a ghost e- side is (zeta_b, momentum of e+)
-    double pz[4], mz[4];
-    R px[4], py[4], mx[4], my[4];
-    traces_of<QT>(u, minus ? o : e, lp, false, pz, px, py);
-    if (ghost) {
-      for (int g = 0; g < 4; ++g) { mz[g] = zb; mx[g] = px[g]; my[g] = py[g]; }
-    } else {
-      traces_of<QT>(u, minus ? e : o, lm, true, mz, mx, my);
-    }
-    int kind;
-    if (type == DGSWE_BC_LAND) kind = EK_WALL_P;
-    else if (!wetp && !wetm) kind = EK_NONE;
-    else if (wetp && wetm) kind = ghost ? EK_LLF_P : EK_LLF;
-    else {
-      // one side dry: the sign of the LLF mass flux decides
-      R mf = (R)0;
-      for (int g = 0; g < 4; ++g) {
-        R Fg[3];
-        llf<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], edge_hb(hA, hB, g), nx, ny, wetp, wetm, Fg);
-        mf += (R)gl4_w(g) * Fg[0];
-      }
-      const bool flood = wetp ? (mf > (R)0) : (mf < (R)0);
-      kind = flood ? (ghost ? EK_LLF_P : EK_LLF) : (wetp ? EK_WALL_P : (ghost ? EK_NONE : EK_WALL_M));
-    }
+    const int j = ecode[l] >> 1;
+    const bool minus = (ecode[l] & 1) != 0;
+    const int kind = L.kind[j];
     const bool take = minus ? (kind == EK_LLF || kind == EK_WALL_M) : (kind == EK_LLF || kind == EK_LLF_P || kind == EK_WALL_P);
     if (!take) continue;
     const R sg = (minus && kind == EK_LLF) ? (R)-1 : (R)1;
-    const double hlA = eb.x * iA;
+    const double hlA = L.hl[j] * iA;
 #pragma unroll 1
     for (int g = 0; g < 4; ++g) {
-      R Fg[3];
-      const double hq = edge_hb(hA, hB, g);
-      if (kind == EK_WALL_P) wall<R>(p.g, pz[g], px[g], py[g], hq, nx, ny, wetp, Fg);
-      else if (kind == EK_WALL_M) wall<R>(p.g, mz[g], mx[g], my[g], hq, -nx, -ny, wetm, Fg);
-      else if (p.flux == 1 && wetp && wetm) roe<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], hq, nx, ny, Fg);
-      else llf<R>(p.g, pz[g], px[g], py[g], mz[g], mx[g], my[g], hq, nx, ny, wetp, wetm, Fg);
-      // own basis at the point (e- runs the edge backwards)
       double xi, eta, fb[6];
       edge_point2(l, minus ? -gl4_s(g) : gl4_s(g), xi, eta);
       basis2(xi, eta, fb);
       const double wg = hlA * gl4_w(g);
-      const double fz = (double)(sg * Fg[0]) * wg;
-      const R fx = sg * Fg[1] * (R)wg, fy = sg * Fg[2] * (R)wg;
-      for (int j = 0; j < 6; ++j) {
-        rz[j] -= fz * fb[j];
-        rq[j] -= fx * (R)fb[j];
-        rq[6 + j] -= fy * (R)fb[j];
+      const double fz = (double)sg * L.fz[g * L.eds + j] * wg;
+      const R fx = sg * L.fq[g * L.eds + j] * (R)wg, fy = sg * L.fq[(4 + g) * L.eds + j] * (R)wg;
+      for (int jj = 0; jj < 6; ++jj) {
+        rz[jj] -= fz * fb[jj];
+        rq[jj] -= fx * (R)fb[jj];
+        rq[6 + jj] -= fy * (R)fb[jj];
       }
     }
   }
@@ -570,6 +628,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     DevMesh m, DevState s, Params p, const Rec2<QT> *__restrict__ u,
                                                  const Rec2<QT> *__restrict__ base, St<QT> wout, StageCoef sc,
                                                  int slot, int want_dt) {
+  extern __shared__ double lds2_raw[];
   __shared__ double red[kBlock / 64];
   const int c = chunk_of_block(blockIdx.x, m.nch);
   if (c < 0) return;
@@ -582,13 +641,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
   const unsigned long long dtbits = ctl->dtmin[slot];
   const double t0 = ctl->t[slot];
   double dt = 0.0;
-  // No lane leaves early (the CFL reduction has barriers): an inactive
-  // workgroup computes and stores nothing.
+  // No lane leaves early (the barriers must match): an inactive workgroup
+  // computes and stores nothing.
   const bool active = status == 0 && dt_from_bits(p, dtbits, dt);
   const bool act = active && tid < k.cc;
+  const Lds2<QT> L = lds2_view<QT>(m.ed_max, lds2_raw);
+  // edges of the chunk at the stage time (ocean tide), two per lane at most
+  if (active) {
+    const double ts = t0 + sc.c * dt;
+    const bool tide = F.n_tide > 0 || F.tide_offset != 0.0;
+    const double zb = tide ? tide_level(F, ts) : 0.0;
+    if (tid < k.ne_loc) edge_phase2<QT>(m, p, k, u, zb, tid, L);
+    if (tid + kBlock < k.ne_loc) edge_phase2<QT>(m, p, k, u, zb, tid + kBlock, L);
+  }
+  __syncthreads();
   double out[6], cand = INFINITY;
   QT oqv[12];
-  const bool fin = rhs2_element<QT>(m, s, p, k, F, u, base, sc, act ? tid : k.cc - 1, t0, dt, out, oqv, cand);
+  bool fin = true;
+  if (act) fin = rhs2_element<QT>(m, s, p, k, F, u, base, sc, tid, L, out, oqv, cand, dt);
   const int e = k.c0 + tid;
   if (act) {
     for (int j = 0; j < 6; ++j) wout.z[j * ne + e] = out[j];
@@ -623,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_post_only2(DevMesh m, Params p, CSt<
 // ---------------------------------------------------------------- launchers
 // register budget of k_rhs2 (waves per SIMD), overridable with the
 // environment variable DGSWE_RHS2_WPE = 1..4
-constexpr int kRhs2WpeFp64 = 2, kRhs2WpeMixed = 2;
+constexpr int kRhs2WpeFp64 = 3, kRhs2WpeMixed = 2;
 
 static inline unsigned nblk2(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -647,8 +717,9 @@ static void stage2_qt(const DevMesh &m, const DevState &s, const Params &p, cons
       return (w >= 1 && w <= 4) ? w : 0;
     }();
     const int wpe = wpe_env ? wpe_env : (p.waves ? p.waves : (sizeof(QT) == 8 ? kRhs2WpeFp64 : kRhs2WpeMixed));
+    const size_t lds = lds2_bytes<QT>(m.ed_max);
 #define DGSWE_RHS2(W) \
-  hipLaunchKernelGGL((k_rhs2<QT, W>), dim3(m.nch), dim3(kBlock), 0, st, m, s, p, r, b, o, sc, slot, want_dt)
+  hipLaunchKernelGGL((k_rhs2<QT, W>), dim3(m.nch), dim3(kBlock), lds, st, m, s, p, r, b, o, sc, slot, want_dt)
     switch (wpe) {
       case 1: DGSWE_RHS2(1); break;
       case 2: DGSWE_RHS2(2); break;

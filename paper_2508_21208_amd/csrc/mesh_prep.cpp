@@ -374,15 +374,7 @@ void build_chunks(Prep &P, int C) {
 namespace dgswe {
 
 void p2_records(Prep &P) {
-  const size_t ne = (size_t)P.ne, ned = (size_t)P.ned;
-  P.ed2a.resize(ned);
-  P.ed2b.resize(ned);
-  for (size_t d = 0; d < ned; ++d) {
-    union { double v; unsigned long long u; } x;
-    x.u = (unsigned long long)(uint32_t)P.ed_info[d];
-    P.ed2a[d] = make_double2(P.ed_nx[d], P.ed_ny[d]);
-    P.ed2b[d] = make_double2(P.ed_hlen[d], x.v);
-  }
+  const size_t ne = (size_t)P.ne;
   P.hmean.resize(ne);
   for (size_t e = 0; e < ne; ++e) P.hmean[e] = (P.hbv[e] + P.hbv[ne + e] + P.hbv[2 * ne + e]) / 3.0;
 }

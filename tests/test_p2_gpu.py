@@ -111,6 +111,26 @@ def test_p2_ragged_small_meshes(nx, ny):
     assert dg["steps"] == o.steps
 
 
+def test_p2_rechunked_mesh_of_isolated_triangles():
+    """700 triangles that share no edge: 768 local edges in a chunk of 256,
+    more than the kernel's two edges per lane, so the mesh is chunked more
+    finely; each closed basin's momentum decays towards the residue of
+    cancelling wall pressure terms, so it is measured against its early
+    scale (L2 norm ~0.1)"""
+    from _cases import isolated_triangles
+    m = isolated_triangles(700)
+    zn = 0.2 * np.sin(m.xy[:, 0] / 70.0) * np.cos(m.xy[:, 1] / 90.0)
+    wl = W.Workload("isolated_700", m, W.state_from_nodal(m.tri, zn), W.default_params(),
+                    W.default_forcing(manning_n=0.02), 60)
+    wg, dg, wo, o = run_both(wl, 60)
+    err = rel_l2(wg, wo)
+    for v in (1, 2):
+        err[v] = np.linalg.norm(wg[v] - wo[v]) / max(np.linalg.norm(wo[v]), 1e-2)
+    assert max(err) <= TOL, err
+    assert dg["steps"] == o.steps
+    assert dg["t"] == pytest.approx(o.t, rel=1e-12)
+
+
 def test_p2_hurricane_4m_full_size():
     wl = hurricane_4m()
     wg, dg, wo, o = run_both(wl, 2)
