@@ -41,7 +41,8 @@ METRIC = "elem-stage updates/s @4M tri p=1, FP64 vs mixed/batched; p50/p99 solve
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hurricane_4M.json")
 KERNEL_SOURCES = ("paper_2508_21208_amd/csrc/dgswe_kernels.hip", "paper_2508_21208_amd/csrc/dgswe_p2.hip",
-                  "paper_2508_21208_amd/csrc/dgswe_device.h",
+                  "paper_2508_21208_amd/csrc/dgswe_p1.h", "paper_2508_21208_amd/csrc/dgswe_p2.h",
+                  "paper_2508_21208_amd/csrc/dgswe_ens.hip", "paper_2508_21208_amd/csrc/dgswe_device.h",
                   "paper_2508_21208_amd/csrc/dgswe_internal.h", "paper_2508_21208_amd/csrc/mesh_prep.cpp",
                   "paper_2508_21208_amd/csrc/dgswe_api.hip")
 
@@ -91,12 +92,27 @@ B_ALG_P2 = {("k_pp2", "fp64"): 324.0, ("k_rhs2", "fp64"): 548.0,
             ("k_pp2", "mixed"): 228.0, ("k_rhs2", "mixed"): 408.0}
 
 
-def algorithmic_bytes(kernel: str, ne: int, ned: int, nn: int, precision: str = "fp64") -> float:
+def algorithmic_bytes(kernel: str, ne, ned: int, nn: int, precision: str = "fp64") -> float:
     """Algorithmic bytes of one launch: k_stage carries the whole p = 1
     stage (B_ALG_FP64 or B_ALG_MIXED per element), k_pp2 and k_rhs2 the
     p = 2 stage (B_ALG_P2); k_forcing reads node coordinates and writes the
     nodal wind stress and pressure (40 B per node); k_vbounds forms the
-    vertex-based limiter's node ranges."""
+    vertex-based limiter's node ranges.  For an ensemble of both orders ne
+    is {1: p = 1 elements, 2: p = 2 elements}: k_stage12 carries the p = 1
+    stage of the first and the p = 2 right-hand side of the second,
+    k_stage1pp2 the p = 1 stage and the p = 2 post-processing."""
+    if isinstance(ne, dict):
+        n1, n2 = ne.get(1, 0), ne.get(2, 0)
+        b1 = B_ALG_MIXED if precision == "mixed" else B_ALG_FP64
+        if kernel == "k_stage12":
+            return b1 * n1 + B_ALG_P2[("k_rhs2", precision)] * n2
+        if kernel == "k_stage1pp2":
+            return b1 * n1 + B_ALG_P2[("k_pp2", precision)] * n2
+        if kernel == "k_stage":
+            return b1 * n1
+        if (kernel, precision) in B_ALG_P2:
+            return B_ALG_P2[(kernel, precision)] * n2
+        ne = n1 + n2
     if kernel == "k_stage":
         return (B_ALG_MIXED if precision == "mixed" else B_ALG_FP64) * ne
     if (kernel, precision) in B_ALG_P2:
@@ -135,12 +151,13 @@ def stored_traffic(kernel: str, precision: str):
     return None if k is None else k["bytes_per_launch"]
 
 
-PROFILED = ("k_stage", "k_pp2", "k_rhs2")
+PROFILED = ("k_stage", "k_pp2", "k_rhs2", "k_stage12", "k_stage1pp2")
 
 
 def kernel_key(name: str):
-    """(kernel, 'fp64' | 'mixed') for a k_stage<NT, WPE, T, STAGE>,
-    k_pp2<T, STAGE> or k_rhs2<T, STAGE, WPE> kernel name, else None."""
+    """(kernel, 'fp64' | 'mixed') for a k_stage<NT, WPE, T, STAGE, VL, P>,
+    k_pp2<T, STAGE, P>, k_rhs2<T, WPE, P> or k_stage12<T, STAGE, WPE, P>
+    kernel name, else None."""
     for k in PROFILED:
         tag = k + "<"
         if tag in name:
@@ -271,7 +288,7 @@ def _omp_threads(n):
         return False
 
 
-def cpu_baseline(wl, steps=50, single_s=8.0):
+def cpu_baseline(wl, steps=50, single_s=12.0):
     """The FP64 oracle as it stands on the same mesh and forcing: `steps`
     steps on all the host threads OpenMP is given, then a bounded sample on
     one thread."""
@@ -439,52 +456,55 @@ def mixed_error_vs_oracle(stream):
     return out
 
 
-def measure_batched(ens, steps, warmup, stream, profile):
-    """The ensemble as one batch in mixed precision: (elapsed s, total
-    elements, members, per-kernel HIP-event times)."""
-    import torch
-    from paper_2508_21208_amd.dgswe import DGSWE_MIXED, Batch, dgswe_profile, dgswe_profile_read
-    ne = sum(w.mesh.n_elems for w in ens)
-    t0 = time.perf_counter()
-    b = Batch([w.mesh for w in ens], dict(ens[0].params, precision=DGSWE_MIXED), [w.forcing for w in ens],
-              hip_stream=stream.cuda_stream)
-    for i, w in enumerate(ens):
-        b.set_state(i, w.w0, 0.0, w.postprocess_initial)
-    log(f"batched: ready in {time.perf_counter() - t0:.1f} s")
-    b.step(warmup)
-    b.diagnostics(0)
-    torch.cuda.synchronize()
-    if profile:
-        dgswe_profile(b.h, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = dgswe_profile_read(b.h) if profile else {}
-    ts = [b.diagnostics(i)["t"] for i in range(len(ens))]
-    b.close()
-    log(f"batched: timed {steps} steps in {elapsed:.4f} s; member times {min(ts):.1f}-{max(ts):.1f} s")
-    kernels = {k: {"avg_us": 1e3 * ms / n, "launches": n, "total_ms": ms} for k, (ms, n) in prof.items() if n}
-    return elapsed, ne, len(ens), kernels
+def tune_ensemble_orders(ens, orders, stream):
+    """Chunk size (and at p = 2 the register budget) per order from the
+    autotuner, timed on the median-size member mesh of that order in mixed
+    precision; returns ({order: params}, {order: table})."""
+    from paper_2508_21208_amd import workloads as W
+    from paper_2508_21208_amd.autotune import tune
+    from paper_2508_21208_amd.dgswe import DGSWE_MIXED
+    out, tables = {}, {}
+    for p in (1, 2):
+        idx = sorted((i for i, o in enumerate(orders) if o == p), key=lambda i: ens[i].mesh.n_elems)
+        if not idx:
+            continue
+        w = ens[idx[len(idx) // 2]]
+        prm = dict(w.params, precision=DGSWE_MIXED, p=p, **({"cfl": 0.1} if p == 2 else {}))
+        w0 = w.w0 if p == 1 else np.concatenate([w.w0, np.zeros((3, 3, w.w0.shape[2]))], axis=1)
+        best, table = tune(w.mesh, prm, w.forcing, w0, w.postprocess_initial, steps=20, hip_stream=stream.cuda_stream,
+                           use_cache=False)
+        out[p] = {k: best[k] for k in ("chunk", "waves")}
+        tables[p] = {"mesh_elems": w.mesh.n_elems,
+                     "us_per_step": {f"chunk {r[0]}, waves {r[1]}": round(r[2], 1) for r in table}}
+        log(f"ensemble tuning p = {p} on {w.mesh.n_elems} triangles: {out[p]}")
+    return out, tables
 
 
-def measure_ensemble_orders(ens, steps, warmup, stream):
-    """The same ensemble with seeded orders p in {1, 2} per member, mixed
-    precision, 6-step graphs (dgswe.Ensemble: one batch per order)."""
+def measure_ensemble(ens, steps, warmup, stream, profile, tuned=None, fused=True, graphs=6, persistent=0,
+                     orders=None):
+    """The storm-surge ensemble (NEXT-2 configuration): seeded orders p in
+    {1, 2}, mixed precision, the p = 2 members at CFL 0.1, chunk sizes from
+    the autotuner, step graphs; fused: both orders advanced by
+    dgswe_step_pair (one stage launch for every member), else batch by
+    batch.  Returns the variant record; with profile the
+    kernels' HIP-event averages come from a second, plain (graph-free) run."""
     import torch
     from paper_2508_21208_amd import workloads as W
-    from paper_2508_21208_amd.dgswe import DGSWE_MIXED, Ensemble
-    orders = W.ensemble_orders(len(ens))
+    from paper_2508_21208_amd.dgswe import DGSWE_MIXED, Ensemble, dgswe_mesh_info, dgswe_profile, dgswe_profile_read
+    orders = orders if orders is not None else W.ensemble_orders(len(ens))
     ne = {p: sum(w.mesh.n_elems for w, o in zip(ens, orders) if o == p) for p in (1, 2)}
+    op = {1: dict(persistent=persistent, **(tuned or {}).get(1, {})),
+          2: dict(cfl=0.1, persistent=persistent, **(tuned or {}).get(2, {}))}
     t0 = time.perf_counter()
     e = Ensemble([w.mesh for w in ens], orders, dict(ens[0].params, precision=DGSWE_MIXED),
-                 [w.forcing for w in ens], hip_stream=stream.cuda_stream, order_params={2: dict(cfl=0.1)})
-    e.use_graphs(6)
+                 [w.forcing for w in ens], hip_stream=stream.cuda_stream, order_params=op, fused=fused)
+    e.use_graphs(graphs)
     for i, w in enumerate(ens):
         e.set_state(i, w.w0, 0.0, w.postprocess_initial)
-    log(f"ensemble p in {{1, 2}}: {orders.count(1)} p=1 members ({ne[1]} el), {orders.count(2)} p=2 members "
-        f"({ne[2]} el), ready in {time.perf_counter() - t0:.1f} s")
+    info = {p: dgswe_mesh_info(b.h) for p, b in e.batches.items()}
+    tag = f"ensemble fused={fused} graphs={graphs} persistent={persistent}"
+    log(f"{tag}: {orders.count(1)} p=1 members ({ne[1]} el), {orders.count(2)} p=2 members ({ne[2]} el), "
+        f"ready in {time.perf_counter() - t0:.1f} s")
     e.step(warmup)
     e.diagnostics(0)
     torch.cuda.synchronize()
@@ -493,12 +513,34 @@ def measure_ensemble_orders(ens, steps, warmup, stream):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ts = [e.diagnostics(i)["t"] for i in range(len(ens))]
+    kernels = {}
+    if profile:
+        for b in e.batches.values():
+            dgswe_profile(b.h, 1)
+        e.step(20)
+        torch.cuda.synchronize()
+        for b in e.batches.values():
+            for k, (ms, n) in dgswe_profile_read(b.h).items():
+                if n:
+                    r = kernels.setdefault(k, {"total_ms": 0.0, "launches": 0})
+                    r["total_ms"] += ms
+                    r["launches"] += n
+            dgswe_profile(b.h, 0)
+        for r in kernels.values():
+            r["avg_us"] = 1e3 * r["total_ms"] / r["launches"]
     e.close()
-    log(f"ensemble p in {{1, 2}}: timed {steps} steps in {elapsed:.4f} s; member times {min(ts):.1f}-{max(ts):.1f} s")
-    return {"value": 2 * (ne[1] + ne[2]) * steps / elapsed, "unit": "elem-stage/s", "precision": "mixed",
-            "members_p1": orders.count(1), "members_p2": orders.count(2), "n_elems_p1": ne[1], "n_elems_p2": ne[2],
-            "ms_per_step": 1e3 * elapsed / steps, "graphs": 6,
-            "note": "element-stages of both orders counted alike; a p = 2 element-stage does about 2.6x the work"}
+    log(f"{tag}: timed {steps} steps in {elapsed:.4f} s; member times {min(ts):.1f}-{max(ts):.1f} s")
+    nn = sum(int(v["n_nodes"]) for v in info.values())
+    ned = sum(int(v["n_edges"]) for v in info.values())
+    rec = {"value": 2 * (ne[1] + ne[2]) * steps / elapsed, "unit": "elem-stage/s", "precision": "mixed",
+           "members": len(ens), "members_p1": orders.count(1), "members_p2": orders.count(2),
+           "n_elems_p1": ne[1], "n_elems_p2": ne[2], "n_nodes": nn, "n_edges": ned,
+           "ms_per_step": 1e3 * elapsed / steps, "graphs": graphs, "fused_one_launch": fused,
+           "persistent": persistent, "chunk_params": op, "kernels": kernels,
+           "note": "element-stages of both orders counted alike; a p = 2 element-stage does about 2.6x the work"}
+    if kernels:
+        rec["roofline"] = roofline(kernels, {1: ne[1], 2: ne[2]}, ned, nn, "mixed")
+    return rec
 
 
 def measure_serving(n_requests, pool_rate_hint, stream):
@@ -591,7 +633,7 @@ def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
            "bytes_per_launch": int(b), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
     if dom == "k_stage" and precision == "mixed":
-        b2 = B_ALG_MIXED_AS_BUILT * ne
+        b2 = B_ALG_MIXED_AS_BUILT * (ne.get(1, 0) if isinstance(ne, dict) else ne)
         out["as_built"] = {"bytes_per_element_stage": B_ALG_MIXED_AS_BUILT, "bytes_per_launch": int(b2),
                            "frac": round(b2 / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
     return out
@@ -707,19 +749,38 @@ def main():
             except DgsweError as ex:
                 variants[name] = {"error": str(ex), **extra}
     if not args.no_batched:
-        from paper_2508_21208_amd import workloads as W
         t0 = time.perf_counter()
         ens = W.cfg_ensemble()
-        log(f"batched: {len(ens)} members, {sum(w.mesh.n_elems for w in ens)} elements, generated in "
+        orders = W.ensemble_orders(len(ens))
+        log(f"ensemble: {len(ens)} members, {sum(w.mesh.n_elems for w in ens)} elements, generated in "
             f"{time.perf_counter() - t0:.1f} s")
-        el3, ne3, nm3, k3 = measure_batched(ens, args.steps, args.warmup, stream, profile)
-        variants["batched"] = {"value": ne3 * 2 * args.steps / el3, "unit": "elem-stage/s",
-                               "ms_per_step": 1e3 * el3 / args.steps, "members": nm3, "n_elems": ne3,
-                               "precision": "mixed", "roofline": roofline(k3, ne3, 0, 0, "mixed", with_traffic=False),
-                               "kernels": k3}
-        if k3:
-            log("batched kernels: " + json.dumps(k3))
-        variants["batched_p12"] = measure_ensemble_orders(ens, args.steps, args.warmup, stream)
+        tuned, tables = tune_ensemble_orders(ens, orders, stream)
+        # how the two orders' batches are advanced: each batch on its own
+        # stream (they overlap on the GPU), or together by dgswe_step_pair
+        # (one stream; per stage the p = 2 post-processing, then one launch
+        # of both orders' stage work; or the "split": the p = 1 stage with
+        # the p = 2 post-processing in one launch, then the p = 2 right-hand
+        # side), with one workgroup per chunk or persistent workgroups
+        modes = {}
+        for name, kw, env in (("two_streams", dict(fused=False), None),
+                              ("one_launch", dict(fused=True), None),
+                              ("one_launch_split", dict(fused=True), "DGSWE_PAIR_SPLIT"),
+                              ("one_launch_persistent", dict(fused=True, persistent=2), None)):
+            if env:
+                os.environ[env] = "1"
+            try:
+                modes[name] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
+                                               orders=orders, **kw)
+            finally:
+                if env:
+                    del os.environ[env]
+            log(f"ensemble {name}: {modes[name]['ms_per_step']:.3f} ms per step")
+        best = min(modes, key=lambda k: modes[k]["ms_per_step"])
+        variants["batched"] = dict(modes[best], mode=best, autotune=tables,
+                                   modes_ms_per_step={k: v["ms_per_step"] for k, v in modes.items()})
+        variants["batched_modes"] = {k: v for k, v in modes.items() if k != best}
+        variants["batched_p1_only"] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
+                                                       orders=[1] * len(ens))
         del ens
 
     if not args.no_graphs:

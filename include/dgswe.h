@@ -93,7 +93,12 @@ typedef struct {
   int32_t chunk;     /* launch tuning: elements per workgroup chunk, 64..256
                         (0: 256); results do not depend on it */
   int32_t waves;     /* launch tuning: waves per SIMD the p = 2 stage kernel's
-                        registers are budgeted for, 1..4 (0: 2) */
+                        registers are budgeted for, 1..4 (0: 3 in FP64, 2 in
+                        mixed precision) */
+  int32_t persistent; /* launch tuning: 0 = one workgroup per chunk; N > 0 =
+                        N resident workgroups per compute unit, each taking
+                        chunks in turn (the same chunks per XCD); results do
+                        not depend on it */
 } dgswe_params;
 
 /* Numerical flux (Sec. 2.2 names local Lax-Friedrichs and Roe).  flux = 1
@@ -129,17 +134,20 @@ typedef struct {
  *
  * Degree p = 2 (the paper builds p = 1 and states that the formulation
  * extends to higher degrees, Sec. 2.2): six modes per variable, a degree-4
- * six-point area rule and four-point Gauss-Lobatto edges; the limiter keeps
- * an element's quadratic modes unless the p = 1 limiter would act on its
- * linear part or the full field leaves the neighbour-mean range at a vertex
- * or an edge midpoint (then the element is limited as a p = 1 element); the
- * wet/dry step drops the quadratic modes of an element whose depth falls
- * below H0 at a vertex or an edge midpoint and then applies the p = 1 rule.
- * The CFL number should be smaller than at p = 1 (about 0.1). */
+ * six-point area rule and four-point Gauss-Lobatto edges.  The limiter
+ * scales modes 1-5 of each variable by the largest factor <= 1 that keeps
+ * the field inside the range of the element's and its face neighbours'
+ * means at the vertices and edge midpoints (the p = 1 limiter when the
+ * quadratic modes vanish); the wet/dry step leaves a dry element (mean
+ * depth <= H0) flat and at rest and, in a wet element whose depth falls
+ * below H0 at a vertex, an interior edge quadrature point or an area
+ * point, scales the depth's deviation from its mean so that the lowest of
+ * those points is at H0.  Both are continuous in the state.  The CFL
+ * number should be smaller than at p = 1 (about 0.1). */
 
 /* Fill `p` with the defaults: p=1, FP64, g=9.81, rho0=1000, h0=0.01,
  * cfl=0.2, dt_fixed=0, dt_max=0, limiter=1, wetdry=1, rk=22, flux=0, chunk=0,
- * waves=0. */
+ * waves=0, persistent=0. */
 void dgswe_default_params(dgswe_params *p);
 
 /* Environment variables read when a solver, batch or pool is created (for
@@ -315,6 +323,20 @@ dgswe_status dgswe_member_set_forcing(dgswe_solver *s, int32_t member, const dgs
  * DGSWE_E_ALLDRY) stop all further steps of that member and are reported
  * by its next read. */
 dgswe_status dgswe_step(dgswe_solver *s, int32_t n_steps);
+
+/* Advance a p = 1 solver (batch or pool) and a p = 2 solver together by
+ * n_steps steps, for ensembles whose members have both orders (Sec. 2.2:
+ * the formulation carries to higher degrees).  Per RK stage one launch
+ * post-processes the p = 2 stage input (limiter, wet/dry) and one launch
+ * does the stage of every chunk of both solvers; each member's result is
+ * bitwise the one dgswe_step gives its solver alone.  The two must share
+ * the device, the precision, the time stepper and the persistent setting,
+ * and p1 must not use the vertex-based limiter (DGSWE_E_INVALID otherwise).
+ * The work runs on p1's stream; if p2 has another stream, p2's earlier work
+ * is waited for and p2's later work waits for the pair.  p1's
+ * steps_per_graph (dgswe_use_graphs) applies to the pair.  Asynchronous
+ * like dgswe_step; errors are reported by each solver's next read. */
+dgswe_status dgswe_step_pair(dgswe_solver *p1, dgswe_solver *p2, int32_t n_steps);
 
 /* Step graphs: steps_per_graph > 0 (rounded up to a multiple of 6) makes
  * dgswe_step enqueue its steps in whole graphs of that many steps, each

@@ -20,12 +20,14 @@ _cache: dict = {}
 
 def candidates(params: dict):
     chunks = (64, 128, 192, 256)
-    waves = (1, 2, 3) if int(params.get("p", 1)) == 2 else (0,)
+    waves = (2, 3) if int(params.get("p", 1)) == 2 else (0,)
     return [(c, w) for c in chunks for w in waves]
 
 
-def tune(mesh, params: dict, forcing: dict, w0, postprocess=True, steps=20, hip_stream=None, use_cache=True):
-    """Returns (best params dict, table of (chunk, waves, us per step))."""
+def tune(mesh, params: dict, forcing: dict, w0, postprocess=True, steps=20, hip_stream=None, use_cache=True,
+         repeats=3):
+    """Returns (best params dict, table of (chunk, waves, us per step)); each
+    candidate's time is the median of `repeats` runs of `steps` steps."""
     key = (int(params.get("p", 1)), int(params.get("precision", 0)), int(math.log10(max(1, mesh.n_elems))))
     if use_cache and key in _cache:
         best = _cache[key]
@@ -38,10 +40,13 @@ def tune(mesh, params: dict, forcing: dict, w0, postprocess=True, steps=20, hip_
         s.step(3)
         s.diagnostics()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.step(steps)
-        s.diagnostics()
-        table.append((c, w, 1e6 * (time.perf_counter() - t0) / steps))
+        runs = []
+        for _ in range(max(1, repeats)):
+            t0 = time.perf_counter()
+            s.step(steps)
+            s.diagnostics()
+            runs.append(1e6 * (time.perf_counter() - t0) / steps)
+        table.append((c, w, sorted(runs)[len(runs) // 2]))
         s.close()
     best = min(table, key=lambda r: r[2])
     _cache[key] = best[:2]

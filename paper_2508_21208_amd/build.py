@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgswe.so")
-SOURCES = ["dgswe_api.hip", "dgswe_kernels.hip", "dgswe_p2.hip", "mesh_prep.cpp"]
+SOURCES = ["dgswe_api.hip", "dgswe_kernels.hip", "dgswe_p2.hip", "dgswe_ens.hip", "mesh_prep.cpp"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions stay disabled in every HIP build of this project.

@@ -13,6 +13,7 @@
 // only and are rebuilt when a member joins or leaves, so a step launches one
 // grid over exactly the active work.  A batch is a pool sized to its meshes.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -97,8 +98,10 @@ hipError_t scratch_on(int device, double **out) {
   return hipSuccess;
 }
 
-enum KernelId { K_FORCING = 0, K_STAGE, K_PP2, K_RHS2, K_VBOUNDS, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage", "k_pp2", "k_rhs2", "k_vbounds"};
+enum KernelId { K_FORCING = 0, K_STAGE, K_PP2, K_RHS2, K_VBOUNDS, K_STAGE12, K_STAGE1PP2, K_COUNT };
+const char *kKernelNames[K_COUNT] = {"k_forcing", "k_stage",   "k_pp2",      "k_rhs2",
+                                     "k_vbounds", "k_stage12", "k_stage1pp2"};
+
 
 // First-fit allocator over [0, cap) with coalescing of freed ranges.
 class Arena {
@@ -220,6 +223,15 @@ struct dgswe_solver {
   int graph_steps = 0;
   bool capturing = false;
   hipGraphExec_t graph[6] = {};
+  // graphs of dgswe_step_pair (this solver the p = 1 side): per (rotation,
+  // parity) of both solvers, for the partner with id pair_id as it was at
+  // generation pair_gen
+  hipGraphExec_t pair_graph[36] = {};
+  unsigned long long id = 0;       // unique per solver of the process
+  unsigned long long pair_id = 0;
+  unsigned gen = 0;                // bumped whenever this solver's graphs are dropped
+  unsigned pair_gen = 0;
+  hipEvent_t pair_ev = nullptr;    // orders this solver's stream around dgswe_step_pair
   // kernel timing
   bool prof = false;
   struct Rec { int k; hipEvent_t a, b; };
@@ -263,16 +275,28 @@ hipError_t upload(dgswe_solver *S, const T **dst, const std::vector<T> &v) {
   return e;
 }
 
+void drop_pair_graphs(dgswe_solver *S) {
+  for (hipGraphExec_t &g : S->pair_graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+  S->pair_id = 0;
+}
+
 void drop_graphs(dgswe_solver *S) {
   S->forcing_fresh = false;
+  ++S->gen;
   for (hipGraphExec_t &g : S->graph) {
     if (g) (void)hipGraphExecDestroy(g);
     g = nullptr;
   }
+  drop_pair_graphs(S);
 }
 
 void free_all(dgswe_solver *S) {
   drop_graphs(S);
+  if (S->pair_ev) (void)hipEventDestroy(S->pair_ev);
+  S->pair_ev = nullptr;
   if (S->stage_in) (void)hipHostFree(S->stage_in);
   if (S->stage_out) (void)hipHostFree(S->stage_out);
   S->stage_in = S->stage_out = nullptr;
@@ -339,6 +363,7 @@ bool validate_params(const dgswe_params *p, std::string &msg) {
   if (p->flux != 0 && p->flux != 1) { msg = "flux must be 0 (LLF) or 1 (Roe)"; return false; }
   if (p->chunk != 0 && (p->chunk < 64 || p->chunk > 256)) { msg = "chunk must be 0 or in [64, 256]"; return false; }
   if (p->waves < 0 || p->waves > 4) { msg = "waves must be in [0, 4]"; return false; }
+  if (p->persistent < 0 || p->persistent > 8) { msg = "persistent must be in [0, 8]"; return false; }
   if (p->limiter < 0 || p->limiter > 2) { msg = "limiter must be 0, 1 or 2"; return false; }
   if (p->limiter == 2 && p->p != 1) { msg = "the vertex-based limiter (limiter = 2) needs p = 1"; return false; }
   if (p->precision != DGSWE_FP64 && p->precision != DGSWE_MIXED) {
@@ -470,6 +495,8 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
                           void *hip_stream, dgswe_solver **out) {
   dgswe_solver *S = new (std::nothrow) dgswe_solver();
   if (!S) return fail(nullptr, DGSWE_E_NOMEM, "host allocation failed");
+  static std::atomic<unsigned long long> next_id{1};
+  S->id = next_id++;
   hipError_t e = hipGetDevice(&S->device);
   if (e != hipSuccess) { delete S; return fail(nullptr, DGSWE_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
   if (hip_stream) {
@@ -481,6 +508,13 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   }
   S->uprm = *prm;
   if (const char *ev = std::getenv("DGSWE_FORCING_EVERY_STAGE")) S->forcing_every_stage = std::atoi(ev) != 0;
+  // measured alternatives (see Params)
+  {
+    const char *ev = std::getenv("DGSWE_RHS2_MFMA");
+    S->prm.rhs2_mfma = ev && std::atoi(ev) == 1;
+    ev = std::getenv("DGSWE_PAIR_SPLIT");
+    S->prm.pair_split = ev && std::atoi(ev) == 1;
+  }
   S->precision = prm->precision;
   S->order = prm->p;
   S->nm = prm->p == 2 ? 6 : 3;
@@ -492,6 +526,12 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   pp.limiter = prm->limiter; pp.wetdry = prm->wetdry ? 1 : 0;
   pp.flux = prm->flux;
   pp.waves = prm->waves;
+  pp.persistent = prm->persistent;
+  pp.n_cu = 0;
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess) pp.n_cu = ncu;
+  }
   for (int a = 0; a < A_COUNT; ++a) S->arena[a].init(cap[a]);
   S->chunk_cap = chunk_cap;
   S->mh.resize((size_t)slots);
@@ -1156,6 +1196,126 @@ dgswe_status graph_steps(dgswe_solver *S) {
   return DGSWE_OK;
 }
 
+// Enqueue n steps of a p = 1 solver A and a p = 2 solver B on A's stream,
+// each stage one k_pp2 launch for B's stage input and one launch of both
+// solvers' stage work (launch_stage12); forcing and bookkeeping per solver
+// as in enqueue_steps.
+dgswe_status enqueue_pair(dgswe_solver *A, dgswe_solver *B, int32_t n_steps) {
+  StageCoef sc[5];
+  const int ns = rk_stages(A->uprm.rk, sc);
+  const int wda = A->prm.dt_fixed > 0.0 ? 0 : 1, wdb = B->prm.dt_fixed > 0.0 ? 0 : 1;
+  bool fa = A->forcing_fresh && !A->capturing, fb = B->forcing_fresh && !B->capturing;
+  const bool ra = sc[ns - 1].c == 1.0 && !A->forcing_every_stage;
+  const bool rb = sc[ns - 1].c == 1.0 && !B->forcing_every_stage;
+  DevState &sa = A->s, &sb = B->s;
+  for (int i = 0; i < n_steps; ++i) {
+    const int la = (int)(A->steps_enq & 1), lb = (int)(B->steps_enq & 1);
+    const int ca = A->cur, cb = B->cur;
+    hipError_t e = hipSuccess;
+    for (int stage = 0; stage < ns && e == hipSuccess; ++stage) {
+      if (A->nfblk > 0 && !(stage == 0 && fa)) {
+        Timed t(A, K_FORCING);
+        e = launch_forcing(A->m, sa, A->prm, A->nfblk, la, sc[stage].c, A->stream);
+      }
+      if (e == hipSuccess && B->nfblk > 0 && !(stage == 0 && fb)) {
+        Timed t(A, K_FORCING);
+        e = launch_forcing(B->m, sb, B->prm, B->nfblk, lb, sc[stage].c, A->stream);
+      }
+      if (e != hipSuccess) break;
+      void *rec = stage == 0 ? sb.wpp : sb.buf[(cb + stage + 2) % 3];
+      if (A->prm.pair_split) {
+        // the p = 1 stage with the p = 2 post-processing, then the p = 2
+        // right-hand side
+        {
+          Timed t(A, K_STAGE1PP2);
+          e = launch_stage1pp2(A->m, sa, A->prm, sa.buf[(ca + stage) % 3], stage == 0 ? nullptr : sa.wpp,
+                               sa.buf[(ca + stage + 1) % 3], stage == 0 ? sa.wpp : nullptr, la,
+                               sc[stage].last ? wda : 0, B->m, sb, B->prm, sb.buf[(cb + stage) % 3], rec, lb,
+                               stage == 0, sc[stage], A->precision, A->stream);
+        }
+        if (e != hipSuccess) break;
+        Timed t(A, K_RHS2);
+        e = launch_rhs2(B->m, sb, B->prm, rec, stage == 0 ? nullptr : sb.wpp, sb.buf[(cb + stage + 1) % 3], lb,
+                        stage == 0, sc[stage], sc[stage].last ? wdb : 0, B->precision, A->stream);
+        continue;
+      }
+      {
+        Timed t(A, K_PP2);
+        e = launch_pp2(B->m, sb, B->prm, sb.buf[(cb + stage) % 3], rec, lb, stage == 0 ? 0 : 1, B->precision,
+                       A->stream);
+      }
+      if (e != hipSuccess) break;
+      Timed t(A, K_STAGE12);
+      e = launch_stage12(A->m, sa, A->prm, sa.buf[(ca + stage) % 3], stage == 0 ? nullptr : sa.wpp,
+                         sa.buf[(ca + stage + 1) % 3], stage == 0 ? sa.wpp : nullptr, la,
+                         sc[stage].last ? wda : 0, B->m, sb, B->prm, rec, stage == 0 ? nullptr : sb.wpp,
+                         sb.buf[(cb + stage + 1) % 3], lb, sc[stage].last ? wdb : 0, stage == 0, sc[stage],
+                         A->precision, A->stream);
+    }
+    if (e != hipSuccess) return hip_fail(A, e, "kernel launch");
+    A->cur = (ca + ns) % 3;
+    B->cur = (cb + ns) % 3;
+    for (MemberHost &h : A->mh) h.cur_is_pp = false;
+    for (MemberHost &h : B->mh) h.cur_is_pp = false;
+    A->steps_enq += 1;
+    B->steps_enq += 1;
+    fa = ra;
+    fb = rb;
+  }
+  if (!A->capturing) {
+    A->forcing_fresh = fa;
+    B->forcing_fresh = fb;
+  }
+  return DGSWE_OK;
+}
+
+// One graph launch of A's graph_steps steps of the pair, captured on first
+// use per (rotation, parity) of both solvers.
+dgswe_status pair_graph_steps(dgswe_solver *A, dgswe_solver *B) {
+  if (A->pair_id != B->id || A->pair_gen != B->gen) {
+    drop_pair_graphs(A);
+    A->pair_id = B->id;
+    A->pair_gen = B->gen;
+  }
+  const int key = ((A->cur * 2 + (int)(A->steps_enq & 1)) * 3 + B->cur) * 2 + (int)(B->steps_enq & 1);
+  if (!A->pair_graph[key]) {
+    const int ca = A->cur, cb = B->cur;
+    const long long ea = A->steps_enq, eb = B->steps_enq;
+    hipError_t e = hipStreamBeginCapture(A->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(A, e, "hipStreamBeginCapture");
+    A->capturing = B->capturing = true;
+    dgswe_status st = enqueue_pair(A, B, A->graph_steps);
+    A->capturing = B->capturing = false;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(A->stream, &g);
+    // the capture only recorded: put the bookkeeping back
+    A->cur = ca; B->cur = cb;
+    A->steps_enq = ea; B->steps_enq = eb;
+    if (st != DGSWE_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(A, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&A->pair_graph[key], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      A->pair_graph[key] = nullptr;
+      return hip_fail(A, e, "hipGraphInstantiate");
+    }
+  }
+  hipError_t e = hipGraphLaunch(A->pair_graph[key], A->stream);
+  if (e != hipSuccess) return hip_fail(A, e, "hipGraphLaunch");
+  StageCoef sc[5];
+  const int ns = rk_stages(A->uprm.rk, sc);
+  for (dgswe_solver *S : {A, B}) {
+    for (MemberHost &h : S->mh) h.cur_is_pp = false;
+    S->forcing_fresh = sc[ns - 1].c == 1.0 && !S->forcing_every_stage;
+    S->cur = (S->cur + ns * A->graph_steps) % 3;
+    S->steps_enq += A->graph_steps;
+  }
+  return DGSWE_OK;
+}
+
 // Entry points return a status and never let an exception cross the C ABI:
 // a failed host allocation (std::bad_alloc) becomes DGSWE_E_NOMEM, anything
 // else DGSWE_E_DEVICE, with the message in dgswe_last_error.
@@ -1188,6 +1348,7 @@ void dgswe_default_params(dgswe_params *p) {
   p->flux = 0;
   p->chunk = 0;
   p->waves = 0;
+  p->persistent = 0;
   p->p = 1;
   p->precision = DGSWE_FP64;
   p->g = 9.81;
@@ -1258,6 +1419,51 @@ dgswe_status dgswe_step(dgswe_solver *S, int32_t n_steps) {
       }
     }
     return enqueue_steps(S, left);
+  });
+}
+
+dgswe_status dgswe_step_pair(dgswe_solver *A, dgswe_solver *B, int32_t n_steps) {
+  return guard(A, [&]() -> dgswe_status {
+    if (!A || !B) return fail(A, DGSWE_E_INVALID, "solver is NULL");
+    if (n_steps < 0) return fail(A, DGSWE_E_INVALID, "n_steps < 0");
+    if (A->order != 1 || B->order != 2) return fail(A, DGSWE_E_INVALID, "the pair is a p = 1 and a p = 2 solver");
+    if (A->device != B->device) return fail(A, DGSWE_E_INVALID, "the pair must share a device");
+    if (A == B) return fail(A, DGSWE_E_INVALID, "the pair needs two solvers");
+    if (A->precision != B->precision || A->uprm.rk != B->uprm.rk)
+      return fail(A, DGSWE_E_INVALID, "the pair must share the precision and the time stepper");
+    if (A->prm.limiter == 2) return fail(A, DGSWE_E_INVALID, "the pair does not take the vertex-based limiter");
+    if (A->block != 256 || B->block != 256) return fail(A, DGSWE_E_INVALID, "the pair needs 256-lane workgroups");
+    if (A->prm.persistent != B->prm.persistent)
+      return fail(A, DGSWE_E_INVALID, "the pair must share the persistent setting");
+    if (B->m.nch == 0) return dgswe_step(A, n_steps);
+    if (A->m.nch == 0) return dgswe_step(B, n_steps);
+    // everything runs on A's stream; B's stream (if another) is ordered
+    // before and after it with events
+    const bool two = A->stream != B->stream;
+    hipError_t e = hipSuccess;
+    if (two) {
+      for (hipEvent_t *ev : {&A->pair_ev, &B->pair_ev})
+        if (!*ev && (e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
+          return hip_fail(A, e, "hipEventCreate");
+      e = hipEventRecord(B->pair_ev, B->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(A->stream, B->pair_ev, 0);
+      if (e != hipSuccess) return hip_fail(A, e, "stream ordering");
+    }
+    int32_t left = n_steps;
+    dgswe_status st = DGSWE_OK;
+    if (A->graph_steps > 0 && !A->prof) {
+      while (st == DGSWE_OK && left >= A->graph_steps) {
+        st = pair_graph_steps(A, B);
+        left -= A->graph_steps;
+      }
+    }
+    if (st == DGSWE_OK) st = enqueue_pair(A, B, left);
+    if (two) {
+      e = hipEventRecord(A->pair_ev, A->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(B->stream, A->pair_ev, 0);
+      if (e != hipSuccess && st == DGSWE_OK) return hip_fail(A, e, "stream ordering");
+    }
+    return st;
   });
 }
 

@@ -117,7 +117,24 @@ struct Params {
   int wetdry;
   int flux;  // 0: LLF, 1: Roe on edges wet on both sides
   int waves; // register budget of the p = 2 stage kernel (waves per SIMD), 0: default
+  int persistent;  // 0: one workgroup per chunk; N: N resident workgroups per CU
+  int n_cu;        // compute units of the device
+  // measured alternatives, read from the environment when a solver is
+  // created (DGSWE_RHS2_MFMA, DGSWE_PAIR_SPLIT): the p = 2 momentum at the
+  // area points on the matrix cores; dgswe_step_pair's other split of a stage
+  int rhs2_mfma;
+  int pair_split;
 };
+
+// Workgroups of a stage launch over n work items: one per item, or (with
+// persistent workgroups) N per compute unit, a multiple of the 8 XCDs so
+// that every item a workgroup takes maps to its own XCD.
+inline unsigned stage_grid(const Params &p, int n) {
+  if (p.persistent <= 0 || p.n_cu <= 0) return (unsigned)n;
+  long long g = (long long)p.persistent * p.n_cu;
+  g = (g + 7) / 8 * 8;
+  return (unsigned)(g < n ? g : n);
+}
 
 // Buffers of one solver touched by the step.  The state lives in three
 // rotating buffers (structure of arrays, so a wavefront reads and writes 64
@@ -230,6 +247,19 @@ hipError_t launch_pp2(const DevMesh &m, const DevState &s, const Params &p, cons
 hipError_t launch_rhs2(const DevMesh &m, const DevState &s, const Params &p, const void *rec, const void *rbase,
                        void *wout, int slot, int first, const StageCoef &sc, int want_dt, int precision,
                        hipStream_t st);
+// One RK stage of a p = 1 batch (buffers as launch_stage) and a p = 2
+// batch (records of its stage input made by launch_pp2, RK base records,
+// raw output) in one launch; sc is the stage of both.
+hipError_t launch_stage12(const DevMesh &m1, const DevState &s1, const Params &p1, const void *win1,
+                          const void *wbase1, void *wout1, void *wpp1, int slot1, int want_dt1, const DevMesh &m2,
+                          const DevState &s2, const Params &p2, const void *rec2, const void *base2, void *wout2,
+                          int slot2, int want_dt2, int first, const StageCoef &sc, int precision, hipStream_t st);
+// The p = 1 stage of a p = 1 batch together with the post-processing of a
+// p = 2 batch's stage input into records (k_pp2's work) in one launch.
+hipError_t launch_stage1pp2(const DevMesh &m1, const DevState &s1, const Params &p1, const void *win1,
+                            const void *wbase1, void *wout1, void *wpp1, int slot1, int want_dt1, const DevMesh &m2,
+                            const DevState &s2, const Params &p2, const void *win2, void *rec2, int slot2, int first,
+                            const StageCoef &sc, int precision, hipStream_t st);
 // p = 2 read-back: elements [e0, e0 + count) as FP64 [18][count] (perm as
 // for launch_post_only)
 hipError_t launch_post_only2(const DevMesh &m, const Params &p, const void *win, int pp, int e0, int count,

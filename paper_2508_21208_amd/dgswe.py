@@ -28,14 +28,14 @@ EXPORTED = ("dgswe_default_params", "dgswe_create_mesh", "dgswe_set_state", "dgs
             "dgswe_member_set_state", "dgswe_member_set_forcing", "dgswe_member_read_state",
             "dgswe_member_info", "dgswe_create_pool", "dgswe_prepare_mesh", "dgswe_prepared_free",
             "dgswe_prepared_elems", "dgswe_member_add_prepared", "dgswe_member_add", "dgswe_member_remove",
-            "dgswe_pool_usage", "dgswe_use_graphs", "dgswe_member_read_state_device")
+            "dgswe_pool_usage", "dgswe_use_graphs", "dgswe_member_read_state_device", "dgswe_step_pair")
 
 
 class dgswe_params(C.Structure):
     _fields_ = [("p", C.c_int32), ("precision", C.c_int32), ("g", C.c_double), ("rho0", C.c_double),
                 ("h0", C.c_double), ("cfl", C.c_double), ("dt_fixed", C.c_double), ("dt_max", C.c_double),
                 ("limiter", C.c_int32), ("wetdry", C.c_int32), ("rk", C.c_int32), ("flux", C.c_int32),
-                ("chunk", C.c_int32), ("waves", C.c_int32)]
+                ("chunk", C.c_int32), ("waves", C.c_int32), ("persistent", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -138,6 +138,8 @@ def load_library(path: str = LIB_PATH):
     L.dgswe_use_graphs.restype = C.c_int
     L.dgswe_member_read_state_device.argtypes = [vp, C.c_int32, vp, vp]
     L.dgswe_member_read_state_device.restype = C.c_int
+    L.dgswe_step_pair.argtypes = [vp, vp, C.c_int32]
+    L.dgswe_step_pair.restype = C.c_int
     _lib = L
     return L
 
@@ -313,6 +315,10 @@ def dgswe_set_forcing(h, f: dict, n_elems: int | None = None, n_nodes: int | Non
 
 def dgswe_step(h, n_steps):
     _check(h, load_library().dgswe_step(h, int(n_steps)))
+
+
+def dgswe_step_pair(h1, h2, n_steps):
+    _check(h1, load_library().dgswe_step_pair(h1, h2, int(n_steps)))
 
 
 def dgswe_use_graphs(h, steps_per_graph):
@@ -494,16 +500,19 @@ class Batch:
 class Ensemble:
     """Members of both polynomial orders advanced together.  A batch holds
     one order (its state layout has one mode count per variable), so the
-    ensemble keeps one batch per order present, on the same stream, and
-    steps them in turn: per RK stage one stage launch for all p = 1 members
-    and one pair (post-processing, right-hand side) for all p = 2 members.
-    Member i is meshes[i] at order orders[i]; order_params[p] overrides
-    params for the batch of order p (e.g. a smaller CFL number at p = 2).
-    Each member's result equals its solo run at its order, bitwise."""
+    ensemble keeps one batch per order present, and dgswe_step_pair
+    advances them together (fused=True, the default): per RK stage one
+    post-processing launch for the p = 2 members and one stage launch for
+    every member of both orders, on the p = 1 batch's stream.  fused=False
+    steps the batches in turn.  Member i is
+    meshes[i] at order orders[i]; order_params[p] overrides params for the
+    batch of order p (e.g. a smaller CFL number at p = 2).  Each member's
+    result equals its solo run at its order, bitwise."""
 
     def __init__(self, meshes, orders, params: dict | None = None, forcings=None, hip_stream=None,
-                 order_params: dict | None = None):
+                 order_params: dict | None = None, fused=True):
         self.batches = {}
+        self.fused = bool(fused)
         self.where = []  # member -> (order, index in that order's batch)
         meshes = list(meshes)
         orders = [int(o) for o in orders]
@@ -548,6 +557,9 @@ class Ensemble:
         b.set_state(j, w, t, postprocess)
 
     def step(self, n=1):
+        if self.fused and len(self.batches) == 2:
+            dgswe_step_pair(self.batches[1].h, self.batches[2].h, n)
+            return
         for p in sorted(self.batches):
             self.batches[p].step(n)
 

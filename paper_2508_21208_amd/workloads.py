@@ -288,7 +288,7 @@ def coastal_initial_state(mesh: Mesh) -> np.ndarray:
 # --------------------------------------------------------------------------
 def default_params(**kw) -> dict:
     p = dict(p=1, precision=0, g=G, rho0=RHO0, h0=H0, cfl=0.2, dt_fixed=0.0,
-             dt_max=0.0, limiter=1, wetdry=1, rk=22, flux=0, chunk=0, waves=0)
+             dt_max=0.0, limiter=1, wetdry=1, rk=22, flux=0, chunk=0, waves=0, persistent=0)
     p.update(kw)
     return p
 

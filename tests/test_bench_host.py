@@ -59,3 +59,25 @@ def test_mixed_roofline_uses_207_bytes_and_reports_the_built_count():
 
 def test_cpu_model_is_named():
     assert bench.cpu_model() != ""
+
+
+def test_ensemble_bytes_and_kernel_names():
+    """the fused stage of an ensemble of both orders carries the p = 1
+    stage of its p = 1 elements and the p = 2 right-hand side of the rest"""
+    ne = {1: 1000, 2: 3000}
+    b = bench.algorithmic_bytes("k_stage12", ne, 0, 0, "mixed")
+    assert b == bench.B_ALG_MIXED * 1000 + bench.B_ALG_P2[("k_rhs2", "mixed")] * 3000
+    assert bench.algorithmic_bytes("k_pp2", ne, 0, 0, "mixed") == bench.B_ALG_P2[("k_pp2", "mixed")] * 3000
+    assert bench.algorithmic_bytes("k_forcing", ne, 0, 500, "mixed") == 40.0 * 500
+    assert bench.kernel_key("void dgswe::k_stage12<float, 1, 2, false>(dgswe::DevMesh, ...)") == ("k_stage12", "mixed")
+    assert bench.kernel_key("void dgswe::k_stage<256, 2, double, 0, false, false>(...)") == ("k_stage", "fp64")
+    assert bench.kernel_key("void dgswe::k_rhs2<double, 3, false>(...)") == ("k_rhs2", "fp64")
+
+
+def test_roofline_of_a_p1_only_ensemble():
+    """a p = 1 ensemble (element counts per order) keeps the as-built mixed
+    figure of the stage kernel"""
+    k = {"k_stage": {"avg_us": 100.0, "total_ms": 1.0, "launches": 10}}
+    r = bench.roofline(k, {1: 1_000_000, 2: 0}, 0, 0, "mixed", with_traffic=False)
+    assert r["kernel"] == "k_stage" and r["bytes_per_launch"] == int(bench.B_ALG_MIXED * 1_000_000)
+    assert r["as_built"]["bytes_per_launch"] == int(bench.B_ALG_MIXED_AS_BUILT * 1_000_000)

@@ -1,6 +1,8 @@
 """An ensemble with members of both orders (dgswe.Ensemble: one batch per
-order on one stream, step graphs on): every member's state, time and step
-count equal its solo run at its order, bitwise."""
+order; on a shared stream both advance through dgswe_step_pair, one stage
+launch for every member): every member's state, time and step count equal
+its solo run at its order, bitwise, with and without step graphs and
+persistent workgroups."""
 import numpy as np
 import pytest
 
@@ -22,23 +24,36 @@ def members():
     return out
 
 
-@pytest.mark.parametrize("prec", [0, DGSWE_MIXED])
-def test_mixed_order_ensemble_equals_solo_runs(prec):
+CASES = [(0, False, 6, 0, 0), (DGSWE_MIXED, False, 6, 0, 0), (0, True, 0, 0, 0), (DGSWE_MIXED, True, 6, 0, 0),
+         (0, True, 0, 2, 0), (DGSWE_MIXED, True, 6, 3, 0), (0, True, 6, 0, 1), (DGSWE_MIXED, True, 0, 2, 1)]
+
+
+@pytest.mark.parametrize("prec,fused,graphs,persistent,split", CASES)
+def test_mixed_order_ensemble_equals_solo_runs(prec, fused, graphs, persistent, split, monkeypatch):
+    import torch
+    if split:
+        # the other split of a pair stage (p = 1 stage with the p = 2
+        # post-processing, then the p = 2 right-hand side)
+        monkeypatch.setenv("DGSWE_PAIR_SPLIT", "1")
     mem = members()
     orders = [1, 2, 2, 1, 2]
-    params = W.default_params(precision=prec, dt_max=0.3)
+    params = W.default_params(precision=prec, dt_max=0.3, persistent=persistent)
     op = {2: dict(cfl=0.1)}
-    ens = Ensemble([m for m, _, _ in mem], orders, params, [f for _, f, _ in mem], order_params=op)
-    ens.use_graphs(6)
+    stream = torch.cuda.current_stream().cuda_stream if fused else None
+    ens = Ensemble([m for m, _, _ in mem], orders, params, [f for _, f, _ in mem], order_params=op,
+                   hip_stream=stream, fused=fused)
+    assert ens.fused == fused
+    ens.use_graphs(graphs)
     for i, (_, _, w0) in enumerate(mem):
         ens.set_state(i, w0, 0.0, True)
-    say(f"ensemble precision={prec}: orders {orders}, 13 steps")
+    say(f"ensemble precision={prec} fused={fused} graphs={graphs} persistent={persistent} split={split}: "
+        f"orders {orders}, 13 steps")
     ens.step(13)
     got = [ens.state(i) for i in range(len(mem))]
     dg = [ens.diagnostics(i) for i in range(len(mem))]
     ens.close()
     for i, ((m, f, w0), p) in enumerate(zip(mem, orders)):
-        prm = dict(params, p=p, **op.get(p, {}))
+        prm = dict(params, p=p, persistent=0, **op.get(p, {}))
         s = Solver(m, prm, f)
         w = w0 if p == 1 else np.concatenate([w0, np.zeros((3, 3, w0.shape[2]))], axis=1)
         s.set_state(w, 0.0, True)

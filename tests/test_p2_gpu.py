@@ -242,3 +242,31 @@ def test_p2_shallow_open_boundary_ghost_wets_and_dries():
     wl = shallow_open_boundary()
     wg, dg, wo, o = run_both(wl, wl.steps)
     check(wg, dg, wo, o)
+
+
+@pytest.mark.parametrize("prec", [0, DGSWE_MIXED])
+def test_p2_mfma_variant_matches_oracle(prec, monkeypatch):
+    """the measured MFMA variant of the right-hand side (the momentum at the
+    area points as 16x16x4 matrix products, DGSWE_RHS2_MFMA=1) keeps the
+    parity bars: FP64 relative L2 <= 1e-12, mixed within 1e-4 m"""
+    monkeypatch.setenv("DGSWE_RHS2_MFMA", "1")
+    wl = coastal_small()
+    p = dict(wl.params, **P2, precision=prec)
+    w0 = pad(wl.w0)
+    say(f"p=2 MFMA variant, precision {prec}: 60 steps")
+    s = Solver(wl.mesh, p, wl.forcing)
+    s.set_state(w0, 0.0, True)
+    s.step(60)
+    wg = s.state()
+    dg = s.diagnostics()
+    s.close()
+    monkeypatch.delenv("DGSWE_RHS2_MFMA")
+    o = Oracle(wl.mesh, dict(p, precision=0), wl.forcing, order=2)
+    o.set_state(w0, 0.0, True)
+    o.step(60)
+    wo = o.state()
+    if prec == 0:
+        check(wg, dg, wo, o)
+    else:
+        V = np.array([[1, -1, -1, 1, 1, 1], [1, 1, -1, 1, -1, 1], [1, 0, 2, 0, 0, 3]], float)
+        assert np.abs(V @ (wg[0] - wo[0])).max() <= 1e-4
