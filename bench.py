@@ -309,7 +309,7 @@ def cpu_baseline(wl, steps=50, single_s=12.0):
         t0 = time.perf_counter()
         o.step(1)
         t1 = time.perf_counter() - t0
-        n1 = max(0, int(single_s / max(t1, 1e-3)) - 1)
+        n1 = max(2, int(single_s / max(t1, 1e-3)) - 1)
         t0 = time.perf_counter()
         if n1:
             o.step(n1)
@@ -757,17 +757,17 @@ def main():
         tuned, tables = tune_ensemble_orders(ens, orders, stream)
         # how the two orders' batches are advanced: each batch on its own
         # stream (they overlap on the GPU), or together by dgswe_step_pair
-        # (one stream; per stage the p = 2 post-processing, then one launch
-        # of both orders' stage work; or the "split": the p = 1 stage with
-        # the p = 2 post-processing in one launch, then the p = 2 right-hand
-        # side), with one workgroup per chunk or persistent workgroups
+        # on one stream (per stage the p = 1 stage with the p = 2
+        # post-processing in one launch, then the p = 2 right-hand side; or
+        # the p = 2 post-processing, then one launch of both orders' stage
+        # work), with one workgroup per chunk or persistent workgroups
         modes = {}
         for name, kw, env in (("two_streams", dict(fused=False), None),
-                              ("one_launch", dict(fused=True), None),
-                              ("one_launch_split", dict(fused=True), "DGSWE_PAIR_SPLIT"),
-                              ("one_launch_persistent", dict(fused=True, persistent=2), None)):
+                              ("pair", dict(fused=True), None),
+                              ("pair_both_stages_one_launch", dict(fused=True), "DGSWE_PAIR_SPLIT"),
+                              ("pair_persistent", dict(fused=True, persistent=2), None)):
             if env:
-                os.environ[env] = "1"
+                os.environ[env] = "0"
             try:
                 modes[name] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
                                                orders=orders, **kw)

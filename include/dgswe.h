@@ -327,9 +327,12 @@ dgswe_status dgswe_step(dgswe_solver *s, int32_t n_steps);
 /* Advance a p = 1 solver (batch or pool) and a p = 2 solver together by
  * n_steps steps, for ensembles whose members have both orders (Sec. 2.2:
  * the formulation carries to higher degrees).  Per RK stage one launch
- * post-processes the p = 2 stage input (limiter, wet/dry) and one launch
- * does the stage of every chunk of both solvers; each member's result is
- * bitwise the one dgswe_step gives its solver alone.  The two must share
+ * does the stage of every p = 1 chunk together with the post-processing
+ * (limiter, wet/dry) of every p = 2 chunk, then one launch the p = 2
+ * right-hand side (the environment variable DGSWE_PAIR_SPLIT=0 selects the
+ * other arrangement: the p = 2 post-processing, then one launch of both
+ * orders' stage work); each member's result is bitwise the one dgswe_step
+ * gives its solver alone.  The two must share
  * the device, the precision, the time stepper and the persistent setting,
  * and p1 must not use the vertex-based limiter (DGSWE_E_INVALID otherwise).
  * The work runs on p1's stream; if p2 has another stream, p2's earlier work

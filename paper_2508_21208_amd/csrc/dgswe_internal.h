@@ -120,8 +120,10 @@ struct Params {
   int persistent;  // 0: one workgroup per chunk; N: N resident workgroups per CU
   int n_cu;        // compute units of the device
   // measured alternatives, read from the environment when a solver is
-  // created (DGSWE_RHS2_MFMA, DGSWE_PAIR_SPLIT): the p = 2 momentum at the
-  // area points on the matrix cores; dgswe_step_pair's other split of a stage
+  // created: DGSWE_RHS2_MFMA=1 puts the p = 2 momentum at the area points on
+  // the matrix cores; DGSWE_PAIR_SPLIT=0 makes dgswe_step_pair run a stage
+  // as (p = 2 post-processing) then (both orders' stage work) instead of
+  // (p = 1 stage with the p = 2 post-processing) then (p = 2 right-hand side)
   int rhs2_mfma;
   int pair_split;
 };

@@ -24,17 +24,16 @@ def members():
     return out
 
 
-CASES = [(0, False, 6, 0, 0), (DGSWE_MIXED, False, 6, 0, 0), (0, True, 0, 0, 0), (DGSWE_MIXED, True, 6, 0, 0),
-         (0, True, 0, 2, 0), (DGSWE_MIXED, True, 6, 3, 0), (0, True, 6, 0, 1), (DGSWE_MIXED, True, 0, 2, 1)]
+CASES = [(0, False, 6, 0, 1), (DGSWE_MIXED, False, 6, 0, 1), (0, True, 0, 0, 1), (DGSWE_MIXED, True, 6, 0, 1),
+         (0, True, 0, 2, 1), (DGSWE_MIXED, True, 6, 3, 1), (0, True, 6, 0, 0), (DGSWE_MIXED, True, 0, 2, 0)]
 
 
 @pytest.mark.parametrize("prec,fused,graphs,persistent,split", CASES)
 def test_mixed_order_ensemble_equals_solo_runs(prec, fused, graphs, persistent, split, monkeypatch):
     import torch
-    if split:
-        # the other split of a pair stage (p = 1 stage with the p = 2
-        # post-processing, then the p = 2 right-hand side)
-        monkeypatch.setenv("DGSWE_PAIR_SPLIT", "1")
+    # split = 0: the other arrangement of a pair stage (the p = 2
+    # post-processing, then one launch of both orders' stage work)
+    monkeypatch.setenv("DGSWE_PAIR_SPLIT", str(split))
     mem = members()
     orders = [1, 2, 2, 1, 2]
     params = W.default_params(precision=prec, dt_max=0.3, persistent=persistent)
