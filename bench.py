@@ -137,9 +137,11 @@ def source_hash() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(kernel: str, precision: str):
+def stored_traffic(kernel: str, precision: str, section: str = "kernels"):
     """HBM bytes per launch of `kernel` measured with rocprofv3 counters for
-    the current sources, or None (no record, or the kernels changed since)."""
+    the current sources, or None (no record, or the kernels changed since).
+    section "kernels": the 4M-triangle runs; "ensemble": the 64-member
+    ensemble's launches."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -147,7 +149,7 @@ def stored_traffic(kernel: str, precision: str):
         return None
     if rec.get("source_sha256") != source_hash():
         return None
-    k = rec.get("kernels", {}).get(kernel, {}).get(precision)
+    k = rec.get(section, {}).get(kernel, {}).get(precision)
     return None if k is None else k["bytes_per_launch"]
 
 
@@ -172,53 +174,101 @@ CMD_TRACE = ("rocprofv3 --kernel-trace --stats -d $OUT/prof -o bench --output-fo
              "--no-rk --no-graphs")
 CMD_PMC = ("rocprofv3 --pmc {c} -d $OUT/pmc/{c} -o run --output-format csv -- python3 $REPO/bench.py --steps 3 "
            "--warmup 1 --no-cpu-baseline --no-profile --copy-probe --no-batched --no-serving --no-rk --no-graphs")
+CMD_SUMMARIZE = ("cd $REPO && python3 bench.py --summarize-pmc $OUT/pmc --kernel-trace $OUT/prof/bench_kernel_trace.csv "
+                 "--ensemble-kernel-trace $OUT/prof_ens/bench_kernel_trace.csv --summary-md "
+                 "profiles/k_stage_hurricane_4M.md")
+CMD_TRACE_ENS = ("rocprofv3 --kernel-trace --stats -d $OUT/prof_ens -o bench --output-format csv -- "
+                 "python3 $REPO/bench.py --only-batched --steps 50 --warmup 5 --no-profile")
+CMD_PMC_ENS = ("rocprofv3 --pmc {c} -d $OUT/pmc/ensemble/{c} -o run --output-format csv -- python3 $REPO/bench.py "
+               "--only-batched --steps 3 --warmup 1 --no-profile --copy-probe")
 
 
-def summarize_pmc(pmc_dir: str, stats_csv: str | None, out_md: str | None):
+def _pmc_rows(pmc_dir, tag):
+    with open(os.path.join(pmc_dir, tag, "run_counter_collection.csv")) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _pmc_traffic(pmc_dir, largest_grid):
+    """(calibration, {(kernel, precision): record}) from the FETCH_SIZE and
+    WRITE_SIZE runs under pmc_dir.  largest_grid: per kernel and precision
+    keep only the dispatches of the largest grid (the 4M runs also hold the
+    small mixed-precision error check; the ensemble run the autotuner's
+    single-member launches and the persistent workgroups' smaller grids)."""
+    copy_bytes = 2 * 1024 ** 3
+    calib, vals = {}, {}
+    for tag in ("FETCH_SIZE", "WRITE_SIZE"):
+        rows = _pmc_rows(pmc_dir, tag)
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        big = max(copies)
+        scale = copy_bytes / (big * 1024.0)
+        calib[tag] = {"copy_KiB": big, "bytes_per_KiB": round(scale * 1024.0, 1), "factor": round(scale, 3)}
+        for r in rows:
+            kk = kernel_key(r["Kernel_Name"])
+            if kk:
+                grid = int(float(r.get("Grid_Size") or 0))
+                vals.setdefault(kk, {}).setdefault(tag, []).append((grid, float(r["Counter_Value"])))
+    out = {}
+    for kk, d in vals.items():
+        if len(d) < 2:
+            continue
+        if largest_grid:
+            g = max(x[0] for x in d["FETCH_SIZE"] + d["WRITE_SIZE"])
+            d = {t: [x for x in v if x[0] == g] for t, v in d.items()}
+            if not d["FETCH_SIZE"] or not d["WRITE_SIZE"]:
+                continue
+        fk = sum(x[1] for x in d["FETCH_SIZE"]) / len(d["FETCH_SIZE"])
+        wk = sum(x[1] for x in d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
+        b = fk * 1024.0 * calib["FETCH_SIZE"]["factor"] + wk * 1024.0 * calib["WRITE_SIZE"]["factor"]
+        rec = {"fetch_KiB": round(fk, 1), "write_KiB": round(wk, 1),
+               "dispatches": [len(d["FETCH_SIZE"]), len(d["WRITE_SIZE"])], "bytes_per_launch": round(b)}
+        if largest_grid:
+            rec["grid_size"] = g
+        out[kk] = rec
+    return calib, out
+
+
+def _trace_groups(trace_csv):
+    """{kernel name: {grid work-items: [durations in us]}} of the stage
+    kernels and k_forcing in a rocprofv3 kernel_trace.csv"""
+    groups = {}
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            if not (kernel_key(r["Kernel_Name"]) or "k_forcing" in r["Kernel_Name"]):
+                continue
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            groups.setdefault(r["Kernel_Name"], {}).setdefault(grid, []).append(dur)
+    return groups
+
+
+def summarize_pmc(pmc_dir: str, trace_csv: str | None, out_md: str | None, ens_trace_csv: str | None = None):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
     dispatch) of `bench.py --copy-probe` into HBM bytes per launch of each
     stage kernel and precision.  Each counter is scaled by what it reads for
     the 2 GiB device copy in the same run (bytes moved / counter reading).
-    out_md: the p = 1 summary; the p = 2 one goes beside it."""
-    def load(tag):
-        with open(os.path.join(pmc_dir, tag, "run_counter_collection.csv")) as fh:
-            return list(csv.DictReader(fh))
-    copy_bytes = 2 * 1024 ** 3
+    The same two runs of `bench.py --only-batched` under pmc_dir/ensemble,
+    if present, give the ensemble's launches.  out_md: the p = 1 summary;
+    the p = 2 and ensemble ones go beside it."""
     res = {"source_sha256": source_hash(), "kernels": {}, "calibration": {}}
-    vals = {}
-    for tag in ("FETCH_SIZE", "WRITE_SIZE"):
-        rows = load(tag)
-        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        big = max(copies)
-        scale = copy_bytes / (big * 1024.0)
-        res["calibration"][tag] = {"copy_KiB": big, "bytes_per_KiB": round(scale * 1024.0, 1), "factor": round(scale, 3)}
-        for r in rows:
-            kk = kernel_key(r["Kernel_Name"])
-            if kk:
-                vals.setdefault(kk, {}).setdefault(tag, []).append(float(r["Counter_Value"]))
-    for (k, prec), d in vals.items():
-        if len(d) < 2:
-            continue
-        fk = sum(d["FETCH_SIZE"]) / len(d["FETCH_SIZE"])
-        wk = sum(d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
-        b = fk * 1024.0 * res["calibration"]["FETCH_SIZE"]["factor"] + wk * 1024.0 * res["calibration"]["WRITE_SIZE"]["factor"]
-        res["kernels"].setdefault(k, {})[prec] = {"fetch_KiB": round(fk, 1), "write_KiB": round(wk, 1),
-                                                   "dispatches": [len(d["FETCH_SIZE"]), len(d["WRITE_SIZE"])],
-                                                   "bytes_per_launch": round(b)}
+    res["calibration"], per = _pmc_traffic(pmc_dir, True)
+    for (k, prec), r in per.items():
+        res["kernels"].setdefault(k, {})[prec] = r
+    ens_dir = os.path.join(pmc_dir, "ensemble")
+    if os.path.isdir(ens_dir):
+        res["ensemble_calibration"], per = _pmc_traffic(ens_dir, True)
+        res["ensemble"] = {}
+        for (k, prec), r in per.items():
+            res["ensemble"].setdefault(k, {})[prec] = r
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(res, fh, indent=1)
     print(json.dumps(res, indent=1))
     if not out_md:
         return
-    rows = []
-    if stats_csv:
-        with open(stats_csv) as fh:
-            rows = list(csv.DictReader(fh))
+    groups = _trace_groups(trace_csv) if trace_csv else {}
     c = res["calibration"]
     head = ["Commands, on one MI355X, with REPO = the repository root and OUT = an output folder:", "", "```",
             "cd /tmp && export TMPDIR=/tmp", CMD_TRACE, CMD_PMC.format(c="FETCH_SIZE"), CMD_PMC.format(c="WRITE_SIZE"),
-            "cd $REPO && python3 bench.py --summarize-pmc $OUT/pmc --kernel-stats "
-            "$OUT/prof/bench_kernel_stats.csv --summary-md profiles/k_stage_hurricane_4M.md", "```", "",
+            CMD_SUMMARIZE, "```", "",
             "One bench process runs the p = 1 FP64 headline, the p = 1 mixed variant, then p = 2 in FP64 and "
             "mixed, on the same 4M-triangle mesh.", "",
             f"Kernel sources sha256 (bench.py reports this traffic only for these sources): `{res['source_sha256']}`",
@@ -230,25 +280,24 @@ def summarize_pmc(pmc_dir: str, stats_csv: str | None, out_md: str | None):
 
     def section(title, kernels):
         out = [f"# {title}", ""] + head
-        sel = [r for r in rows if (kernel_key(r["Name"]) or ("",))[0] in kernels]
+        sel = {n: by for n, by in groups.items() if (kernel_key(n) or ("",))[0] in kernels}
         if sel:
-            out += ["## Kernel trace (`--kernel-trace --stats`, 50 timed + 5 warm-up steps per variant)", "",
-                    "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
-            for r in sel:
-                nm = r["Name"].split("(")[0].replace("dgswe::", "")
-                out.append(f"| `{nm}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
-                           f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+            out += ["## Kernel trace (`--kernel-trace`; the 4M-mesh launches, i.e. the largest grid of each kernel)",
+                    "", "| kernel | launches | avg us | min us | max us |", "|---|---|---|---|---|"]
+            big = {n: by[max(by)] for n, by in sel.items()}
+            for n, d in sorted(big.items()):
+                nm = n.split("(")[0].replace("dgswe::", "")
+                out.append(f"| `{nm}` | {len(d)} | {sum(d) / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |")
             out.append("")
             for k in kernels:
                 for prec in ("fp64", "mixed"):
-                    ss = [r for r in sel if kernel_key(r["Name"]) == (k, prec)]
-                    if ss:
-                        n = sum(int(r["Calls"]) for r in ss)
-                        tot = sum(float(r["TotalDurationNs"]) for r in ss)
-                        out.append(f"{k} {prec}, both RK stages: {n} launches, average {tot / n / 1e3:.1f} us "
-                                   f"(bench.py reports the HIP-event average over the same kernels).")
+                    ds = [x for n, d in big.items() if kernel_key(n) == (k, prec) for x in d]
+                    if ds:
+                        out.append(f"{k} {prec}, both RK stages: {len(ds)} launches, average "
+                                   f"{sum(ds) / len(ds):.1f} us (bench.py reports the HIP-event average over the "
+                                   f"same kernels).")
             out.append("")
-        out += ["## HBM traffic per launch (mean over both RK stages)", "",
+        out += ["## HBM traffic per launch (mean over both RK stages, 4M-mesh launches)", "",
                 "| kernel | precision | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch (calibrated) |",
                 "|---|---|---|---|---|"]
         for k in kernels:
@@ -264,6 +313,48 @@ def summarize_pmc(pmc_dir: str, stats_csv: str | None, out_md: str | None):
     with open(p2_md, "w") as fh:
         fh.write("\n".join(section("k_pp2 and k_rhs2 (p = 2) on the 4M-triangle hurricane workload: kernel times "
                                    "and HBM traffic", ("k_pp2", "k_rhs2"))))
+    if "ensemble" not in res:
+        return
+    ce = res["ensemble_calibration"]
+    out = ["# The 64-member storm-surge ensemble (27 members at p = 1, 37 at p = 2, mixed precision): kernel "
+           "times and HBM traffic", "",
+           "Commands, on one MI355X, with REPO = the repository root and OUT = an output folder:", "", "```",
+           "cd /tmp && export TMPDIR=/tmp", CMD_TRACE_ENS, CMD_PMC_ENS.format(c="FETCH_SIZE"),
+           CMD_PMC_ENS.format(c="WRITE_SIZE"),
+           CMD_SUMMARIZE,
+           "```", "",
+           "One bench process tunes the chunk size per order on the median member mesh, then advances the "
+           "ensemble in each arrangement (two streams; the pair with the p = 1 stage and the p = 2 "
+           "post-processing in one launch, then the p = 2 right-hand side; both orders' stage work in one "
+           "launch; persistent workgroups), then all 64 members at p = 1.", "",
+           f"Kernel sources sha256: `{res['source_sha256']}`", ""]
+    if ens_trace_csv:
+        # per kernel instance, the launches of its largest grid (the
+        # ensemble-sized ones; the autotuner runs on single member meshes)
+        groups = _trace_groups(ens_trace_csv)
+        out += ["## Kernel trace (`--kernel-trace`): the ensemble-sized launches (largest grid) of each kernel", "",
+                "| kernel | grid (work-items) | launches | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+        rows = []
+        for name, by in groups.items():
+            g = max(by)
+            d = by[g]
+            rows.append((sum(d), name.split("(")[0].replace("dgswe::", ""), g, d))
+        for tot, nm, g, d in sorted(rows, reverse=True):
+            out.append(f"| `{nm}` | {g} | {len(d)} | {tot / len(d):.1f} | {min(d):.1f} | {max(d):.1f} |")
+        out += ["", "Launch counts: 55 per arrangement and stage (5 warm-up + 50 timed steps), more for a kernel "
+                "that several arrangements launch.", ""]
+    out += ["## HBM traffic per launch (the ensemble-sized launches: the largest grid of each kernel)", "",
+            "| kernel | precision | grid (work-items) | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | bytes per launch "
+            "(calibrated) |", "|---|---|---|---|---|---|---|"]
+    for k in PROFILED:
+        for prec, d in res["ensemble"].get(k, {}).items():
+            out.append(f"| {k} | {prec} | {d['grid_size']} | {d['dispatches'][0]} | {d['fetch_KiB']:.0f} | "
+                       f"{d['write_KiB']:.0f} | {d['bytes_per_launch'] / 1e9:.3f} GB |")
+    out += ["", "Calibration: a 2 GiB device copy in the same runs reads "
+            f"{ce['FETCH_SIZE']['copy_KiB']:.0f} KiB FETCH_SIZE and {ce['WRITE_SIZE']['copy_KiB']:.0f} KiB "
+            f"WRITE_SIZE.", ""]
+    with open(os.path.join(os.path.dirname(out_md), "ensemble_64_members_mixed.md"), "w") as fh:
+        fh.write("\n".join(out))
 
 
 def cpu_model() -> str:
@@ -539,7 +630,7 @@ def measure_ensemble(ens, steps, warmup, stream, profile, tuned=None, fused=True
            "persistent": persistent, "chunk_params": op, "kernels": kernels,
            "note": "element-stages of both orders counted alike; a p = 2 element-stage does about 2.6x the work"}
     if kernels:
-        rec["roofline"] = roofline(kernels, {1: ne[1], 2: ne[2]}, ned, nn, "mixed")
+        rec["roofline"] = roofline(kernels, {1: ne[1], 2: ne[2]}, ned, nn, "mixed", section="ensemble")
     return rec
 
 
@@ -618,7 +709,7 @@ def measure_autotune(stream):
     return out
 
 
-def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
+def roofline(kernels, ne, ned, nn, precision, with_traffic=True, section="kernels"):
     if not kernels:
         return None
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
@@ -628,7 +719,7 @@ def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
     for k in kernels:
         kb = algorithmic_bytes(k, ne, ned, nn, precision)
         kernels[k]["alg_GBs"] = round(kb / (kernels[k]["avg_us"] * 1e-6) / 1e9, 1)
-    traffic = stored_traffic(dom, precision) if with_traffic else None
+    traffic = stored_traffic(dom, precision, section) if with_traffic else None
     out = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
            "bytes_per_launch": int(b), "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
@@ -637,6 +728,62 @@ def roofline(kernels, ne, ned, nn, precision, with_traffic=True):
         out["as_built"] = {"bytes_per_element_stage": B_ALG_MIXED_AS_BUILT, "bytes_per_launch": int(b2),
                            "frac": round(b2 / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
     return out
+
+
+def measure_batched(args, stream, profile):
+    """The batched ensemble variants: the best arrangement as "batched",
+    the others under "batched_modes", and all 64 members at p = 1."""
+    from paper_2508_21208_amd import workloads as W
+    variants = {}
+    t0 = time.perf_counter()
+    ens = W.cfg_ensemble()
+    orders = W.ensemble_orders(len(ens))
+    log(f"ensemble: {len(ens)} members, {sum(w.mesh.n_elems for w in ens)} elements, generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    tuned, tables = tune_ensemble_orders(ens, orders, stream)
+    # how the two orders' batches are advanced: each batch on its own
+    # stream (they overlap on the GPU), or together by dgswe_step_pair
+    # on one stream (per stage the p = 1 stage with the p = 2
+    # post-processing in one launch, then the p = 2 right-hand side; or
+    # the p = 2 post-processing, then one launch of both orders' stage
+    # work), with one workgroup per chunk or persistent workgroups
+    modes = {}
+    for name, kw, env in (("two_streams", dict(fused=False), None),
+                          ("pair", dict(fused=True), None),
+                          ("pair_both_stages_one_launch", dict(fused=True), "DGSWE_PAIR_SPLIT"),
+                          ("pair_persistent", dict(fused=True, persistent=2), None)):
+        if env:
+            os.environ[env] = "0"
+        try:
+            modes[name] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
+                                           orders=orders, **kw)
+        finally:
+            if env:
+                del os.environ[env]
+        log(f"ensemble {name}: {modes[name]['ms_per_step']:.3f} ms per step")
+    best = min(modes, key=lambda k: modes[k]["ms_per_step"])
+    variants["batched"] = dict(modes[best], mode=best, autotune=tables,
+                               modes_ms_per_step={k: v["ms_per_step"] for k, v in modes.items()})
+    variants["batched_modes"] = {k: v for k, v in modes.items() if k != best}
+    variants["batched_p1_only"] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
+                                                   orders=[1] * len(ens))
+    del ens
+    return variants
+
+
+def copy_probe(dev):
+    """a plain device copy of 2 GiB, three times: the reference for the HBM
+    counters"""
+    import torch
+    n = 2 * 1024 ** 3 // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: 3 x (read 2 GiB + write 2 GiB)")
+    del src, dst
 
 
 def main():
@@ -662,11 +809,14 @@ def main():
                     help="also run a plain device copy of 2 GiB (3 times) to calibrate HBM counters")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="no GPU run: turn rocprofv3 FETCH_SIZE/WRITE_SIZE runs under DIR into the traffic record")
-    ap.add_argument("--kernel-stats", help="with --summarize-pmc: rocprofv3 kernel_stats.csv to tabulate")
+    ap.add_argument("--kernel-trace", help="with --summarize-pmc: rocprofv3 kernel_trace.csv of the 4M run")
     ap.add_argument("--summary-md", help="with --summarize-pmc: write a markdown summary here")
+    ap.add_argument("--ensemble-kernel-trace", help="with --summarize-pmc: kernel_trace.csv of an --only-batched run")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched ensemble variants (for the ensemble's profiles); prints them")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc, args.kernel_stats, args.summary_md)
+        summarize_pmc(args.summarize_pmc, args.kernel_trace, args.summary_md, args.ensemble_kernel_trace)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; a multi-GPU run (domain "
@@ -677,6 +827,15 @@ def main():
     import torch
     from paper_2508_21208_amd import workloads as W
 
+    if args.only_batched:
+        torch.cuda.init()
+        dev = torch.device("cuda:0")
+        out = {"variants": measure_batched(args, torch.cuda.current_stream(dev), not args.no_profile),
+               "steps": args.steps, "warmup": args.warmup}
+        if args.copy_probe:
+            copy_probe(dev)
+        print(json.dumps(out), flush=True)
+        return
     t0 = time.perf_counter()
     wl = W.cfg_hurricane(n_target=args.elems)
     log(f"mesh {wl.mesh.n_elems} elements, {wl.mesh.n_nodes} nodes in {time.perf_counter() - t0:.1f} s")
@@ -749,39 +908,7 @@ def main():
             except DgsweError as ex:
                 variants[name] = {"error": str(ex), **extra}
     if not args.no_batched:
-        t0 = time.perf_counter()
-        ens = W.cfg_ensemble()
-        orders = W.ensemble_orders(len(ens))
-        log(f"ensemble: {len(ens)} members, {sum(w.mesh.n_elems for w in ens)} elements, generated in "
-            f"{time.perf_counter() - t0:.1f} s")
-        tuned, tables = tune_ensemble_orders(ens, orders, stream)
-        # how the two orders' batches are advanced: each batch on its own
-        # stream (they overlap on the GPU), or together by dgswe_step_pair
-        # on one stream (per stage the p = 1 stage with the p = 2
-        # post-processing in one launch, then the p = 2 right-hand side; or
-        # the p = 2 post-processing, then one launch of both orders' stage
-        # work), with one workgroup per chunk or persistent workgroups
-        modes = {}
-        for name, kw, env in (("two_streams", dict(fused=False), None),
-                              ("pair", dict(fused=True), None),
-                              ("pair_both_stages_one_launch", dict(fused=True), "DGSWE_PAIR_SPLIT"),
-                              ("pair_persistent", dict(fused=True, persistent=2), None)):
-            if env:
-                os.environ[env] = "0"
-            try:
-                modes[name] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
-                                               orders=orders, **kw)
-            finally:
-                if env:
-                    del os.environ[env]
-            log(f"ensemble {name}: {modes[name]['ms_per_step']:.3f} ms per step")
-        best = min(modes, key=lambda k: modes[k]["ms_per_step"])
-        variants["batched"] = dict(modes[best], mode=best, autotune=tables,
-                                   modes_ms_per_step={k: v["ms_per_step"] for k, v in modes.items()})
-        variants["batched_modes"] = {k: v for k, v in modes.items() if k != best}
-        variants["batched_p1_only"] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
-                                                       orders=[1] * len(ens))
-        del ens
+        variants.update(measure_batched(args, stream, profile))
 
     if not args.no_graphs:
         variants["graphs_small_mesh"] = measure_graphs(stream)
@@ -791,15 +918,7 @@ def main():
         variants["serving"] = measure_serving(args.serving_requests, hint, stream)
 
     if args.copy_probe:
-        n = 2 * 1024 ** 3 // 8
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: 3 x (read 2 GiB + write 2 GiB)")
-        del src, dst
+        copy_probe(dev)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -81,3 +81,41 @@ def test_roofline_of_a_p1_only_ensemble():
     r = bench.roofline(k, {1: 1_000_000, 2: 0}, 0, 0, "mixed", with_traffic=False)
     assert r["kernel"] == "k_stage" and r["bytes_per_launch"] == int(bench.B_ALG_MIXED * 1_000_000)
     assert r["as_built"]["bytes_per_launch"] == int(bench.B_ALG_MIXED_AS_BUILT * 1_000_000)
+
+
+def _pmc_csv(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w") as fh:
+        fh.write("Dispatch_Id,Grid_Size,Kernel_Name,Counter_Name,Counter_Value\n")
+        for i, (grid, name, val) in enumerate(rows):
+            fh.write(f'{i},{grid},"{name}",X,{val}\n')
+
+
+def test_summarize_pmc_calibrates_and_keeps_the_ensemble_sized_launches(tmp_path, monkeypatch):
+    """the counters scale by the 2 GiB copy of the same run; in the ensemble
+    run only the largest grid of each kernel counts (the autotuner's
+    single-member launches and the persistent grids are smaller)"""
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    copy = "__amd_rocclr_copyBuffer"
+    st = "void dgswe::k_stage<256, 2, double, 0, false, false>(dgswe::DevMesh)"
+    st1 = "void dgswe::k_stage<256, 2, double, 1, false, false>(dgswe::DevMesh)"
+    sp = "void dgswe::k_stage1pp2<float, 0, 2, false>(dgswe::DevMesh)"
+    spp = "void dgswe::k_stage1pp2<float, 0, 2, true>(dgswe::DevMesh)"
+    kib = 2 * 1024 ** 2  # a 2 GiB copy in KiB
+    for tag, f in (("FETCH_SIZE", 0.5), ("WRITE_SIZE", 1.0)):
+        _pmc_csv(tmp_path / "pmc" / tag, [(1 << 20, copy, kib * f), (1000, st, 100.0), (1000, st1, 300.0)])
+        _pmc_csv(tmp_path / "pmc" / "ensemble" / tag,
+                 [(1 << 20, copy, kib * f), (5000, sp, 1000.0), (5000, sp, 3000.0), (800, spp, 7.0), (64, sp, 9.0)])
+    md = tmp_path / "out" / "k_stage.md"
+    md.parent.mkdir()
+    bench.summarize_pmc(str(tmp_path / "pmc"), None, str(md))
+    rec = json.loads((tmp_path / "traffic.json").read_text())
+    assert rec["calibration"]["FETCH_SIZE"]["factor"] == 2.0 and rec["calibration"]["WRITE_SIZE"]["factor"] == 1.0
+    k = rec["kernels"]["k_stage"]["fp64"]
+    assert k["dispatches"] == [2, 2] and k["bytes_per_launch"] == round(200.0 * 1024 * 2 + 200.0 * 1024)
+    assert k["grid_size"] == 1000
+    e = rec["ensemble"]["k_stage1pp2"]["mixed"]
+    assert e["grid_size"] == 5000 and e["dispatches"] == [2, 2]
+    assert e["bytes_per_launch"] == round(2000.0 * 1024 * 2 + 2000.0 * 1024)
+    assert (tmp_path / "out" / "ensemble_64_members_mixed.md").exists()
+    assert (tmp_path / "out" / "k_rhs2_k_pp2_hurricane_4M_p2.md").exists()
