@@ -241,6 +241,64 @@ def _trace_groups(trace_csv):
     return groups
 
 
+CMD_COUNTERS = ('ARGS="--steps 3 --warmup 1 --no-cpu-baseline --no-profile --no-batched --no-serving --no-rk '
+                '--no-graphs"',
+                "timeout -s KILL 240 rocprofv3 --pmc SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY "
+                "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_INSTS_VALU SQ_INSTS_VMEM_RD GRBM_GUI_ACTIVE -d $OUT/c1 -o run "
+                "--output-format csv -- python3 $REPO/bench.py $ARGS",
+                "timeout -s KILL 240 rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum SQ_LDS_BANK_CONFLICT SQ_INSTS_LDS "
+                "SQ_WAIT_ANY SQ_ACTIVE_INST_ANY GRBM_GUI_ACTIVE -d $OUT/c2 -o run --output-format csv -- "
+                "python3 $REPO/bench.py $ARGS")
+
+
+def summarize_counters(cdir: str, kernels: tuple, title: str, out_md: str):
+    """Issue, wait and cache counters per kernel instance (the 4M-mesh
+    launches: largest grid) from the two rocprofv3 --pmc runs c1 and c2 of
+    CMD_COUNTERS under cdir, as a markdown table."""
+    per = {}
+    for tag in ("c1", "c2"):
+        for r in _pmc_rows(cdir, tag):
+            kk = kernel_key(r["Kernel_Name"])
+            if not kk or kk[0] not in kernels:
+                continue
+            grid = int(float(r.get("Grid_Size") or 0))
+            d = per.setdefault(r["Kernel_Name"], {}).setdefault(grid, {})
+            d.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    rows = []
+    for name, by in sorted(per.items()):
+        c = {k: sum(v) / len(v) for k, v in by[max(by)].items()}
+        n = {k: len(v) for k, v in by[max(by)].items()}
+        wv, cyc = c.get("SQ_WAVES", 0.0), c.get("SQ_WAVE_CYCLES", 0.0)
+        if not wv or not cyc:
+            continue
+        hit, miss = c.get("TCC_HIT_sum", 0.0), c.get("TCC_MISS_sum", 0.0)
+        pct = lambda k: f"{100.0 * c.get(k, 0.0) / cyc:.1f}"
+        nm = name.split("(")[0].replace("dgswe::", "").replace("void ", "")
+        lds_act = c.get("SQ_ACTIVE_INST_LDS", 0.0)
+        rows.append(f"| `{nm}` | {n.get('SQ_WAVES', 0)} | {wv:.0f} | {c.get('SQ_INSTS_VALU', 0.0) / wv:.0f} | "
+                    f"{c.get('SQ_INSTS_LDS', 0.0) / wv:.0f} | {c.get('SQ_INSTS_VMEM_RD', 0.0) / wv:.0f} | "
+                    f"{pct('SQ_ACTIVE_INST_ANY')} | {pct('SQ_ACTIVE_INST_VALU')} | {pct('SQ_ACTIVE_INST_LDS')} | "
+                    f"{pct('SQ_WAIT_INST_ANY')} | {pct('SQ_WAIT_ANY')} | "
+                    f"{100.0 * c.get('SQ_LDS_BANK_CONFLICT', 0.0) / lds_act if lds_act else 0.0:.0f} | "
+                    f"{100.0 * hit / (hit + miss) if hit + miss else 0.0:.1f} | {miss * 128 / 1e9:.3f} GB |")
+    out = [f"# {title}", "", "Commands, on one MI355X, with REPO = the repository root and OUT = an output folder:",
+           "", "```", "cd /tmp && export TMPDIR=/tmp", *CMD_COUNTERS,
+           f"cd $REPO && python3 bench.py --summarize-counters $OUT --counter-kernels {','.join(kernels)} "
+           f"--summary-md {out_md if out_md.startswith('profiles/') else 'profiles/' + os.path.basename(out_md)}",
+           "```", "", f"Kernel sources sha256: `{source_hash()}`", "",
+           "Averages per launch over the 4M-mesh dispatches of each kernel instance (largest grid). Per-wave "
+           "counts divide by SQ_WAVES; time shares divide by SQ_WAVE_CYCLES, the cycles the waves were resident: "
+           "issuing = SQ_ACTIVE_INST_ANY, VALU = SQ_ACTIVE_INST_VALU, LDS = SQ_ACTIVE_INST_LDS, waiting on "
+           "dependencies = SQ_WAIT_INST_ANY, waiting (any) = SQ_WAIT_ANY; bank conflicts as a share of the LDS "
+           "cycles; L2 bytes missed = TCC_MISS_sum x 128 B.", "",
+           "| kernel | dispatches | waves | VALU / wave | LDS / wave | VMEM reads / wave | issuing % | VALU % | "
+           "LDS % | waiting on dependencies % | waiting (any) % | LDS bank-conflict share % | L2 hit rate % | "
+           "L2 misses x 128 B |", "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|", *rows, ""]
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(out))
+    print("\n".join(rows))
+
+
 def summarize_pmc(pmc_dir: str, trace_csv: str | None, out_md: str | None, ens_trace_csv: str | None = None):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
     dispatch) of `bench.py --copy-probe` into HBM bytes per launch of each
@@ -811,10 +869,19 @@ def main():
                     help="no GPU run: turn rocprofv3 FETCH_SIZE/WRITE_SIZE runs under DIR into the traffic record")
     ap.add_argument("--kernel-trace", help="with --summarize-pmc: rocprofv3 kernel_trace.csv of the 4M run")
     ap.add_argument("--summary-md", help="with --summarize-pmc: write a markdown summary here")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="no GPU run: tabulate the issue/wait/cache counter runs c1, c2 under DIR")
+    ap.add_argument("--counter-kernels", default="k_stage", help="with --summarize-counters: kernels to tabulate")
     ap.add_argument("--ensemble-kernel-trace", help="with --summarize-pmc: kernel_trace.csv of an --only-batched run")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched ensemble variants (for the ensemble's profiles); prints them")
     args = ap.parse_args()
+    if args.summarize_counters:
+        ks = tuple(args.counter_kernels.split(","))
+        title = ("k_stage (p = 1)" if ks == ("k_stage",) else " and ".join(ks) + " (p = 2)") + \
+            " on the 4M-triangle hurricane workload: issue, wait and cache counters"
+        summarize_counters(args.summarize_counters, ks, title, args.summary_md)
+        return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc, args.kernel_trace, args.summary_md, args.ensemble_kernel_trace)
         return

@@ -559,7 +559,7 @@ dgswe_status alloc_solver(const dgswe_params *prm, int block, const long long ca
   else { al(&m.eg1, E); al(&m.eg2, E); al(&m.le_a, LE); al(&m.le_b, LE); }
   al(&m.lgid, L); al(&m.lhb01, L); al(&m.lhb2, L); al(&m.lnb, L);
   al(&m.h2, R2);
-  if (S->order == 2) al(&m.hmean, E);
+  if (S->order == 2) { al(&m.hmean, E); al(&m.le_g, LE); }
   if (pp.limiter == 2 && 3 * E > 0x7fffffffULL) ok = false;  // incidence positions are int
   if (pp.limiter == 2) { al(&m.nd_rng, N); al(&m.nd_el, 3 * E); al(&m.evb, E); }
   chk(dev_alloc(S, &S->d_chunk_rec, (size_t)std::max(1, chunk_cap) * kChunkRec));
@@ -727,7 +727,12 @@ dgswe_status place_member(dgswe_solver *S, int slot, const Prep &q) {
     for (int i = 0; i < q.h2_off[q.nch]; ++i) r2[(size_t)i] = q.h2[(size_t)i] + e0;
     chk(put(m.h2, (size_t)off[A_RING2], r2.data(), r2.size()));
   }
-  if (S->order == 2) chk(put(m.hmean, e0, q.hmean.data(), ne));
+  if (S->order == 2) {
+    chk(put(m.hmean, e0, q.hmean.data(), ne));
+    std::vector<int2> g(q.le_g.begin(), q.le_g.begin() + need[A_LEDGE]);
+    for (int2 &x : g) { x.x += e0; x.y += e0; }
+    chk(put(m.le_g, (size_t)off[A_LEDGE], g.data(), g.size()));
+  }
   if (e != hipSuccess) {
     for (int a = 0; a < A_COUNT; ++a) S->arena[a].give(off[a], need[a]);
     return hip_fail(S, e, "upload");

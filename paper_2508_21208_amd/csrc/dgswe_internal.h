@@ -94,6 +94,9 @@ struct DevMesh {
   const float4 *le_f;          // mixed: (nx, ny, len/2, ids as bits)
   // p = 2: mean bathymetry per element (the wet/dry test of a neighbour)
   const double *hmean;
+  // p = 2: global ids (e+, e-) of each local edge (e- = e+ on a boundary),
+  // so the edge pass reaches the two records without the local-id lookup
+  const int2 *le_g;
 };
 
 // One stage of an SSP Runge-Kutta scheme in Shu-Osher form: the stage
@@ -170,6 +173,7 @@ struct Prep {
   std::vector<double> le_nx, le_ny, le_hl;                // per local edge
   // element-centric edge records of the p = 2 kernels (see DevMesh)
   std::vector<double> hmean;
+  std::vector<int2> le_g;                                  // per local edge: global (e+, e-)
   std::vector<uint32_t> le_ids;                            // packed ids (see DevMesh)
   std::vector<uint16_t> el_ledge;                          // [3][ne] local edge code per local edge
   // packed records (see DevMesh)
@@ -194,7 +198,8 @@ void chunk_records(const Prep &P, const std::vector<int> &chunk_member, std::vec
 // local edge codes).
 void build_chunks(Prep &P, int C);
 
-// The p = 2 per-element mean bathymetry (hmean).
+// The p = 2 per-element mean bathymetry (hmean) and the global ids of the
+// two sides of each local edge (le_g).
 void p2_records(Prep &P);
 
 // Returns 0 on success, else a DGSWE status code with a message in `err`.

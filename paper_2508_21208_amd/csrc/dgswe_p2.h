@@ -240,10 +240,7 @@ HD void load_pp2(const DevMesh &m, const Params &p, CSt<QT> w, int e, bool pp, d
 // record is read here (from cache: it was read before), so only the traces
 // stay in registers.
 template <class QT>
-HD void traces_of(const Rec2<QT> *__restrict__ u, int r, int l, bool rev, double tz[4], QT tx[4], QT ty[4]) {
-  double z[6];
-  QT q[12];
-  load_rec<QT>(u, r, z, q);
+HD void traces_from(const double z[6], const QT q[12], int l, bool rev, double tz[4], QT tx[4], QT ty[4]) {
   for (int g = 0; g < 4; ++g) {
     double xi, eta, f[6];
     edge_point2(l, rev ? -gl4_s(g) : gl4_s(g), xi, eta);
@@ -258,6 +255,14 @@ HD void traces_of(const Rec2<QT> *__restrict__ u, int r, int l, bool rev, double
     }
     tz[g] = sz; tx[g] = sx; ty[g] = sy;
   }
+}
+
+template <class QT>
+HD void traces_of(const Rec2<QT> *__restrict__ u, int r, int l, bool rev, double tz[4], QT tx[4], QT ty[4]) {
+  double z[6];
+  QT q[12];
+  load_rec<QT>(u, r, z, q);
+  traces_from<QT>(z, q, l, rev, tz, tx, ty);
 }
 
 // bathymetry at point g of an edge with end values hA (s = -1), hB (s = +1)
@@ -304,48 +309,82 @@ HD Lds2<QT> lds2_view(int ed_max, void *base) {
   return L;
 }
 
-// Chunk-local edge j: both sides' traces from the records, the wet/dry
-// rules (as for p = 1), the flux at the four points into LDS.
+// the record of chunk-local edge j: normal, half length, packed ids and
+// the global ids of its two sides
 template <class QT>
-HD void edge_phase2(const DevMesh &m, const Params &p, const ChunkInfo &k, const Rec2<QT> *__restrict__ u,
-                    double zb, int j, const Lds2<QT> &L) {
-  using R = QT;
-  const size_t r = (size_t)(k.leo + j);
-  R nx, ny;
+struct Edge2In {
+  QT nx, ny;
   double hl;
   uint32_t ids;
+  int gp, gm;
+};
+
+template <class QT>
+HD Edge2In<QT> load_edge2(const DevMesh &m, const ChunkInfo &k, int j) {
+  const size_t r = (size_t)(k.leo + j);
+  Edge2In<QT> E;
   if constexpr (sizeof(QT) == 8) {
     const double2 a = m.le_a[r], b = m.le_b[r];
-    nx = a.x; ny = a.y; hl = b.x;
-    ids = info_bits(b.y);
+    E.nx = a.x; E.ny = a.y; E.hl = b.x;
+    E.ids = info_bits(b.y);
   } else {
     const float4 a = m.le_f[r];
-    nx = a.x; ny = a.y; hl = (double)a.z;
-    ids = info_bits(a.w);
+    E.nx = a.x; E.ny = a.y; E.hl = (double)a.z;
+    E.ids = info_bits(a.w);
   }
+  const int2 g = m.le_g[r];
+  E.gp = g.x;
+  E.gm = g.y;  // = gp on a boundary edge
+  return E;
+}
+
+// Chunk-local edge j (record E): both sides' traces from the records, the
+// wet/dry rules (as for p = 1), the flux at the four points into LDS.
+template <class QT>
+HD void edge_phase2(const DevMesh &m, const Params &p, const ChunkInfo &k, const Rec2<QT> *__restrict__ u,
+                    double zb, int j, const Edge2In<QT> &E, const Lds2<QT> &L) {
+  using R = QT;
+  const R nx = E.nx, ny = E.ny;
+  const double hl = E.hl;
+  const uint32_t ids = E.ids;
   const int info = (int)(ids >> 24);
   const int lp = info & 3, lm = (info >> 2) & 3, type = info >> 4;
-  const int ip = (int)(ids & 0xFFFu), im = (int)((ids >> 12) & 0xFFFu);
+  const int ip = (int)(ids & 0xFFFu);
   const bool ghost = type != 0;
-  const int gp = m.lgid[k.lo + ip];
-  const int gm = ghost ? gp : m.lgid[k.lo + im];
+  const int gp = E.gp, gm = E.gm;
   // bathymetry at the edge ends: vertices lp+1 (s = -1) and lp+2 (s = +1) of e+
+  // every load of the edge at once: both records (gm = gp on a boundary
+  // edge, whose second copy goes unused), mean bathymetries, edge-end
+  // bathymetry; one wait for memory instead of one per dependent step
+  double zp6[6], zm6[6];
+  R qp12[12], qm12[12];
+  load_rec<QT>(u, gp, zp6, qp12);
+  load_rec<QT>(u, gm, zm6, qm12);
+  const double hmp = m.hmean[gp], hmm = m.hmean[gm];
   const double2 h01 = m.lhb01[k.lo + ip];
   const double h2 = m.lhb2[k.lo + ip];
+#ifdef __HIP_DEVICE_COMPILE__
+  // FP64: keep every load above the arithmetic (measured faster; in the
+  // mixed path the scheduler's own order measured faster)
+  if constexpr (sizeof(QT) == 8) __builtin_amdgcn_sched_barrier(0);
+#endif
   const int va = lp == 2 ? 0 : lp + 1, vb = lp == 0 ? 2 : lp - 1;
   const double hA = va == 0 ? h01.x : (va == 1 ? h01.y : h2);
   const double hB = vb == 0 ? h01.x : (vb == 1 ? h01.y : h2);
-  const bool wetp = p.wetdry ? (u[gp].z[0] + m.hmean[gp] > p.h0) : true;
-  const bool wetm = ghost ? (p.wetdry ? (zb + 0.5 * (hA + hB) > p.h0) : true)
-                          : (p.wetdry ? (u[gm].z[0] + m.hmean[gm] > p.h0) : true);
+  // (both candidates of wetm formed unconditionally: a select, so the
+  // mean-bathymetry load is not sunk into a branch that then waits for
+  // every outstanding load)
+  const bool wm_in = zm6[0] + hmm > p.h0, wm_ghost = zb + 0.5 * (hA + hB) > p.h0;
+  const bool wetp = p.wetdry ? (zp6[0] + hmp > p.h0) : true;
+  const bool wetm = p.wetdry ? (ghost ? wm_ghost : wm_in) : true;
   // e+ and e- traces; a ghost e- side is (zeta_b, momentum of e+)
   double pz[4], mz[4];
   R px[4], py[4], mx[4], my[4];
-  traces_of<QT>(u, gp, lp, false, pz, px, py);
+  traces_from<QT>(zp6, qp12, lp, false, pz, px, py);
   if (ghost) {
     for (int g = 0; g < 4; ++g) { mz[g] = zb; mx[g] = px[g]; my[g] = py[g]; }
   } else {
-    traces_of<QT>(u, gm, lm, true, mz, mx, my);
+    traces_from<QT>(zm6, qm12, lm, true, mz, mx, my);
   }
   int kind;
   if (type == DGSWE_BC_LAND) kind = EK_WALL_P;
@@ -496,15 +535,15 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   const size_t ne = (size_t)m.ne;
   const int e = k.c0 + i;
 
+  // every load that needs no index first (own record, vertex bathymetry,
+  // area, gradients, node ids and edge codes, Manning n), then the nodal
+  // forcing through the node ids: two waits for memory
+  double z[6];
+  R q[12];
+  load_rec<QT>(u, e, z, q);
   double h[3];
   for (int j = 0; j < 3; ++j) h[j] = m.hbv[j * ne + e];
-  const double hm = mean3(h);
-  const bool wet = p.wetdry ? (u[e].z[0] + hm > p.h0) : true;
   const double2 ai = m.eai[e];
-  const double iA = rcp_nr(ai.x);
-
-  // physical gradients of the reference coordinates from those of phi_10
-  // and phi_01: J^-T e1 = g1 - g2/3, J^-T e2 = 2/3 g2
   R g1x, g1y, g2x, g2y;
   if constexpr (sizeof(QT) == 8) {
     const double2 a = m.eg1[e], b = m.eg2[e];
@@ -513,12 +552,22 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
     const float4 a = m.egf[e];
     g1x = a.x; g1y = a.y; g2x = a.z; g2y = a.w;
   }
+  const int4 nd = m.enode[e];
+  const R man = manning_of(m, k, i, (QT)0);
+#ifdef __HIP_DEVICE_COMPILE__
+  if constexpr (sizeof(QT) == 8) __builtin_amdgcn_sched_barrier(0);
+#endif
+  const double hm = mean3(h);
+  const bool wet = p.wetdry ? (z[0] + hm > p.h0) : true;
+  const double iA = rcp_nr(ai.x);
+
+  // physical gradients of the reference coordinates from those of phi_10
+  // and phi_01: J^-T e1 = g1 - g2/3, J^-T e2 = 2/3 g2
   const R c1x = g1x - g2x * (R)(1.0 / 3.0), c1y = g1y - g2y * (R)(1.0 / 3.0);
   const R c2x = g2x * (R)(2.0 / 3.0), c2y = g2y * (R)(2.0 / 3.0);
 
   // nodal forcing: wind stress at the vertices, pressure gradient from
   // vertex differences (FP64, large common offset)
-  const int4 nd = m.enode[e];
   const int node[3] = {nd.x, nd.y, nd.z};
   R tx[3], ty[3];
   double pa[3];
@@ -537,13 +586,11 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   const double dp1 = pa[1] - pa[0], dp2 = pa[2] - pa[0];
   const R pm1 = (R)(0.5 * dp1), pm2 = (R)((2.0 * dp2 - dp1) * (1.0 / 6.0));
   const R dpx = pm1 * g1x + pm2 * g2x, dpy = pm1 * g1y + pm2 * g2y;
-  const R man = manning_of(m, k, i, (QT)0);
 
   // chunk-local edge codes of the three local edges (edge << 1 | 1 on the
   // e- side)
-  const int4 nw = m.enode[e];
   int ecode[3];
-  for (int l = 0; l < 3; ++l) ecode[l] = (nw.w >> (10 * l)) & 0x3FF;
+  for (int l = 0; l < 3; ++l) ecode[l] = (nd.w >> (10 * l)) & 0x3FF;
 
   // area part: rz[k] = (1/A) sum_q w_q A grad phi_k . F_zeta (FP64 sums of
   // R terms), rq[v][k] likewise for the momentum rows with the sources
@@ -551,10 +598,6 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   R rq[12];
   for (int j = 0; j < 12; ++j) rq[j] = (R)0;
   {
-    // the element's own record, live during the area integrals only
-    double z[6];
-    R q[12];
-    load_rec<QT>(u, e, z, q);
     const R gr = (R)p.g, gn2 = gr * man * man, irho = (R)(1.0 / p.rho0), h0 = (R)p.h0;
 #pragma unroll 1
     for (int qd = 0; qd < 6; ++qd) {
@@ -622,6 +665,17 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   }
 
   rz[0] += F.rain;  // uniform rain projects on mode 0 alone
+  // mixed: the RK base (later stages) is loaded here, so its latency
+  // overlaps the edge integrals instead of following them; without a base
+  // the element's own record stands in (unused), so the load is
+  // unconditional and nothing waits for it before its use.  FP64 loads it
+  // after the edge integrals (early, its registers spill at 3 waves per
+  // SIMD: measured slower).
+  constexpr bool kEarlyBase = sizeof(QT) == 4;
+  double bz[6];
+  R bq[12];
+  const bool use_base = base != nullptr;
+  if constexpr (kEarlyBase) load_rec<QT>(use_base ? base : u, e, bz, bq);
   // edges, from LDS: the side takes the flux its kind gives it, e- with the
   // opposite sign for a flux both sides share, integrated with its own basis
   // (e- runs the edge backwards)
@@ -651,16 +705,12 @@ HD bool rhs2_element(const DevMesh &m, const DevState &s, const Params &p, const
   }
 
   // inverse mass diagonal and the RK combination
-  double z[6];
-  R q[12];
-  load_rec<QT>(u, e, z, q);
-  double bz[6];
-  R bq[12];
-  const bool use_base = base != nullptr;
-  if (use_base) load_rec<QT>(base, e, bz, bq);
-  else {
-    for (int j = 0; j < 6; ++j) bz[j] = 0.0;
-    for (int j = 0; j < 12; ++j) bq[j] = (R)0;
+  if constexpr (!kEarlyBase) {
+    if (use_base) load_rec<QT>(base, e, bz, bq);
+    else {
+      for (int j = 0; j < 6; ++j) bz[j] = 0.0;
+      for (int j = 0; j < 12; ++j) bq[j] = (R)0;
+    }
   }
   const double hdt = sc.h * dt;
   bool fin = true;
@@ -710,8 +760,19 @@ __device__ __forceinline__ void rhs2_chunk(DevMesh m, DevState s, Params p, cons
     const double ts = t0 + sc.c * dt;
     const bool tide = F.n_tide > 0 || F.tide_offset != 0.0;
     const double zb = tide ? tide_level(F, ts) : 0.0;
-    if (tid < k.ne_loc) edge_phase2<QT>(m, p, k, u, zb, tid, L);
-    if (tid + kBlock < k.ne_loc) edge_phase2<QT>(m, p, k, u, zb, tid + kBlock, L);
+    const int j0 = tid < k.ne_loc ? tid : k.ne_loc - 1;
+    const int j1 = tid + kBlock < k.ne_loc ? tid + kBlock : k.ne_loc - 1;
+    if constexpr (sizeof(QT) == 4) {
+      // mixed: both records first, so the second edge's record is in
+      // registers when the first edge's flux is done (in FP64 the extra
+      // registers spill at 3 waves per SIMD: measured slower there)
+      const Edge2In<QT> E0 = load_edge2<QT>(m, k, j0), E1 = load_edge2<QT>(m, k, j1);
+      if (tid < k.ne_loc) edge_phase2<QT>(m, p, k, u, zb, tid, E0, L);
+      if (tid + kBlock < k.ne_loc) edge_phase2<QT>(m, p, k, u, zb, tid + kBlock, E1, L);
+    } else {
+      if (tid < k.ne_loc) edge_phase2<QT>(m, p, k, u, zb, tid, load_edge2<QT>(m, k, j0), L);
+      if (tid + kBlock < k.ne_loc) edge_phase2<QT>(m, p, k, u, zb, tid + kBlock, load_edge2<QT>(m, k, j1), L);
+    }
   }
   __syncthreads();
   double out[6], cand = INFINITY;

@@ -377,6 +377,11 @@ void p2_records(Prep &P) {
   const size_t ne = (size_t)P.ne;
   P.hmean.resize(ne);
   for (size_t e = 0; e < ne; ++e) P.hmean[e] = (P.hbv[e] + P.hbv[ne + e] + P.hbv[2 * ne + e]) / 3.0;
+  P.le_g.resize(P.le_gid.size());
+  for (size_t r = 0; r < P.le_gid.size(); ++r) {
+    const int d = P.le_gid[r];
+    P.le_g[r] = make_int2(P.ed_ep[d], P.ed_em[d] < 0 ? P.ed_ep[d] : P.ed_em[d]);
+  }
 }
 
 void chunk_records(const Prep &P, const std::vector<int> &chunk_member, std::vector<int> &rec) {

@@ -119,3 +119,26 @@ def test_summarize_pmc_calibrates_and_keeps_the_ensemble_sized_launches(tmp_path
     assert e["bytes_per_launch"] == round(2000.0 * 1024 * 2 + 2000.0 * 1024)
     assert (tmp_path / "out" / "ensemble_64_members_mixed.md").exists()
     assert (tmp_path / "out" / "k_rhs2_k_pp2_hurricane_4M_p2.md").exists()
+
+
+def test_summarize_counters_tabulates_the_largest_grid(tmp_path):
+    """per-wave counts and time shares from the two counter runs, for the
+    4M-mesh launches only"""
+    name = "void dgswe::k_rhs2<double, 3, false, false>(dgswe::DevMesh)"
+    c1 = {"SQ_WAVES": 100, "SQ_WAVE_CYCLES": 1000, "SQ_INSTS_VALU": 4000, "SQ_INSTS_VMEM_RD": 50,
+          "SQ_ACTIVE_INST_VALU": 300, "SQ_WAIT_INST_ANY": 200, "SQ_ACTIVE_INST_LDS": 40}
+    c2 = {"TCC_HIT_sum": 60, "TCC_MISS_sum": 40, "SQ_INSTS_LDS": 1300, "SQ_ACTIVE_INST_ANY": 450, "SQ_WAIT_ANY": 350,
+          "SQ_LDS_BANK_CONFLICT": 10}
+    for tag, cs in (("c1", c1), ("c2", c2)):
+        os.makedirs(tmp_path / tag)
+        with open(tmp_path / tag / "run_counter_collection.csv", "w") as fh:
+            fh.write("Dispatch_Id,Grid_Size,Kernel_Name,Counter_Name,Counter_Value\n")
+            for k, v in cs.items():
+                fh.write(f'1,5000,"{name}",{k},{v}\n')
+                fh.write(f'2,64,"{name}",{k},{v * 7}\n')  # a small launch: ignored
+    md = tmp_path / "c.md"
+    bench.summarize_counters(str(tmp_path), ("k_rhs2",), "t", str(md))
+    row = [l for l in md.read_text().splitlines() if l.startswith("| `k_rhs2")][0]
+    cells = [x.strip() for x in row.strip("|").split("|")]
+    assert cells[1:] == ["1", "100", "40", "13", "0", "45.0", "30.0", "4.0", "20.0", "35.0", "25", "60.0",
+                         f"{40 * 128 / 1e9:.3f} GB"]
