@@ -145,9 +145,14 @@ HD bool dt_from_bits(const Params &p, unsigned long long bits, double &dt) {
 }
 HD bool step_dt(const Ctrl *c, const Params &p, int slot, double &dt) { return dt_from_bits(p, c->dtmin[slot], dt); }
 
+// (unrolled over the constituent slots, so the constants are read with
+// constant offsets - scalar loads - and no vector load inside a loop makes
+// the kernel wait for every load it has in flight)
 HD double tide_level(const Member &f, double t) {
   double z = f.tide_offset;
-  for (int i = 0; i < f.n_tide; ++i) z += f.tide_amp[i] * cos(f.tide_omega[i] * t + f.tide_phase[i]);
+#pragma unroll
+  for (int i = 0; i < kMaxTide; ++i)
+    if (i < f.n_tide) z += f.tide_amp[i] * cos(f.tide_omega[i] * t + f.tide_phase[i]);
   return z;
 }
 

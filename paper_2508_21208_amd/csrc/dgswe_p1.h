@@ -756,6 +756,10 @@ __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CS
     active = false;
   }
   if (STAGE == 0 && active && k.first && tid == 0) ctl->dtmin[slot ^ 1] = double_to_bits(INFINITY);
+  // the ocean tide at the stage time (its cosine waits for every load in
+  // flight; here the state loads are about to be waited for anyway)
+  const double ts = t0 + sc.c * dt;
+  const double zb = tide ? tide_level(F, ts) : 0.0;
   if (a0) {
     store_state_lds<QT>(L, i0, st0);
     for (int q = 0; q < 3; ++q) L.LH[q * L.nls + i0] = h0[q];
@@ -776,8 +780,6 @@ __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CS
   if (a0) phase_post<QT, VL>(p, k, L, pp_in, i0, h0, nb0, to_wpp, wpp, ne, s.vb, ev0);
   if (a1) phase_post<QT, VL>(p, k, L, pp_in, i1, h1, nb1, to_wpp, wpp, ne, s.vb, ev1);
   __syncthreads();
-  const double ts = t0 + sc.c * dt;
-  const double zb = tide ? tide_level(F, ts) : 0.0;
   if (tid < k.ne_loc) phase_edge<QT>(p, L, zb, tid, r0);
   if (tid + NT < k.ne_loc) phase_edge<QT>(p, L, zb, tid + NT, r1);
   __syncthreads();
