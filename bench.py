@@ -177,10 +177,11 @@ CMD_PMC = ("rocprofv3 --pmc {c} -d $OUT/pmc/{c} -o run --output-format csv -- py
 CMD_SUMMARIZE = ("cd $REPO && python3 bench.py --summarize-pmc $OUT/pmc --kernel-trace $OUT/prof/bench_kernel_trace.csv "
                  "--ensemble-kernel-trace $OUT/prof_ens/bench_kernel_trace.csv --summary-md "
                  "profiles/k_stage_hurricane_4M.md")
+ENSEMBLE_PROFILE_CHUNK = 256
 CMD_TRACE_ENS = ("rocprofv3 --kernel-trace --stats -d $OUT/prof_ens -o bench --output-format csv -- "
-                 "python3 $REPO/bench.py --only-batched --steps 50 --warmup 5 --no-profile")
+                 "python3 $REPO/bench.py --only-batched --ensemble-chunk 256 --steps 50 --warmup 5 --no-profile")
 CMD_PMC_ENS = ("rocprofv3 --pmc {c} -d $OUT/pmc/ensemble/{c} -o run --output-format csv -- python3 $REPO/bench.py "
-               "--only-batched --steps 3 --warmup 1 --no-profile --copy-probe")
+               "--only-batched --ensemble-chunk 256 --steps 3 --warmup 1 --no-profile --copy-probe")
 
 
 def _pmc_rows(pmc_dir, tag):
@@ -212,7 +213,10 @@ def _pmc_traffic(pmc_dir, largest_grid):
         if len(d) < 2:
             continue
         if largest_grid:
-            g = max(x[0] for x in d["FETCH_SIZE"] + d["WRITE_SIZE"])
+            common = {x[0] for x in d["FETCH_SIZE"]} & {x[0] for x in d["WRITE_SIZE"]}
+            if not common:
+                continue
+            g = max(common)
             d = {t: [x for x in v if x[0] == g] for t, v in d.items()}
             if not d["FETCH_SIZE"] or not d["WRITE_SIZE"]:
                 continue
@@ -314,6 +318,7 @@ def summarize_pmc(pmc_dir: str, trace_csv: str | None, out_md: str | None, ens_t
     ens_dir = os.path.join(pmc_dir, "ensemble")
     if os.path.isdir(ens_dir):
         res["ensemble_calibration"], per = _pmc_traffic(ens_dir, True)
+        res["ensemble_chunk"] = ENSEMBLE_PROFILE_CHUNK
         res["ensemble"] = {}
         for (k, prec), r in per.items():
             res["ensemble"].setdefault(k, {})[prec] = r
@@ -381,8 +386,8 @@ def summarize_pmc(pmc_dir: str, trace_csv: str | None, out_md: str | None, ens_t
            CMD_PMC_ENS.format(c="WRITE_SIZE"),
            CMD_SUMMARIZE,
            "```", "",
-           "One bench process tunes the chunk size per order on the median member mesh, then advances the "
-           "ensemble in each arrangement (two streams; the pair with the p = 1 stage and the p = 2 "
+           "One bench process (chunks of 256 elements for both orders, the size the autotuner picks in the "
+           "benched run) advances the ensemble in each arrangement (two streams; the pair with the p = 1 stage and the p = 2 "
            "post-processing in one launch, then the p = 2 right-hand side; both orders' stage work in one "
            "launch; persistent workgroups), then all 64 members at p = 1.", "",
            f"Kernel sources sha256: `{res['source_sha256']}`", ""]
@@ -688,7 +693,10 @@ def measure_ensemble(ens, steps, warmup, stream, profile, tuned=None, fused=True
            "persistent": persistent, "chunk_params": op, "kernels": kernels,
            "note": "element-stages of both orders counted alike; a p = 2 element-stage does about 2.6x the work"}
     if kernels:
-        rec["roofline"] = roofline(kernels, {1: ne[1], 2: ne[2]}, ned, nn, "mixed", section="ensemble")
+        # the ensemble's measured traffic belongs to its profiled chunk size
+        same = all(op[o].get("chunk", 256) == ENSEMBLE_PROFILE_CHUNK for o in (1, 2))
+        rec["roofline"] = roofline(kernels, {1: ne[1], 2: ne[2]}, ned, nn, "mixed", with_traffic=same,
+                                   section="ensemble")
     return rec
 
 
@@ -798,7 +806,10 @@ def measure_batched(args, stream, profile):
     orders = W.ensemble_orders(len(ens))
     log(f"ensemble: {len(ens)} members, {sum(w.mesh.n_elems for w in ens)} elements, generated in "
         f"{time.perf_counter() - t0:.1f} s")
-    tuned, tables = tune_ensemble_orders(ens, orders, stream)
+    if args.ensemble_chunk:
+        tuned, tables = {1: dict(chunk=args.ensemble_chunk), 2: dict(chunk=args.ensemble_chunk)}, None
+    else:
+        tuned, tables = tune_ensemble_orders(ens, orders, stream)
     # how the two orders' batches are advanced: each batch on its own
     # stream (they overlap on the GPU), or together by dgswe_step_pair
     # on one stream (per stage the p = 1 stage with the p = 2
@@ -873,6 +884,9 @@ def main():
                     help="no GPU run: tabulate the issue/wait/cache counter runs c1, c2 under DIR")
     ap.add_argument("--counter-kernels", default="k_stage", help="with --summarize-counters: kernels to tabulate")
     ap.add_argument("--ensemble-kernel-trace", help="with --summarize-pmc: kernel_trace.csv of an --only-batched run")
+    ap.add_argument("--ensemble-chunk", type=int, default=0,
+                    help="chunk size of both orders in the ensemble runs instead of the autotuner's choice (so "
+                         "that separate profiler runs launch the same grids)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched ensemble variants (for the ensemble's profiles); prints them")
     args = ap.parse_args()
