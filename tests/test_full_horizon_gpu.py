@@ -8,8 +8,8 @@
 One FP64 oracle run per workload (a session fixture; it prints its progress
 straight to the terminal, since it runs for minutes) serves two checks:
   * the FP64 HIP path: relative L2 <= 1e-12 per variable, equal step count,
-    equal wet and dry counts, model time, mass (correctly rounded sum) and
-    volume to 1e-12;
+    the same wet/dry status of every element (and so equal counts), model
+    time, mass (correctly rounded sum) and volume to 1e-12;
   * the mixed FP32/FP64 path: elevation at every vertex of the elements
     at least 2 H0 deep in both runs within 1e-4 m, and depth-averaged
     velocity at element means within 1e-4 m/s (elements wet on both sides
@@ -143,6 +143,13 @@ def _gpu(wl, steps, precision):
     return w, d
 
 
+def _wet_mismatches(wl, wa, wb):
+    """elements wet (mean depth above H0) in one state and not in the other"""
+    hmean = wl.mesh.hb[wl.mesh.tri].mean(axis=1)
+    h0 = wl.params["h0"]
+    return int(np.sum((wa[0, 0] + hmean > h0) != (wb[0, 0] + hmean > h0)))
+
+
 def _vertex_zeta(w):
     z0, z1, z2 = w[0, 0], w[0, 1], w[0, 2]
     return np.stack([z0 - z1 - z2, z0 + z1 - z2, z0 + 2.0 * z2])
@@ -154,8 +161,10 @@ def test_fp64_matches_oracle_over_the_horizon(name, oracle_run):
     wl = o.wl
     wg, dg = _gpu(wl, HORIZON[name], "fp64")
     err = rel_l2(wg, o.w)
+    n_mis = _wet_mismatches(wl, wg, o.w)
     rec = {"steps": o.steps, "n_elems": wl.mesh.n_elems, "t_end": dg["t"], "rel_l2": [float(x) for x in err],
            "n_wet": [dg["n_wet"], o.n_wet], "n_dry": [dg["n_dry"], o.n_dry], "oracle_s": round(o.seconds, 1),
+           "wet_status_mismatches": n_mis,
            "mass_rel_diff": abs(dg["mass"] - o.mass) / max(abs(o.mass), 1e-300)}
     _report(f"{name}/fp64", rec)
     say(f"{wl.name}: FP64 after {o.steps} steps: rel L2 {err}, wet {dg['n_wet']} / {o.n_wet}")
@@ -163,6 +172,7 @@ def test_fp64_matches_oracle_over_the_horizon(name, oracle_run):
     assert dg["steps"] == o.steps == HORIZON[name]
     assert dg["t"] == pytest.approx(o.t, rel=1e-12)
     assert dg["n_wet"] == o.n_wet and dg["n_dry"] == o.n_dry
+    assert n_mis == 0, n_mis
     assert dg["mass"] == pytest.approx(o.mass, rel=1e-12, abs=1e-6)
     assert dg["volume"] == pytest.approx(o.volume, rel=1e-12)
 
@@ -189,6 +199,7 @@ def test_mixed_within_bar_of_oracle_over_the_horizon(name, oracle_run):
            "n_within_2H0": int(front.sum()), "n_within_2H0_over_1e-4": n_over,
            "velocity_mean_max_ms": ev, "t_end": dg["t"], "t_oracle": o.t, "dt_diff_s": abs(dg["t"] - o.t),
            "rel_l2": [float(x) for x in rel_l2(wg, o.w)], "n_wet": [dg["n_wet"], o.n_wet],
+           "wet_status_mismatches": _wet_mismatches(wl, wg, o.w),
            "worst_element_mean_depth_m": float(Ho[worst])}
     _report(f"{name}/mixed", rec)
     say(f"{wl.name}: MIXED after {o.steps} steps: elevation {ez_wet:.3e} m (>= 2 H0 deep), {ez_front:.3e} m "
