@@ -171,7 +171,7 @@ struct Prep {
   int C = 0, nch = 0, nl_max = 0, nm_max = 0, ed_max = 0, n2_max = 0;
   std::vector<int> ch_off, h1_off, h1, h2_off, h2, le_off, le_gid, lo_off;
   std::vector<double> le_nx, le_ny, le_hl;                // per local edge
-  // element-centric edge records of the p = 2 kernels (see DevMesh)
+  // p = 2 extras (see DevMesh): mean bathymetry, global ids of each local edge's sides
   std::vector<double> hmean;
   std::vector<int2> le_g;                                  // per local edge: global (e+, e-)
   std::vector<uint32_t> le_ids;                            // packed ids (see DevMesh)

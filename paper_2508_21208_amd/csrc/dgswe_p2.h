@@ -235,10 +235,8 @@ HD void load_pp2(const DevMesh &m, const Params &p, CSt<QT> w, int e, bool pp, d
 }
 
 // ---------------------------------------------------------------- edge
-// Traces of record r (element id) at the four points of its local edge l;
-// rev: the points in the opposite direction (the e- side of an edge).  The
-// record is read here (from cache: it was read before), so only the traces
-// stay in registers.
+// Traces of an element's modes (z, q) at the four points of its local edge
+// l; rev: the points in the opposite direction (the e- side of an edge).
 template <class QT>
 HD void traces_from(const double z[6], const QT q[12], int l, bool rev, double tz[4], QT tx[4], QT ty[4]) {
   for (int g = 0; g < 4; ++g) {
@@ -255,14 +253,6 @@ HD void traces_from(const double z[6], const QT q[12], int l, bool rev, double t
     }
     tz[g] = sz; tx[g] = sx; ty[g] = sy;
   }
-}
-
-template <class QT>
-HD void traces_of(const Rec2<QT> *__restrict__ u, int r, int l, bool rev, double tz[4], QT tx[4], QT ty[4]) {
-  double z[6];
-  QT q[12];
-  load_rec<QT>(u, r, z, q);
-  traces_from<QT>(z, q, l, rev, tz, tx, ty);
 }
 
 // bathymetry at point g of an edge with end values hA (s = -1), hB (s = +1)
