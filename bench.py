@@ -625,8 +625,10 @@ def tune_ensemble_orders(ens, orders, stream):
         w = ens[idx[len(idx) // 2]]
         prm = dict(w.params, precision=DGSWE_MIXED, p=p, **({"cfl": 0.1} if p == 2 else {}))
         w0 = w.w0 if p == 1 else np.concatenate([w.w0, np.zeros((3, 3, w.w0.shape[2]))], axis=1)
+        # explicit chunk sizes only (no "0: the library's choice"), so the
+        # measured ensemble traffic can be matched to the chunk size it ran at
         best, table = tune(w.mesh, prm, w.forcing, w0, w.postprocess_initial, steps=20, hip_stream=stream.cuda_stream,
-                           use_cache=False)
+                           use_cache=False, auto=False)
         out[p] = {k: best[k] for k in ("chunk", "waves")}
         tables[p] = {"mesh_elems": w.mesh.n_elems,
                      "us_per_step": {f"chunk {r[0]}, waves {r[1]}": round(r[2], 1) for r in table}}
@@ -760,7 +762,8 @@ def measure_graphs(stream, steps=600):
 
 def measure_autotune(stream):
     """The launch autotuner on two coastal meshes (10k and 130k triangles,
-    FP64, tide): microseconds per step for each chunk size."""
+    FP64, tide): microseconds per step for each chunk size ("auto": the
+    library's per-mesh default)."""
     from paper_2508_21208_amd import workloads as W
     from paper_2508_21208_amd.autotune import tune
     out = {}
@@ -768,9 +771,10 @@ def measure_autotune(stream):
         m = W.coastal_mesh(n, seed, hmin=1000.0 if n < 30_000 else 200.0, hmax=15000.0 if n < 30_000 else 5000.0)
         best, table = tune(m, W.default_params(dt_max=0.3), W.default_forcing(manning_n=0.025, **W.m2_tide(1.0)),
                            W.coastal_initial_state(m), steps=40, hip_stream=stream.cuda_stream, use_cache=False)
-        default = [r[2] for r in table if r[0] == 256][0]
-        out[str(m.n_elems)] = {"us_per_step": {str(r[0]): round(r[2], 1) for r in table}, "best_chunk": best["chunk"],
-                               "speedup_vs_256": default / min(r[2] for r in table)}
+        default = [r[2] for r in table if r[0] == 0][0]
+        out[str(m.n_elems)] = {"us_per_step": {("auto" if r[0] == 0 else str(r[0])): round(r[2], 1) for r in table},
+                               "best_chunk": best["chunk"] or "auto",
+                               "speedup_vs_default": default / min(r[2] for r in table)}
     log("autotune: " + json.dumps(out))
     return out
 

@@ -91,7 +91,10 @@ typedef struct {
                         32, 42, 52 = SSPRK(s,2) with s = 3, 4, 5 stages */
   int32_t flux;      /* numerical flux: 0 = local Lax-Friedrichs, 1 = Roe */
   int32_t chunk;     /* launch tuning: elements per workgroup chunk, 64..256
-                        (0: 256); results do not depend on it */
+                        (0: chosen per mesh - at p = 1 the largest size up
+                        to 256 whose LDS lets the most stage workgroups share
+                        a compute unit, else 256); results do not depend on
+                        it */
   int32_t waves;     /* launch tuning: waves per SIMD the p = 2 stage kernel's
                         registers are budgeted for, 1..4 (0: 3 in FP64, 2 in
                         mixed precision) */
@@ -152,7 +155,8 @@ void dgswe_default_params(dgswe_params *p);
 
 /* Environment variables read when a solver, batch or pool is created (for
  * tuning and testing; none of them changes any result, bitwise):
- *   DGSWE_CHUNK=n          chunk size (64..256), overrides params.chunk;
+ *   DGSWE_CHUNK=n          chunk size (64..256, or 0: chosen per mesh),
+ *                          overrides params.chunk;
  *   DGSWE_BLOCK=n          stage-kernel block size (only 256 is accepted);
  *   DGSWE_RHS2_WPE=n       p = 2: waves per SIMD the right-hand-side kernel's
  *                          registers are held to (1..4), overrides

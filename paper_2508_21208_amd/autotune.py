@@ -5,7 +5,9 @@ own forcing and state, and returns the fastest.  The configurations change
 only how the work is split over workgroups, never the results (bitwise).
 
 Small meshes favour small chunks (more workgroups for a short grid, less
-time per chunk), large ones the default 256 (less halo recomputation).
+time per chunk), large ones large chunks (less halo recomputation); at
+p = 1 chunk 0 is also a candidate: the library's own per-mesh choice, the
+largest chunk whose LDS lets the most workgroups share a compute unit.
 Results are cached per (order, precision, mesh-size decade).
 """
 from __future__ import annotations
@@ -18,23 +20,26 @@ from .dgswe import Solver
 _cache: dict = {}
 
 
-def candidates(params: dict):
-    chunks = (64, 128, 192, 256)
-    waves = (2, 3) if int(params.get("p", 1)) == 2 else (0,)
+def candidates(params: dict, auto: bool = True):
+    p2 = int(params.get("p", 1)) == 2
+    chunks = (64, 128, 192, 256) if p2 or not auto else (0, 64, 128, 192, 256)
+    waves = (2, 3) if p2 else (0,)
     return [(c, w) for c in chunks for w in waves]
 
 
 def tune(mesh, params: dict, forcing: dict, w0, postprocess=True, steps=20, hip_stream=None, use_cache=True,
-         repeats=3):
+         repeats=3, auto=True):
     """Returns (best params dict, table of (chunk, waves, us per step)); each
-    candidate's time is the median of `repeats` runs of `steps` steps."""
-    key = (int(params.get("p", 1)), int(params.get("precision", 0)), int(math.log10(max(1, mesh.n_elems))))
+    candidate's time is the median of `repeats` runs of `steps` steps.
+    auto=False leaves out chunk 0 (the library's per-mesh choice), so that
+    the result names an explicit chunk size."""
+    key = (int(params.get("p", 1)), int(params.get("precision", 0)), int(math.log10(max(1, mesh.n_elems))), auto)
     if use_cache and key in _cache:
         best = _cache[key]
         return dict(params, chunk=best[0], waves=best[1]), None
     import torch
     table = []
-    for c, w in candidates(params):
+    for c, w in candidates(params, auto):
         s = Solver(mesh, dict(params, chunk=c, waves=w), forcing, hip_stream=hip_stream)
         s.set_state(w0, 0.0, postprocess)
         s.step(3)

@@ -457,9 +457,31 @@ bool chunks_fit(const Prep &P, int precision, int block) {
 // 64 every mesh fits (at most 256 local elements, 192 local edges, about
 // 50 KB of LDS at p = 1), so no valid mesh is refused.  The p = 2 kernels
 // take a chunk's local edges (two per lane) but not its halo elements.
+//
+// chunk = 0 (the default) at p = 1: the largest chunk size of at most 256 -
+// down to 160, in steps of 8 - whose LDS lets the most workgroups share a
+// compute unit (kStageWgPerCu: 3 in FP64, 4 in mixed precision, the number
+// the stage kernel's registers allow), else 256.  On the 4M hurricane mesh
+// that is 232 in FP64 (3 workgroups per CU instead of 2 at 256: 373 against
+// 415 us per stage launch) and 256 in mixed precision.  At p = 2: 256.
+int auto_chunk(Prep &P, int order, int precision, int block) {
+  if (order != 1) return 256;
+  const int want = precision == DGSWE_MIXED ? kStageWgPerCuMixed : kStageWgPerCuFp64;
+  const size_t cap = kLdsPerCu / (size_t)want - kLdsSlack;
+  for (int c = 256; c >= 160; c -= 8) {
+    build_chunks(P, c);
+    if (!chunks_fit(P, precision, block)) continue;
+    DevMesh t{};
+    t.nl_max = P.nl_max; t.nm_max = P.nm_max; t.ed_max = P.ed_max; t.n2_max = P.n2_max; t.C = P.C;
+    if (stage_lds_bytes(t, precision) <= cap) return c;
+  }
+  return 256;
+}
+
 int prep_one(const dgswe_mesh &d, int order, int precision, int chunk, int block, Prep &P, std::string &msg) {
   int rc = prepare_mesh(d.n_nodes, d.node_xy, d.node_hb, d.n_elems, d.tri, d.n_bnd, d.bnd_nodes, d.bnd_type, P, msg);
   if (rc != DGSWE_OK) return rc;
+  if (chunk == 0) chunk = std::min(auto_chunk(P, order, precision, block), block);
   for (int c = chunk;; c = std::max(64, c - 32)) {
     build_chunks(P, c);
     if (order == 2 ? P.ed_max <= 2 * block : chunks_fit(P, precision, block)) break;
@@ -482,11 +504,11 @@ void arena_need(const Prep &q, int order, long long need[A_COUNT]) {
 }
 
 bool chunk_config(const dgswe_params *prm, int &chunk, int &block) {
-  chunk = prm && prm->chunk > 0 ? prm->chunk : 256;
+  chunk = prm && prm->chunk > 0 ? prm->chunk : 0;  // 0: chosen per mesh (auto_chunk)
   block = 256;
   if (const char *ev = std::getenv("DGSWE_CHUNK")) chunk = std::atoi(ev);
   if (const char *ev = std::getenv("DGSWE_BLOCK")) block = std::atoi(ev);
-  return stage_block_ok(block) && chunk >= 64 && chunk <= block;
+  return stage_block_ok(block) && (chunk == 0 || (chunk >= 64 && chunk <= block));
 }
 
 // Device arrays for the given arena capacities, `slots` members and

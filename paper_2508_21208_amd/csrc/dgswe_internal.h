@@ -274,6 +274,13 @@ hipError_t launch_post_only2(const DevMesh &m, const Params &p, const void *win,
 size_t stage_lds_bytes(const DevMesh &m, int precision);
 // LDS one stage-kernel workgroup may use (two workgroups share a CU's 160 KB)
 constexpr size_t kStageLdsMax = 80 * 1024;
+// LDS of a gfx950 compute unit, and the workgroups of the p = 1 stage kernel
+// its registers allow per CU (152 VGPRs in FP64: 3 waves per SIMD; 100-108 in
+// mixed precision: 4); kLdsSlack covers the kernel's static LDS and the
+// allocation granularity
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr int kStageWgPerCuFp64 = 3, kStageWgPerCuMixed = 4;
+constexpr size_t kLdsSlack = 1024;
 // bytes of one state buffer: (3 zeta modes FP64 + 6 momentum modes) per
 // element at p = 1, (6 + 12) at p = 2
 size_t state_bytes(size_t ne, int precision, int order);

@@ -213,10 +213,11 @@ HD int edge_flux(const double zp[3], const R qp[6], const double zm[3], const R 
   return mode;
 }
 
-// Per-element inputs of the area integrals and of the RK update, loaded in
-// phase L and kept in registers: vertex bathymetry, wind stress at the
-// vertices, the pressure gradient modes, Manning n, 2 x inradius, the
-// chunk-local edges and (second stage) the post-processed RK base.
+// Per-element inputs of the area integrals and of the RK update: Manning n,
+// the member's Coriolis parameter and rain rate and the chunk-local edges
+// (loaded in phase L), vertex bathymetry, wind stress at the vertices, the
+// pressure gradient modes and 2 x inradius (phase A) and (second stage) the
+// post-processed RK base (phase A, after the area integrals).
 template <class QT>
 struct ElemPre {
   double h[3];
@@ -332,44 +333,44 @@ HD void load_pp_global(const DevMesh &m, const Params &p, const double *vb, CSt<
 
 // ---------------------------------------------------------------- fused stage phases
 // LDS layout of one chunk (sizes from the mesh maxima):
-//   SZ[3][nl_max] double, SQ[6][nl_max] QT: states of chunk + ring 1
-//                 (post-processed in phase P)
-//   MZ[n2_max]    double: unlimited zeta means of ring 2 (the zeta mean of
-//                 chunk and ring 1 is SZ[0][i], never changed by phase P)
-//   GA[C]         double: element areas
+//   SZ[3][nl_max] double, SQ[6][nl_max] QT: states of chunk + ring 1.  Phase
+//                 P writes back the post-processed slopes (modes 1, 2) but
+//                 never the means, which stay the unlimited means that the
+//                 neighbours' limiters read concurrently; a dry element's
+//                 momentum is zero after its post-processing, so phases E and
+//                 A read its momentum means as 0 (WET = 0)
+//   MZ[n2_max]    double, MQ[2][n2_max] QT: unlimited zeta, Qx, Qy means of
+//                 ring 2
 //   LH[3][nl_max] double: vertex bathymetry of chunk + ring 1
-//   MQ[2][nm_max] QT: unlimited Qx, Qy means of chunk + ring 1 + ring 2
 //   EM[6][ed_max] QT: edge moments
-//   GG[4][C]      QT: gradients of phi_10, phi_01 of the chunk elements
 //   EMODE[ed_max], WET[nl_max] bytes
+// (The chunk elements' geometry is read in phase A, not kept in LDS.)
 template <class QT>
 struct Lds {
-  double *SZ, *MZ, *GA, *LH;
-  QT *SQ, *MQ, *EM, *GG;
+  double *SZ, *MZ, *LH;
+  QT *SQ, *MQ, *EM;
   unsigned char *EMODE, *WET;
-  int nls, nms, eds, cs;  // strides
+  int nls, n2s, eds;  // strides
 };
 
 template <class QT>
 HD size_t lds_bytes(const DevMesh &m) {
-  return 8 * (6 * (size_t)m.nl_max + (size_t)m.n2_max + (size_t)m.C) +
-         sizeof(QT) * (6 * (size_t)m.nl_max + 2 * (size_t)m.nm_max + 6 * (size_t)m.ed_max + 4 * (size_t)m.C) +
-         (size_t)m.ed_max + (size_t)m.nl_max;
+  return 8 * (6 * (size_t)m.nl_max + (size_t)m.n2_max) +
+         sizeof(QT) * (6 * (size_t)m.nl_max + 2 * (size_t)m.n2_max + 6 * (size_t)m.ed_max) + (size_t)m.ed_max +
+         (size_t)m.nl_max;
 }
 
 template <class QT>
 HD Lds<QT> lds_view(const DevMesh &m, void *base) {
   Lds<QT> L;
-  L.nls = m.nl_max; L.nms = m.nm_max; L.eds = m.ed_max; L.cs = m.C;
+  L.nls = m.nl_max; L.n2s = m.n2_max; L.eds = m.ed_max;
   L.SZ = (double *)base;
   L.MZ = L.SZ + 3 * (size_t)L.nls;
-  L.GA = L.MZ + (size_t)m.n2_max;
-  L.LH = L.GA + (size_t)L.cs;
+  L.LH = L.MZ + (size_t)L.n2s;
   L.SQ = (QT *)(L.LH + 3 * (size_t)L.nls);
   L.MQ = L.SQ + 6 * (size_t)L.nls;
-  L.EM = L.MQ + 2 * (size_t)L.nms;
-  L.GG = L.EM + 6 * (size_t)L.eds;
-  L.EMODE = (unsigned char *)(L.GG + 4 * (size_t)L.cs);
+  L.EM = L.MQ + 2 * (size_t)L.n2s;
+  L.EMODE = (unsigned char *)(L.EM + 6 * (size_t)L.eds);
   L.WET = L.EMODE + L.eds;
   return L;
 }
@@ -443,21 +444,19 @@ HD void load_state_reg(CSt<QT> w, size_t ne, int g, StateReg<QT> &S) {
   for (int j = 0; j < 6; ++j) S.q[j] = w.q[j * ne + g];
 }
 
-// local element i of chunk + ring 1 into LDS (state, unlimited means)
+// local element i of chunk + ring 1 into LDS (its state)
 template <class QT>
 HD void store_state_lds(const Lds<QT> &L, int i, const StateReg<QT> &S) {
   for (int j = 0; j < 3; ++j) L.SZ[j * L.nls + i] = S.z[j];
   for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = S.q[j];
-  L.MQ[i] = S.q[0];
-  L.MQ[L.nms + i] = S.q[3];
 }
 
-// ring-2 element j of local index nl + j: unlimited means only
+// ring-2 element j (local index nl + j): unlimited means only
 template <class QT>
-HD void load_h2_lds(const Lds<QT> &L, CSt<QT> w, size_t ne, int nl, int j, int g) {
+HD void load_h2_lds(const Lds<QT> &L, CSt<QT> w, size_t ne, int j, int g) {
   L.MZ[j] = w.z[g];
-  L.MQ[nl + j] = w.q[g];
-  L.MQ[L.nms + nl + j] = w.q[3 * ne + g];
+  L.MQ[j] = w.q[g];
+  L.MQ[L.n2s + j] = w.q[3 * ne + g];
 }
 
 // geometry of a chunk element
@@ -492,10 +491,16 @@ HD void load_elem_node(const DevMesh &m, const ChunkInfo &k, int i, int node[3],
 }
 
 
+// the post-processed slopes of local element i into LDS; the means stay
+// (the zeta mean is unchanged by the post-processing; the momentum means of
+// a dry element, zeroed by it, are read as 0 through its WET flag)
 template <class QT>
-HD void store_geo_lds(const Lds<QT> &L, int i, const GeoReg<QT> &G) {
-  for (int j = 0; j < 4; ++j) L.GG[j * L.cs + i] = G.g[j];
-  L.GA[i] = G.area;
+HD void write_back_pp(const Lds<QT> &L, int i, const double u[9]) {
+  for (int j = 1; j < 3; ++j) L.SZ[j * L.nls + i] = u[j];
+  for (int j = 1; j < 3; ++j) {
+    L.SQ[j * L.nls + i] = (QT)u[3 + j];
+    L.SQ[(3 + j) * L.nls + i] = (QT)u[6 + j];
+  }
 }
 
 // phase P for local element i of chunk + ring 1 (h: its vertex bathymetry,
@@ -516,8 +521,7 @@ HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp
     load_vbounds(vb, ev, lo, hi);
     limit_vertex(u, lo, hi);
     wetdry_fix(u, h, hmean, p);
-    for (int j = 1; j < 3; ++j) L.SZ[j * L.nls + i] = u[j];
-    for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = (QT)u[3 + j];
+    write_back_pp<QT>(L, i, u);
   } else if (pp_in) {
     double nbm[3][3];
     bool has[3];
@@ -525,14 +529,13 @@ HD void phase_post(const Params &p, const ChunkInfo &k, const Lds<QT> &L, int pp
       const uint16_t f = nb[q];
       has[q] = f != kNone;
       const int fi = has[q] ? f : 0;
-      nbm[0][q] = fi < nl ? L.SZ[fi] : L.MZ[fi - nl];
-      nbm[1][q] = (double)L.MQ[fi];
-      nbm[2][q] = (double)L.MQ[L.nms + fi];
+      const bool in = fi < nl;  // chunk + ring 1: unlimited means in SZ, SQ
+      nbm[0][q] = in ? L.SZ[fi] : L.MZ[fi - nl];
+      nbm[1][q] = (double)(in ? L.SQ[fi] : L.MQ[fi - nl]);
+      nbm[2][q] = (double)(in ? L.SQ[3 * L.nls + fi] : L.MQ[L.n2s + fi - nl]);
     }
     postprocess(u, nbm, has, h, hmean, p);
-    // the zeta mean SZ[0][i] is unchanged (neighbours read it concurrently)
-    for (int j = 1; j < 3; ++j) L.SZ[j * L.nls + i] = u[j];
-    for (int j = 0; j < 6; ++j) L.SQ[j * L.nls + i] = (QT)u[3 + j];
+    write_back_pp<QT>(L, i, u);
   }
   L.WET[i] = (p.wetdry ? (u[0] + hmean > p.h0) : true) ? 1 : 0;
   if (to_wpp && i < k.cc) {
@@ -552,11 +555,14 @@ HD void phase_edge(const Params &p, const Lds<QT> &L, double zb, int j, const Ed
   QT qp[6], qm[6];
   for (int q = 0; q < 3; ++q) zp[q] = L.SZ[q * L.nls + ip];
   for (int q = 0; q < 6; ++q) qp[q] = L.SQ[q * L.nls + ip];
+  const bool wetp = L.WET[ip] != 0;
+  if (!wetp) qp[0] = qp[3] = (QT)0;  // a dry element's momentum is zero
   bool wetm = false;
   if (type == 0) {
     for (int q = 0; q < 3; ++q) zm[q] = L.SZ[q * L.nls + im];
     for (int q = 0; q < 6; ++q) qm[q] = L.SQ[q * L.nls + im];
     wetm = L.WET[im] != 0;
+    if (!wetm) qm[0] = qm[3] = (QT)0;
   } else {
     for (int q = 0; q < 3; ++q) zm[q] = 0.0;
     for (int q = 0; q < 6; ++q) qm[q] = (QT)0;
@@ -566,21 +572,9 @@ HD void phase_edge(const Params &p, const Lds<QT> &L, double zb, int j, const Ed
   const double hA = L.LH[va * L.nls + ip], hB = L.LH[vb * L.nls + ip];
   QT mom[6];
   const int mode =
-      edge_flux<QT>(zp, qp, zm, qm, lp, lm, type, L.WET[ip] != 0, wetm, hA, hB, R.nx, R.ny, R.hl, zb, p, mom);
+      edge_flux<QT>(zp, qp, zm, qm, lp, lm, type, wetp, wetm, hA, hB, R.nx, R.ny, R.hl, zb, p, mom);
   for (int q = 0; q < 6; ++q) L.EM[q * L.eds + j] = mom[q];
   L.EMODE[j] = (unsigned char)mode;
-}
-
-// the parts of ElemPre that need no index: Manning n and (second stage)
-// the RK base
-template <class QT>
-HD void load_elem_pre(const DevMesh &m, const ChunkInfo &k, int i, const CSt<QT> *wbase, ElemPre<QT> &P) {
-  const size_t ne = (size_t)m.ne;
-  const int e = k.c0 + i;
-  if (wbase) {
-    for (int j = 0; j < 3; ++j) P.wbz[j] = wbase->z[j * ne + e];
-    for (int j = 0; j < 6; ++j) P.wbq[j] = wbase->q[j * ne + e];
-  }
 }
 
 // nodal forcing at the element's vertices (node: its node ids); the nodal
@@ -602,25 +596,39 @@ HD void load_elem_forcing(const DevMesh &m, const DevState &s, const int node[3]
   P.pm2 = (QT)((2.0 * dp2 - dp1) * (1.0 / 6.0));
 }
 
-// phase A for chunk element i; returns the CFL candidate of the output when
-// want_dt, and sets bad on a non-finite output.  base: combine with the
-// post-processed RK base held in P, out = a base + b (w + hdt L(w)), else
-// out = w + hdt L(w).
+// phase A for chunk element i (node: its node ids); returns the CFL
+// candidate of the output when want_dt, and sets bad on a non-finite
+// output.  base: combine with the post-processed RK base wb, out = a base +
+// b (w + hdt L(w)), else out = w + hdt L(w).  The element's geometry and
+// nodal forcing are loaded here and its RK base after the area integrals,
+// so none of them holds registers through the earlier phases (that is what
+// lets the stage kernel run 3 waves per SIMD in FP64).
 template <class QT>
-HD double phase_area(const Params &p, const ChunkInfo &k, const Lds<QT> &L, const ElemPre<QT> &P, bool base,
-                     double ca, double cb, St<QT> wout, size_t ne, double dt, int want_dt, int i, bool &bad) {
+HD double phase_area(const DevMesh &m, const DevState &s, const Params &p, const ChunkInfo &k, const Lds<QT> &L,
+                     const ElemPre<QT> &P0, const int node[3], const CSt<QT> &wb, bool base, double ca, double cb,
+                     St<QT> wout, size_t ne, double dt, int want_dt, int i, bool &bad) {
   const size_t e = (size_t)(k.c0 + i);
+  ElemPre<QT> P = P0;
+  GeoReg<QT> G;
+  load_geo(m, k, i, G, P.inr2);
+  load_elem_forcing<QT>(m, s, node, P);
+  for (int q = 0; q < 3; ++q) P.h[q] = L.LH[q * L.nls + i];
   double z[3];
   QT q[6];
   for (int j = 0; j < 3; ++j) z[j] = L.SZ[j * L.nls + i];
   for (int j = 0; j < 6; ++j) q[j] = L.SQ[j * L.nls + i];
   const bool wet = L.WET[i] != 0;
+  if (!wet) q[0] = q[3] = (QT)0;  // a dry element's momentum is zero
   double rz[3];
   QT rq[6];
-  area_terms<QT>(z, q, wet, P, L.GG[i], L.GG[L.cs + i], L.GG[2 * L.cs + i], L.GG[3 * L.cs + i], p, rz, rq);
+  area_terms<QT>(z, q, wet, P, G.g[0], G.g[1], G.g[2], G.g[3], p, rz, rq);
+  if (base) {
+    for (int j = 0; j < 3; ++j) P.wbz[j] = wb.z[j * ne + e];
+    for (int j = 0; j < 6; ++j) P.wbq[j] = wb.q[j * ne + e];
+  }
   // fixed-order gather of the three edges: R_k / A -= edge_k / A (the zeta
   // rows in FP64, so each edge's mass moment cancels between its sides)
-  const double iAd = rcp_nr(L.GA[i]);
+  const double iAd = rcp_nr(G.area);
   const QT iA = (QT)iAd;
   for (int l = 0; l < 3; ++l) {
     const int code = P.ledge[l];
@@ -718,10 +726,7 @@ __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CS
   const int j0 = tid < k.ne_loc ? tid : k.ne_loc - 1, j1 = tid + NT < k.ne_loc ? tid + NT : k.ne_loc - 1;
   load_edge_rec(m, k, j0, r0);
   load_edge_rec(m, k, j1, r1);
-  GeoReg<QT> geo;
-  load_geo(m, k, cei, geo, pre.inr2);
   const bool use_base = STAGE != 0 && sc.a != 0.0;
-  load_elem_pre<QT>(m, k, cei, use_base ? &wbase : nullptr, pre);
   pre.manning = manning_of(m, k, cei, (QT)0);
   pre.coriolis = (QT)F.coriolis;
   pre.rain = F.rain;
@@ -733,7 +738,6 @@ __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CS
   StateReg<QT> st0, st1;
   load_state_reg<QT>(win, ne, g0, st0);
   load_state_reg<QT>(win, ne, g1, st1);
-  load_elem_forcing<QT>(m, s, node, pre);
   const double mz2 = win.z[g2];
   const QT mx2 = win.q[g2], my2 = win.q[3 * ne + g2];
   // Every lane reads its member's status word, dt, time and post-processing
@@ -746,7 +750,7 @@ __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CS
   const double t0 = ctl->t[slot];
   const int pp_in = STAGE == 0 ? ctl->pp_in : 1;
   const bool tide = F.n_tide > 0 || F.tide_offset != 0.0;
-  for (int j = tid + NT; j < k.n2; j += NT) load_h2_lds<QT>(L, win, ne, nl, j, m.h2[k.h2o + j]);
+  for (int j = tid + NT; j < k.n2; j += NT) load_h2_lds<QT>(L, win, ne, j, m.h2[k.h2o + j]);
   // the go/no-go decision (uniform unless the status changes while the
   // workgroup reads it)
   double dt = 0.0;
@@ -768,13 +772,11 @@ __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CS
     store_state_lds<QT>(L, i1, st1);
     for (int q = 0; q < 3; ++q) L.LH[q * L.nls + i1] = h1[q];
   }
-  if (ae) store_geo_lds<QT>(L, tid, geo);
   if (a2) {
     L.MZ[tid] = mz2;
-    L.MQ[nl + tid] = mx2;
-    L.MQ[L.nms + nl + tid] = my2;
+    L.MQ[tid] = mx2;
+    L.MQ[L.n2s + tid] = my2;
   }
-  for (int q = 0; q < 3; ++q) pre.h[q] = h0[q];
   __syncthreads();
   const bool to_wpp = STAGE == 0 && active;
   if (a0) phase_post<QT, VL>(p, k, L, pp_in, i0, h0, nb0, to_wpp, wpp, ne, s.vb, ev0);
@@ -786,7 +788,8 @@ __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CS
   double cand = INFINITY;
   bool bad = false;
   if (ae && active)
-    cand = phase_area<QT>(p, k, L, pre, use_base, sc.a, sc.b, wout, ne, sc.h * dt, want_dt, tid, bad);
+    cand = phase_area<QT>(m, s, p, k, L, pre, node, wbase, use_base, sc.a, sc.b, wout, ne, sc.h * dt, want_dt,
+                          tid, bad);
   if (bad) atomicCAS(&ctl->status, 0, (int)DGSWE_E_NONFINITE);
   if (want_dt) {
     const double bm = block_min<NT>(cand, red);

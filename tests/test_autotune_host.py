@@ -53,13 +53,14 @@ def fakes(monkeypatch):
 def test_median_of_repeats():
     """each candidate is timed `repeats` times and its median kept"""
     mesh = types.SimpleNamespace(n_elems=12_000)
-    COST.update({(64, 0): 3e-5, (128, 0): 2e-5, (192, 0): 2.5e-5, (256, 0): 2.8e-5})
+    COST.update({(0, 0): 2.2e-5, (64, 0): 3e-5, (128, 0): 2e-5, (192, 0): 2.5e-5, (256, 0): 2.8e-5})
     best, table = AT.tune(mesh, {"p": 1, "precision": 0}, {}, None, steps=10, repeats=5)
-    assert best["chunk"] == 128 and len(table) == 4
+    assert best["chunk"] == 128 and len(table) == 5
 
 
 def test_candidates():
-    assert AT.candidates({"p": 1}) == [(64, 0), (128, 0), (192, 0), (256, 0)]
+    assert AT.candidates({"p": 1}) == [(0, 0), (64, 0), (128, 0), (192, 0), (256, 0)]
+    assert AT.candidates({"p": 1}, auto=False) == [(64, 0), (128, 0), (192, 0), (256, 0)]
     c2 = AT.candidates({"p": 2})
     assert len(c2) == 8 and {w for _, w in c2} == {2, 3} and {c for c, _ in c2} == {64, 128, 192, 256}
 
