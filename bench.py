@@ -177,11 +177,13 @@ CMD_PMC = ("rocprofv3 --pmc {c} -d $OUT/pmc/{c} -o run --output-format csv -- py
 CMD_SUMMARIZE = ("cd $REPO && python3 bench.py --summarize-pmc $OUT/pmc --kernel-trace $OUT/prof/bench_kernel_trace.csv "
                  "--ensemble-kernel-trace $OUT/prof_ens/bench_kernel_trace.csv --summary-md "
                  "profiles/k_stage_hurricane_4M.md")
-ENSEMBLE_PROFILE_CHUNK = 256
+# the ensemble's launch parameters in its benched line and profiles: the
+# library's defaults (chunk 0: chosen per mesh; p = 2 register budget 0)
+ENSEMBLE_DEFAULTS = {1: {"chunk": 0, "waves": 0}, 2: {"chunk": 0, "waves": 0}}
 CMD_TRACE_ENS = ("rocprofv3 --kernel-trace --stats -d $OUT/prof_ens -o bench --output-format csv -- "
-                 "python3 $REPO/bench.py --only-batched --ensemble-chunk 256 --steps 50 --warmup 5 --no-profile")
+                 "python3 $REPO/bench.py --only-batched --no-ensemble-autotune --steps 50 --warmup 5 --no-profile")
 CMD_PMC_ENS = ("rocprofv3 --pmc {c} -d $OUT/pmc/ensemble/{c} -o run --output-format csv -- python3 $REPO/bench.py "
-               "--only-batched --ensemble-chunk 256 --steps 3 --warmup 1 --no-profile --copy-probe")
+               "--only-batched --no-ensemble-autotune --steps 3 --warmup 1 --no-profile --copy-probe")
 
 
 def _pmc_rows(pmc_dir, tag):
@@ -318,7 +320,7 @@ def summarize_pmc(pmc_dir: str, trace_csv: str | None, out_md: str | None, ens_t
     ens_dir = os.path.join(pmc_dir, "ensemble")
     if os.path.isdir(ens_dir):
         res["ensemble_calibration"], per = _pmc_traffic(ens_dir, True)
-        res["ensemble_chunk"] = ENSEMBLE_PROFILE_CHUNK
+        res["ensemble_launch"] = "library defaults (chunk 0, waves 0)"
         res["ensemble"] = {}
         for (k, prec), r in per.items():
             res["ensemble"].setdefault(k, {})[prec] = r
@@ -386,8 +388,8 @@ def summarize_pmc(pmc_dir: str, trace_csv: str | None, out_md: str | None, ens_t
            CMD_PMC_ENS.format(c="WRITE_SIZE"),
            CMD_SUMMARIZE,
            "```", "",
-           "One bench process (chunks of 256 elements for both orders, the size the autotuner picks in the "
-           "benched run) advances the ensemble in each arrangement (two streams; the pair with the p = 1 stage and the p = 2 "
+           "One bench process (the library's default launch parameters: chunk sizes chosen per mesh) "
+           "advances the ensemble in each arrangement (two streams; the pair with the p = 1 stage and the p = 2 "
            "post-processing in one launch, then the p = 2 right-hand side; both orders' stage work in one "
            "launch; persistent workgroups), then all 64 members at p = 1.", "",
            f"Kernel sources sha256: `{res['source_sha256']}`", ""]
@@ -625,10 +627,8 @@ def tune_ensemble_orders(ens, orders, stream):
         w = ens[idx[len(idx) // 2]]
         prm = dict(w.params, precision=DGSWE_MIXED, p=p, **({"cfl": 0.1} if p == 2 else {}))
         w0 = w.w0 if p == 1 else np.concatenate([w.w0, np.zeros((3, 3, w.w0.shape[2]))], axis=1)
-        # explicit chunk sizes only (no "0: the library's choice"), so the
-        # measured ensemble traffic can be matched to the chunk size it ran at
         best, table = tune(w.mesh, prm, w.forcing, w0, w.postprocess_initial, steps=20, hip_stream=stream.cuda_stream,
-                           use_cache=False, auto=False)
+                           use_cache=False)
         out[p] = {k: best[k] for k in ("chunk", "waves")}
         tables[p] = {"mesh_elems": w.mesh.n_elems,
                      "us_per_step": {f"chunk {r[0]}, waves {r[1]}": round(r[2], 1) for r in table}}
@@ -695,8 +695,9 @@ def measure_ensemble(ens, steps, warmup, stream, profile, tuned=None, fused=True
            "persistent": persistent, "chunk_params": op, "kernels": kernels,
            "note": "element-stages of both orders counted alike; a p = 2 element-stage does about 2.6x the work"}
     if kernels:
-        # the ensemble's measured traffic belongs to its profiled chunk size
-        same = all(op[o].get("chunk", 256) == ENSEMBLE_PROFILE_CHUNK for o in (1, 2))
+        # the ensemble's measured traffic belongs to its profiled launch
+        # parameters (the library's defaults)
+        same = persistent == 0 and all(op[o].get(k, 0) == v for o in (1, 2) for k, v in ENSEMBLE_DEFAULTS[o].items())
         rec["roofline"] = roofline(kernels, {1: ne[1], 2: ne[2]}, ned, nn, "mixed", with_traffic=same,
                                    section="ensemble")
     return rec
@@ -801,8 +802,11 @@ def roofline(kernels, ne, ned, nn, precision, with_traffic=True, section="kernel
 
 
 def measure_batched(args, stream, profile):
-    """The batched ensemble variants: the best arrangement as "batched",
-    the others under "batched_modes", and all 64 members at p = 1."""
+    """The batched ensemble variants: the library's default arrangement
+    (dgswe_step_pair, "pair") at the library's default launch parameters as
+    "batched" (what its profiles measure), the other arrangements and the
+    autotuner's launch parameters under "batched_modes", and all 64 members
+    at p = 1."""
     from paper_2508_21208_amd import workloads as W
     variants = {}
     t0 = time.perf_counter()
@@ -810,10 +814,8 @@ def measure_batched(args, stream, profile):
     orders = W.ensemble_orders(len(ens))
     log(f"ensemble: {len(ens)} members, {sum(w.mesh.n_elems for w in ens)} elements, generated in "
         f"{time.perf_counter() - t0:.1f} s")
-    if args.ensemble_chunk:
-        tuned, tables = {1: dict(chunk=args.ensemble_chunk), 2: dict(chunk=args.ensemble_chunk)}, None
-    else:
-        tuned, tables = tune_ensemble_orders(ens, orders, stream)
+    defaults = {o: dict(v) for o, v in ENSEMBLE_DEFAULTS.items()}
+    tuned, tables = (None, None) if args.no_ensemble_autotune else tune_ensemble_orders(ens, orders, stream)
     # how the two orders' batches are advanced: each batch on its own
     # stream (they overlap on the GPU), or together by dgswe_step_pair
     # on one stream (per stage the p = 1 stage with the p = 2
@@ -828,17 +830,20 @@ def measure_batched(args, stream, profile):
         if env:
             os.environ[env] = "0"
         try:
-            modes[name] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
+            modes[name] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=defaults,
                                            orders=orders, **kw)
         finally:
             if env:
                 del os.environ[env]
         log(f"ensemble {name}: {modes[name]['ms_per_step']:.3f} ms per step")
-    best = min(modes, key=lambda k: modes[k]["ms_per_step"])
-    variants["batched"] = dict(modes[best], mode=best, autotune=tables,
+    if tuned is not None:
+        modes["pair_autotuned"] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
+                                                   orders=orders, fused=True)
+        log(f"ensemble pair_autotuned: {modes['pair_autotuned']['ms_per_step']:.3f} ms per step")
+    variants["batched"] = dict(modes["pair"], mode="pair", autotune=tables,
                                modes_ms_per_step={k: v["ms_per_step"] for k, v in modes.items()})
-    variants["batched_modes"] = {k: v for k, v in modes.items() if k != best}
-    variants["batched_p1_only"] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=tuned,
+    variants["batched_modes"] = {k: v for k, v in modes.items() if k != "pair"}
+    variants["batched_p1_only"] = measure_ensemble(ens, args.steps, args.warmup, stream, profile, tuned=defaults,
                                                    orders=[1] * len(ens))
     del ens
     return variants
@@ -888,9 +893,8 @@ def main():
                     help="no GPU run: tabulate the issue/wait/cache counter runs c1, c2 under DIR")
     ap.add_argument("--counter-kernels", default="k_stage", help="with --summarize-counters: kernels to tabulate")
     ap.add_argument("--ensemble-kernel-trace", help="with --summarize-pmc: kernel_trace.csv of an --only-batched run")
-    ap.add_argument("--ensemble-chunk", type=int, default=0,
-                    help="chunk size of both orders in the ensemble runs instead of the autotuner's choice (so "
-                         "that separate profiler runs launch the same grids)")
+    ap.add_argument("--no-ensemble-autotune", action="store_true",
+                    help="skip the ensemble's autotuned mode (the profiles measure the default launch parameters)")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched ensemble variants (for the ensemble's profiles); prints them")
     args = ap.parse_args()
