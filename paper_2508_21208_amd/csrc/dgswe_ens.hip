@@ -47,8 +47,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     int c = 0;
     const int which = item12_of_block(b, m1.nch, m2.nch, c);
     if (which == 1)
-      stage1_chunk<kBlock, QT, STAGE, false>(m1, s1, p1, win1, wbase1, wout1, wpp1, sc, slot1, want_dt1, c, lds_raw,
-                                             red);
+      // (phase A's nodal forcing loaded in phase A: the p = 2 work shares
+      // the registers)
+      stage1_chunk<kBlock, QT, STAGE, false, false>(m1, s1, p1, win1, wbase1, wout1, wpp1, sc, slot1, want_dt1, c,
+                                                    lds_raw, red);
     else if (which == 2)
       rhs2_chunk<QT>(m2, s2, p2, rec2, base2, wout2, sc, slot2, want_dt2, c, lds_raw, red);
   };
@@ -79,8 +81,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     int c = 0;
     const int which = item12_of_block(b, m1.nch, m2.nch, c);
     if (which == 1)
-      stage1_chunk<kBlock, QT, STAGE, false>(m1, s1, p1, win1, wbase1, wout1, wpp1, sc, slot1, want_dt1, c, lds_raw,
-                                             red);
+      // (phase A's nodal forcing loaded in phase A: the p = 2 work shares
+      // the registers)
+      stage1_chunk<kBlock, QT, STAGE, false, false>(m1, s1, p1, win1, wbase1, wout1, wpp1, sc, slot1, want_dt1, c,
+                                                    lds_raw, red);
     else if (which == 2)
       pp2_chunk<QT, STAGE>(m2, s2, p2, win2, rec2, slot2, c);
   };

@@ -275,7 +275,7 @@ size_t stage_lds_bytes(const DevMesh &m, int precision);
 // LDS one stage-kernel workgroup may use (two workgroups share a CU's 160 KB)
 constexpr size_t kStageLdsMax = 80 * 1024;
 // LDS of a gfx950 compute unit, and the workgroups of the p = 1 stage kernel
-// its registers allow per CU (152 VGPRs in FP64: 3 waves per SIMD; 100-108 in
+// its registers allow per CU (164 VGPRs in FP64: 3 waves per SIMD; 124 in
 // mixed precision: 4); kLdsSlack covers the kernel's static LDS and the
 // allocation granularity
 constexpr size_t kLdsPerCu = 160 * 1024;

@@ -7,9 +7,9 @@
 //   L  load the chunk and its ring-1 halo (full state) and the ring-2 halo
 //      (means) of the previous stage's UNLIMITED result, and issue the loads
 //      of phases P and E (bathymetry, neighbour lists, edge records) so they
-//      arrive while L completes (phase A loads its own: geometry, nodal
-//      forcing, RK base - registers held from L through E would cost the
-//      third wave per SIMD);
+//      arrive while L completes (phase A's inputs - geometry, nodal forcing,
+//      RK base - are requested after phase P or in phase A: registers held
+//      from L through E would cost the third wave per SIMD);
 //   P  slope limiter + wet/dry of the chunk and ring 1 (the paper's SLOPELIM
 //      and WETDRY kernels), so every state the edges need is post-processed;
 //   E  each edge touching the chunk: traces of both sides at the three

@@ -215,9 +215,10 @@ HD int edge_flux(const double zp[3], const R qp[6], const double zm[3], const R 
 
 // Per-element inputs of the area integrals and of the RK update: Manning n,
 // the member's Coriolis parameter and rain rate and the chunk-local edges
-// (loaded in phase L), vertex bathymetry, wind stress at the vertices, the
-// pressure gradient modes and 2 x inradius (phase A) and (second stage) the
-// post-processed RK base (phase A, after the area integrals).
+// (loaded in phase L), 2 x inradius (after phase P), wind stress at the
+// vertices and the pressure gradient modes (after phase P in the mixed path,
+// in phase A in FP64), vertex bathymetry (phase A, from LDS) and (second
+// stage) the post-processed RK base (phase A, after the area integrals).
 template <class QT>
 struct ElemPre {
   double h[3];
@@ -596,22 +597,21 @@ HD void load_elem_forcing(const DevMesh &m, const DevState &s, const int node[3]
   P.pm2 = (QT)((2.0 * dp2 - dp1) * (1.0 / 6.0));
 }
 
-// phase A for chunk element i (node: its node ids); returns the CFL
-// candidate of the output when want_dt, and sets bad on a non-finite
-// output.  base: combine with the post-processed RK base wb, out = a base +
-// b (w + hdt L(w)), else out = w + hdt L(w).  The element's geometry and
-// nodal forcing are loaded here and its RK base after the area integrals,
-// so none of them holds registers through the earlier phases (that is what
-// lets the stage kernel run 3 waves per SIMD in FP64).
-template <class QT>
+// phase A for chunk element i (node: its node ids; G: its geometry);
+// returns the CFL candidate of the output when want_dt, and sets bad on a
+// non-finite output.  base: combine with the post-processed RK base wb, out
+// = a base + b (w + hdt L(w)), else out = w + hdt L(w).  The RK base is
+// loaded after the area integrals and, unless P0 holds it already (the
+// mixed path), the nodal forcing at the start, so they hold no registers
+// through the earlier phases (that is what lets the stage kernel run 3
+// waves per SIMD in FP64).
+template <class QT, bool FORCING_IN_P0>
 HD double phase_area(const DevMesh &m, const DevState &s, const Params &p, const ChunkInfo &k, const Lds<QT> &L,
-                     const ElemPre<QT> &P0, const int node[3], const CSt<QT> &wb, bool base, double ca, double cb,
-                     St<QT> wout, size_t ne, double dt, int want_dt, int i, bool &bad) {
+                     const ElemPre<QT> &P0, const int node[3], const GeoReg<QT> &G, const CSt<QT> &wb, bool base,
+                     double ca, double cb, St<QT> wout, size_t ne, double dt, int want_dt, int i, bool &bad) {
   const size_t e = (size_t)(k.c0 + i);
   ElemPre<QT> P = P0;
-  GeoReg<QT> G;
-  load_geo(m, k, i, G, P.inr2);
-  load_elem_forcing<QT>(m, s, node, P);
+  if (!FORCING_IN_P0) load_elem_forcing<QT>(m, s, node, P);
   for (int q = 0; q < 3; ++q) P.h[q] = L.LH[q * L.nls + i];
   double z[3];
   QT q[6];
@@ -683,7 +683,7 @@ HD double phase_area(const DevMesh &m, const DevState &s, const Params &p, const
 // its member's forcing and control block.  The first stage also writes the
 // post-processed w^n of its chunk to wpp, the RK base that the second stage
 // reads.
-template <int NT, class QT, int STAGE, bool VL>
+template <int NT, class QT, int STAGE, bool VL, bool FE = (sizeof(QT) == 4)>
 __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CSt<QT> win, CSt<QT> wbase,
                                              St<QT> wout, St<QT> wpp, StageCoef sc, int slot, int want_dt, int c,
                                              double *lds_raw, double *red) {
@@ -782,14 +782,21 @@ __device__ __forceinline__ void stage1_chunk(DevMesh m, DevState s, Params p, CS
   if (a0) phase_post<QT, VL>(p, k, L, pp_in, i0, h0, nb0, to_wpp, wpp, ne, s.vb, ev0);
   if (a1) phase_post<QT, VL>(p, k, L, pp_in, i1, h1, nb1, to_wpp, wpp, ne, s.vb, ev1);
   __syncthreads();
+  // phase A's geometry (and with FE - by default in the mixed path, where
+  // the registers allow - its nodal forcing) requested now, so it arrives
+  // during phase E
+  constexpr bool kForcingEarly = FE;
+  GeoReg<QT> geo;
+  load_geo(m, k, cei, geo, pre.inr2);
+  if (kForcingEarly) load_elem_forcing<QT>(m, s, node, pre);
   if (tid < k.ne_loc) phase_edge<QT>(p, L, zb, tid, r0);
   if (tid + NT < k.ne_loc) phase_edge<QT>(p, L, zb, tid + NT, r1);
   __syncthreads();
   double cand = INFINITY;
   bool bad = false;
   if (ae && active)
-    cand = phase_area<QT>(m, s, p, k, L, pre, node, wbase, use_base, sc.a, sc.b, wout, ne, sc.h * dt, want_dt,
-                          tid, bad);
+    cand = phase_area<QT, kForcingEarly>(m, s, p, k, L, pre, node, geo, wbase, use_base, sc.a, sc.b, wout, ne,
+                                         sc.h * dt, want_dt, tid, bad);
   if (bad) atomicCAS(&ctl->status, 0, (int)DGSWE_E_NONFINITE);
   if (want_dt) {
     const double bm = block_min<NT>(cand, red);
