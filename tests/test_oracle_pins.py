@@ -414,6 +414,51 @@ def test_wetdry_invariants():
     assert np.allclose(Hv.mean(axis=1), Hbar, atol=1e-12)
 
 
+def test_wetdry_postprocess_single_element_closed_form():
+    """Wet/dry post-processing of one element (reading Z9), worked by hand
+    on a single triangle (limiter off, H0 = 0.01 m), vertex depths H_v:
+      * (0.0, 0.05, 0.11): one vertex short by D = 0.01, surplus above H0
+        S = 0.04 + 0.10 = 0.14, so the others give D in proportion to their
+        surplus: (0.01, 0.05 - 0.01 * 4/14, 0.11 - 0.01 * 10/14);
+      * (-0.02, 0.005, 0.2): two vertices short (D = 0.035), one donor:
+        (0.01, 0.01, 0.165);
+      * (0.0, 0.0, 0.045): mean depth 0.015, just above H0, so still wet
+        (D = 0.02, one donor): (0.01, 0.01, 0.025);
+      * (-0.03, 0.01, 0.035): mean depth 0.005 <= H0, dry: flat at 0.005,
+        momentum zero;
+      * (0.01, 0.5, 1.0): no vertex below H0: unchanged, bitwise.
+    In every case the zeta mean (mode 0) is kept bitwise, and a wet
+    element's momentum is untouched."""
+    xy = np.array([[0.0, 0.0], [100.0, 0.0], [0.0, 100.0]])
+    hb = np.array([-1.0, 2.0, 3.0])
+    tri = np.array([[0, 1, 2]], np.int32)
+    bnd = np.array([[0, 1], [1, 2], [2, 0]], np.int32)
+    m = W.Mesh(xy, hb, tri, bnd, np.full(3, W.BC_LAND, np.int32))
+    o = O.Oracle(m, W.default_params(limiter=0), W.default_forcing())
+    cases = (
+        ((0.0, 0.05, 0.11), (0.01, 0.05 - 0.01 * 4 / 14, 0.11 - 0.01 * 10 / 14), False),
+        ((-0.02, 0.005, 0.2), (0.01, 0.01, 0.165), False),
+        ((0.0, 0.0, 0.045), (0.01, 0.01, 0.025), False),
+        ((-0.03, 0.01, 0.035), (0.005, 0.005, 0.005), True),
+        ((0.01, 0.5, 1.0), (0.01, 0.5, 1.0), False),
+    )
+    q = np.array([[0.3, -0.1, 0.05], [-0.2, 0.04, 0.02]])  # momentum modes
+    for Hv, expect, dry in cases:
+        w = np.zeros((3, 3, 1))
+        w[0, :, 0] = W.modes_from_vertices(np.array(Hv) - hb)
+        w[1:, :, 0] = q
+        out = o.postprocess(w)
+        assert out[0, 0, 0] == w[0, 0, 0]
+        got = _vertices(out[0][None])[0, 0] + hb
+        assert np.allclose(got, expect, rtol=0.0, atol=1e-14), (Hv, got)
+        if dry:
+            assert np.all(out[1:] == 0.0)
+        else:
+            assert np.array_equal(out[1:], w[1:])
+        if Hv == expect:
+            assert np.array_equal(out, w)
+
+
 # ---------------------------------------------------------------- integral invariants
 def test_lake_at_rest_is_preserved():
     """Well-balancedness: zeta = const, Q = 0 over varying bathymetry stays at rest."""
